@@ -1,0 +1,177 @@
+"""Layered primitive equations of Section 2 (oracle; test infrastructure only).
+
+Layers k = 0 .. L-1 run from the surface down; layer interfaces i = 0 .. L,
+interface i being the top of layer i.  Velocity and thickness sit at layer
+mid-depth, the vertical velocity w at interfaces (Section 2, vertical
+staggering).  Notation follows the paper:
+
+* \\bar(phi)^m_k = (phi_k + phi_{k+1}) / 2            (interfaces -> layer)
+* D_{z^m}(phi)_k = (phi_k - phi_{k+1}) / h_k            (interfaces -> layer)
+* D_{z^t}(phi)_k = (phi_{k-1} - phi_k) / \\bar(h)^t_k    (layers -> interface)
+
+Readings of what the paper leaves to MPAS (each stated where it is used):
+
+* thickness at edges is the mean of the two cells (h_e);
+* hydrostatic pressure (hydrocon) with zero surface pressure; the pressure
+  gradient in tilted layers is [grad p + g rho_e grad z_mid] / rho0 with
+  z_mid = -H + sum_{l>k} h_l + h_k/2, evaluated from the differences of the two
+  columns (algebraically the difference of the two hydrostatic sums);
+* z-star: the layer-thickness tendency is the column-total thickness-flux
+  divergence distributed by the reference thickness fractions, and w follows
+  from the thickness equation upwards from w_{L} = 0; isopycnal: w = 0;
+* vertical boundary conditions: w = 0 at the surface and the bottom, no
+  surface stress, bottom stress c_drag |u| u at the lowest layer (the drag
+  condition of Section 5), with |u|^2 = K_c1 + K_c2 of the bottom layer.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import trisk
+
+
+@dataclass
+class Setup:
+    """Static inputs of a run: mesh, parameters and frozen column data."""
+    mesh: object
+    params: object
+    H: np.ndarray          # (C,) bottom depth
+    h_ref: np.ndarray      # (C, L)
+    rho: np.ndarray        # (C, L)
+    cell_mask: np.ndarray  # (C,) bool
+    edge_mask: np.ndarray  # (E,) bool
+
+    @classmethod
+    def from_case(cls, case) -> "Setup":
+        cm = case.cell_mask.astype(bool)
+        c = case.mesh.cellsOnEdge
+        return cls(case.mesh, case.params, case.H.astype(float), case.h_ref.astype(float),
+                   case.rho.astype(float), cm, cm[c[:, 0]] & cm[c[:, 1]])
+
+    @property
+    def L(self) -> int:
+        return self.h_ref.shape[1]
+
+
+def colsum(x: np.ndarray) -> np.ndarray:
+    """sum_{k=1}^{L} x_k, accumulated from the top layer down."""
+    acc = np.zeros(x.shape[0])
+    for k in range(x.shape[1]):
+        acc = acc + x[:, k]
+    return acc
+
+
+def safe_ratio(num: np.ndarray, den: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """num / den on active entities, 0 elsewhere (dry edges have den = 0)."""
+    out = np.zeros_like(num)
+    np.divide(num, den, out=out, where=mask)
+    return out
+
+
+def mask_edges(x: np.ndarray, st: Setup) -> np.ndarray:
+    m = st.edge_mask if x.ndim == 1 else st.edge_mask[:, None]
+    return np.where(m, x, 0.0)
+
+
+def D_zt(phi: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """D_{z^t}(phi) at interior interfaces 1..L-1; 0 at the surface and the bottom."""
+    N, L = phi.shape
+    out = np.zeros((N, L + 1))
+    hbar_t = 0.5 * (h[:, :-1] + h[:, 1:])
+    np.divide(phi[:, :-1] - phi[:, 1:], hbar_t, out=out[:, 1:L], where=hbar_t > 0)
+    return out
+
+
+def thickness_flux_divergence(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
+    """div(h_k u_k) per layer, with h at edges the mean of the two cells."""
+    flux = mask_edges(trisk.cell_to_edge(h, st.mesh) * u, st)
+    return trisk.divergence(flux, st.mesh)
+
+
+def vertical_velocity(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
+    """w at the L+1 interfaces of every column (Section 2, z-star paragraph).
+
+    z-star keeps each layer a fixed fraction of the column, so the thickness
+    tendency of layer k is h_ref_k / sum h_ref times minus the column-total
+    flux divergence; (layerthickness) then fixes w_k - w_{k+1}, integrated
+    upwards from w = 0 at the bottom.  Isopycnal: w = 0.
+    """
+    C, L = h.shape
+    w = np.zeros((C, L + 1))
+    if st.params.vcoord == 1:
+        return w
+    div = thickness_flux_divergence(h, u, st)
+    frac = safe_ratio(st.h_ref, colsum(st.h_ref)[:, None], st.cell_mask[:, None])
+    th = -frac * colsum(div)[:, None]
+    for k in range(L - 1, -1, -1):
+        w[:, k] = w[:, k + 1] - div[:, k] - th[:, k]
+    return np.where(st.cell_mask[:, None], w, 0.0)
+
+
+def T_h(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
+    """T^h_k(h, u) = -div(h_k u_k) - D_{z^m}(w)_k h_k  (Section 2, grouping T^h)."""
+    div = thickness_flux_divergence(h, u, st)
+    w = vertical_velocity(h, u, st)
+    th = -div - (w[:, :-1] - w[:, 1:])
+    return np.where(st.cell_mask[:, None], th, 0.0)
+
+
+def pressure_gradient_force(h: np.ndarray, st: Setup) -> np.ndarray:
+    """-(1/rho0) grad p_k in z-star layers, normal component at edges.
+
+    p_k = sum_{l<k} rho_l g h_l + rho_k g h_k / 2 (hydrocon, p^s = 0) and
+    z_k = -H + sum_{l>k} h_l + h_k / 2; the force is
+    -[(p_c2 - p_c1) + g rho_e (z_c2 - z_c1)] / (rho0 d_e), with both column
+    differences summed from the per-layer differences.
+    """
+    m, p = st.mesh, st.params
+    c1, c2 = m.cellsOnEdge[:, 0], m.cellsOnEdge[:, 1]
+    E, L = m.nEdges, h.shape[1]
+    drh = st.rho[c2] * h[c2] - st.rho[c1] * h[c1]
+    dh = h[c2] - h[c1]
+    dp = np.zeros((E, L))
+    acc = np.zeros(E)
+    for k in range(L):
+        dp[:, k] = p.gravity * (acc + 0.5 * drh[:, k])
+        acc = acc + drh[:, k]
+    dz = np.zeros((E, L))
+    acc = np.zeros(E)
+    dH = st.H[c2] - st.H[c1]
+    for k in range(L - 1, -1, -1):
+        dz[:, k] = -dH + acc + 0.5 * dh[:, k]
+        acc = acc + dh[:, k]
+    rho_e = 0.5 * (st.rho[c1] + st.rho[c2])
+    return -(dp + p.gravity * rho_e * dz) / (p.rho0 * m.dcEdge[:, None])
+
+
+def T_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
+    """T^u_k(u) = -grad|u|^2/2 - (k.curl u) u^perp - \\bar(w D_{z^t} u)^m - grad p/rho0 + nu_h lap u."""
+    m, p = st.mesh, st.params
+    he = trisk.cell_to_edge(h, m)
+    K = trisk.kinetic_energy(u, m)
+    q = trisk.vorticity_on_edges(trisk.curl(u, m), m)
+    vort = trisk.tangential_flux(q, u, m)
+    w_e = trisk.cell_to_edge(vertical_velocity(h, u, st), m)
+    w_e[:, 0] = 0.0
+    w_e[:, -1] = 0.0
+    wdz = w_e * D_zt(u, he)
+    vadv = 0.5 * (wdz[:, :-1] + wdz[:, 1:])
+    tu = (-trisk.gradient(K, m) + vort - vadv + pressure_gradient_force(h, st)
+          + p.nu_h * trisk.laplacian(u, m))
+    return mask_edges(tu, st)
+
+
+def D_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
+    """D^u_k(u) = D_{z^m}(nu_v D_{z^t}(u))_k with no surface stress and bottom drag."""
+    m, p = st.mesh, st.params
+    he = trisk.cell_to_edge(h, m)
+    tau = p.nu_v * D_zt(u, he)
+    K = trisk.kinetic_energy(u, m)
+    kb = K[:, -1]
+    speed = np.sqrt(kb[m.cellsOnEdge[:, 0]] + kb[m.cellsOnEdge[:, 1]])
+    tau[:, 0] = 0.0
+    tau[:, -1] = p.c_drag * speed * u[:, -1]
+    du = safe_ratio(tau[:, :-1] - tau[:, 1:], he, st.edge_mask[:, None])
+    return mask_edges(du, st)
