@@ -1,0 +1,209 @@
+/*
+ * ssprkse.h -- C ABI of the MI355X (gfx950) split-explicit ocean step.
+ *
+ * Implements one step of the SSPRK2-SE / SSPRK3-SE multirate schemes of
+ * Lan, Ju, Wang, Gunzburger & Jones, "High-Order Multirate Explicit
+ * Time-Stepping Schemes for the Baroclinic-Barotropic Split Dynamics in
+ * Primitive Equations" (arXiv 2105.13484), on an unstructured TRiSK C-grid:
+ *
+ *   - the baroclinic forward-Euler stages (Algorithm 1, Section 3.1) over all
+ *     layers at the large step dt,
+ *   - the barotropic SSPRK2 / SSPRK3 substep loops (Algorithms 3 and 4) at
+ *     dt / M with the interpolated forcing Interp_2 / Interp_3 (force2,
+ *     force3),
+ *   - the layer-thickness stages with the flux-form SSH reconciliation of
+ *     Section 3.4.
+ *
+ * Memory model: the library never allocates device memory.  The caller
+ * provides one device buffer for each mesh and one for each state (sizes
+ * from sse_mesh_device_bytes / sse_state_workspace_bytes) and a HIP stream;
+ * all kernels run on that stream.  Host-side handles are malloc'd by the
+ * library and freed by the *_destroy calls.
+ *
+ * Numbering: all host arrays passed in or out use the caller's entity
+ * numbering; indices are 0-based int32, -1 marks an absent neighbour.
+ * 3D arrays are row-major [entity][layer], layer 0 at the surface.
+ *
+ * Errors: every call returns an sse_status; on failure sse_last_error()
+ * returns a thread-local message.  No call throws.  Calls on one handle are
+ * not thread-safe; different handles may be used from different threads.
+ */
+#ifndef SSPRKSE_H
+#define SSPRKSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSE_OK = 0,
+    SSE_EINVAL = 1,      /* invalid argument, mesh table or parameter        */
+    SSE_ENOMEM = 2,      /* caller buffer smaller than the size required      */
+    SSE_EDEVICE = 3,     /* a HIP runtime call failed                         */
+    SSE_ENONFINITE = 4,  /* NaN/Inf in the input or produced by a step        */
+    SSE_ESTATE = 5       /* handle used in the wrong state (e.g. not initialised) */
+} sse_status;
+
+enum { SSE_SCHEME_SSPRK2 = 2, SSE_SCHEME_SSPRK3 = 3 };
+enum { SSE_FP64 = 0, SSE_MIXED = 1 };
+enum { SSE_ZSTAR = 0, SSE_ISOPYCNAL = 1 };
+/* Reconciliation of Section 3.4: OFF sets u^A = 0; EXACT uses the fluxes the
+ * thickness actually received in earlier stages (F^zeta_1, F^zeta_2) inside
+ * F^h of the averaged final stage, so the layer SSH equals the barotropic
+ * SSH at every stage; LITERAL uses the printed F^h_2 (SSPRK2-SE) and F^h_3
+ * (SSPRK3-SE). */
+enum { SSE_RECONCILE_OFF = 0, SSE_RECONCILE_EXACT = 1, SSE_RECONCILE_LITERAL = 2 };
+
+/*
+ * Mesh description (host memory, caller numbering; copied by
+ * sse_mesh_create, so the caller may free it afterwards).  Conventions of
+ * the TRiSK C-grid (Section 5 opening; Thuburn et al. 2009):
+ *   cells_on_edge[e] = (c1, c2), the edge normal points from c1 to c2;
+ *   vertices_on_edge[e] = (v1, v2), the tangent k x n points from v1 to v2;
+ *   edges_on_cell[i][0..n_edges_on_cell[i]) counter-clockwise;
+ *   edges_on_edge / weights_on_edge: v_e = sum_j W[e][j] u[edges_on_edge[e][j]]
+ *   reconstructs the tangential velocity; missing entries -1 with weight 0.
+ * Lengths in metres, areas in m^2, Coriolis parameter in s^-1.
+ */
+typedef struct {
+    int32_t n_cells, n_edges, n_vertices;
+    int32_t max_edges;            /* columns of edges_on_cell (<= 6)          */
+    int32_t max_edges2;           /* columns of edges_on_edge (<= 10)         */
+    const int32_t *cells_on_edge;     /* [E][2]                               */
+    const int32_t *edges_on_cell;     /* [C][max_edges]                       */
+    const int32_t *n_edges_on_cell;   /* [C]                                  */
+    const int32_t *vertices_on_edge;  /* [E][2]                               */
+    const int32_t *edges_on_vertex;   /* [V][3]                               */
+    const int32_t *edges_on_edge;     /* [E][max_edges2]                      */
+    const int32_t *n_edges_on_edge;   /* [E]                                  */
+    const double *weights_on_edge;    /* [E][max_edges2]                      */
+    const double *dc_edge;            /* [E] cell-centre distance d_e         */
+    const double *dv_edge;            /* [E] vertex distance l_e              */
+    const double *f_edge;             /* [E] Coriolis parameter at edges      */
+    const double *area_cell;          /* [C]                                  */
+    const double *bottom_depth;       /* [C] H (total column height at rest)  */
+    const double *area_triangle;      /* [V]                                  */
+    const uint8_t *cell_mask;         /* [C] 1 = ocean, 0 = land              */
+} sse_mesh_desc;
+
+/*
+ * Run parameters.  Every physical constant is explicit:
+ *   n_layers L (1..128); scheme SSE_SCHEME_SSPRK2 | SSE_SCHEME_SSPRK3;
+ *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 | SSE_MIXED;
+ *   vcoord SSE_ZSTAR | SSE_ISOPYCNAL (Section 2, vertical coordinate);
+ *   reconcile SSE_RECONCILE_*; dt > 0 (s); gravity g; rho0 (Boussinesq
+ *   reference density); nu_h, nu_v (Laplacian horizontal and vertical
+ *   viscosity, m^2/s); c_drag (bottom drag of Section 5, dimensionless).
+ */
+typedef struct {
+    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile;
+    double dt, gravity, rho0, nu_h, nu_v, c_drag;
+} sse_params;
+
+typedef struct sse_mesh sse_mesh;
+typedef struct sse_state sse_state;
+
+/* Thread-local description of the last failure ("" if none). */
+const char *sse_last_error(void);
+
+/* Library version string. */
+const char *sse_version(void);
+
+/* Host-only check of a mesh description: index ranges, the two-cell and
+ * two-vertex structure of every edge, positive lengths and areas, and the
+ * antisymmetry l_e d_e W[e][e'] = -l_e' d_e' W[e'][e] that makes the Coriolis
+ * term energy neutral.  Touches no GPU.  SSE_EINVAL on the first violation. */
+int sse_mesh_validate(const sse_mesh_desc *d);
+
+/* Device bytes a mesh occupies (for the caller's allocation). */
+int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes);
+
+/* Validate, lay out and upload a mesh into dev_buf (>= sse_mesh_device_bytes,
+ * 256-byte aligned, owned by the caller and kept alive until destroy).
+ * stream: hipStream_t used for the upload (NULL = default stream); the call
+ * returns after the upload completed. */
+int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t bytes, void *stream,
+                    sse_mesh **out);
+int sse_mesh_destroy(sse_mesh *m);
+
+/* Device workspace of one state (prognostic fields, stage buffers, the 2D
+ * accumulators of the reconciliation and the barotropic loop). */
+int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p, size_t *bytes);
+
+/* Create a state on mesh m in the caller's device workspace (>= the size
+ * above, 256-byte aligned); all kernels of this state run on `stream`
+ * (a hipStream_t, NULL = default stream).  SSE_ENOMEM if bytes is too small,
+ * SSE_EINVAL on bad parameters. */
+int sse_state_create(const sse_mesh *m, const sse_params *p, void *dev_workspace, size_t bytes,
+                     void *stream, sse_state **out);
+int sse_state_destroy(sse_state *s);
+
+/* Set the initial state from host arrays in the caller's numbering:
+ * h [C][L] layer thicknesses, u [E][L] normal velocities, rho [C][L] frozen
+ * layer densities (EOS evaluated by the caller), h_ref [C][L] z-star
+ * reference thicknesses (may be NULL for isopycnal).  zeta is derived as
+ * sum_k h_k - H (Section 2, definition of zeta); velocities on edges next to
+ * land are forced to 0.  SSE_ENONFINITE if any input is NaN/Inf. */
+int sse_state_init(sse_state *s, const double *h, const double *u, const double *rho,
+                   const double *h_ref);
+
+/* Enqueue n steps t -> t + n dt on the state's stream, wait, and check the
+ * state for NaN/Inf.  SSE_ENONFINITE after a blow-up (the state keeps the
+ * values of the last step, for inspection). */
+int sse_step(sse_state *s, int32_t n);
+
+/* Enqueue n steps and return immediately; sse_sync waits and reports
+ * SSE_ENONFINITE like sse_step. */
+int sse_step_async(sse_state *s, int32_t n);
+int sse_sync(sse_state *s);
+
+/* Copy the state to host arrays in the caller's numbering; any pointer may be
+ * NULL.  h [C][L], u [E][L], zeta [C] = sum h - H, ubar [E] = the barotropic
+ * velocity of (BBspl) for the current u and h.  Waits for the stream. */
+int sse_read_state(const sse_state *s, double *h, double *u, double *zeta, double *ubar);
+
+/* Per-kernel-class timing with HIP events on the state's stream.
+ * class_mask: bit c set = record an event pair around every launch of class c
+ * during subsequent steps (0 disables timing).  sse_profile_read returns, per
+ * class, the number of launches and the summed milliseconds, then resets.
+ * Classes: 0 baroclinic edge pass, 1 baroclinic cell pass, 2 vertex pass,
+ * 3 barotropic substep evaluation, 4 thickness stage, 5 other 2D/assembly. */
+enum { SSE_PROF_FE_EDGE = 0, SSE_PROF_FE_CELL = 1, SSE_PROF_FE_VERTEX = 2,
+       SSE_PROF_BT_EVAL = 3, SSE_PROF_THICKNESS = 4, SSE_PROF_OTHER = 5, SSE_PROF_NCLASS = 6 };
+int sse_profile_enable(sse_state *s, int class_mask);
+int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
+
+/*
+ * Per-kernel debug entry points (host arrays, caller numbering).  They use
+ * the state's stage buffers as scratch and leave its prognostic fields
+ * untouched.
+ */
+
+/* Algorithm 1, Baroclinic_FEuler(u, ut = u - ubar, zeta, h, dt):
+ * inputs u [E][L], ubar [E], zeta [C], h [C][L]; outputs ut1 [E][L] (after the
+ * G-bar subtraction) and G [E]. */
+int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const double *ubar,
+                                const double *zeta, const double *h, double dt,
+                                double *ut1, double *G);
+
+/* Algorithm 3 (scheme 2) or 4 (scheme 3) with M substeps over dt and G frozen:
+ * inputs ubar [E], zeta [C], G [E]; outputs ubar1 [E], zeta1 [C] and the
+ * accumulated flux F^zeta [E] of Section 3.4. */
+int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double dt,
+                                 const double *ubar, const double *zeta, const double *G,
+                                 double *ubar1, double *zeta1, double *Fzeta);
+
+/* One thickness stage h_out = h_in + dt T^h(h_in, u + uA) (Section 3.4 revised
+ * thickness updates) with the state's vertical coordinate: inputs h_in [C][L],
+ * u [E][L], uA [E]; outputs h_out [C][L] and zeta_out [C] = sum h_out - H. */
+int sse_debug_thickness_stage(sse_state *s, const double *h_in, const double *u, const double *uA,
+                              double dt, double *h_out, double *zeta_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSPRKSE_H */

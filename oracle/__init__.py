@@ -23,7 +23,7 @@ Primitive Equations" (arXiv 2105.13484).
                    flux-form SSH reconciliation of Section 3.4.
 
 Everything is FP64 NumPy with whole-array operations; column sums over the
-layers run sequentially from the top layer down.
+layers use a fixed pairwise order (``layered.colsum``).
 
 Parity unpinned: the discrete forms of the nonlinear terms (pressure gradient
 in tilted layers, z-star vertical velocity, vertical boundary conditions,

@@ -55,12 +55,27 @@ class Setup:
         return self.h_ref.shape[1]
 
 
+COLSUM_WIDTH = 128
+
+
 def colsum(x: np.ndarray) -> np.ndarray:
-    """sum_{k=1}^{L} x_k, accumulated from the top layer down."""
-    acc = np.zeros(x.shape[0])
-    for k in range(x.shape[1]):
-        acc = acc + x[:, k]
-    return acc
+    """sum_{k=1}^{L} x_k in a fixed pairwise order.
+
+    The layers are padded with zeros to 128 and added by repeated halving
+    (x_i + x_{i+64}, then + the partner 32 apart, ...).  The paper fixes no
+    summation order; a fixed pairwise one keeps the cancellation-prone column
+    diagnostics (zeta = sum h - H, the split, G-bar) reproducible.
+    """
+    N, L = x.shape
+    if L > COLSUM_WIDTH:
+        raise ValueError("at most 128 layers")
+    a = np.zeros((N, COLSUM_WIDTH))
+    a[:, :L] = x
+    half = COLSUM_WIDTH // 2
+    while half >= 1:
+        a = a[:, :half] + a[:, half:2 * half]
+        half //= 2
+    return a[:, 0]
 
 
 def safe_ratio(num: np.ndarray, den: np.ndarray, mask: np.ndarray) -> np.ndarray:
@@ -111,10 +126,19 @@ def vertical_velocity(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
 
 
 def T_h(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
-    """T^h_k(h, u) = -div(h_k u_k) - D_{z^m}(w)_k h_k  (Section 2, grouping T^h)."""
+    """T^h_k(h, u) = -div(h_k u_k) - D_{z^m}(w)_k h_k  (Section 2, grouping T^h).
+
+    z-star: with w from ``vertical_velocity`` this is exactly the distributed
+    column-total divergence -frac_k sum_l div_l, which is evaluated directly
+    (the difference form would cancel the baroclinic divergences in
+    floating point).  Isopycnal: w = 0, T^h = -div(h u).
+    """
     div = thickness_flux_divergence(h, u, st)
-    w = vertical_velocity(h, u, st)
-    th = -div - (w[:, :-1] - w[:, 1:])
+    if st.params.vcoord == 1:
+        th = -div
+    else:
+        frac = safe_ratio(st.h_ref, colsum(st.h_ref)[:, None], st.cell_mask[:, None])
+        th = -frac * colsum(div)[:, None]
     return np.where(st.cell_mask[:, None], th, 0.0)
 
 

@@ -1,0 +1,653 @@
+// C ABI: mesh upload, state workspace, the SSPRK2-SE / SSPRK3-SE step
+// orchestration, state init/read, debug entry points and per-class timing.
+//
+// Step structure (Section 3 of the paper; the reconciliation of Section 3.4):
+//   SSPRK3-SE  FE1 -> BT1 -> TH1 -> FE2 -> BT2 -> TH2 -> FE3 -> BT3 -> TH3 -> assemble
+//   SSPRK2-SE  FE1 -> BT1 -> TH1 -> FE2 -> BT2 -> TH2 -> assemble
+// FE = baroclinic forward Euler (Algorithm 1: cell, vertex and edge passes),
+// BT = barotropic substep loop (Algorithm 3 or 4), TH = thickness stage with
+// the reconciliation deficits.  Everything is enqueued on the state's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sse_kernels.h"
+
+using namespace sse;
+
+namespace {
+
+struct Work {
+    double *U, *T1, *T2;                                     // [E][L]
+    double *Hs, *H1, *H2, *B, *Wt, *frac, *rho;             // [C][L]
+    double *Z;                                              // [V][L]
+    double *ubar_n, *ub1, *ub2, *ub_half, *ubar_new, *G0, *G1, *Gh, *Gi, *Fz1, *Fz2, *Fz3, *Sh1, *Fh1, *Sh2,
+        *Fh2, *Sh3, *Pp, *Ftot, *uA, *bt_u1, *bt_uh;        // [E]
+    double *zeta_n, *z1, *z_half, *Kbot, *bt_z1, *bt_zh, *bt_zout;  // [C]
+    int *flag;
+};
+
+constexpr int kN3E = 3, kN3C = 7, kN3V = 1, kN2E = 22, kN2C = 7;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t workspace_bytes(int C, int E, int V, int L) {
+    size_t b = 0;
+    b += kN3E * align_up((size_t)E * L * 8);
+    b += kN3C * align_up((size_t)C * L * 8);
+    b += kN3V * align_up((size_t)V * L * 8);
+    b += kN2E * align_up((size_t)E * 8);
+    b += kN2C * align_up((size_t)C * 8);
+    b += kAlign;  // flag
+    return b;
+}
+
+Work carve(void *buf, int C, int E, int V, int L) {
+    char *p = static_cast<char *>(buf);
+    auto take = [&](size_t n) {
+        double *r = reinterpret_cast<double *>(p);
+        p += align_up(n);
+        return r;
+    };
+    Work w{};
+    double **e3[] = {&w.U, &w.T1, &w.T2};
+    for (auto q : e3) *q = take((size_t)E * L * 8);
+    double **c3[] = {&w.Hs, &w.H1, &w.H2, &w.B, &w.Wt, &w.frac, &w.rho};
+    for (auto q : c3) *q = take((size_t)C * L * 8);
+    w.Z = take((size_t)V * L * 8);
+    double **e2[] = {&w.ubar_n, &w.ub1, &w.ub2, &w.ub_half, &w.ubar_new, &w.G0, &w.G1, &w.Gh, &w.Gi, &w.Fz1, &w.Fz2,
+                     &w.Fz3, &w.Sh1, &w.Fh1, &w.Sh2, &w.Fh2, &w.Sh3, &w.Pp, &w.Ftot, &w.uA, &w.bt_u1, &w.bt_uh};
+    for (auto q : e2) *q = take((size_t)E * 8);
+    double **c2[] = {&w.zeta_n, &w.z1, &w.z_half, &w.Kbot, &w.bt_z1, &w.bt_zh, &w.bt_zout};
+    for (auto q : c2) *q = take((size_t)C * 8);
+    w.flag = reinterpret_cast<int *>(p);
+    return w;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return SSE_EDEVICE;
+}
+
+#define SSE_HIP(call)                                   \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+
+bool all_finite(const double *x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct sse_state {
+    const sse_mesh *mesh = nullptr;
+    sse_params p{};
+    hipStream_t stream = nullptr;
+    Work w{};
+    size_t bytes = 0;
+    bool initialized = false;
+    // profiling
+    bool prof = false;
+    int prof_mask = 0;
+    std::vector<hipEvent_t> events;
+    std::vector<int> rec_class;
+    size_t ev_used = 0;
+    long nlaunch[SSE_PROF_NCLASS] = {};
+    double ms[SSE_PROF_NCLASS] = {};
+};
+
+namespace {
+
+// ---- per-class event timing ------------------------------------------------
+void prof_flush(sse_state *s) {
+    if (s->ev_used == 0) return;
+    hipStreamSynchronize(s->stream);
+    for (size_t i = 0; i < s->ev_used / 2; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, s->events[2 * i], s->events[2 * i + 1]) == hipSuccess) {
+            s->ms[s->rec_class[i]] += t;
+            s->nlaunch[s->rec_class[i]] += 1;
+        }
+    }
+    s->ev_used = 0;
+    s->rec_class.clear();
+}
+
+struct ProfScope {
+    sse_state *s;
+    int cls;
+    bool active;
+    ProfScope(sse_state *st, int c)
+        : s(st), cls(c), active(st->prof && !st->events.empty() && ((st->prof_mask >> c) & 1)) {
+        if (!active) return;
+        if (s->ev_used + 2 > s->events.size()) prof_flush(s);
+        hipEventRecord(s->events[s->ev_used], s->stream);
+    }
+    ~ProfScope() {
+        if (!active) return;
+        hipEventRecord(s->events[s->ev_used + 1], s->stream);
+        s->ev_used += 2;
+        s->rec_class.push_back(cls);
+    }
+};
+
+// ---- building blocks -------------------------------------------------------
+void fe_pass(sse_state *s, const double *X, const double *add, const double *sub, const double *h,
+             const double *zeta, int comb, double *out, double *G, double *sum_h, double *sum_hu, double *sum_hp,
+             double pa, double pb, double *Gi, const double *Ga, const double *Gb, int interp) {
+    const DevMesh &m = s->mesh->d;
+    const sse_params &p = s->p;
+    Work &w = s->w;
+    const bool zstar = p.vcoord == SSE_ZSTAR;
+    {
+        ProfScope ps(s, SSE_PROF_FE_CELL);
+        FECellArgs a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, p.nu_h, w.B, w.Wt, w.Kbot};
+        launch_fe_cell(a, s->stream);
+    }
+    {
+        ProfScope ps(s, SSE_PROF_FE_VERTEX);
+        FEVertexArgs a{m, p.n_layers, X, add, w.Z};
+        launch_fe_vertex(a, s->stream);
+    }
+    {
+        ProfScope ps(s, SSE_PROF_FE_EDGE);
+        FEEdgeArgs a{};
+        a.m = m;
+        a.L = p.n_layers;
+        a.X = X;
+        a.ubar_add = add;
+        a.ubar_sub = sub;
+        a.h = h;
+        a.rho = w.rho;
+        a.B = w.B;
+        a.Wtop = w.Wt;
+        a.Kbot = w.Kbot;
+        a.Z = w.Z;
+        a.zeta = zeta;
+        a.Un = (comb != COMB_NONE || (sum_hp && pa != 0.0)) ? w.U : nullptr;
+        a.ubar_n = w.ubar_n;
+        a.comb = comb;
+        a.out = out;
+        a.G = G;
+        a.sum_h = sum_h;
+        a.sum_hu = sum_hu;
+        a.sum_hp = sum_hp;
+        a.psum_a = pa;
+        a.psum_b = pb;
+        a.Gi = Gi;
+        a.Ga = Ga;
+        a.Gb = Gb;
+        a.interp = interp;
+        a.dt = p.dt;
+        a.g = p.gravity;
+        a.rho0 = p.rho0;
+        a.nu_h = p.nu_h;
+        a.nu_v = p.nu_v;
+        a.c_drag = p.c_drag;
+        launch_fe_edge(a, s->stream);
+    }
+}
+
+// Algorithm 3 (scheme 2) / Algorithm 4 (scheme 3): M substeps of dt / M with
+// G frozen, accumulating F^zeta.  The inputs are not modified.
+void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, const double *in_z, const double *G,
+             double *out_u, double *out_z, double *F) {
+    const DevMesh &m = s->mesh->d;
+    Work &w = s->w;
+    BTEvalArgs a{};
+    a.m = m;
+    a.G = G;
+    a.F = F;
+    a.tau = dt / M;
+    a.g = s->p.gravity;
+    for (int j = 0; j < M; ++j) {
+        const double *bu = j == 0 ? in_u : out_u;
+        const double *bz = j == 0 ? in_z : out_z;
+        if (scheme == SSE_SCHEME_SSPRK3) {
+            const double w1 = 1.0 / (6.0 * M), w3 = 2.0 / (3.0 * M);
+            { ProfScope ps(s, SSE_PROF_BT_EVAL);
+              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = w.bt_u1; a.zo = w.bt_z1;
+              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval(a, s->stream); }
+            { ProfScope ps(s, SSE_PROF_BT_EVAL);
+              a.ua = w.bt_u1; a.za = w.bt_z1; a.ub = bu; a.zb = bz; a.uo = w.bt_uh; a.zo = w.bt_zh;
+              a.wF = w1; a.zeroF = 0; a.comb = COMB_34; launch_bt_eval(a, s->stream); }
+            { ProfScope ps(s, SSE_PROF_BT_EVAL);
+              a.ua = w.bt_uh; a.za = w.bt_zh; a.ub = bu; a.zb = bz; a.uo = out_u; a.zo = out_z;
+              a.wF = w3; a.zeroF = 0; a.comb = COMB_THIRD; launch_bt_eval(a, s->stream); }
+        } else {
+            const double w1 = 1.0 / (2.0 * M);
+            { ProfScope ps(s, SSE_PROF_BT_EVAL);
+              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = w.bt_u1; a.zo = w.bt_z1;
+              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval(a, s->stream); }
+            { ProfScope ps(s, SSE_PROF_BT_EVAL);
+              a.ua = w.bt_u1; a.za = w.bt_z1; a.ub = bu; a.zb = bz; a.uo = out_u; a.zo = out_z;
+              a.wF = w1; a.zeroF = 0; a.comb = COMB_HALF; launch_bt_eval(a, s->stream); }
+        }
+    }
+}
+
+void recon(sse_state *s, int mode, const double *Fz, const double *Fh, const double *Sh, const double *Pp,
+           const double *ub_new, const double *ub2, double *ub_half) {
+    ProfScope ps(s, SSE_PROF_OTHER);
+    Work &w = s->w;
+    ReconArgs a{};
+    a.m = s->mesh->d;
+    a.mode = mode;
+    a.rec = s->p.reconcile;
+    a.Fz = Fz;
+    a.Fh = Fh;
+    a.Sh = Sh;
+    a.Pp = Pp;
+    a.ub_n = w.ubar_n;
+    a.ub_new = ub_new;
+    a.Fz1 = w.Fz1;
+    a.Fz2 = w.Fz2;
+    a.Fh1 = w.Fh1;
+    a.Fh2 = w.Fh2;
+    a.Ftot = w.Ftot;
+    a.uA = w.uA;
+    a.ub2 = ub2;
+    a.ub_half = ub_half;
+    launch_recon(a, s->stream);
+}
+
+// Thickness stage.  z-star uses the 2D total flux w.Ftot; isopycnal rebuilds
+// the per-layer velocity c1 X1 + c2 X2 + ca1 a1 + u^A.
+void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, double *h_out, double *zeta_out,
+               const double *X1, double c1, const double *X2, double c2, const double *a1, double ca1, double dt) {
+    ProfScope ps(s, SSE_PROF_THICKNESS);
+    Work &w = s->w;
+    if (s->p.vcoord == SSE_ZSTAR) {
+        THArgs a{s->mesh->d, s->p.n_layers, h_in, h_n, w.frac, w.Ftot, comb, dt, h_out, zeta_out, w.flag};
+        launch_thickness(a, s->stream);
+    } else {
+        THIsoArgs a{};
+        a.m = s->mesh->d;
+        a.L = s->p.n_layers;
+        a.h_in = h_in;
+        a.h_n = h_n;
+        a.X1 = X1;
+        a.X2 = X2;
+        a.c1 = c1;
+        a.c2 = c2;
+        a.a1 = a1;
+        a.ca1 = ca1;
+        a.a2 = nullptr;
+        a.ca2 = 0.0;
+        a.uA = w.uA;
+        a.comb = comb;
+        a.dt = dt;
+        a.h_out = h_out;
+        a.zeta_out = zeta_out;
+        a.nonfinite = w.flag;
+        launch_thickness_iso(a, s->stream);
+    }
+}
+
+void assemble(sse_state *s, const double *X, const double *ubar_bt) {
+    ProfScope ps(s, SSE_PROF_OTHER);
+    Work &w = s->w;
+    AssembleArgs a{s->mesh->d, s->p.n_layers, X, ubar_bt, w.Hs, w.U, w.ubar_n, w.flag};
+    launch_assemble(a, s->stream);
+}
+
+void step_ssprk3(sse_state *s) {
+    Work &w = s->w;
+    const int M = s->p.substeps;
+    const double dt = s->p.dt;
+    // Stage 1: baroclinic FE from (u^n, ut^n, zeta^n, h^n); predictor loop; thickness.
+    fe_pass(s, w.U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, w.T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
+            nullptr, nullptr, nullptr, 0);
+    bt_loop(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
+    thickness(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, w.U, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
+    // Stage 2: FE from (u-hat^{n+1}, ut-hat^{n+1}, zeta-hat^{n+1}, h-hat^{n+1}); second loop; thickness.
+    fe_pass(s, w.T1, w.ub1, nullptr, w.H1, w.z1, COMB_34, w.T2, w.G1, w.Sh2, w.Fh2, nullptr, 0, 0, nullptr,
+            nullptr, nullptr, 0);
+    bt_loop(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
+    recon(s, 0, w.Fz2, w.Fh2, w.Sh2, nullptr, nullptr, w.ub2, w.ub_half);
+    thickness(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, w.T1, 1.0, nullptr, 0.0, w.ub1, 1.0, dt);
+    // Stage 3: FE from the n+1/2 stage -> ut^{n+1}; G interpolated by Interp_3.
+    fe_pass(s, w.T2, w.ub_half, nullptr, w.H2, w.z_half, COMB_THIRD, w.T1, w.Gh, w.Sh3, nullptr, w.Pp, 1.0, 1.0,
+            w.Gi, w.G0, w.G1, 3);
+    // Step 2: corrector loop from (ubar^n, zeta^n).
+    bt_loop(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
+    // Step 3: last thickness stage with u^A_3, then u^{n+1} and its split.
+    recon(s, 1, w.Fz3, nullptr, w.Sh3, w.Pp, w.ubar_new, nullptr, nullptr);
+    thickness(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, w.U, 0.5, w.T1, 0.5, w.ubar_new, 0.5, dt);
+    assemble(s, w.T1, w.ubar_new);
+}
+
+void step_ssprk2(sse_state *s) {
+    Work &w = s->w;
+    const int M = s->p.substeps;
+    const double dt = s->p.dt;
+    fe_pass(s, w.U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, w.T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
+            nullptr, nullptr, nullptr, 0);
+    bt_loop(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
+    thickness(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, w.U, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
+    fe_pass(s, w.T1, w.ub1, nullptr, w.H1, w.z1, COMB_HALF, w.T2, w.G1, w.Sh2, nullptr, w.Pp, 0.0, 1.0, w.Gi,
+            w.G0, nullptr, 2);
+    bt_loop(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
+    recon(s, 2, w.Fz2, nullptr, w.Sh2, w.Pp, w.ubar_new, nullptr, nullptr);
+    thickness(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, w.T2, 1.0, nullptr, 0.0, w.ubar_new, 1.0, dt);
+    assemble(s, w.T2, w.ubar_new);
+}
+
+int check_params(const sse_params *p) {
+    if (!p) { set_error("params is NULL"); return SSE_EINVAL; }
+    if (p->n_layers < 1 || p->n_layers > 2 * kWave) { set_error("n_layers must be in [1, 128]"); return SSE_EINVAL; }
+    if (p->scheme != SSE_SCHEME_SSPRK2 && p->scheme != SSE_SCHEME_SSPRK3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
+    if (p->substeps < 1) { set_error("substeps must be >= 1"); return SSE_EINVAL; }
+    if (p->precision != SSE_FP64) { set_error("only precision SSE_FP64 is implemented"); return SSE_EINVAL; }
+    if (p->vcoord != SSE_ZSTAR && p->vcoord != SSE_ISOPYCNAL) { set_error("vcoord must be ZSTAR or ISOPYCNAL"); return SSE_EINVAL; }
+    if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
+    const double v[] = {p->dt, p->gravity, p->rho0};
+    for (double x : v)
+        if (!(x > 0) || !std::isfinite(x)) { set_error("dt, gravity and rho0 must be positive"); return SSE_EINVAL; }
+    const double nn[] = {p->nu_h, p->nu_v, p->c_drag};
+    for (double x : nn)
+        if (!(x >= 0) || !std::isfinite(x)) { set_error("nu_h, nu_v and c_drag must be >= 0"); return SSE_EINVAL; }
+    return SSE_OK;
+}
+
+int read_flag(sse_state *s) {
+    int flag = 0;
+    SSE_HIP(hipMemcpyAsync(&flag, s->w.flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    SSE_HIP(hipStreamSynchronize(s->stream));
+    if (s->prof) prof_flush(s);
+    if (flag) { set_error("non-finite value in the state (the step blew up)"); return SSE_ENONFINITE; }
+    return SSE_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Mesh
+// ===========================================================================
+extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t bytes, void *stream, sse_mesh **out) {
+    if (!out) { set_error("out is NULL"); return SSE_EINVAL; }
+    *out = nullptr;
+    std::string err;
+    int rc = validate_desc(d, err);
+    if (rc != SSE_OK) { set_error(err); return rc; }
+    MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
+    if (!dev_buf || bytes < lay.total) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
+    if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
+    HostMeshTables t;
+    build_tables(d, t);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(dev_buf);
+    const void *src[] = {t.cell_edges.data(), t.cell_nbrs.data(), t.cell_nedges.data(), t.cell_div.data(),
+                         t.cell_ke.data(), t.cell_edges_t.data(), t.cell_nbrs_t.data(), t.cell_div_t.data(),
+                         t.H.data(), t.cmask.data(), t.edge_cells.data(), t.edge_verts.data(), t.eoe.data(),
+                         t.neoe.data(), t.w.data(), t.wf.data(), t.dc.data(), t.dv.data(), t.emask.data(),
+                         t.vert_edges.data(), t.vert_curl.data()};
+    const size_t C = d->n_cells, E = d->n_edges, V = d->n_vertices;
+    const size_t nb[] = {C * 6 * 4, C * 6 * 4, C * 4, C * 6 * 8, C * 6 * 8, C * 6 * 4, C * 6 * 4, C * 6 * 8,
+                         C * 8, C, E * 2 * 4, E * 2 * 4, E * 10 * 4, E * 4, E * 10 * 8, E * 10 * 8, E * 8, E * 8, E,
+                         V * 3 * 4, V * 3 * 8};
+    for (int i = 0; i < 21; ++i) SSE_HIP(hipMemcpyAsync(base + lay.off[i], src[i], nb[i], hipMemcpyHostToDevice, s));
+    SSE_HIP(hipStreamSynchronize(s));
+    sse_mesh *m = new sse_mesh();
+    m->C = d->n_cells;
+    m->E = d->n_edges;
+    m->V = d->n_vertices;
+    m->n_ocean_cells = t.n_ocean_cells;
+    m->dev_buf = dev_buf;
+    m->dev_bytes = bytes;
+    DevMesh &dm = m->d;
+    dm.C = m->C;
+    dm.E = m->E;
+    dm.V = m->V;
+    auto P = [&](int i) { return static_cast<void *>(base + lay.off[i]); };
+    dm.cell_edges = (const int32_t *)P(0);
+    dm.cell_nbrs = (const int32_t *)P(1);
+    dm.cell_nedges = (const int32_t *)P(2);
+    dm.cell_div = (const double *)P(3);
+    dm.cell_ke = (const double *)P(4);
+    dm.cell_edges_t = (const int32_t *)P(5);
+    dm.cell_nbrs_t = (const int32_t *)P(6);
+    dm.cell_div_t = (const double *)P(7);
+    dm.H = (const double *)P(8);
+    dm.cmask = (const uint8_t *)P(9);
+    dm.edge_cells = (const int32_t *)P(10);
+    dm.edge_verts = (const int32_t *)P(11);
+    dm.eoe = (const int32_t *)P(12);
+    dm.neoe = (const int32_t *)P(13);
+    dm.w = (const double *)P(14);
+    dm.wf = (const double *)P(15);
+    dm.dc = (const double *)P(16);
+    dm.dv = (const double *)P(17);
+    dm.emask = (const uint8_t *)P(18);
+    dm.vert_edges = (const int32_t *)P(19);
+    dm.vert_curl = (const double *)P(20);
+    m->cells_on_edge = t.edge_cells;
+    *out = m;
+    return SSE_OK;
+}
+
+extern "C" int sse_mesh_destroy(sse_mesh *m) {
+    delete m;
+    return SSE_OK;
+}
+
+// ===========================================================================
+// State
+// ===========================================================================
+extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p, size_t *bytes) {
+    if (!m || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
+    int rc = check_params(p);
+    if (rc) return rc;
+    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers);
+    return SSE_OK;
+}
+
+extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *dev_workspace, size_t bytes,
+                                void *stream, sse_state **out) {
+    if (!m || !out) { set_error("NULL argument"); return SSE_EINVAL; }
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers);
+    if (!dev_workspace || bytes < need) { set_error("state workspace too small"); return SSE_ENOMEM; }
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) { set_error("state workspace must be 256-byte aligned"); return SSE_EINVAL; }
+    sse_state *s = new sse_state();
+    s->mesh = m;
+    s->p = *p;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers);
+    s->bytes = bytes;
+    *out = s;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_destroy(sse_state *s) {
+    if (!s) return SSE_OK;
+    for (auto e : s->events) hipEventDestroy(e);
+    delete s;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, const double *rho, const double *h_ref) {
+    if (!s || !h || !u || !rho) { set_error("NULL argument"); return SSE_EINVAL; }
+    const sse_mesh *m = s->mesh;
+    const int L = s->p.n_layers;
+    const size_t CL = (size_t)m->C * L, EL = (size_t)m->E * L;
+    if (s->p.vcoord == SSE_ZSTAR && !h_ref) { set_error("z-star needs h_ref"); return SSE_EINVAL; }
+    if (!all_finite(h, CL) || !all_finite(u, EL) || !all_finite(rho, CL) || (h_ref && !all_finite(h_ref, CL))) {
+        set_error("non-finite value in the initial state");
+        return SSE_ENONFINITE;
+    }
+    std::vector<double> frac(CL, 0.0), um(u, u + EL);
+    std::vector<uint8_t> emask(m->E);
+    std::vector<uint8_t> cmask(m->C);
+    SSE_HIP(hipMemcpy(cmask.data(), m->d.cmask, m->C, hipMemcpyDeviceToHost));
+    for (int e = 0; e < m->E; ++e) {
+        const bool wet = cmask[m->cells_on_edge[2 * e]] && cmask[m->cells_on_edge[2 * e + 1]];
+        if (!wet) std::fill(um.begin() + (size_t)e * L, um.begin() + (size_t)(e + 1) * L, 0.0);
+    }
+    if (h_ref) {
+        for (int i = 0; i < m->C; ++i) {
+            if (!cmask[i]) continue;
+            double tot = 0.0;
+            for (int k = 0; k < L; ++k) tot += h_ref[(size_t)i * L + k];
+            if (!(tot > 0)) { set_error("h_ref must have a positive column sum on ocean cells"); return SSE_EINVAL; }
+            for (int k = 0; k < L; ++k) frac[(size_t)i * L + k] = h_ref[(size_t)i * L + k] / tot;
+        }
+    }
+    Work &w = s->w;
+    SSE_HIP(hipMemcpyAsync(w.Hs, h, CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(w.U, um.data(), EL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(w.rho, rho, CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(w.frac, frac.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s->stream));
+    launch_zeta_from_h(m->d, L, w.Hs, w.zeta_n, s->stream);
+    AssembleArgs a{m->d, L, w.U, nullptr, w.Hs, w.U, w.ubar_n, w.flag};
+    launch_assemble(a, s->stream);
+    SSE_HIP(hipGetLastError());
+    SSE_HIP(hipStreamSynchronize(s->stream));
+    s->initialized = true;
+    return SSE_OK;
+}
+
+extern "C" int sse_step_async(sse_state *s, int32_t n) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    if (!s->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
+    if (n < 0) { set_error("n must be >= 0"); return SSE_EINVAL; }
+    if (s->prof && s->events.empty()) {
+        s->events.resize(8192);
+        for (auto &e : s->events) SSE_HIP(hipEventCreate(&e));
+    }
+    for (int i = 0; i < n; ++i) {
+        if (s->p.scheme == SSE_SCHEME_SSPRK3)
+            step_ssprk3(s);
+        else
+            step_ssprk2(s);
+    }
+    SSE_HIP(hipGetLastError());
+    return SSE_OK;
+}
+
+extern "C" int sse_sync(sse_state *s) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    return read_flag(s);
+}
+
+extern "C" int sse_step(sse_state *s, int32_t n) {
+    int rc = sse_step_async(s, n);
+    if (rc) return rc;
+    return sse_sync(s);
+}
+
+extern "C" int sse_read_state(const sse_state *cs, double *h, double *u, double *zeta, double *ubar) {
+    if (!cs) { set_error("NULL state"); return SSE_EINVAL; }
+    if (!cs->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
+    const sse_mesh *m = cs->mesh;
+    const int L = cs->p.n_layers;
+    const Work &w = cs->w;
+    hipStream_t st = cs->stream;
+    if (h) SSE_HIP(hipMemcpyAsync(h, w.Hs, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
+    if (u) SSE_HIP(hipMemcpyAsync(u, w.U, (size_t)m->E * L * 8, hipMemcpyDeviceToHost, st));
+    if (zeta) SSE_HIP(hipMemcpyAsync(zeta, w.zeta_n, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
+    if (ubar) SSE_HIP(hipMemcpyAsync(ubar, w.ubar_n, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipStreamSynchronize(st));
+    return SSE_OK;
+}
+
+extern "C" int sse_profile_enable(sse_state *s, int class_mask) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    prof_flush(s);
+    s->prof_mask = class_mask & ((1 << SSE_PROF_NCLASS) - 1);
+    s->prof = s->prof_mask != 0;
+    return SSE_OK;
+}
+
+extern "C" int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    prof_flush(s);
+    for (int c = 0; c < SSE_PROF_NCLASS; ++c) {
+        if (launches) launches[c] = (int32_t)s->nlaunch[c];
+        if (milliseconds) milliseconds[c] = s->ms[c];
+        s->nlaunch[c] = 0;
+        s->ms[c] = 0.0;
+    }
+    return SSE_OK;
+}
+
+// ===========================================================================
+// Debug entry points
+// ===========================================================================
+extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const double *ubar, const double *zeta,
+                                           const double *h, double dt, double *ut1, double *G) {
+    if (!s || !u || !ubar || !zeta || !h || !ut1 || !G) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (!s->initialized) { set_error("state not initialised (rho and h_ref are needed)"); return SSE_ESTATE; }
+    const sse_mesh *m = s->mesh;
+    const int L = s->p.n_layers;
+    Work &w = s->w;
+    hipStream_t st = s->stream;
+    SSE_HIP(hipMemcpyAsync(w.T2, u, (size_t)m->E * L * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.ub2, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.H1, h, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
+    const double saved = s->p.dt;
+    s->p.dt = dt;
+    fe_pass(s, w.T2, nullptr, w.ub2, w.H1, w.z1, COMB_NONE, w.T1, w.G0, w.Sh1, nullptr, nullptr, 0, 0, nullptr,
+            nullptr, nullptr, 0);
+    s->p.dt = saved;
+    SSE_HIP(hipGetLastError());
+    SSE_HIP(hipMemcpyAsync(ut1, w.T1, (size_t)m->E * L * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(G, w.G0, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipStreamSynchronize(st));
+    return SSE_OK;
+}
+
+extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double dt, const double *ubar,
+                                            const double *zeta, const double *G, double *ubar1, double *zeta1,
+                                            double *Fzeta) {
+    if (!s || !ubar || !zeta || !G || !ubar1 || !zeta1 || !Fzeta) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (scheme != 2 && scheme != 3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
+    if (M < 1 || !(dt > 0)) { set_error("M must be >= 1 and dt > 0"); return SSE_EINVAL; }
+    const sse_mesh *m = s->mesh;
+    Work &w = s->w;
+    hipStream_t st = s->stream;
+    SSE_HIP(hipMemcpyAsync(w.ub1, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.G0, G, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    bt_loop(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+    SSE_HIP(hipGetLastError());
+    SSE_HIP(hipMemcpyAsync(ubar1, w.ub2, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(zeta1, w.bt_zout, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(Fzeta, w.Fz1, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipStreamSynchronize(st));
+    return SSE_OK;
+}
+
+extern "C" int sse_debug_thickness_stage(sse_state *s, const double *h_in, const double *u, const double *uA,
+                                         double dt, double *h_out, double *zeta_out) {
+    if (!s || !h_in || !u || !uA || !h_out || !zeta_out) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (!s->initialized) { set_error("state not initialised (h_ref is needed)"); return SSE_ESTATE; }
+    const sse_mesh *m = s->mesh;
+    const int L = s->p.n_layers;
+    Work &w = s->w;
+    hipStream_t st = s->stream;
+    SSE_HIP(hipMemcpyAsync(w.H1, h_in, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.T2, u, (size_t)m->E * L * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.uA, uA, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum(m->d, L, w.H1, w.T2, w.uA, w.Ftot, st);
+    thickness(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, w.T2, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
+    SSE_HIP(hipGetLastError());
+    SSE_HIP(hipMemcpyAsync(h_out, w.H2, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(zeta_out, w.z_half, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipStreamSynchronize(st));
+    return SSE_OK;
+}

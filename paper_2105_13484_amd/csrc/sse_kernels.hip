@@ -1,0 +1,694 @@
+// HIP kernels of the split-explicit step for gfx950.
+//
+// Column kernels (3D): one 64-lane wavefront owns one vertical column of a
+// cell, an edge or a vertex; lane k holds layer k (layers >= 64 live in a
+// second register chunk).  Mesh indices are therefore wave-uniform and every
+// neighbour access is one contiguous 8L-byte column read; vertical sums and
+// scans are cross-lane operations inside the wavefront.  Lanes past the last
+// layer carry zeros so that sums and scans need no masking.
+//
+// 2D kernels (barotropic loop, reconciliation): one thread per edge or cell,
+// reading slot-major neighbour tables.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sse_kernels.h"
+
+namespace sse {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return __shfl(x, 0, kWave);  // one value for the whole column
+}
+
+__device__ __forceinline__ double wave_incl_prefix(double x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        double y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ double wave_incl_suffix(double x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        double y = __shfl_down(x, d, kWave);
+        if (l + d < kWave) x += y;
+    }
+    return x;
+}
+
+template <int NK>
+__device__ __forceinline__ double col_sum(const double (&v)[NK]) {
+    double s = v[0];
+#pragma unroll
+    for (int c = 1; c < NK; ++c) s += v[c];
+    return wave_sum(s);
+}
+
+// o_k = sum_{l<k} v_l
+template <int NK>
+__device__ __forceinline__ void col_excl_prefix(const double (&v)[NK], double (&o)[NK]) {
+    const int l = lane_id();
+    double carry = 0.0;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        double inc = wave_incl_prefix(v[c]);
+        double exc = __shfl_up(inc, 1, kWave);
+        o[c] = (l == 0 ? 0.0 : exc) + carry;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+}
+
+// o_k = sum_{l>k} v_l
+template <int NK>
+__device__ __forceinline__ void col_excl_suffix(const double (&v)[NK], double (&o)[NK]) {
+    const int l = lane_id();
+    double carry = 0.0;
+#pragma unroll
+    for (int c = NK - 1; c >= 0; --c) {
+        double inc = wave_incl_suffix(v[c]);
+        double exc = __shfl_down(inc, 1, kWave);
+        o[c] = (l == kWave - 1 ? 0.0 : exc) + carry;
+        carry += __shfl(inc, 0, kWave);
+    }
+}
+
+// o_k = sum_{l>=k} v_l
+template <int NK>
+__device__ __forceinline__ void col_incl_suffix(const double (&v)[NK], double (&o)[NK]) {
+    double carry = 0.0;
+#pragma unroll
+    for (int c = NK - 1; c >= 0; --c) {
+        double inc = wave_incl_suffix(v[c]);
+        o[c] = inc + carry;
+        carry += __shfl(inc, 0, kWave);
+    }
+}
+
+// o_k = v_{k-1}, o_0 = 0
+template <int NK>
+__device__ __forceinline__ void col_up1(const double (&v)[NK], double (&o)[NK]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        double prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : 0.0;
+        double y = __shfl_up(v[c], 1, kWave);
+        o[c] = (l == 0) ? prev_last : y;
+    }
+}
+
+// o_k = v_{k+1}; zero past the last layer (lanes past L hold zeros)
+template <int NK>
+__device__ __forceinline__ void col_down1(const double (&v)[NK], double (&o)[NK]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        double next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : 0.0;
+        double y = __shfl_down(v[c], 1, kWave);
+        o[c] = (l == kWave - 1) ? next_first : y;
+    }
+}
+
+__device__ __forceinline__ double combine(int mode, double b, double x) {
+    switch (mode) {
+        case COMB_34: return 0.75 * b + 0.25 * x;
+        case COMB_THIRD: return b / 3.0 + 2.0 * x / 3.0;
+        case COMB_HALF: return 0.5 * (b + x);
+        default: return x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Baroclinic forward Euler (Algorithm 1): cell pass
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
+    const int lane = lane_id();
+    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const DevMesh &m = a.m;
+    if (i >= m.C) return;
+    const int L = a.L;
+    const size_t base = (size_t)i * L;
+    if (!m.cmask[i]) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            if (k < L) { a.B[base + k] = 0.0; a.Wtop[base + k] = 0.0; }
+        }
+        if (lane == 0) a.Kbot[i] = 0.0;
+        return;
+    }
+    double hi[NK], divhu[NK], divu[NK], K[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        hi[c] = (k < L) ? a.h[base + k] : 0.0;
+        divhu[c] = divu[c] = K[c] = 0.0;
+    }
+    const int n = m.cell_nedges[i];
+    for (int j = 0; j < n; ++j) {
+        const int e = m.cell_edges[i * kMaxEdges + j];
+        const int nb = m.cell_nbrs[i * kMaxEdges + j];
+        const double cd = m.cell_div[i * kMaxEdges + j];
+        const double ck = m.cell_ke[i * kMaxEdges + j];
+        const double add = a.ubar_add ? a.ubar_add[e] : 0.0;
+        const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            if (k < L) {
+                double u = a.X[eb + k] + add;
+                double he = 0.5 * (hi[c] + a.h[nbb + k]);
+                divhu[c] += cd * (he * u);
+                divu[c] += cd * u;
+                K[c] += ck * (u * u);
+            }
+        }
+    }
+    double w[NK];
+    if (a.frac) {
+        // z-star: T^h_k = -frac_k sum_l div(h u)_l, and w_k - w_{k+1} = -div_k - T^h_k
+        const double tot = col_sum<NK>(divhu);
+        double src[NK];
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            double th = (k < L) ? -a.frac[base + k] * tot : 0.0;
+            src[c] = (k < L) ? (-divhu[c] - th) : 0.0;
+        }
+        col_incl_suffix<NK>(src, w);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) w[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        if (k < L) {
+            a.B[base + k] = K[c] - a.nu_h * divu[c];
+            a.Wtop[base + k] = w[c];
+            if (k == L - 1) a.Kbot[i] = K[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Baroclinic forward Euler: vertex pass (relative vorticity)
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs a) {
+    const int lane = lane_id();
+    const int v = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const DevMesh &m = a.m;
+    if (v >= m.V) return;
+    const int L = a.L;
+    double z[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) z[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int e = m.vert_edges[v * 3 + j];
+        const double cr = m.vert_curl[v * 3 + j];
+        const double add = a.ubar_add ? a.ubar_add[e] : 0.0;
+        const size_t eb = (size_t)e * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            if (k < L) z[c] += cr * (a.X[eb + k] + add);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        if (k < L) a.Z[(size_t)v * L + k] = z[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Baroclinic forward Euler: edge pass (Algorithm 1 and the stage combination)
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int E = m.E;
+    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (e >= E) return;
+    const int L = a.L;
+    const size_t base = (size_t)e * L;
+    if (!m.emask[e]) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            if (k < L) a.out[base + k] = 0.0;
+        }
+        if (lane == 0) {
+            a.G[e] = 0.0;
+            a.sum_h[e] = 0.0;
+            if (a.sum_hu) a.sum_hu[e] = 0.0;
+            if (a.sum_hp) a.sum_hp[e] = 0.0;
+            if (a.Gi) a.Gi[e] = 0.0;
+        }
+        return;
+    }
+    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
+    const double dce = m.dc[e], dve = m.dv[e];
+    const double add_e = a.ubar_add ? a.ubar_add[e] : 0.0;
+    const double sub_e = a.ubar_sub ? a.ubar_sub[e] : 0.0;
+    const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
+    const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
+
+    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], q[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        bool ok = k < L;
+        double x = ok ? a.X[base + k] : 0.0;
+        u[c] = ok ? x + add_e : 0.0;
+        ut[c] = ok ? x - sub_e : 0.0;
+        h1[c] = ok ? a.h[b1 + k] : 0.0;
+        h2[c] = ok ? a.h[b2 + k] : 0.0;
+        he[c] = 0.5 * (h1[c] + h2[c]);
+        r1[c] = ok ? a.rho[b1 + k] : 0.0;
+        r2[c] = ok ? a.rho[b2 + k] : 0.0;
+        q[c] = ok ? 0.5 * (a.Z[bv1 + k] + a.Z[bv2 + k]) : 0.0;
+    }
+
+    // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
+    // -(k.curl u) u^perp, both through the TRiSK tangential reconstruction.
+    double cor[NK], vor[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) cor[c] = vor[c] = 0.0;
+    const int ne = m.neoe[e];
+    for (int j = 0; j < ne; ++j) {
+        const int ep = m.eoe[(size_t)j * E + e];
+        const double wj = m.w[(size_t)j * E + e];
+        const double wfj = m.wf[(size_t)j * E + e];
+        const int pv1 = m.edge_verts[2 * ep], pv2 = m.edge_verts[2 * ep + 1];
+        const double padd = a.ubar_add ? a.ubar_add[ep] : 0.0;
+        const double psub = a.ubar_sub ? a.ubar_sub[ep] : 0.0;
+        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv1 * L, pb2 = (size_t)pv2 * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            int k = lane + c * kWave;
+            if (k < L) {
+                double xp = a.X[pb + k];
+                double up = xp + padd, utp = xp - psub;
+                double qp = 0.5 * (a.Z[pb1 + k] + a.Z[pb2 + k]);
+                cor[c] += wfj * utp;
+                vor[c] += (wj * (0.5 * (q[c] + qp))) * up;
+            }
+        }
+    }
+
+    // Pressure gradient in z-star layers from the column differences.
+    double drh[NK], dh[NK], sp[NK], ss[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        drh[c] = r2[c] * h2[c] - r1[c] * h1[c];
+        dh[c] = h2[c] - h1[c];
+    }
+    col_excl_prefix<NK>(drh, sp);
+    col_excl_suffix<NK>(dh, ss);
+    const double dH = m.H[c2] - m.H[c1];
+
+    // Vertical advection and vertical viscosity at interior interfaces.
+    double uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
+    col_up1<NK>(u, uu);
+    col_up1<NK>(he, hu);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        if (k >= 1 && k < L) {
+            double dzt = (uu[c] - u[c]) / (0.5 * (hu[c] + he[c]));
+            double we = 0.5 * (a.Wtop[b1 + k] + a.Wtop[b2 + k]);
+            at[c] = we * dzt;
+            tau[c] = a.nu_v * dzt;
+        } else {
+            at[c] = 0.0;
+            tau[c] = 0.0;
+        }
+    }
+    col_down1<NK>(at, atn);
+    col_down1<NK>(tau, taun);
+    const double speed = sqrt(a.Kbot[c1] + a.Kbot[c2]);
+    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) / dce;
+
+    double ut1[NK], hut1[NK], hu_in[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        if (k < L) {
+            if (k == L - 1) taun[c] = a.c_drag * speed * u[c];
+            double dp = a.g * (sp[c] + 0.5 * drh[c]);
+            double dz = -dH + ss[c] + 0.5 * dh[c];
+            double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) / (a.rho0 * dce);
+            double gradB = (a.B[b2 + k] - a.B[b1 + k]) / dce;
+            double curlp = (a.Z[bv2 + k] - a.Z[bv1 + k]) / dve;
+            double vadv = 0.5 * (at[c] + atn[c]);
+            double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
+            double du = (tau[c] - taun[c]) / he[c];
+            ut1[c] = ut[c] + a.dt * (cor[c] + tu + du + gz);
+        } else {
+            ut1[c] = 0.0;
+        }
+        hut1[c] = he[c] * ut1[c];
+        hu_in[c] = he[c] * u[c];
+    }
+    const double Sh = col_sum<NK>(he);
+    const double G = col_sum<NK>(hut1) / Sh / a.dt;
+    double outv[NK], hp[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        double x = ut1[c] - a.dt * G;
+        double utn = 0.0;
+        if (a.Un && k < L) utn = a.Un[base + k] - a.ubar_n[e];
+        outv[c] = (k < L) ? combine(a.comb, utn, x) : 0.0;
+        if (k < L) a.out[base + k] = outv[c];
+        hp[c] = he[c] * (a.psum_a * utn + a.psum_b * outv[c]);
+    }
+    double shu = 0.0, shp = 0.0;
+    if (a.sum_hu) shu = col_sum<NK>(hu_in);
+    if (a.sum_hp) shp = col_sum<NK>(hp);
+    if (lane == 0) {
+        a.G[e] = G;
+        a.sum_h[e] = Sh;
+        if (a.sum_hu) a.sum_hu[e] = shu;
+        if (a.sum_hp) a.sum_hp[e] = shp;
+        if (a.Gi) {
+            if (a.interp == 3)
+                a.Gi[e] = a.Ga[e] / 6.0 + a.Gb[e] / 6.0 + 2.0 * G / 3.0;
+            else
+                a.Gi[e] = 0.5 * a.Ga[e] + 0.5 * G;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Barotropic forward-Euler evaluation (Algorithms 3 and 4, one stage)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlocks) {
+    const DevMesh &m = a.m;
+    if ((int)blockIdx.x < nEdgeBlocks) {
+        const int e = blockIdx.x * blockDim.x + threadIdx.x;
+        if (e >= m.E) return;
+        if (!m.emask[e]) {
+            a.uo[e] = 0.0;
+            if (a.F && a.zeroF) a.F[e] = 0.0;
+            return;
+        }
+        const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+        const double ua = a.ua[e];
+        const double z1 = a.za[c1], z2 = a.za[c2];
+        double cor = 0.0;
+        const int ne = m.neoe[e];
+        for (int j = 0; j < ne; ++j)
+            cor += m.wf[(size_t)j * m.E + e] * a.ua[m.eoe[(size_t)j * m.E + e]];
+        const double ru = cor - a.g * (z2 - z1) / m.dc[e] + a.G[e];
+        const double base = a.ub[e];
+        a.uo[e] = combine(a.comb, base, ua + a.tau * ru);
+        if (a.F) {
+            const double flux = ua * (0.5 * ((z1 + m.H[c1]) + (z2 + m.H[c2])));
+            a.F[e] = (a.zeroF ? 0.0 : a.F[e]) + a.wF * flux;
+        }
+    } else {
+        const int i = (blockIdx.x - nEdgeBlocks) * blockDim.x + threadIdx.x;
+        if (i >= m.C) return;
+        if (!m.cmask[i]) { a.zo[i] = 0.0; return; }
+        const double zi = a.za[i] + m.H[i];
+        double div = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxEdges; ++j) {
+            const double cd = m.cell_div_t[(size_t)j * m.C + i];
+            const int e = m.cell_edges_t[(size_t)j * m.C + i];
+            const int nb = m.cell_nbrs_t[(size_t)j * m.C + i];
+            const double zn = a.za[nb] + m.H[nb];
+            div += cd * (a.ua[e] * (0.5 * (zi + zn)));
+        }
+        const double base = a.zb[i];
+        a.zo[i] = combine(a.comb, base, a.za[i] + a.tau * (-div));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Thickness stage (z-star): h_out = comb(h_n, h_in + dt T^h), zeta = sum h - H
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (i >= m.C) return;
+    const int L = a.L;
+    const size_t base = (size_t)i * L;
+    double divF = 0.0;
+    const bool wet = m.cmask[i] != 0;
+    if (wet) {
+        const int n = m.cell_nedges[i];
+        for (int j = 0; j < n; ++j)
+            divF += m.cell_div[i * kMaxEdges + j] * a.Ftot[m.cell_edges[i * kMaxEdges + j]];
+    }
+    double hv[NK];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        hv[c] = 0.0;
+        if (k < L) {
+            double th = wet ? -a.frac[base + k] * divF : 0.0;
+            double x = a.h_in[base + k] + a.dt * th;
+            double b = (a.comb != COMB_NONE) ? a.h_n[base + k] : 0.0;
+            hv[c] = combine(a.comb, b, x);
+            a.h_out[base + k] = hv[c];
+            bad |= !isfinite(hv[c]);
+        }
+    }
+    const double s = col_sum<NK>(hv);
+    if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
+    if (bad && a.nonfinite) *a.nonfinite = 1;
+}
+
+// Thickness stage (isopycnal): per-layer flux divergence, w = 0.
+template <int NK>
+__global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs a) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (i >= m.C) return;
+    const int L = a.L;
+    const size_t base = (size_t)i * L;
+    const bool wet = m.cmask[i] != 0;
+    double hi[NK], div[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        hi[c] = (k < L) ? a.h_in[base + k] : 0.0;
+        div[c] = 0.0;
+    }
+    if (wet) {
+        const int n = m.cell_nedges[i];
+        for (int j = 0; j < n; ++j) {
+            const int e = m.cell_edges[i * kMaxEdges + j];
+            const int nb = m.cell_nbrs[i * kMaxEdges + j];
+            const double cd = m.cell_div[i * kMaxEdges + j];
+            const double ae = (a.a1 ? a.ca1 * a.a1[e] : 0.0) + (a.a2 ? a.ca2 * a.a2[e] : 0.0) + (a.uA ? a.uA[e] : 0.0);
+            const bool ew = m.emask[e] != 0;
+            const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
+#pragma unroll
+            for (int c = 0; c < NK; ++c) {
+                int k = lane + c * kWave;
+                if (k < L && ew) {
+                    double u = a.c1 * a.X1[eb + k] + (a.X2 ? a.c2 * a.X2[eb + k] : 0.0) + ae;
+                    double he = 0.5 * (hi[c] + a.h_in[nbb + k]);
+                    div[c] += cd * (he * u);
+                }
+            }
+        }
+    }
+    double hv[NK];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        hv[c] = 0.0;
+        if (k < L) {
+            double x = hi[c] + a.dt * (-div[c]);
+            double b = (a.comb != COMB_NONE) ? a.h_n[base + k] : 0.0;
+            hv[c] = combine(a.comb, b, x);
+            a.h_out[base + k] = hv[c];
+            bad |= !isfinite(hv[c]);
+        }
+    }
+    const double s = col_sum<NK>(hv);
+    if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
+    if (bad && a.nonfinite) *a.nonfinite = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Reconciliation deficits D^e and adjusted total fluxes (Section 3.4)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) recon_kernel(ReconArgs a) {
+    const DevMesh &m = a.m;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.E) return;
+    if (a.ub_half) a.ub_half[e] = 0.75 * a.ub_n[e] + 0.25 * a.ub2[e];
+    if (!m.emask[e]) {
+        a.Ftot[e] = 0.0;
+        if (a.uA) a.uA[e] = 0.0;
+        return;
+    }
+    const double Sh = a.Sh[e];
+    double Ftot, uA = 0.0;
+    if (a.mode == 0) {
+        const double Fh = a.Fh[e];
+        if (a.rec) uA = (a.Fz[e] - Fh) / Sh;
+        Ftot = Fh + uA * Sh;
+    } else if (a.mode == 1) {
+        const double P = a.Pp[e] + (a.ub_n[e] + a.ub_new[e]) * Sh;
+        if (a.rec) {
+            const double f1 = (a.rec == SSE_RECONCILE_EXACT) ? a.Fz1[e] : a.Fh1[e];
+            const double f2 = (a.rec == SSE_RECONCILE_EXACT) ? a.Fz2[e] : a.Fh2[e];
+            const double Fh3 = (f1 + f2 + 2.0 * P) / 6.0;
+            uA = 1.5 * (a.Fz[e] - Fh3) / Sh;
+        }
+        Ftot = 0.5 * P + uA * Sh;
+    } else {
+        const double P = a.Pp[e] + a.ub_new[e] * Sh;
+        if (a.rec) {
+            const double f1 = (a.rec == SSE_RECONCILE_EXACT) ? a.Fz1[e] : a.Fh1[e];
+            const double Fh2 = 0.5 * (f1 + P);
+            uA = 2.0 * (a.Fz[e] - Fh2) / Sh;
+        }
+        Ftot = P + uA * Sh;
+    }
+    a.Ftot[e] = Ftot;
+    if (a.uA) a.uA[e] = uA;
+}
+
+// ---------------------------------------------------------------------------
+// u^{n+1} = ubar^{n+1} + ut^{n+1}; split (BBspl) with h^{n+1}
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (e >= m.E) return;
+    const int L = a.L;
+    const size_t base = (size_t)e * L;
+    const bool wet = m.emask[e] != 0;
+    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    const double ub = (a.ubar_bt && wet) ? a.ubar_bt[e] : 0.0;
+    double he[NK], hu[NK];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        he[c] = hu[c] = 0.0;
+        if (k < L) {
+            double u = wet ? (a.ubar_bt ? ub + a.X[base + k] : a.X[base + k]) : 0.0;
+            a.U[base + k] = u;
+            he[c] = 0.5 * (a.h[(size_t)c1 * L + k] + a.h[(size_t)c2 * L + k]);
+            hu[c] = he[c] * u;
+            bad |= !isfinite(u);
+        }
+    }
+    const double sh = col_sum<NK>(he);
+    const double shu = col_sum<NK>(hu);
+    if (lane == 0) a.ubar[e] = wet ? shu / sh : 0.0;
+    if (bad && a.nonfinite) *a.nonfinite = 1;
+}
+
+template <int NK>
+__global__ void __launch_bounds__(kBlock) zeta_kernel(DevMesh m, int L, const double *h, double *zeta) {
+    const int lane = lane_id();
+    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (i >= m.C) return;
+    double hv[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        hv[c] = (k < L) ? h[(size_t)i * L + k] : 0.0;
+    }
+    const double s = col_sum<NK>(hv);
+    if (lane == 0) zeta[i] = m.cmask[i] ? s - m.H[i] : 0.0;
+}
+
+// F_e = sum_k h_e (X_k + uA_e)
+template <int NK>
+__global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const double *X,
+                                                               const double *uA, double *F) {
+    const int lane = lane_id();
+    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    if (e >= m.E) return;
+    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    const double ua = uA ? uA[e] : 0.0;
+    double f[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        int k = lane + c * kWave;
+        f[c] = 0.0;
+        if (k < L) {
+            double he = 0.5 * (h[(size_t)c1 * L + k] + h[(size_t)c2 * L + k]);
+            f[c] = he * (X[(size_t)e * L + k] + ua);
+        }
+    }
+    const double s = col_sum<NK>(f);
+    if (lane == 0) F[e] = m.emask[e] ? s : 0.0;
+}
+
+__global__ void copy_kernel(const double *src, double *dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline dim3 col_grid(int n) { return dim3((n + kColsPerBlock - 1) / kColsPerBlock); }
+static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+#define SSE_DISPATCH_NK(L, KERNEL, GRID, ...)                                   \
+    do {                                                                        \
+        if ((L) <= kWave)                                                       \
+            KERNEL<1><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);                     \
+        else                                                                    \
+            KERNEL<2><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);                     \
+    } while (0)
+
+void launch_fe_cell(const FECellArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_cell_kernel, col_grid(a.m.C), a); }
+void launch_fe_vertex(const FEVertexArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_vertex_kernel, col_grid(a.m.V), a); }
+void launch_fe_edge(const FEEdgeArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_edge_kernel, col_grid(a.m.E), a); }
+void launch_thickness(const THArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_kernel, col_grid(a.m.C), a); }
+void launch_thickness_iso(const THIsoArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_iso_kernel, col_grid(a.m.C), a); }
+void launch_assemble(const AssembleArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, assemble_kernel, col_grid(a.m.E), a); }
+void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s) {
+    SSE_DISPATCH_NK(L, zeta_kernel, col_grid(m.C), m, L, h, zeta);
+}
+void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const double *X, const double *uA, double *F,
+                          hipStream_t s) {
+    SSE_DISPATCH_NK(L, edge_flux_sum_kernel, col_grid(m.E), m, L, h, X, uA, F);
+}
+
+void launch_bt_eval(const BTEvalArgs &a, hipStream_t s) {
+    const int nEB = (a.m.E + 255) / 256, nCB = (a.m.C + 255) / 256;
+    bt_eval_kernel<<<dim3(nEB + nCB), 256, 0, s>>>(a, nEB);
+}
+
+void launch_recon(const ReconArgs &a, hipStream_t s) { recon_kernel<<<flat_grid(a.m.E), 256, 0, s>>>(a); }
+
+void launch_copy(const double *src, double *dst, size_t n, hipStream_t s) {
+    if (n) copy_kernel<<<flat_grid(n), 256, 0, s>>>(src, dst, n);
+}
+
+}  // namespace sse

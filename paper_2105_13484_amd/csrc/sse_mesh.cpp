@@ -1,0 +1,226 @@
+// Host-side mesh validation and construction of the device table images.
+//
+// The TRiSK operators (Section 5 opening of the paper; Thuburn et al. 2009,
+// Ringler et al. 2010) are applied on the GPU through precomputed
+// per-entity coefficients:
+//   divergence  (div F)_i  = sum_j [s_{i,e_j} l_{e_j} / A_i] F_{e_j}
+//   kinetic en. K_i        = sum_j [l_{e_j} d_{e_j} / (4 A_i)] u_{e_j}^2
+//   curl        zeta_v     = sum_j [r_{v,e_j} d_{e_j} / A_v] u_{e_j}
+//   Coriolis    -f k x u   = sum_j [W_{e,j} (f_e + f_{e_j}) / 2] u_{e_j}
+// with s = +1 where the edge normal leaves the cell and r = +1 where the
+// vertex is the edge's second vertex.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sse_internal.h"
+
+namespace sse {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace sse
+
+extern "C" const char *sse_last_error(void) { return sse::g_last_error.c_str(); }
+
+extern "C" const char *sse_version(void) { return "ssprkse 0.1 (gfx950)"; }
+
+namespace sse {
+
+static std::string fmt(const char *f, long a = 0, long b = 0, long c = 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, f, a, b, c);
+    return buf;
+}
+
+int validate_desc(const sse_mesh_desc *d, std::string &err) {
+    if (!d) { err = "mesh description is NULL"; return SSE_EINVAL; }
+    const long C = d->n_cells, E = d->n_edges, V = d->n_vertices;
+    if (C <= 0 || E <= 0 || V <= 0) { err = "mesh counts must be positive"; return SSE_EINVAL; }
+    if (d->max_edges < 3 || d->max_edges > kMaxEdges) { err = "max_edges must be in [3, 6]"; return SSE_EINVAL; }
+    if (d->max_edges2 < 1 || d->max_edges2 > kMaxEdges2) { err = "max_edges2 must be in [1, 10]"; return SSE_EINVAL; }
+    const void *req[] = {d->cells_on_edge, d->edges_on_cell, d->n_edges_on_cell, d->vertices_on_edge,
+                         d->edges_on_vertex, d->edges_on_edge, d->n_edges_on_edge, d->weights_on_edge,
+                         d->dc_edge, d->dv_edge, d->f_edge, d->area_cell, d->bottom_depth,
+                         d->area_triangle, d->cell_mask};
+    for (const void *p : req)
+        if (!p) { err = "a required mesh table is NULL"; return SSE_EINVAL; }
+    const int me = d->max_edges, me2 = d->max_edges2;
+    for (long e = 0; e < E; ++e) {
+        for (int s = 0; s < 2; ++s) {
+            long c = d->cells_on_edge[2 * e + s], v = d->vertices_on_edge[2 * e + s];
+            if (c < 0 || c >= C) { err = fmt("cells_on_edge[%ld] out of range", e); return SSE_EINVAL; }
+            if (v < 0 || v >= V) { err = fmt("vertices_on_edge[%ld] out of range", e); return SSE_EINVAL; }
+        }
+        if (d->cells_on_edge[2 * e] == d->cells_on_edge[2 * e + 1]) { err = fmt("edge %ld joins a cell to itself", e); return SSE_EINVAL; }
+        if (!(d->dc_edge[e] > 0) || !(d->dv_edge[e] > 0) || !std::isfinite(d->dc_edge[e]) || !std::isfinite(d->dv_edge[e])) {
+            err = fmt("edge %ld has a non-positive length", e); return SSE_EINVAL;
+        }
+        if (!std::isfinite(d->f_edge[e])) { err = fmt("f_edge[%ld] is not finite", e); return SSE_EINVAL; }
+        int n = d->n_edges_on_edge[e];
+        if (n < 0 || n > me2) { err = fmt("n_edges_on_edge[%ld] = %ld out of range", e, n); return SSE_EINVAL; }
+        for (int j = 0; j < n; ++j) {
+            long ep = d->edges_on_edge[e * me2 + j];
+            if (ep < 0 || ep >= E) { err = fmt("edges_on_edge[%ld][%ld] out of range", e, j); return SSE_EINVAL; }
+            if (!std::isfinite(d->weights_on_edge[e * me2 + j])) { err = fmt("weights_on_edge[%ld][%ld] not finite", e, j); return SSE_EINVAL; }
+        }
+    }
+    for (long i = 0; i < C; ++i) {
+        int n = d->n_edges_on_cell[i];
+        if (n < 3 || n > me) { err = fmt("n_edges_on_cell[%ld] = %ld out of range", i, n); return SSE_EINVAL; }
+        if (!(d->area_cell[i] > 0) || !std::isfinite(d->area_cell[i])) { err = fmt("area_cell[%ld] not positive", i); return SSE_EINVAL; }
+        if (!(d->bottom_depth[i] >= 0) || !std::isfinite(d->bottom_depth[i])) { err = fmt("bottom_depth[%ld] invalid", i); return SSE_EINVAL; }
+        if (d->cell_mask[i] && !(d->bottom_depth[i] > 0)) { err = fmt("ocean cell %ld has zero depth", i); return SSE_EINVAL; }
+        for (int j = 0; j < n; ++j) {
+            long e = d->edges_on_cell[i * me + j];
+            if (e < 0 || e >= E) { err = fmt("edges_on_cell[%ld][%ld] out of range", i, j); return SSE_EINVAL; }
+            if (d->cells_on_edge[2 * e] != i && d->cells_on_edge[2 * e + 1] != i) {
+                err = fmt("edge %ld listed on cell %ld does not touch it", e, i); return SSE_EINVAL;
+            }
+        }
+    }
+    for (long v = 0; v < V; ++v) {
+        if (!(d->area_triangle[v] > 0) || !std::isfinite(d->area_triangle[v])) { err = fmt("area_triangle[%ld] not positive", v); return SSE_EINVAL; }
+        for (int j = 0; j < 3; ++j) {
+            long e = d->edges_on_vertex[3 * v + j];
+            if (e < 0 || e >= E) { err = fmt("edges_on_vertex[%ld][%ld] out of range", v, j); return SSE_EINVAL; }
+            if (d->vertices_on_edge[2 * e] != v && d->vertices_on_edge[2 * e + 1] != v) {
+                err = fmt("edge %ld listed on vertex %ld does not touch it", e, v); return SSE_EINVAL;
+            }
+        }
+    }
+    // Energy neutrality of the Coriolis weights: l_e d_e W_ee' = -l_e' d_e' W_e'e.
+    for (long e = 0; e < E; ++e) {
+        int n = d->n_edges_on_edge[e];
+        double scale = 0;
+        for (int j = 0; j < n; ++j)
+            scale = std::fmax(scale, std::fabs(d->dv_edge[e] * d->dc_edge[e] * d->weights_on_edge[e * me2 + j]));
+        for (int j = 0; j < n; ++j) {
+            long ep = d->edges_on_edge[e * me2 + j];
+            int np = d->n_edges_on_edge[ep], found = -1;
+            for (int q = 0; q < np; ++q)
+                if (d->edges_on_edge[ep * me2 + q] == e) { found = q; break; }
+            if (found < 0) { err = fmt("edges_on_edge is not symmetric at edges %ld/%ld", e, ep); return SSE_EINVAL; }
+            double a = d->dv_edge[e] * d->dc_edge[e] * d->weights_on_edge[e * me2 + j];
+            double b = d->dv_edge[ep] * d->dc_edge[ep] * d->weights_on_edge[ep * me2 + found];
+            if (std::fabs(a + b) > 1e-10 * (scale + 1e-300)) {
+                err = fmt("weights_on_edge are not antisymmetric at edges %ld/%ld", e, ep); return SSE_EINVAL;
+            }
+        }
+    }
+    return SSE_OK;
+}
+
+MeshLayout mesh_layout(int C, int E, int V) {
+    MeshLayout L;
+    size_t sizes[] = {
+        (size_t)C * 6 * 4, (size_t)C * 6 * 4, (size_t)C * 4, (size_t)C * 6 * 8, (size_t)C * 6 * 8,
+        (size_t)C * 6 * 4, (size_t)C * 6 * 4, (size_t)C * 6 * 8, (size_t)C * 8, (size_t)C,
+        (size_t)E * 2 * 4, (size_t)E * 2 * 4, (size_t)E * 10 * 4, (size_t)E * 4, (size_t)E * 10 * 8,
+        (size_t)E * 10 * 8, (size_t)E * 8, (size_t)E * 8, (size_t)E,
+        (size_t)V * 3 * 4, (size_t)V * 3 * 8};
+    size_t off = 0;
+    int n = sizeof(sizes) / sizeof(sizes[0]);
+    for (int i = 0; i < n; ++i) {
+        L.off[i] = off;
+        off += (sizes[i] + kAlign - 1) / kAlign * kAlign;
+    }
+    L.total = off;
+    return L;
+}
+
+void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
+    const int C = d->n_cells, E = d->n_edges, V = d->n_vertices;
+    const int me = d->max_edges, me2 = d->max_edges2;
+    t.cell_edges.assign((size_t)C * 6, 0);
+    t.cell_nbrs.assign((size_t)C * 6, 0);
+    t.cell_nedges.assign(C, 0);
+    t.cell_div.assign((size_t)C * 6, 0.0);
+    t.cell_ke.assign((size_t)C * 6, 0.0);
+    t.H.assign(C, 0.0);
+    t.cmask.assign(C, 0);
+    t.n_ocean_cells = 0;
+    for (int i = 0; i < C; ++i) {
+        int n = d->n_edges_on_cell[i];
+        t.cell_nedges[i] = n;
+        t.H[i] = d->bottom_depth[i];
+        t.cmask[i] = d->cell_mask[i] ? 1 : 0;
+        t.n_ocean_cells += t.cmask[i];
+        for (int j = 0; j < 6; ++j) {
+            if (j < n) {
+                int e = d->edges_on_cell[i * me + j];
+                int c1 = d->cells_on_edge[2 * e], c2 = d->cells_on_edge[2 * e + 1];
+                double s = (c1 == i) ? 1.0 : -1.0;
+                t.cell_edges[i * 6 + j] = e;
+                t.cell_nbrs[i * 6 + j] = (c1 == i) ? c2 : c1;
+                t.cell_div[i * 6 + j] = s * d->dv_edge[e] / d->area_cell[i];
+                t.cell_ke[i * 6 + j] = 0.25 * d->dv_edge[e] * d->dc_edge[e] / d->area_cell[i];
+            } else {  // padding: a valid index with zero coefficients
+                t.cell_edges[i * 6 + j] = t.cell_edges[i * 6];
+                t.cell_nbrs[i * 6 + j] = t.cell_nbrs[i * 6];
+            }
+        }
+    }
+    t.cell_edges_t.assign((size_t)C * 6, 0);
+    t.cell_nbrs_t.assign((size_t)C * 6, 0);
+    t.cell_div_t.assign((size_t)C * 6, 0.0);
+    for (int i = 0; i < C; ++i)
+        for (int j = 0; j < 6; ++j) {
+            t.cell_edges_t[(size_t)j * C + i] = t.cell_edges[i * 6 + j];
+            t.cell_nbrs_t[(size_t)j * C + i] = t.cell_nbrs[i * 6 + j];
+            t.cell_div_t[(size_t)j * C + i] = t.cell_div[i * 6 + j];
+        }
+    t.edge_cells.assign(d->cells_on_edge, d->cells_on_edge + 2 * (size_t)E);
+    t.edge_verts.assign(d->vertices_on_edge, d->vertices_on_edge + 2 * (size_t)E);
+    t.eoe.assign((size_t)E * 10, 0);
+    t.neoe.assign(E, 0);
+    t.w.assign((size_t)E * 10, 0.0);
+    t.wf.assign((size_t)E * 10, 0.0);
+    t.dc.assign(d->dc_edge, d->dc_edge + E);
+    t.dv.assign(d->dv_edge, d->dv_edge + E);
+    t.emask.assign(E, 0);
+    for (int e = 0; e < E; ++e) {
+        int c1 = d->cells_on_edge[2 * e], c2 = d->cells_on_edge[2 * e + 1];
+        t.emask[e] = (d->cell_mask[c1] && d->cell_mask[c2]) ? 1 : 0;
+        int n = d->n_edges_on_edge[e];
+        t.neoe[e] = n;
+        for (int j = 0; j < 10; ++j) {
+            if (j < n) {
+                int ep = d->edges_on_edge[e * me2 + j];
+                double wj = d->weights_on_edge[e * me2 + j];
+                t.eoe[(size_t)j * E + e] = ep;
+                t.w[(size_t)j * E + e] = wj;
+                t.wf[(size_t)j * E + e] = wj * (0.5 * (d->f_edge[e] + d->f_edge[ep]));
+            } else {
+                t.eoe[(size_t)j * E + e] = e;
+            }
+        }
+    }
+    t.vert_edges.assign(d->edges_on_vertex, d->edges_on_vertex + 3 * (size_t)V);
+    t.vert_curl.assign((size_t)V * 3, 0.0);
+    for (int v = 0; v < V; ++v)
+        for (int j = 0; j < 3; ++j) {
+            int e = d->edges_on_vertex[3 * v + j];
+            double r = (d->vertices_on_edge[2 * e + 1] == v) ? 1.0 : -1.0;
+            t.vert_curl[v * 3 + j] = r * d->dc_edge[e] / d->area_triangle[v];
+        }
+}
+
+}  // namespace sse
+
+extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
+    std::string err;
+    int rc = sse::validate_desc(d, err);
+    if (rc != SSE_OK) sse::set_error(err);
+    return rc;
+}
+
+extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
+    if (!d || !bytes) { sse::set_error("NULL argument"); return SSE_EINVAL; }
+    if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { sse::set_error("mesh counts must be positive"); return SSE_EINVAL; }
+    *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
+    return SSE_OK;
+}

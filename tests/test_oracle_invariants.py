@@ -148,3 +148,27 @@ def test_single_layer_reduction(scheme):
         ubar, ut = S.split(u, h, st)
         assert np.abs(ut).max() <= 1e-15 * np.abs(u).max()
         np.testing.assert_allclose(h[:, 0] - base.H, S.ssh(h, st), rtol=0, atol=1e-12 * base.H.max())
+
+
+def _growth(reconcile, scheme, steps=12, eps=1e-15):
+    case = smooth_case(n=10, L=5, scheme=scheme, reconcile=reconcile, M=6, dt=180.0)
+    st = Setup.from_case(case)
+    rng = np.random.default_rng(0)
+    u1, h1 = case.u.copy(), case.h.copy()
+    u2, h2 = case.u.copy(), case.h * (1 + eps * rng.standard_normal(case.h.shape))
+    for _ in range(steps):
+        u1, h1 = S.step(u1, h1, st)
+        u2, h2 = S.step(u2, h2, st)
+    return np.linalg.norm(u2 - u1) / np.linalg.norm(u1)
+
+
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_reconciliation_conditioning(scheme):
+    """A roundoff-sized perturbation of the layer thicknesses stays at roundoff
+    with the exact reconciliation but is amplified by orders of magnitude
+    without it: the layer SSH then carries a fast mode that the barotropic
+    solve does not control (Remark 3.1 and the stability discussion of
+    Section 5 on reconciliation)."""
+    exact, off = _growth(1, scheme), _growth(0, scheme)
+    assert exact < 1e-11
+    assert off > 100 * exact
