@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -95,6 +96,7 @@ struct sse_state {
     size_t bytes = 0;
     bool initialized = false;
     // profiling
+    int edge_variant = -1;   // -1: direct gathers; 0 / 1: LDS tiles of 8 / 16 edges
     bool prof = false;
     int prof_mask = 0;
     std::vector<hipEvent_t> events;
@@ -192,7 +194,10 @@ void fe_pass(sse_state *s, const double *X, const double *add, const double *sub
         a.nu_h = p.nu_h;
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
-        launch_fe_edge(a, s->stream);
+        if (s->edge_variant >= 0)
+            launch_fe_edge_tiled(a, s->mesh->tiles[s->edge_variant], s->stream);
+        else
+            launch_fe_edge(a, s->stream);
     }
 }
 
@@ -381,7 +386,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     int rc = validate_desc(d, err);
     if (rc != SSE_OK) { set_error(err); return rc; }
     MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
-    if (!dev_buf || bytes < lay.total) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
+    const size_t need = lay.total + tiles_bytes(d, 8) + tiles_bytes(d, 16);
+    if (!dev_buf || bytes < need) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
     HostMeshTables t;
     build_tables(d, t);
@@ -391,12 +397,13 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.cell_ke.data(), t.cell_edges_t.data(), t.cell_nbrs_t.data(), t.cell_div_t.data(),
                          t.H.data(), t.cmask.data(), t.edge_cells.data(), t.edge_verts.data(), t.eoe.data(),
                          t.neoe.data(), t.w.data(), t.wf.data(), t.dc.data(), t.dv.data(), t.emask.data(),
-                         t.vert_edges.data(), t.vert_curl.data()};
+                         t.vert_edges.data(), t.vert_curl.data(), t.eoe_v.data(), t.inv_dc.data(),
+                         t.inv_dv.data(), t.wpair.data()};
     const size_t C = d->n_cells, E = d->n_edges, V = d->n_vertices;
     const size_t nb[] = {C * 6 * 4, C * 6 * 4, C * 4, C * 6 * 8, C * 6 * 8, C * 6 * 4, C * 6 * 4, C * 6 * 8,
                          C * 8, C, E * 2 * 4, E * 2 * 4, E * 10 * 4, E * 4, E * 10 * 8, E * 10 * 8, E * 8, E * 8, E,
-                         V * 3 * 4, V * 3 * 8};
-    for (int i = 0; i < 21; ++i) SSE_HIP(hipMemcpyAsync(base + lay.off[i], src[i], nb[i], hipMemcpyHostToDevice, s));
+                         V * 3 * 4, V * 3 * 8, E * 10 * 8, E * 8, E * 8, E * 20 * 8};
+    for (int i = 0; i < 25; ++i) SSE_HIP(hipMemcpyAsync(base + lay.off[i], src[i], nb[i], hipMemcpyHostToDevice, s));
     SSE_HIP(hipStreamSynchronize(s));
     sse_mesh *m = new sse_mesh();
     m->C = d->n_cells;
@@ -431,7 +438,39 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.emask = (const uint8_t *)P(18);
     dm.vert_edges = (const int32_t *)P(19);
     dm.vert_curl = (const double *)P(20);
+    dm.eoe_v = (const int2 *)P(21);
+    dm.inv_dc = (const double *)P(22);
+    dm.inv_dv = (const double *)P(23);
+    dm.wpair = (const double *)P(24);
     m->cells_on_edge = t.edge_cells;
+    // Gather lists of the LDS-staged edge pass for tiles of 8 and 16 edges.
+    size_t cursor = lay.total;
+    const int Ts[2] = {8, 16};
+    for (int q = 0; q < 2; ++q) {
+        HostTiles ht;
+        DevTiles &dt = m->tiles[q];
+        if (!build_tiles(d, Ts[q], ht)) { dt.T = 0; continue; }
+        auto put = [&](const void *src, size_t n) -> const void * {
+            char *dst = base + cursor;
+            if (n) hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+            cursor += (n + kAlign - 1) / kAlign * kAlign;
+            return dst;
+        };
+        dt.T = ht.T;
+        dt.nT = ht.nT;
+        dt.max_ue = ht.max_ue;
+        dt.max_uv = ht.max_uv;
+        dt.max_uc = ht.max_uc;
+        dt.ue_off = (const int32_t *)put(ht.ue_off.data(), ht.ue_off.size() * 4);
+        dt.uv_off = (const int32_t *)put(ht.uv_off.data(), ht.uv_off.size() * 4);
+        dt.uc_off = (const int32_t *)put(ht.uc_off.data(), ht.uc_off.size() * 4);
+        dt.ue = (const int32_t *)put(ht.ue.data(), ht.ue.size() * 4);
+        dt.uv = (const int32_t *)put(ht.uv.data(), ht.uv.size() * 4);
+        dt.uc = (const int32_t *)put(ht.uc.data(), ht.uc.size() * 4);
+        dt.loc = (const uint8_t *)put(ht.loc.data(), ht.loc.size());
+        SSE_HIP(hipStreamSynchronize(s));
+    }
+    if (cursor > need) { delete m; set_error("internal: tile tables overflow the mesh buffer"); return SSE_EINVAL; }
     *out = m;
     return SSE_OK;
 }
@@ -467,6 +506,21 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->stream = static_cast<hipStream_t>(stream);
     s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers);
     s->bytes = bytes;
+    // Edge-pass variant.  Measured on an MI355X at 512x512 cells x 60 layers
+    // (FP64), the direct-gather kernel beats both LDS tilings: at 480 bytes
+    // per column the tiles stay small, their halos triple the staged data,
+    // and the staging runs at L2 speed.  The tiled forms stay selectable
+    // (SSE_EDGE_VARIANT = 0 / 1) for meshes or precisions where they win.
+    int dev = 0, lds_max = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_max = 65536;
+    set_tiled_lds_limit((size_t)lds_max);
+    s->edge_variant = -1;
+    if (const char *ev = std::getenv("SSE_EDGE_VARIANT")) {
+        const int v = std::atoi(ev);
+        if (v == -1 || ((v == 0 || v == 1) && m->tiles[v].T && fe_edge_tiled_lds(m->tiles[v], p->n_layers) <= (size_t)lds_max))
+            s->edge_variant = v;
+    }
     *out = s;
     return SSE_OK;
 }

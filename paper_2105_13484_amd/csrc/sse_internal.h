@@ -16,6 +16,7 @@ constexpr int kMaxEdges = 6;    // edges per cell (hexagons / pentagons)
 constexpr int kMaxEdges2 = 10;  // edges in the tangential-reconstruction stencil
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kColsPerBlock = 4;
+constexpr int kXcd = 8;           // accelerator complex dies of an MI355X
 constexpr int kBlock = kWave * kColsPerBlock;
 constexpr size_t kAlign = 256;
 
@@ -41,14 +42,32 @@ struct DevMesh {
     const int32_t *edge_verts = nullptr;    // [E][2]
     const int32_t *eoe = nullptr;           // [10][E]
     const int32_t *neoe = nullptr;          // [E]
+    const int2 *eoe_v = nullptr;            // [10][E] (v1, v2) of each stencil edge
     const double *w = nullptr;              // [10][E]  W_{e,j}
     const double *wf = nullptr;             // [10][E]  W_{e,j} (f_e + f_j) / 2
+    const double *wpair = nullptr;          // [E][10][2] (W_{e,j}, W_{e,j} (f_e + f_j) / 2), entity-major
     const double *dc = nullptr;             // [E]
     const double *dv = nullptr;             // [E]
+    const double *inv_dc = nullptr;         // [E] 1 / d_e
+    const double *inv_dv = nullptr;         // [E] 1 / l_e
     const uint8_t *emask = nullptr;         // [E]
     // vertices
     const int32_t *vert_edges = nullptr;    // [V][3]
     const double *vert_curl = nullptr;      // [V][3]  r_{v,e} d_e / A_v
+};
+
+// Gather lists of the LDS-staged baroclinic edge pass.  The edges are cut
+// into tiles of T consecutive edges; for every tile the unique edge columns
+// (the tiles' edges and their reconstruction stencils), vertex columns and
+// cell columns it reads are listed once, and every edge stores the 8-bit
+// positions of its operands in those lists.
+constexpr int kLocPerEdge = 36;  // self, c1, c2, v1, v2, stencil[10], stencil vertices[10][2], pad
+struct DevTiles {
+    int T = 0, nT = 0;
+    int max_ue = 0, max_uv = 0, max_uc = 0;  // largest list sizes over the tiles
+    const int32_t *ue_off = nullptr, *uv_off = nullptr, *uc_off = nullptr;  // [nT + 1]
+    const int32_t *ue = nullptr, *uv = nullptr, *uc = nullptr;              // global ids
+    const uint8_t *loc = nullptr;                                           // [E][kLocPerEdge]
 };
 
 }  // namespace sse
@@ -58,6 +77,7 @@ struct sse_mesh {
     int C = 0, E = 0, V = 0;
     int n_ocean_cells = 0;
     std::vector<int32_t> cells_on_edge;     // host copy (for debug helpers)
+    sse::DevTiles tiles[2];                 // T = 8 and T = 16
     void *dev_buf = nullptr;
     size_t dev_bytes = 0;
 };
@@ -78,14 +98,23 @@ struct HostMeshTables {
     std::vector<int32_t> cell_edges, cell_nbrs, cell_nedges, cell_edges_t, cell_nbrs_t;
     std::vector<double> cell_div, cell_ke, cell_div_t, H;
     std::vector<uint8_t> cmask;
-    std::vector<int32_t> edge_cells, edge_verts, eoe, neoe;
-    std::vector<double> w, wf, dc, dv;
+    std::vector<int32_t> edge_cells, edge_verts, eoe, neoe, eoe_v;
+    std::vector<double> w, wf, dc, dv, inv_dc, inv_dv, wpair;
     std::vector<uint8_t> emask;
     std::vector<int32_t> vert_edges;
     std::vector<double> vert_curl;
     int n_ocean_cells = 0;
 };
 void build_tables(const sse_mesh_desc *d, HostMeshTables &t);
+
+struct HostTiles {
+    int T = 0, nT = 0, max_ue = 0, max_uv = 0, max_uc = 0;
+    std::vector<int32_t> ue_off, uv_off, uc_off, ue, uv, uc;
+    std::vector<uint8_t> loc;
+};
+// Returns false if a tile needs more than 255 entries in one list.
+bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t);
+size_t tiles_bytes(const sse_mesh_desc *d, int T);
 
 void set_error(const std::string &msg);
 

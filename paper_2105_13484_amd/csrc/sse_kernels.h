@@ -133,6 +133,10 @@ struct AssembleArgs {
     int *nonfinite;
 };
 
+// LDS bytes the tiled edge pass needs for tile set t and L layers.
+size_t fe_edge_tiled_lds(const DevTiles &t, int L);
+void launch_fe_edge_tiled(const FEEdgeArgs &a, const DevTiles &t, hipStream_t s);
+void set_tiled_lds_limit(size_t bytes);
 void launch_fe_cell(const FECellArgs &a, hipStream_t s);
 void launch_fe_vertex(const FEVertexArgs &a, hipStream_t s);
 void launch_fe_edge(const FEEdgeArgs &a, hipStream_t s);

@@ -19,6 +19,28 @@ namespace sse {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8) and every XCD has its own L2.  Launches use 8 * ceil(nb / 8)
+// blocks and renumber them so that XCD x processes the contiguous logical
+// range [x * per, (x + 1) * per): neighbouring columns then share one L2.
+// Returns -1 for the padding blocks.
+__device__ __forceinline__ int xcd_block(int nb) {
+    const int per = (nb + kXcd - 1) / kXcd;
+    const int b = blockIdx.x;
+    const int logical = (b % kXcd) * per + b / kXcd;
+    return logical < nb ? logical : -1;
+}
+
+// Index of the column owned by this wavefront among n columns (-1: none).
+// readfirstlane tells the compiler the value is wave-uniform, so mesh-table
+// reads that depend on it become scalar loads instead of 64 identical vector
+// loads.
+__device__ __forceinline__ int column_id(int n) {
+    const int lb = xcd_block((n + kColsPerBlock - 1) / kColsPerBlock);
+    const int col = lb * kColsPerBlock + (threadIdx.x >> 6);
+    return __builtin_amdgcn_readfirstlane(lb < 0 ? n : col);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
@@ -132,8 +154,8 @@ __device__ __forceinline__ double combine(int mode, double b, double x) {
 template <int NK>
 __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
     const int lane = lane_id();
-    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
     const DevMesh &m = a.m;
+    const int i = column_id(m.C);
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -153,8 +175,10 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
         hi[c] = (k < L) ? a.h[base + k] : 0.0;
         divhu[c] = divu[c] = K[c] = 0.0;
     }
-    const int n = m.cell_nedges[i];
-    for (int j = 0; j < n; ++j) {
+    // Padded slots hold a valid index with zero coefficients, so the stencil
+    // is unrolled to its full width and all its loads issue together.
+#pragma unroll
+    for (int j = 0; j < kMaxEdges; ++j) {
         const int e = m.cell_edges[i * kMaxEdges + j];
         const int nb = m.cell_nbrs[i * kMaxEdges + j];
         const double cd = m.cell_div[i * kMaxEdges + j];
@@ -206,8 +230,8 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
 template <int NK>
 __global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs a) {
     const int lane = lane_id();
-    const int v = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
     const DevMesh &m = a.m;
+    const int v = column_id(m.V);
     if (v >= m.V) return;
     const int L = a.L;
     double z[NK];
@@ -240,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
     const int E = m.E;
-    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int e = column_id(E);
     if (e >= E) return;
     const int L = a.L;
     const size_t base = (size_t)e * L;
@@ -261,18 +285,18 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
     }
     const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
     const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
-    const double dce = m.dc[e], dve = m.dv[e];
+    const double idc = m.inv_dc[e], idv = m.inv_dv[e];
     const double add_e = a.ubar_add ? a.ubar_add[e] : 0.0;
     const double sub_e = a.ubar_sub ? a.ubar_sub[e] : 0.0;
     const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
     const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
 
-    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], q[NK];
+    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], za[NK], zb[NK], q[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        bool ok = k < L;
-        double x = ok ? a.X[base + k] : 0.0;
+        const int k = lane + c * kWave;
+        const bool ok = k < L;
+        const double x = ok ? a.X[base + k] : 0.0;
         u[c] = ok ? x + add_e : 0.0;
         ut[c] = ok ? x - sub_e : 0.0;
         h1[c] = ok ? a.h[b1 + k] : 0.0;
@@ -280,30 +304,35 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
         he[c] = 0.5 * (h1[c] + h2[c]);
         r1[c] = ok ? a.rho[b1 + k] : 0.0;
         r2[c] = ok ? a.rho[b2 + k] : 0.0;
-        q[c] = ok ? 0.5 * (a.Z[bv1 + k] + a.Z[bv2 + k]) : 0.0;
+        za[c] = ok ? a.Z[bv1 + k] : 0.0;
+        zb[c] = ok ? a.Z[bv2 + k] : 0.0;
+        q[c] = 0.5 * (za[c] + zb[c]);
     }
 
     // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
-    // -(k.curl u) u^perp, both through the TRiSK tangential reconstruction.
+    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
+    // stencil slots point at the edge itself with zero weights, so the loop
+    // runs its full width and its loads issue together.
     double cor[NK], vor[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) cor[c] = vor[c] = 0.0;
-    const int ne = m.neoe[e];
-    for (int j = 0; j < ne; ++j) {
-        const int ep = m.eoe[(size_t)j * E + e];
-        const double wj = m.w[(size_t)j * E + e];
-        const double wfj = m.wf[(size_t)j * E + e];
-        const int pv1 = m.edge_verts[2 * ep], pv2 = m.edge_verts[2 * ep + 1];
+    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+#pragma unroll
+    for (int j = 0; j < kMaxEdges2; ++j) {
+        const size_t js = (size_t)j * E + e;
+        const int ep = m.eoe[js];
+        const int2 pv = m.eoe_v[js];
+        const double wj = wp[2 * j], wfj = wp[2 * j + 1];
         const double padd = a.ubar_add ? a.ubar_add[ep] : 0.0;
         const double psub = a.ubar_sub ? a.ubar_sub[ep] : 0.0;
-        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv1 * L, pb2 = (size_t)pv2 * L;
+        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv.x * L, pb2 = (size_t)pv.y * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
+            const int k = lane + c * kWave;
             if (k < L) {
-                double xp = a.X[pb + k];
-                double up = xp + padd, utp = xp - psub;
-                double qp = 0.5 * (a.Z[pb1 + k] + a.Z[pb2 + k]);
+                const double xp = a.X[pb + k];
+                const double up = xp + padd, utp = xp - psub;
+                const double qp = 0.5 * (a.Z[pb1 + k] + a.Z[pb2 + k]);
                 cor[c] += wfj * utp;
                 vor[c] += (wj * (0.5 * (q[c] + qp))) * up;
             }
@@ -327,10 +356,10 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
     col_up1<NK>(he, hu);
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
+        const int k = lane + c * kWave;
         if (k >= 1 && k < L) {
-            double dzt = (uu[c] - u[c]) / (0.5 * (hu[c] + he[c]));
-            double we = 0.5 * (a.Wtop[b1 + k] + a.Wtop[b2 + k]);
+            const double dzt = (uu[c] - u[c]) * (1.0 / (0.5 * (hu[c] + he[c])));
+            const double we = 0.5 * (a.Wtop[b1 + k] + a.Wtop[b2 + k]);
             at[c] = we * dzt;
             tau[c] = a.nu_v * dzt;
         } else {
@@ -341,22 +370,23 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
     col_down1<NK>(at, atn);
     col_down1<NK>(tau, taun);
     const double speed = sqrt(a.Kbot[c1] + a.Kbot[c2]);
-    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) / dce;
+    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) * idc;
+    const double pgf_scale = idc / a.rho0;
 
     double ut1[NK], hut1[NK], hu_in[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
+        const int k = lane + c * kWave;
         if (k < L) {
             if (k == L - 1) taun[c] = a.c_drag * speed * u[c];
-            double dp = a.g * (sp[c] + 0.5 * drh[c]);
-            double dz = -dH + ss[c] + 0.5 * dh[c];
-            double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) / (a.rho0 * dce);
-            double gradB = (a.B[b2 + k] - a.B[b1 + k]) / dce;
-            double curlp = (a.Z[bv2 + k] - a.Z[bv1 + k]) / dve;
-            double vadv = 0.5 * (at[c] + atn[c]);
-            double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
-            double du = (tau[c] - taun[c]) / he[c];
+            const double dp = a.g * (sp[c] + 0.5 * drh[c]);
+            const double dz = -dH + ss[c] + 0.5 * dh[c];
+            const double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) * pgf_scale;
+            const double gradB = (a.B[b2 + k] - a.B[b1 + k]) * idc;
+            const double curlp = (zb[c] - za[c]) * idv;
+            const double vadv = 0.5 * (at[c] + atn[c]);
+            const double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
+            const double du = (tau[c] - taun[c]) * (1.0 / he[c]);
             ut1[c] = ut[c] + a.dt * (cor[c] + tu + du + gz);
         } else {
             ut1[c] = 0.0;
@@ -366,13 +396,224 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
     }
     const double Sh = col_sum<NK>(he);
     const double G = col_sum<NK>(hut1) / Sh / a.dt;
+    const double ubn = a.Un ? a.ubar_n[e] : 0.0;
     double outv[NK], hp[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        double x = ut1[c] - a.dt * G;
-        double utn = 0.0;
-        if (a.Un && k < L) utn = a.Un[base + k] - a.ubar_n[e];
+        const int k = lane + c * kWave;
+        const double x = ut1[c] - a.dt * G;
+        const double utn = (a.Un && k < L) ? a.Un[base + k] - ubn : 0.0;
+        outv[c] = (k < L) ? combine(a.comb, utn, x) : 0.0;
+        if (k < L) a.out[base + k] = outv[c];
+        hp[c] = he[c] * (a.psum_a * utn + a.psum_b * outv[c]);
+    }
+    double shu = 0.0, shp = 0.0;
+    if (a.sum_hu) shu = col_sum<NK>(hu_in);
+    if (a.sum_hp) shp = col_sum<NK>(hp);
+    if (lane == 0) {
+        a.G[e] = G;
+        a.sum_h[e] = Sh;
+        if (a.sum_hu) a.sum_hu[e] = shu;
+        if (a.sum_hp) a.sum_hp[e] = shp;
+        if (a.Gi) {
+            if (a.interp == 3)
+                a.Gi[e] = a.Ga[e] / 6.0 + a.Gb[e] / 6.0 + 2.0 * G / 3.0;
+            else
+                a.Gi[e] = 0.5 * a.Ga[e] + 0.5 * G;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Baroclinic forward Euler: edge pass staged through LDS.
+//
+// One workgroup of T wavefronts owns a tile of T consecutive edges.  It first
+// copies every column the tile reads (stencil edges, their vertices, the
+// edges' cells for h, rho, K - nu div u and w) from global memory into LDS,
+// each column exactly once, then each wavefront evaluates its edge from LDS.
+// On the hexagonal mesh this cuts the column gathers per edge from ~42 to
+// ~12 (T = 8) or ~10 (T = 16).
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ void __launch_bounds__(1024) fe_edge_tiled_kernel(FEEdgeArgs a, DevTiles t) {
+    extern __shared__ double lds[];
+    const DevMesh &m = a.m;
+    const int tile = xcd_block(t.nT);
+    if (tile < 0) return;
+    const int T = t.T, L = a.L, E = m.E;
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ue0 = t.ue_off[tile], nue = t.ue_off[tile + 1] - ue0;
+    const int uv0 = t.uv_off[tile], nuv = t.uv_off[tile + 1] - uv0;
+    const int uc0 = t.uc_off[tile], nuc = t.uc_off[tile + 1] - uc0;
+    double *sX = lds;
+    double *sZ = sX + (size_t)nue * L;
+    double *sH = sZ + (size_t)nuv * L;
+    double *sR = sH + (size_t)nuc * L;
+    double *sB = sR + (size_t)nuc * L;
+    double *sW = sB + (size_t)nuc * L;
+    double *sU = sW + (size_t)nuc * L;
+    const double *ubar_src = a.ubar_add ? a.ubar_add : a.ubar_sub;
+
+    // Stage: every listed column once.  The (column, layer) elements are
+    // spread over all threads of the workgroup so that the list reads and the
+    // column reads of one thread are independent of each other and issue
+    // together.
+    const int ncol = nue + nuv + 4 * nuc;
+    const int nelem = ncol * L;
+    for (int i = threadIdx.x; i < nelem; i += blockDim.x) {
+        const int col = i / L, k = i - col * L;
+        const double *src;
+        if (col < nue) {
+            src = a.X + (size_t)t.ue[ue0 + col] * L;
+        } else if (col < nue + nuv) {
+            src = a.Z + (size_t)t.uv[uv0 + (col - nue)] * L;
+        } else {
+            const int r = col - nue - nuv, arr = r / nuc, q = r - arr * nuc;
+            src = (arr == 0 ? a.h : arr == 1 ? a.rho : arr == 2 ? a.B : a.Wtop) + (size_t)t.uc[uc0 + q] * L;
+        }
+        lds[i] = src[k];
+    }
+    for (int i = threadIdx.x; i < nue; i += blockDim.x) sU[i] = ubar_src ? ubar_src[t.ue[ue0 + i]] : 0.0;
+    __syncthreads();
+
+    const int e = tile * T + wv;
+    if (e >= E) return;
+    const size_t base = (size_t)e * L;
+    if (!m.emask[e]) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = lane + c * kWave;
+            if (k < L) a.out[base + k] = 0.0;
+        }
+        if (lane == 0) {
+            a.G[e] = 0.0;
+            a.sum_h[e] = 0.0;
+            if (a.sum_hu) a.sum_hu[e] = 0.0;
+            if (a.sum_hp) a.sum_hp[e] = 0.0;
+            if (a.Gi) a.Gi[e] = 0.0;
+        }
+        return;
+    }
+    // 8-bit positions of this edge's operands in the staged lists.
+    const uint32_t *lw = reinterpret_cast<const uint32_t *>(t.loc + (size_t)e * kLocPerEdge);
+    uint32_t word[kLocPerEdge / 4];
+#pragma unroll
+    for (int q = 0; q < kLocPerEdge / 4; ++q) word[q] = lw[q];
+    auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
+    const int ls = locb(0), lc1 = locb(1), lc2 = locb(2), lv1 = locb(3), lv2 = locb(4);
+    const bool is_add = a.ubar_add != nullptr, is_sub = a.ubar_sub != nullptr;
+    const double add_e = is_add ? sU[ls] : 0.0, sub_e = is_sub ? sU[ls] : 0.0;
+    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    const double idc = m.inv_dc[e], idv = m.inv_dv[e];
+
+    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], za[NK], zb[NK], q[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        const bool ok = k < L;
+        const double x = ok ? sX[(size_t)ls * L + k] : 0.0;
+        u[c] = ok ? x + add_e : 0.0;
+        ut[c] = ok ? x - sub_e : 0.0;
+        h1[c] = ok ? sH[(size_t)lc1 * L + k] : 0.0;
+        h2[c] = ok ? sH[(size_t)lc2 * L + k] : 0.0;
+        he[c] = 0.5 * (h1[c] + h2[c]);
+        r1[c] = ok ? sR[(size_t)lc1 * L + k] : 0.0;
+        r2[c] = ok ? sR[(size_t)lc2 * L + k] : 0.0;
+        za[c] = ok ? sZ[(size_t)lv1 * L + k] : 0.0;
+        zb[c] = ok ? sZ[(size_t)lv2 * L + k] : 0.0;
+        q[c] = 0.5 * (za[c] + zb[c]);
+    }
+
+    // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
+    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.
+    double cor[NK], vor[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) cor[c] = vor[c] = 0.0;
+    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+#pragma unroll
+    for (int j = 0; j < kMaxEdges2; ++j) {
+        const double wj = wp[2 * j], wfj = wp[2 * j + 1];
+        const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
+        const double pu = sU[sl];
+        const double padd = is_add ? pu : 0.0, psub = is_sub ? pu : 0.0;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = lane + c * kWave;
+            if (k < L) {
+                const double xp = sX[(size_t)sl * L + k];
+                const double up = xp + padd, utp = xp - psub;
+                const double qp = 0.5 * (sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k]);
+                cor[c] += wfj * utp;
+                vor[c] += (wj * (0.5 * (q[c] + qp))) * up;
+            }
+        }
+    }
+
+    // Pressure gradient in z-star layers from the column differences.
+    double drh[NK], dh[NK], sp[NK], ss[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        drh[c] = r2[c] * h2[c] - r1[c] * h1[c];
+        dh[c] = h2[c] - h1[c];
+    }
+    col_excl_prefix<NK>(drh, sp);
+    col_excl_suffix<NK>(dh, ss);
+    const double dH = m.H[c2] - m.H[c1];
+
+    // Vertical advection and vertical viscosity at interior interfaces.
+    double uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
+    col_up1<NK>(u, uu);
+    col_up1<NK>(he, hu);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        if (k >= 1 && k < L) {
+            const double dzt = (uu[c] - u[c]) * (1.0 / (0.5 * (hu[c] + he[c])));
+            const double we = 0.5 * (sW[(size_t)lc1 * L + k] + sW[(size_t)lc2 * L + k]);
+            at[c] = we * dzt;
+            tau[c] = a.nu_v * dzt;
+        } else {
+            at[c] = 0.0;
+            tau[c] = 0.0;
+        }
+    }
+    col_down1<NK>(at, atn);
+    col_down1<NK>(tau, taun);
+    const double speed = sqrt(a.Kbot[c1] + a.Kbot[c2]);
+    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) * idc;
+    const double pgf_scale = idc / a.rho0;
+
+    double ut1[NK], hut1[NK], hu_in[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        if (k < L) {
+            if (k == L - 1) taun[c] = a.c_drag * speed * u[c];
+            const double dp = a.g * (sp[c] + 0.5 * drh[c]);
+            const double dz = -dH + ss[c] + 0.5 * dh[c];
+            const double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) * pgf_scale;
+            const double gradB = (sB[(size_t)lc2 * L + k] - sB[(size_t)lc1 * L + k]) * idc;
+            const double curlp = (zb[c] - za[c]) * idv;
+            const double vadv = 0.5 * (at[c] + atn[c]);
+            const double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
+            const double du = (tau[c] - taun[c]) * (1.0 / he[c]);
+            ut1[c] = ut[c] + a.dt * (cor[c] + tu + du + gz);
+        } else {
+            ut1[c] = 0.0;
+        }
+        hut1[c] = he[c] * ut1[c];
+        hu_in[c] = he[c] * u[c];
+    }
+    const double Sh = col_sum<NK>(he);
+    const double G = col_sum<NK>(hut1) / Sh / a.dt;
+    const double ubn = a.Un ? a.ubar_n[e] : 0.0;
+    double outv[NK], hp[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        const double x = ut1[c] - a.dt * G;
+        const double utn = (a.Un && k < L) ? a.Un[base + k] - ubn : 0.0;
         outv[c] = (k < L) ? combine(a.comb, utn, x) : 0.0;
         if (k < L) a.out[base + k] = outv[c];
         hp[c] = he[c] * (a.psum_a * utn + a.psum_b * outv[c]);
@@ -397,10 +638,16 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
 // ---------------------------------------------------------------------------
 // Barotropic forward-Euler evaluation (Algorithms 3 and 4, one stage)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlocks) {
+__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlocks, int nCellBlocks) {
     const DevMesh &m = a.m;
-    if ((int)blockIdx.x < nEdgeBlocks) {
-        const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD x owns edge blocks [x * pe, (x + 1) * pe) and cell blocks
+    // [x * pc, (x + 1) * pc): one contiguous region of the mesh per L2.
+    const int pe = (nEdgeBlocks + kXcd - 1) / kXcd, pc = (nCellBlocks + kXcd - 1) / kXcd;
+    const int x = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+    if (local < pe) {
+        const int lb = x * pe + local;
+        if (lb >= nEdgeBlocks) return;
+        const int e = lb * blockDim.x + threadIdx.x;
         if (e >= m.E) return;
         if (!m.emask[e]) {
             a.uo[e] = 0.0;
@@ -410,11 +657,13 @@ __global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlo
         const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
         const double ua = a.ua[e];
         const double z1 = a.za[c1], z2 = a.za[c2];
+        // Padded stencil slots point at the edge itself with zero weight: the
+        // loop runs its full width so that all its gathers issue together.
         double cor = 0.0;
-        const int ne = m.neoe[e];
-        for (int j = 0; j < ne; ++j)
+#pragma unroll
+        for (int j = 0; j < kMaxEdges2; ++j)
             cor += m.wf[(size_t)j * m.E + e] * a.ua[m.eoe[(size_t)j * m.E + e]];
-        const double ru = cor - a.g * (z2 - z1) / m.dc[e] + a.G[e];
+        const double ru = cor - a.g * (z2 - z1) * m.inv_dc[e] + a.G[e];
         const double base = a.ub[e];
         a.uo[e] = combine(a.comb, base, ua + a.tau * ru);
         if (a.F) {
@@ -422,7 +671,9 @@ __global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlo
             a.F[e] = (a.zeroF ? 0.0 : a.F[e]) + a.wF * flux;
         }
     } else {
-        const int i = (blockIdx.x - nEdgeBlocks) * blockDim.x + threadIdx.x;
+        const int lb = x * pc + (local - pe);
+        if (lb >= nCellBlocks) return;
+        const int i = lb * blockDim.x + threadIdx.x;
         if (i >= m.C) return;
         if (!m.cmask[i]) { a.zo[i] = 0.0; return; }
         const double zi = a.za[i] + m.H[i];
@@ -447,7 +698,7 @@ template <int NK>
 __global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int i = column_id(m.C);
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -483,7 +734,7 @@ template <int NK>
 __global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int i = column_id(m.C);
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -582,7 +833,7 @@ template <int NK>
 __global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int e = column_id(m.E);
     if (e >= m.E) return;
     const int L = a.L;
     const size_t base = (size_t)e * L;
@@ -612,7 +863,7 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
 template <int NK>
 __global__ void __launch_bounds__(kBlock) zeta_kernel(DevMesh m, int L, const double *h, double *zeta) {
     const int lane = lane_id();
-    const int i = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int i = column_id(m.C);
     if (i >= m.C) return;
     double hv[NK];
 #pragma unroll
@@ -629,7 +880,7 @@ template <int NK>
 __global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const double *X,
                                                                const double *uA, double *F) {
     const int lane = lane_id();
-    const int e = blockIdx.x * kColsPerBlock + (threadIdx.x >> 6);
+    const int e = column_id(m.E);
     if (e >= m.E) return;
     const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
     const double ua = uA ? uA[e] : 0.0;
@@ -655,7 +906,10 @@ __global__ void copy_kernel(const double *src, double *dst, size_t n) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-static inline dim3 col_grid(int n) { return dim3((n + kColsPerBlock - 1) / kColsPerBlock); }
+static inline dim3 col_grid(int n) {
+    const int nb = (n + kColsPerBlock - 1) / kColsPerBlock;
+    return dim3((unsigned)(kXcd * ((nb + kXcd - 1) / kXcd)));
+}
 static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
 #define SSE_DISPATCH_NK(L, KERNEL, GRID, ...)                                   \
@@ -669,6 +923,27 @@ static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n 
 void launch_fe_cell(const FECellArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_cell_kernel, col_grid(a.m.C), a); }
 void launch_fe_vertex(const FEVertexArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_vertex_kernel, col_grid(a.m.V), a); }
 void launch_fe_edge(const FEEdgeArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_edge_kernel, col_grid(a.m.E), a); }
+
+size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
+    return ((size_t)(t.max_ue + t.max_uv + 4 * t.max_uc) * L + t.max_ue) * sizeof(double);
+}
+
+void launch_fe_edge_tiled(const FEEdgeArgs &a, const DevTiles &t, hipStream_t s) {
+    const size_t lds = fe_edge_tiled_lds(t, a.L);
+    const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block(t.T * kWave);
+    if (a.L <= kWave)
+        fe_edge_tiled_kernel<1><<<grid, block, lds, s>>>(a, t);
+    else
+        fe_edge_tiled_kernel<2><<<grid, block, lds, s>>>(a, t);
+}
+
+// Allow the tiled kernels the device's full LDS per workgroup.
+void set_tiled_lds_limit(size_t bytes) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(fe_edge_tiled_kernel<1>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipFuncSetAttribute(reinterpret_cast<const void *>(fe_edge_tiled_kernel<2>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 void launch_thickness(const THArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_kernel, col_grid(a.m.C), a); }
 void launch_thickness_iso(const THIsoArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_iso_kernel, col_grid(a.m.C), a); }
 void launch_assemble(const AssembleArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, assemble_kernel, col_grid(a.m.E), a); }
@@ -682,7 +957,8 @@ void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const double
 
 void launch_bt_eval(const BTEvalArgs &a, hipStream_t s) {
     const int nEB = (a.m.E + 255) / 256, nCB = (a.m.C + 255) / 256;
-    bt_eval_kernel<<<dim3(nEB + nCB), 256, 0, s>>>(a, nEB);
+    const int per = (nEB + kXcd - 1) / kXcd + (nCB + kXcd - 1) / kXcd;
+    bt_eval_kernel<<<dim3(kXcd * per), 256, 0, s>>>(a, nEB, nCB);
 }
 
 void launch_recon(const ReconArgs &a, hipStream_t s) { recon_kernel<<<flat_grid(a.m.E), 256, 0, s>>>(a); }

@@ -9,6 +9,7 @@
 //   Coriolis    -f k x u   = sum_j [W_{e,j} (f_e + f_{e_j}) / 2] u_{e_j}
 // with s = +1 where the edge normal leaves the cell and r = +1 where the
 // vertex is the edge's second vertex.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -121,7 +122,8 @@ MeshLayout mesh_layout(int C, int E, int V) {
         (size_t)C * 6 * 4, (size_t)C * 6 * 4, (size_t)C * 6 * 8, (size_t)C * 8, (size_t)C,
         (size_t)E * 2 * 4, (size_t)E * 2 * 4, (size_t)E * 10 * 4, (size_t)E * 4, (size_t)E * 10 * 8,
         (size_t)E * 10 * 8, (size_t)E * 8, (size_t)E * 8, (size_t)E,
-        (size_t)V * 3 * 4, (size_t)V * 3 * 8};
+        (size_t)V * 3 * 4, (size_t)V * 3 * 8,
+        (size_t)E * 10 * 8, (size_t)E * 8, (size_t)E * 8, (size_t)E * 20 * 8};
     size_t off = 0;
     int n = sizeof(sizes) / sizeof(sizes[0]);
     for (int i = 0; i < n; ++i) {
@@ -199,6 +201,24 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
             }
         }
     }
+    t.wpair.assign((size_t)E * 20, 0.0);
+    for (int e = 0; e < E; ++e)
+        for (int j = 0; j < 10; ++j) {
+            t.wpair[(size_t)e * 20 + 2 * j] = t.w[(size_t)j * E + e];
+            t.wpair[(size_t)e * 20 + 2 * j + 1] = t.wf[(size_t)j * E + e];
+        }
+    t.eoe_v.assign((size_t)E * 10 * 2, 0);
+    t.inv_dc.assign(E, 0.0);
+    t.inv_dv.assign(E, 0.0);
+    for (int e = 0; e < E; ++e) {
+        t.inv_dc[e] = 1.0 / d->dc_edge[e];
+        t.inv_dv[e] = 1.0 / d->dv_edge[e];
+        for (int j = 0; j < 10; ++j) {
+            int ep = t.eoe[(size_t)j * E + e];
+            t.eoe_v[((size_t)j * E + e) * 2] = d->vertices_on_edge[2 * ep];
+            t.eoe_v[((size_t)j * E + e) * 2 + 1] = d->vertices_on_edge[2 * ep + 1];
+        }
+    }
     t.vert_edges.assign(d->edges_on_vertex, d->edges_on_vertex + 3 * (size_t)V);
     t.vert_curl.assign((size_t)V * 3, 0.0);
     for (int v = 0; v < V; ++v)
@@ -207,6 +227,67 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
             double r = (d->vertices_on_edge[2 * e + 1] == v) ? 1.0 : -1.0;
             t.vert_curl[v * 3 + j] = r * d->dc_edge[e] / d->area_triangle[v];
         }
+}
+
+bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t) {
+    const int E = d->n_edges, me2 = d->max_edges2;
+    t.T = T;
+    t.nT = (E + T - 1) / T;
+    t.ue_off.assign(t.nT + 1, 0);
+    t.uv_off.assign(t.nT + 1, 0);
+    t.uc_off.assign(t.nT + 1, 0);
+    t.ue.clear();
+    t.uv.clear();
+    t.uc.clear();
+    t.loc.assign((size_t)E * kLocPerEdge, 0);
+    t.max_ue = t.max_uv = t.max_uc = 0;
+    std::vector<int> ue, uv, uc;
+    auto slot = [](std::vector<int> &list, int id) -> int {
+        for (size_t i = 0; i < list.size(); ++i)
+            if (list[i] == id) return (int)i;
+        list.push_back(id);
+        return (int)list.size() - 1;
+    };
+    for (int tile = 0; tile < t.nT; ++tile) {
+        ue.clear();
+        uv.clear();
+        uc.clear();
+        const int e0 = tile * T, e1 = std::min(E, e0 + T);
+        for (int e = e0; e < e1; ++e) {
+            uint8_t *L = &t.loc[(size_t)e * kLocPerEdge];
+            int ids[5] = {slot(ue, e), slot(uc, d->cells_on_edge[2 * e]), slot(uc, d->cells_on_edge[2 * e + 1]),
+                          slot(uv, d->vertices_on_edge[2 * e]), slot(uv, d->vertices_on_edge[2 * e + 1])};
+            for (int q = 0; q < 5; ++q) L[q] = (uint8_t)ids[q];
+            const int n = d->n_edges_on_edge[e];
+            for (int j = 0; j < kMaxEdges2; ++j) {
+                // padded stencil slots point at the edge itself (zero weight)
+                const int ep = j < n ? d->edges_on_edge[e * me2 + j] : e;
+                L[5 + j] = (uint8_t)slot(ue, ep);
+                L[15 + 2 * j] = (uint8_t)slot(uv, d->vertices_on_edge[2 * ep]);
+                L[16 + 2 * j] = (uint8_t)slot(uv, d->vertices_on_edge[2 * ep + 1]);
+            }
+        }
+        if (ue.size() > 255 || uv.size() > 255 || uc.size() > 255) return false;
+        t.max_ue = std::max(t.max_ue, (int)ue.size());
+        t.max_uv = std::max(t.max_uv, (int)uv.size());
+        t.max_uc = std::max(t.max_uc, (int)uc.size());
+        t.ue.insert(t.ue.end(), ue.begin(), ue.end());
+        t.uv.insert(t.uv.end(), uv.begin(), uv.end());
+        t.uc.insert(t.uc.end(), uc.begin(), uc.end());
+        t.ue_off[tile + 1] = (int32_t)t.ue.size();
+        t.uv_off[tile + 1] = (int32_t)t.uv.size();
+        t.uc_off[tile + 1] = (int32_t)t.uc.size();
+    }
+    return true;
+}
+
+// Upper bound of the device bytes of one tile table set (lists at their
+// worst-case length T * 11, 2T * 11 and 2T per tile).
+size_t tiles_bytes(const sse_mesh_desc *d, int T) {
+    const size_t E = d->n_edges, nT = (E + T - 1) / T;
+    auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
+    return 3 * al((nT + 1) * 4) + al(nT * T * 11 * 4) + al(nT * T * 22 * 4) + al(nT * T * 2 * 4) +
+           al(E * kLocPerEdge);
 }
 
 }  // namespace sse
@@ -221,6 +302,7 @@ extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
 extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
     if (!d || !bytes) { sse::set_error("NULL argument"); return SSE_EINVAL; }
     if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { sse::set_error("mesh counts must be positive"); return SSE_EINVAL; }
-    *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
+    *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total + sse::tiles_bytes(d, 8) +
+             sse::tiles_bytes(d, 16);
     return SSE_OK;
 }

@@ -14,7 +14,7 @@ from ctypes import POINTER, byref, c_double, c_int, c_int32, c_size_t, c_uint8, 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libssprkse.so")
+LIB_PATH = os.environ.get("SSE_LIB_PATH") or os.path.join(_HERE, "libssprkse.so")
 
 SSE_OK, SSE_EINVAL, SSE_ENOMEM, SSE_EDEVICE, SSE_ENONFINITE, SSE_ESTATE = range(6)
 SSE_FP64, SSE_MIXED = 0, 1
