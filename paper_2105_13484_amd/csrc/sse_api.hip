@@ -7,6 +7,11 @@
 // FE = baroclinic forward Euler (Algorithm 1: cell, vertex and edge passes),
 // BT = barotropic substep loop (Algorithm 3 or 4), TH = thickness stage with
 // the reconciliation deficits.  Everything is enqueued on the state's stream.
+//
+// Precision: the orchestration is a template over the real type R of the
+// velocity-like 3D fields and the substep state (double for SSE_FP64, float
+// for SSE_MIXED); thickness, density, SSH and all 2D fields handed between
+// stages are double in both modes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sse_kernels.h"
@@ -22,52 +28,71 @@ using namespace sse;
 
 namespace {
 
+// Device workspace of one state.  Arrays marked R hold the mode's real type.
 struct Work {
-    double *U, *T1, *T2;                                     // [E][L]
-    double *Hs, *H1, *H2, *B, *Wt, *frac, *rho;             // [C][L]
-    double *Z;                                              // [V][L]
+    void *U, *T1, *T2;                       // R [E][L]: u^n and two stage buffers
+    void *B, *Wt;                            // R [C][L]: K - nu_h div u, w at layer tops
+    void *Z;                                 // R [V][L]: relative vorticity
+    void *bt_u1, *bt_uh, *bt_ua, *bt_uo;     // R [E]: substep stages, loop input / output
+    void *bt_z1, *bt_zh, *bt_za, *bt_zo;     // R [C]
+    double *Hs, *H1, *H2, *frac, *rho;       // [C][L]
     double *ubar_n, *ub1, *ub2, *ub_half, *ubar_new, *G0, *G1, *Gh, *Gi, *Fz1, *Fz2, *Fz3, *Sh1, *Fh1, *Sh2,
-        *Fh2, *Sh3, *Pp, *Ftot, *uA, *bt_u1, *bt_uh;        // [E]
-    double *zeta_n, *z1, *z_half, *Kbot, *bt_z1, *bt_zh, *bt_zout;  // [C]
+        *Fh2, *Sh3, *Pp, *Ftot, *uA;         // [E]
+    double *zeta_n, *z1, *z_half, *Kbot, *bt_zout;  // [C]
     int *flag;
 };
 
-constexpr int kN3E = 3, kN3C = 7, kN3V = 1, kN2E = 22, kN2C = 7;
+constexpr int kR3E = 3, kR3C = 2, kR3V = 1, kR2E = 4, kR2C = 4;  // arrays of type R
+constexpr int kD3C = 5, kD2E = 20, kD2C = 5;                    // arrays of type double
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-size_t workspace_bytes(int C, int E, int V, int L) {
+size_t real_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : sizeof(double); }
+
+size_t workspace_bytes(int C, int E, int V, int L, size_t rs) {
     size_t b = 0;
-    b += kN3E * align_up((size_t)E * L * 8);
-    b += kN3C * align_up((size_t)C * L * 8);
-    b += kN3V * align_up((size_t)V * L * 8);
-    b += kN2E * align_up((size_t)E * 8);
-    b += kN2C * align_up((size_t)C * 8);
+    b += kR3E * align_up((size_t)E * L * rs);
+    b += kR3C * align_up((size_t)C * L * rs);
+    b += kR3V * align_up((size_t)V * L * rs);
+    b += kR2E * align_up((size_t)E * rs);
+    b += kR2C * align_up((size_t)C * rs);
+    b += kD3C * align_up((size_t)C * L * 8);
+    b += kD2E * align_up((size_t)E * 8);
+    b += kD2C * align_up((size_t)C * 8);
     b += kAlign;  // flag
     return b;
 }
 
-Work carve(void *buf, int C, int E, int V, int L) {
+Work carve(void *buf, int C, int E, int V, int L, size_t rs) {
     char *p = static_cast<char *>(buf);
     auto take = [&](size_t n) {
-        double *r = reinterpret_cast<double *>(p);
+        void *r = p;
         p += align_up(n);
         return r;
     };
     Work w{};
-    double **e3[] = {&w.U, &w.T1, &w.T2};
-    for (auto q : e3) *q = take((size_t)E * L * 8);
-    double **c3[] = {&w.Hs, &w.H1, &w.H2, &w.B, &w.Wt, &w.frac, &w.rho};
-    for (auto q : c3) *q = take((size_t)C * L * 8);
-    w.Z = take((size_t)V * L * 8);
-    double **e2[] = {&w.ubar_n, &w.ub1, &w.ub2, &w.ub_half, &w.ubar_new, &w.G0, &w.G1, &w.Gh, &w.Gi, &w.Fz1, &w.Fz2,
-                     &w.Fz3, &w.Sh1, &w.Fh1, &w.Sh2, &w.Fh2, &w.Sh3, &w.Pp, &w.Ftot, &w.uA, &w.bt_u1, &w.bt_uh};
-    for (auto q : e2) *q = take((size_t)E * 8);
-    double **c2[] = {&w.zeta_n, &w.z1, &w.z_half, &w.Kbot, &w.bt_z1, &w.bt_zh, &w.bt_zout};
-    for (auto q : c2) *q = take((size_t)C * 8);
+    void **r3e[] = {&w.U, &w.T1, &w.T2};
+    for (auto q : r3e) *q = take((size_t)E * L * rs);
+    void **r3c[] = {&w.B, &w.Wt};
+    for (auto q : r3c) *q = take((size_t)C * L * rs);
+    w.Z = take((size_t)V * L * rs);
+    void **r2e[] = {&w.bt_u1, &w.bt_uh, &w.bt_ua, &w.bt_uo};
+    for (auto q : r2e) *q = take((size_t)E * rs);
+    void **r2c[] = {&w.bt_z1, &w.bt_zh, &w.bt_za, &w.bt_zo};
+    for (auto q : r2c) *q = take((size_t)C * rs);
+    double **d3c[] = {&w.Hs, &w.H1, &w.H2, &w.frac, &w.rho};
+    for (auto q : d3c) *q = static_cast<double *>(take((size_t)C * L * 8));
+    double **d2e[] = {&w.ubar_n, &w.ub1, &w.ub2, &w.ub_half, &w.ubar_new, &w.G0, &w.G1, &w.Gh, &w.Gi, &w.Fz1,
+                      &w.Fz2, &w.Fz3, &w.Sh1, &w.Fh1, &w.Sh2, &w.Fh2, &w.Sh3, &w.Pp, &w.Ftot, &w.uA};
+    for (auto q : d2e) *q = static_cast<double *>(take((size_t)E * 8));
+    double **d2c[] = {&w.zeta_n, &w.z1, &w.z_half, &w.Kbot, &w.bt_zout};
+    for (auto q : d2c) *q = static_cast<double *>(take((size_t)C * 8));
     w.flag = reinterpret_cast<int *>(p);
     return w;
 }
+
+template <typename R>
+R *rp(void *p) { return static_cast<R *>(p); }
 
 int hip_fail(hipError_t e, const char *what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -94,6 +119,7 @@ struct sse_state {
     hipStream_t stream = nullptr;
     Work w{};
     size_t bytes = 0;
+    size_t rs = 8;           // bytes of the real type R
     bool initialized = false;
     // profiling
     int edge_variant = -1;   // -1: direct gathers; 0 / 1: LDS tiles of 8 / 16 edges
@@ -142,26 +168,27 @@ struct ProfScope {
 };
 
 // ---- building blocks -------------------------------------------------------
-void fe_pass(sse_state *s, const double *X, const double *add, const double *sub, const double *h,
-             const double *zeta, int comb, double *out, double *G, double *sum_h, double *sum_hu, double *sum_hp,
-             double pa, double pb, double *Gi, const double *Ga, const double *Gb, int interp) {
+template <typename R>
+void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, const double *h, const double *zeta,
+             int comb, R *out, double *G, double *sum_h, double *sum_hu, double *sum_hp, double pa, double pb,
+             double *Gi, const double *Ga, const double *Gb, int interp) {
     const DevMesh &m = s->mesh->d;
     const sse_params &p = s->p;
     Work &w = s->w;
     const bool zstar = p.vcoord == SSE_ZSTAR;
     {
         ProfScope ps(s, SSE_PROF_FE_CELL);
-        FECellArgs a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, p.nu_h, w.B, w.Wt, w.Kbot};
-        launch_fe_cell(a, s->stream);
+        FECellArgs<R> a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, p.nu_h, rp<R>(w.B), rp<R>(w.Wt), w.Kbot};
+        launch_fe_cell<R>(a, s->stream);
     }
     {
         ProfScope ps(s, SSE_PROF_FE_VERTEX);
-        FEVertexArgs a{m, p.n_layers, X, add, w.Z};
-        launch_fe_vertex(a, s->stream);
+        FEVertexArgs<R> a{m, p.n_layers, X, add, rp<R>(w.Z)};
+        launch_fe_vertex<R>(a, s->stream);
     }
     {
         ProfScope ps(s, SSE_PROF_FE_EDGE);
-        FEEdgeArgs a{};
+        FEEdgeArgs<R> a{};
         a.m = m;
         a.L = p.n_layers;
         a.X = X;
@@ -169,12 +196,12 @@ void fe_pass(sse_state *s, const double *X, const double *add, const double *sub
         a.ubar_sub = sub;
         a.h = h;
         a.rho = w.rho;
-        a.B = w.B;
-        a.Wtop = w.Wt;
+        a.B = rp<R>(w.B);
+        a.Wtop = rp<R>(w.Wt);
         a.Kbot = w.Kbot;
-        a.Z = w.Z;
+        a.Z = rp<R>(w.Z);
         a.zeta = zeta;
-        a.Un = (comb != COMB_NONE || (sum_hp && pa != 0.0)) ? w.U : nullptr;
+        a.Un = (comb != COMB_NONE || (sum_hp && pa != 0.0)) ? rp<R>(w.U) : nullptr;
         a.ubar_n = w.ubar_n;
         a.comb = comb;
         a.out = out;
@@ -195,47 +222,74 @@ void fe_pass(sse_state *s, const double *X, const double *add, const double *sub
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
         if (s->edge_variant >= 0)
-            launch_fe_edge_tiled(a, s->mesh->tiles[s->edge_variant], s->stream);
+            launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
-            launch_fe_edge(a, s->stream);
+            launch_fe_edge<R>(a, s->stream);
     }
 }
 
 // Algorithm 3 (scheme 2) / Algorithm 4 (scheme 3): M substeps of dt / M with
-// G frozen, accumulating F^zeta.  The inputs are not modified.
+// G frozen, accumulating F^zeta in FP64.  The inputs are not modified.  In
+// mixed precision the loop state is FP32: the FP64 inputs are rounded once on
+// entry and the result widened once on exit.
+template <typename R>
 void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, const double *in_z, const double *G,
              double *out_u, double *out_z, double *F) {
     const DevMesh &m = s->mesh->d;
     Work &w = s->w;
-    BTEvalArgs a{};
+    const R *iu;
+    const R *iz;
+    R *ou;
+    R *oz;
+    if constexpr (std::is_same<R, double>::value) {
+        iu = in_u;
+        iz = in_z;
+        ou = out_u;
+        oz = out_z;
+    } else {
+        ProfScope ps(s, SSE_PROF_OTHER);
+        launch_convert<double, R>(in_u, rp<R>(w.bt_ua), m.E, s->stream);
+        launch_convert<double, R>(in_z, rp<R>(w.bt_za), m.C, s->stream);
+        iu = rp<R>(w.bt_ua);
+        iz = rp<R>(w.bt_za);
+        ou = rp<R>(w.bt_uo);
+        oz = rp<R>(w.bt_zo);
+    }
+    R *u1 = rp<R>(w.bt_u1), *uh = rp<R>(w.bt_uh), *z1 = rp<R>(w.bt_z1), *zh = rp<R>(w.bt_zh);
+    BTEvalArgs<R> a{};
     a.m = m;
     a.G = G;
     a.F = F;
     a.tau = dt / M;
     a.g = s->p.gravity;
     for (int j = 0; j < M; ++j) {
-        const double *bu = j == 0 ? in_u : out_u;
-        const double *bz = j == 0 ? in_z : out_z;
+        const R *bu = j == 0 ? iu : ou;
+        const R *bz = j == 0 ? iz : oz;
         if (scheme == SSE_SCHEME_SSPRK3) {
             const double w1 = 1.0 / (6.0 * M), w3 = 2.0 / (3.0 * M);
             { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = w.bt_u1; a.zo = w.bt_z1;
-              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval(a, s->stream); }
+              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
+              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval<R>(a, s->stream); }
             { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = w.bt_u1; a.za = w.bt_z1; a.ub = bu; a.zb = bz; a.uo = w.bt_uh; a.zo = w.bt_zh;
-              a.wF = w1; a.zeroF = 0; a.comb = COMB_34; launch_bt_eval(a, s->stream); }
+              a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = uh; a.zo = zh;
+              a.wF = w1; a.zeroF = 0; a.comb = COMB_34; launch_bt_eval<R>(a, s->stream); }
             { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = w.bt_uh; a.za = w.bt_zh; a.ub = bu; a.zb = bz; a.uo = out_u; a.zo = out_z;
-              a.wF = w3; a.zeroF = 0; a.comb = COMB_THIRD; launch_bt_eval(a, s->stream); }
+              a.ua = uh; a.za = zh; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
+              a.wF = w3; a.zeroF = 0; a.comb = COMB_THIRD; launch_bt_eval<R>(a, s->stream); }
         } else {
             const double w1 = 1.0 / (2.0 * M);
             { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = w.bt_u1; a.zo = w.bt_z1;
-              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval(a, s->stream); }
+              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
+              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval<R>(a, s->stream); }
             { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = w.bt_u1; a.za = w.bt_z1; a.ub = bu; a.zb = bz; a.uo = out_u; a.zo = out_z;
-              a.wF = w1; a.zeroF = 0; a.comb = COMB_HALF; launch_bt_eval(a, s->stream); }
+              a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
+              a.wF = w1; a.zeroF = 0; a.comb = COMB_HALF; launch_bt_eval<R>(a, s->stream); }
         }
+    }
+    if constexpr (!std::is_same<R, double>::value) {
+        ProfScope ps(s, SSE_PROF_OTHER);
+        launch_convert<R, double>(ou, out_u, m.E, s->stream);
+        launch_convert<R, double>(oz, out_z, m.C, s->stream);
     }
 }
 
@@ -266,15 +320,16 @@ void recon(sse_state *s, int mode, const double *Fz, const double *Fh, const dou
 
 // Thickness stage.  z-star uses the 2D total flux w.Ftot; isopycnal rebuilds
 // the per-layer velocity c1 X1 + c2 X2 + ca1 a1 + u^A.
+template <typename R>
 void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, double *h_out, double *zeta_out,
-               const double *X1, double c1, const double *X2, double c2, const double *a1, double ca1, double dt) {
+               const R *X1, double c1, const R *X2, double c2, const double *a1, double ca1, double dt) {
     ProfScope ps(s, SSE_PROF_THICKNESS);
     Work &w = s->w;
     if (s->p.vcoord == SSE_ZSTAR) {
         THArgs a{s->mesh->d, s->p.n_layers, h_in, h_n, w.frac, w.Ftot, comb, dt, h_out, zeta_out, w.flag};
         launch_thickness(a, s->stream);
     } else {
-        THIsoArgs a{};
+        THIsoArgs<R> a{};
         a.m = s->mesh->d;
         a.L = s->p.n_layers;
         a.h_in = h_in;
@@ -285,67 +340,80 @@ void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, do
         a.c2 = c2;
         a.a1 = a1;
         a.ca1 = ca1;
-        a.a2 = nullptr;
-        a.ca2 = 0.0;
         a.uA = w.uA;
         a.comb = comb;
         a.dt = dt;
         a.h_out = h_out;
         a.zeta_out = zeta_out;
         a.nonfinite = w.flag;
-        launch_thickness_iso(a, s->stream);
+        launch_thickness_iso<R>(a, s->stream);
     }
 }
 
-void assemble(sse_state *s, const double *X, const double *ubar_bt) {
+template <typename R>
+void assemble(sse_state *s, const R *X, const double *ubar_bt) {
     ProfScope ps(s, SSE_PROF_OTHER);
     Work &w = s->w;
-    AssembleArgs a{s->mesh->d, s->p.n_layers, X, ubar_bt, w.Hs, w.U, w.ubar_n, w.flag};
-    launch_assemble(a, s->stream);
+    AssembleArgs<R> a{s->mesh->d, s->p.n_layers, X, ubar_bt, w.Hs, rp<R>(w.U), w.ubar_n, w.flag};
+    launch_assemble<R>(a, s->stream);
 }
 
+template <typename R>
 void step_ssprk3(sse_state *s) {
     Work &w = s->w;
     const int M = s->p.substeps;
     const double dt = s->p.dt;
+    R *U = rp<R>(w.U), *T1 = rp<R>(w.T1), *T2 = rp<R>(w.T2);
+    const R *none = nullptr;
     // Stage 1: baroclinic FE from (u^n, ut^n, zeta^n, h^n); predictor loop; thickness.
-    fe_pass(s, w.U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, w.T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
-            nullptr, nullptr, nullptr, 0);
-    bt_loop(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    fe_pass<R>(s, U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
+               nullptr, nullptr, nullptr, 0);
+    bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
-    thickness(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, w.U, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
+    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt);
     // Stage 2: FE from (u-hat^{n+1}, ut-hat^{n+1}, zeta-hat^{n+1}, h-hat^{n+1}); second loop; thickness.
-    fe_pass(s, w.T1, w.ub1, nullptr, w.H1, w.z1, COMB_34, w.T2, w.G1, w.Sh2, w.Fh2, nullptr, 0, 0, nullptr,
-            nullptr, nullptr, 0);
-    bt_loop(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
+    fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_34, T2, w.G1, w.Sh2, w.Fh2, nullptr, 0, 0, nullptr,
+               nullptr, nullptr, 0);
+    bt_loop<R>(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
     recon(s, 0, w.Fz2, w.Fh2, w.Sh2, nullptr, nullptr, w.ub2, w.ub_half);
-    thickness(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, w.T1, 1.0, nullptr, 0.0, w.ub1, 1.0, dt);
+    thickness<R>(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, T1, 1.0, none, 0.0, w.ub1, 1.0, dt);
     // Stage 3: FE from the n+1/2 stage -> ut^{n+1}; G interpolated by Interp_3.
-    fe_pass(s, w.T2, w.ub_half, nullptr, w.H2, w.z_half, COMB_THIRD, w.T1, w.Gh, w.Sh3, nullptr, w.Pp, 1.0, 1.0,
-            w.Gi, w.G0, w.G1, 3);
+    fe_pass<R>(s, T2, w.ub_half, nullptr, w.H2, w.z_half, COMB_THIRD, T1, w.Gh, w.Sh3, nullptr, w.Pp, 1.0, 1.0,
+               w.Gi, w.G0, w.G1, 3);
     // Step 2: corrector loop from (ubar^n, zeta^n).
-    bt_loop(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
+    bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
     // Step 3: last thickness stage with u^A_3, then u^{n+1} and its split.
     recon(s, 1, w.Fz3, nullptr, w.Sh3, w.Pp, w.ubar_new, nullptr, nullptr);
-    thickness(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, w.U, 0.5, w.T1, 0.5, w.ubar_new, 0.5, dt);
-    assemble(s, w.T1, w.ubar_new);
+    thickness<R>(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, U, 0.5, T1, 0.5, w.ubar_new, 0.5, dt);
+    assemble<R>(s, T1, w.ubar_new);
 }
 
+template <typename R>
 void step_ssprk2(sse_state *s) {
     Work &w = s->w;
     const int M = s->p.substeps;
     const double dt = s->p.dt;
-    fe_pass(s, w.U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, w.T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
-            nullptr, nullptr, nullptr, 0);
-    bt_loop(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    R *U = rp<R>(w.U), *T1 = rp<R>(w.T1), *T2 = rp<R>(w.T2);
+    const R *none = nullptr;
+    fe_pass<R>(s, U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
+               nullptr, nullptr, nullptr, 0);
+    bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
-    thickness(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, w.U, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
-    fe_pass(s, w.T1, w.ub1, nullptr, w.H1, w.z1, COMB_HALF, w.T2, w.G1, w.Sh2, nullptr, w.Pp, 0.0, 1.0, w.Gi,
-            w.G0, nullptr, 2);
-    bt_loop(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
+    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt);
+    fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_HALF, T2, w.G1, w.Sh2, nullptr, w.Pp, 0.0, 1.0, w.Gi,
+               w.G0, nullptr, 2);
+    bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
     recon(s, 2, w.Fz2, nullptr, w.Sh2, w.Pp, w.ubar_new, nullptr, nullptr);
-    thickness(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, w.T2, 1.0, nullptr, 0.0, w.ubar_new, 1.0, dt);
-    assemble(s, w.T2, w.ubar_new);
+    thickness<R>(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, T2, 1.0, none, 0.0, w.ubar_new, 1.0, dt);
+    assemble<R>(s, T2, w.ubar_new);
+}
+
+template <typename R>
+void step_one(sse_state *s) {
+    if (s->p.scheme == SSE_SCHEME_SSPRK3)
+        step_ssprk3<R>(s);
+    else
+        step_ssprk2<R>(s);
 }
 
 int check_params(const sse_params *p) {
@@ -353,7 +421,7 @@ int check_params(const sse_params *p) {
     if (p->n_layers < 1 || p->n_layers > 2 * kWave) { set_error("n_layers must be in [1, 128]"); return SSE_EINVAL; }
     if (p->scheme != SSE_SCHEME_SSPRK2 && p->scheme != SSE_SCHEME_SSPRK3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
     if (p->substeps < 1) { set_error("substeps must be >= 1"); return SSE_EINVAL; }
-    if (p->precision != SSE_FP64) { set_error("only precision SSE_FP64 is implemented"); return SSE_EINVAL; }
+    if (p->precision != SSE_FP64 && p->precision != SSE_MIXED) { set_error("precision must be SSE_FP64 or SSE_MIXED"); return SSE_EINVAL; }
     if (p->vcoord != SSE_ZSTAR && p->vcoord != SSE_ISOPYCNAL) { set_error("vcoord must be ZSTAR or ISOPYCNAL"); return SSE_EINVAL; }
     if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
     const double v[] = {p->dt, p->gravity, p->rho0};
@@ -373,6 +441,37 @@ int read_flag(sse_state *s) {
     if (flag) { set_error("non-finite value in the state (the step blew up)"); return SSE_ENONFINITE; }
     return SSE_OK;
 }
+
+// Host <-> device copies of an array of the state's real type from / to FP64
+// host memory (the conversion is done on the host).
+int upload_real(sse_state *s, void *dst, const double *src, size_t n) {
+    if (s->rs == sizeof(double)) {
+        SSE_HIP(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, s->stream));
+        return SSE_OK;
+    }
+    std::vector<float> tmp(src, src + n);
+    SSE_HIP(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipStreamSynchronize(s->stream));  // tmp dies at return
+    return SSE_OK;
+}
+
+int download_real(const sse_state *s, double *dst, const void *src, size_t n) {
+    if (s->rs == sizeof(double)) {
+        SSE_HIP(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, s->stream));
+        return SSE_OK;
+    }
+    std::vector<float> tmp(n);
+    SSE_HIP(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, s->stream));
+    SSE_HIP(hipStreamSynchronize(s->stream));
+    std::copy(tmp.begin(), tmp.end(), dst);
+    return SSE_OK;
+}
+
+#define SSE_TRY(call)               \
+    do {                            \
+        int _rc = (call);           \
+        if (_rc != SSE_OK) return _rc; \
+    } while (0)
 
 }  // namespace
 
@@ -398,12 +497,13 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.H.data(), t.cmask.data(), t.edge_cells.data(), t.edge_verts.data(), t.eoe.data(),
                          t.neoe.data(), t.w.data(), t.wf.data(), t.dc.data(), t.dv.data(), t.emask.data(),
                          t.vert_edges.data(), t.vert_curl.data(), t.eoe_v.data(), t.inv_dc.data(),
-                         t.inv_dv.data(), t.wpair.data()};
-    const size_t C = d->n_cells, E = d->n_edges, V = d->n_vertices;
-    const size_t nb[] = {C * 6 * 4, C * 6 * 4, C * 4, C * 6 * 8, C * 6 * 8, C * 6 * 4, C * 6 * 4, C * 6 * 8,
-                         C * 8, C, E * 2 * 4, E * 2 * 4, E * 10 * 4, E * 4, E * 10 * 8, E * 10 * 8, E * 8, E * 8, E,
-                         V * 3 * 4, V * 3 * 8, E * 10 * 8, E * 8, E * 8, E * 20 * 8};
-    for (int i = 0; i < 25; ++i) SSE_HIP(hipMemcpyAsync(base + lay.off[i], src[i], nb[i], hipMemcpyHostToDevice, s));
+                         t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
+                         t.cell_div_t_f.data(), t.H_f.data()};
+    static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
+    size_t nb[kMeshTables];
+    mesh_table_sizes(d->n_cells, d->n_edges, d->n_vertices, nb);
+    for (int i = 0; i < kMeshTables; ++i)
+        SSE_HIP(hipMemcpyAsync(base + lay.off[i], src[i], nb[i], hipMemcpyHostToDevice, s));
     SSE_HIP(hipStreamSynchronize(s));
     sse_mesh *m = new sse_mesh();
     m->C = d->n_cells;
@@ -442,6 +542,10 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.inv_dc = (const double *)P(22);
     dm.inv_dv = (const double *)P(23);
     dm.wpair = (const double *)P(24);
+    dm.wf_f = (const float *)P(25);
+    dm.inv_dc_f = (const float *)P(26);
+    dm.cell_div_t_f = (const float *)P(27);
+    dm.H_f = (const float *)P(28);
     m->cells_on_edge = t.edge_cells;
     // Gather lists of the LDS-staged edge pass for tiles of 8 and 16 edges.
     size_t cursor = lay.total;
@@ -487,7 +591,7 @@ extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p,
     if (!m || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
     int rc = check_params(p);
     if (rc) return rc;
-    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers);
+    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision));
     return SSE_OK;
 }
 
@@ -497,14 +601,16 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     *out = nullptr;
     int rc = check_params(p);
     if (rc) return rc;
-    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers);
+    const size_t rs = real_size(p->precision);
+    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs);
     if (!dev_workspace || bytes < need) { set_error("state workspace too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) { set_error("state workspace must be 256-byte aligned"); return SSE_EINVAL; }
     sse_state *s = new sse_state();
     s->mesh = m;
     s->p = *p;
     s->stream = static_cast<hipStream_t>(stream);
-    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers);
+    s->rs = rs;
+    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs);
     s->bytes = bytes;
     // Edge-pass variant.  Measured on an MI355X at 512x512 cells x 60 layers
     // (FP64), the direct-gather kernel beats both LDS tilings: at 480 bytes
@@ -518,8 +624,11 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->edge_variant = -1;
     if (const char *ev = std::getenv("SSE_EDGE_VARIANT")) {
         const int v = std::atoi(ev);
-        if (v == -1 || ((v == 0 || v == 1) && m->tiles[v].T && fe_edge_tiled_lds(m->tiles[v], p->n_layers) <= (size_t)lds_max))
-            s->edge_variant = v;
+        if (v == 0 || v == 1) {
+            const size_t lds = rs == 4 ? fe_edge_tiled_lds<float>(m->tiles[v], p->n_layers)
+                                       : fe_edge_tiled_lds<double>(m->tiles[v], p->n_layers);
+            if (m->tiles[v].T && lds <= (size_t)lds_max) s->edge_variant = v;
+        }
     }
     *out = s;
     return SSE_OK;
@@ -543,7 +652,6 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
         return SSE_ENONFINITE;
     }
     std::vector<double> frac(CL, 0.0), um(u, u + EL);
-    std::vector<uint8_t> emask(m->E);
     std::vector<uint8_t> cmask(m->C);
     SSE_HIP(hipMemcpy(cmask.data(), m->d.cmask, m->C, hipMemcpyDeviceToHost));
     for (int e = 0; e < m->E; ++e) {
@@ -561,13 +669,18 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
     }
     Work &w = s->w;
     SSE_HIP(hipMemcpyAsync(w.Hs, h, CL * 8, hipMemcpyHostToDevice, s->stream));
-    SSE_HIP(hipMemcpyAsync(w.U, um.data(), EL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_TRY(upload_real(s, w.U, um.data(), EL));
     SSE_HIP(hipMemcpyAsync(w.rho, rho, CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_HIP(hipMemcpyAsync(w.frac, frac.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s->stream));
     launch_zeta_from_h(m->d, L, w.Hs, w.zeta_n, s->stream);
-    AssembleArgs a{m->d, L, w.U, nullptr, w.Hs, w.U, w.ubar_n, w.flag};
-    launch_assemble(a, s->stream);
+    if (s->rs == 4) {
+        AssembleArgs<float> a{m->d, L, rp<float>(w.U), nullptr, w.Hs, rp<float>(w.U), w.ubar_n, w.flag};
+        launch_assemble<float>(a, s->stream);
+    } else {
+        AssembleArgs<double> a{m->d, L, rp<double>(w.U), nullptr, w.Hs, rp<double>(w.U), w.ubar_n, w.flag};
+        launch_assemble<double>(a, s->stream);
+    }
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipStreamSynchronize(s->stream));
     s->initialized = true;
@@ -583,10 +696,10 @@ extern "C" int sse_step_async(sse_state *s, int32_t n) {
         for (auto &e : s->events) SSE_HIP(hipEventCreate(&e));
     }
     for (int i = 0; i < n; ++i) {
-        if (s->p.scheme == SSE_SCHEME_SSPRK3)
-            step_ssprk3(s);
+        if (s->rs == 4)
+            step_one<float>(s);
         else
-            step_ssprk2(s);
+            step_one<double>(s);
     }
     SSE_HIP(hipGetLastError());
     return SSE_OK;
@@ -611,7 +724,7 @@ extern "C" int sse_read_state(const sse_state *cs, double *h, double *u, double 
     const Work &w = cs->w;
     hipStream_t st = cs->stream;
     if (h) SSE_HIP(hipMemcpyAsync(h, w.Hs, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
-    if (u) SSE_HIP(hipMemcpyAsync(u, w.U, (size_t)m->E * L * 8, hipMemcpyDeviceToHost, st));
+    if (u) SSE_TRY(download_real(cs, u, w.U, (size_t)m->E * L));
     if (zeta) SSE_HIP(hipMemcpyAsync(zeta, w.zeta_n, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
     if (ubar) SSE_HIP(hipMemcpyAsync(ubar, w.ubar_n, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
@@ -649,17 +762,21 @@ extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const 
     const int L = s->p.n_layers;
     Work &w = s->w;
     hipStream_t st = s->stream;
-    SSE_HIP(hipMemcpyAsync(w.T2, u, (size_t)m->E * L * 8, hipMemcpyHostToDevice, st));
+    SSE_TRY(upload_real(s, w.T2, u, (size_t)m->E * L));
     SSE_HIP(hipMemcpyAsync(w.ub2, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.H1, h, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
     const double saved = s->p.dt;
     s->p.dt = dt;
-    fe_pass(s, w.T2, nullptr, w.ub2, w.H1, w.z1, COMB_NONE, w.T1, w.G0, w.Sh1, nullptr, nullptr, 0, 0, nullptr,
-            nullptr, nullptr, 0);
+    if (s->rs == 4)
+        fe_pass<float>(s, rp<float>(w.T2), nullptr, w.ub2, w.H1, w.z1, COMB_NONE, rp<float>(w.T1), w.G0, w.Sh1,
+                       nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, 0);
+    else
+        fe_pass<double>(s, rp<double>(w.T2), nullptr, w.ub2, w.H1, w.z1, COMB_NONE, rp<double>(w.T1), w.G0,
+                        w.Sh1, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, 0);
     s->p.dt = saved;
     SSE_HIP(hipGetLastError());
-    SSE_HIP(hipMemcpyAsync(ut1, w.T1, (size_t)m->E * L * 8, hipMemcpyDeviceToHost, st));
+    SSE_TRY(download_real(s, ut1, w.T1, (size_t)m->E * L));
     SSE_HIP(hipMemcpyAsync(G, w.G0, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
     return SSE_OK;
@@ -677,7 +794,10 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
     SSE_HIP(hipMemcpyAsync(w.ub1, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.G0, G, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
-    bt_loop(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+    if (s->rs == 4)
+        bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+    else
+        bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipMemcpyAsync(ubar1, w.ub2, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(zeta1, w.bt_zout, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
@@ -695,10 +815,17 @@ extern "C" int sse_debug_thickness_stage(sse_state *s, const double *h_in, const
     Work &w = s->w;
     hipStream_t st = s->stream;
     SSE_HIP(hipMemcpyAsync(w.H1, h_in, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
-    SSE_HIP(hipMemcpyAsync(w.T2, u, (size_t)m->E * L * 8, hipMemcpyHostToDevice, st));
+    SSE_TRY(upload_real(s, w.T2, u, (size_t)m->E * L));
     SSE_HIP(hipMemcpyAsync(w.uA, uA, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
-    if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum(m->d, L, w.H1, w.T2, w.uA, w.Ftot, st);
-    thickness(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, w.T2, 1.0, nullptr, 0.0, nullptr, 0.0, dt);
+    if (s->rs == 4) {
+        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<float>(m->d, L, w.H1, rp<float>(w.T2), w.uA, w.Ftot, st);
+        thickness<float>(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, rp<float>(w.T2), 1.0, nullptr, 0.0, nullptr,
+                         0.0, dt);
+    } else {
+        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<double>(m->d, L, w.H1, rp<double>(w.T2), w.uA, w.Ftot, st);
+        thickness<double>(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, rp<double>(w.T2), 1.0, nullptr, 0.0,
+                          nullptr, 0.0, dt);
+    }
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipMemcpyAsync(h_out, w.H2, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(zeta_out, w.z_half, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));

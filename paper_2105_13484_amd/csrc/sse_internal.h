@@ -54,6 +54,11 @@ struct DevMesh {
     // vertices
     const int32_t *vert_edges = nullptr;    // [V][3]
     const double *vert_curl = nullptr;      // [V][3]  r_{v,e} d_e / A_v
+    // FP32 copies of the tables the barotropic loop reads in mixed precision
+    const float *wf_f = nullptr;            // [10][E]
+    const float *inv_dc_f = nullptr;        // [E]
+    const float *cell_div_t_f = nullptr;    // [6][C]
+    const float *H_f = nullptr;             // [C]
 };
 
 // Gather lists of the LDS-staged baroclinic edge pass.  The edges are cut
@@ -84,9 +89,12 @@ struct sse_mesh {
 
 namespace sse {
 
-// Sizes of the device mesh image (bytes) and the offsets of its tables.
+// Sizes of the device mesh image (bytes) and the offsets of its tables, in
+// the order in which mesh_create uploads them.
+constexpr int kMeshTables = 29;
+void mesh_table_sizes(int C, int E, int V, size_t (&sizes)[kMeshTables]);
 struct MeshLayout {
-    size_t off[32] = {};
+    size_t off[kMeshTables] = {};
     size_t total = 0;
 };
 MeshLayout mesh_layout(int C, int E, int V);
@@ -103,6 +111,7 @@ struct HostMeshTables {
     std::vector<uint8_t> emask;
     std::vector<int32_t> vert_edges;
     std::vector<double> vert_curl;
+    std::vector<float> wf_f, inv_dc_f, cell_div_t_f, H_f;
     int n_ocean_cells = 0;
 };
 void build_tables(const sse_mesh_desc *d, HostMeshTables &t);

@@ -1,4 +1,12 @@
 // Kernel argument blocks and host-side launchers (defined in sse_kernels.hip).
+//
+// R is the storage and arithmetic type of the velocity-like 3D fields, of the
+// tendency arithmetic and of the barotropic substep state: double in FP64
+// mode, float in mixed mode.  Layer thicknesses, density, SSH, the pressure
+// gradient (its two terms cancel to the density anomaly), the column sums that
+// feed the barotropic forcing and the reconciliation, the accumulated
+// barotropic transport and every 2D field handed between stages are double in
+// both modes.
 #pragma once
 
 #include "sse_internal.h"
@@ -11,64 +19,68 @@ enum Combine { COMB_NONE = 0, COMB_34 = 1, COMB_THIRD = 2, COMB_HALF = 3 };
 
 // Baroclinic forward Euler, cell pass: K - nu_h div u, z-star w at layer tops,
 // bottom-layer K.  Velocity u = X + ubar_add (ubar_add may be null).
+template <typename R>
 struct FECellArgs {
     DevMesh m;
     int L;
-    const double *X;
+    const R *X;
     const double *ubar_add;
     const double *h;
     const double *frac;      // h_ref / sum h_ref (z-star), null for isopycnal
     double nu_h;
-    double *B;               // [C][L]
-    double *Wtop;            // [C][L]
+    R *B;                    // [C][L]
+    R *Wtop;                 // [C][L]
     double *Kbot;            // [C]
 };
 
 // Baroclinic forward Euler, vertex pass: relative vorticity of u = X + ubar_add.
+template <typename R>
 struct FEVertexArgs {
     DevMesh m;
     int L;
-    const double *X;
+    const R *X;
     const double *ubar_add;
-    double *Z;               // [V][L]
+    R *Z;                    // [V][L]
 };
 
 // Baroclinic forward Euler, edge pass (Algorithm 1 with the stage combination).
+template <typename R>
 struct FEEdgeArgs {
     DevMesh m;
     int L;
-    const double *X;          // stage velocity storage
+    const R *X;               // stage velocity storage
     const double *ubar_add;   // u  = X + ubar_add
     const double *ubar_sub;   // ut = X - ubar_sub
     const double *h;
-    const double *rho;
-    const double *B;
-    const double *Wtop;
+    const double *rho;        // FP64 in both modes (see the pressure gradient)
+    const R *B;
+    const R *Wtop;
     const double *Kbot;
-    const double *Z;
+    const R *Z;
     const double *zeta;
-    const double *Un;         // ut^n = Un - ubar_n (used when comb != NONE or psum_a != 0)
+    const R *Un;              // ut^n = Un - ubar_n (used when comb != NONE or psum_a != 0)
     const double *ubar_n;
     int comb;                 // out = combine(comb, ut^n, ut1)
-    double *out;              // [E][L]
+    R *out;                   // [E][L]
     double *G;                // [E]
     double *sum_h;            // [E] sum_k h_e
     double *sum_hu;           // [E] sum_k h_e u_k (input u), nullable
     double *sum_hp;           // [E] sum_k h_e (psum_a ut^n_k + psum_b out_k), nullable
     double psum_a, psum_b;
-    double *Gi;               // [E] gi0 Ga + gi1 Gb + gi2 G, nullable
+    double *Gi;               // [E] interpolated forcing, nullable
     const double *Ga, *Gb;
-    int interp;               // 2: (Ga + G)/2 form; 3: Ga/6 + Gb/6 + 2G/3
+    int interp;               // 2: Ga/2 + G/2; 3: Ga/6 + Gb/6 + 2G/3
     double dt, g, rho0, nu_h, nu_v, c_drag;
 };
 
 // One forward-Euler evaluation of the barotropic system with frozen forcing,
 // fused with the SSPRK stage combination and the F^zeta accumulation.
+template <typename R>
 struct BTEvalArgs {
     DevMesh m;
-    const double *ua, *za;    // stage input (ubar, zeta)
-    const double *ub, *zb;    // base of the combination
-    double *uo, *zo;          // output
+    const R *ua, *za;         // stage input (ubar, zeta)
+    const R *ub, *zb;         // base of the combination
+    R *uo, *zo;               // output
     const double *G;          // frozen forcing
     double *F;                // accumulated flux (edges), nullable
     double wF;                // weight of this stage's flux
@@ -92,15 +104,16 @@ struct THArgs {
     int *nonfinite;
 };
 
-// Thickness stage, isopycnal: per-layer flux h_e (X + ubar_add + uA).
+// Thickness stage, isopycnal: per-layer flux h_e (c1 X1 + c2 X2 + a_e).
+template <typename R>
 struct THIsoArgs {
     DevMesh m;
     int L;
     const double *h_in, *h_n;
-    const double *X1, *X2;    // stage velocity = c1 X1 + c2 X2 + a_e
+    const R *X1, *X2;
     double c1, c2;
-    const double *a1, *a2;    // a_e = ca1 a1 + ca2 a2 + uA (nullable parts)
-    double ca1, ca2;
+    const double *a1;         // a_e = ca1 a1 + uA (nullable parts)
+    double ca1;
     const double *uA;
     int comb;
     double dt;
@@ -122,32 +135,34 @@ struct ReconArgs {
 };
 
 // u = ubar_bt + X on every layer, then the split (BBspl) of u with h.
+template <typename R>
 struct AssembleArgs {
     DevMesh m;
     int L;
-    const double *X;          // ut^{n+1} (or u itself when ubar_bt is null)
+    const R *X;               // ut^{n+1} (or u itself when ubar_bt is null)
     const double *ubar_bt;
     const double *h;
-    double *U;                // [E][L] output (may alias X when ubar_bt is null)
+    R *U;                     // [E][L] output (may alias X when ubar_bt is null)
     double *ubar;             // [E] split barotropic velocity
     int *nonfinite;
 };
 
-// LDS bytes the tiled edge pass needs for tile set t and L layers.
-size_t fe_edge_tiled_lds(const DevTiles &t, int L);
-void launch_fe_edge_tiled(const FEEdgeArgs &a, const DevTiles &t, hipStream_t s);
+template <typename R> void launch_fe_cell(const FECellArgs<R> &a, hipStream_t s);
+template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, hipStream_t s);
+template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s);
+// LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
+template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
+template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
 void set_tiled_lds_limit(size_t bytes);
-void launch_fe_cell(const FECellArgs &a, hipStream_t s);
-void launch_fe_vertex(const FEVertexArgs &a, hipStream_t s);
-void launch_fe_edge(const FEEdgeArgs &a, hipStream_t s);
-void launch_bt_eval(const BTEvalArgs &a, hipStream_t s);
+template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, hipStream_t s);
+template <typename R> void launch_thickness_iso(const THIsoArgs<R> &a, hipStream_t s);
+template <typename R> void launch_assemble(const AssembleArgs<R> &a, hipStream_t s);
+template <typename R>
+void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const R *X, const double *uA, double *F,
+                          hipStream_t s);
+template <typename Tin, typename Tout> void launch_convert(const Tin *src, Tout *dst, size_t n, hipStream_t s);
 void launch_thickness(const THArgs &a, hipStream_t s);
-void launch_thickness_iso(const THIsoArgs &a, hipStream_t s);
 void launch_recon(const ReconArgs &a, hipStream_t s);
-void launch_assemble(const AssembleArgs &a, hipStream_t s);
 void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s);
-void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const double *X, const double *uA,
-                          double *F, hipStream_t s);
-void launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
 
 }  // namespace sse

@@ -2,13 +2,16 @@
 //
 // Column kernels (3D): one 64-lane wavefront owns one vertical column of a
 // cell, an edge or a vertex; lane k holds layer k (layers >= 64 live in a
-// second register chunk).  Mesh indices are therefore wave-uniform and every
-// neighbour access is one contiguous 8L-byte column read; vertical sums and
-// scans are cross-lane operations inside the wavefront.  Lanes past the last
-// layer carry zeros so that sums and scans need no masking.
+// second register chunk).  Mesh indices are therefore wave-uniform (scalar
+// loads) and every neighbour access is one contiguous column read; vertical
+// sums and scans are cross-lane operations inside the wavefront.  Lanes past
+// the last layer carry zeros so that sums and scans need no masking.
 //
 // 2D kernels (barotropic loop, reconciliation): one thread per edge or cell,
 // reading slot-major neighbour tables.
+//
+// R is double (FP64 mode) or float (mixed mode); the split between the two
+// types is described in sse_kernels.h.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,7 +34,7 @@ __device__ __forceinline__ int xcd_block(int nb) {
     return logical < nb ? logical : -1;
 }
 
-// Index of the column owned by this wavefront among n columns (-1: none).
+// Index of the column owned by this wavefront among n columns (n: none).
 // readfirstlane tells the compiler the value is wave-uniform, so mesh-table
 // reads that depend on it become scalar loads instead of 64 identical vector
 // loads.
@@ -41,109 +44,115 @@ __device__ __forceinline__ int column_id(int n) {
     return __builtin_amdgcn_readfirstlane(lb < 0 ? n : col);
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
     return __shfl(x, 0, kWave);  // one value for the whole column
 }
 
-__device__ __forceinline__ double wave_incl_prefix(double x) {
+template <typename T>
+__device__ __forceinline__ T wave_incl_prefix(T x) {
     const int l = lane_id();
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        double y = __shfl_up(x, d, kWave);
+        T y = __shfl_up(x, d, kWave);
         if (l >= d) x += y;
     }
     return x;
 }
 
-__device__ __forceinline__ double wave_incl_suffix(double x) {
+template <typename T>
+__device__ __forceinline__ T wave_incl_suffix(T x) {
     const int l = lane_id();
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        double y = __shfl_down(x, d, kWave);
+        T y = __shfl_down(x, d, kWave);
         if (l + d < kWave) x += y;
     }
     return x;
 }
 
-template <int NK>
-__device__ __forceinline__ double col_sum(const double (&v)[NK]) {
-    double s = v[0];
+// Sum over the layers: per-lane chunks first, then a butterfly whose result
+// is the pairwise (halving) sum over the layers padded to 128.
+template <int NK, typename T>
+__device__ __forceinline__ T col_sum(const T (&v)[NK]) {
+    T s = v[0];
 #pragma unroll
     for (int c = 1; c < NK; ++c) s += v[c];
     return wave_sum(s);
 }
 
 // o_k = sum_{l<k} v_l
-template <int NK>
-__device__ __forceinline__ void col_excl_prefix(const double (&v)[NK], double (&o)[NK]) {
+template <int NK, typename T>
+__device__ __forceinline__ void col_excl_prefix(const T (&v)[NK], T (&o)[NK]) {
     const int l = lane_id();
-    double carry = 0.0;
+    T carry = T(0);
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        double inc = wave_incl_prefix(v[c]);
-        double exc = __shfl_up(inc, 1, kWave);
-        o[c] = (l == 0 ? 0.0 : exc) + carry;
+        T inc = wave_incl_prefix(v[c]);
+        T exc = __shfl_up(inc, 1, kWave);
+        o[c] = (l == 0 ? T(0) : exc) + carry;
         carry += __shfl(inc, kWave - 1, kWave);
     }
 }
 
 // o_k = sum_{l>k} v_l
-template <int NK>
-__device__ __forceinline__ void col_excl_suffix(const double (&v)[NK], double (&o)[NK]) {
+template <int NK, typename T>
+__device__ __forceinline__ void col_excl_suffix(const T (&v)[NK], T (&o)[NK]) {
     const int l = lane_id();
-    double carry = 0.0;
+    T carry = T(0);
 #pragma unroll
     for (int c = NK - 1; c >= 0; --c) {
-        double inc = wave_incl_suffix(v[c]);
-        double exc = __shfl_down(inc, 1, kWave);
-        o[c] = (l == kWave - 1 ? 0.0 : exc) + carry;
+        T inc = wave_incl_suffix(v[c]);
+        T exc = __shfl_down(inc, 1, kWave);
+        o[c] = (l == kWave - 1 ? T(0) : exc) + carry;
         carry += __shfl(inc, 0, kWave);
     }
 }
 
 // o_k = sum_{l>=k} v_l
-template <int NK>
-__device__ __forceinline__ void col_incl_suffix(const double (&v)[NK], double (&o)[NK]) {
-    double carry = 0.0;
+template <int NK, typename T>
+__device__ __forceinline__ void col_incl_suffix(const T (&v)[NK], T (&o)[NK]) {
+    T carry = T(0);
 #pragma unroll
     for (int c = NK - 1; c >= 0; --c) {
-        double inc = wave_incl_suffix(v[c]);
+        T inc = wave_incl_suffix(v[c]);
         o[c] = inc + carry;
         carry += __shfl(inc, 0, kWave);
     }
 }
 
 // o_k = v_{k-1}, o_0 = 0
-template <int NK>
-__device__ __forceinline__ void col_up1(const double (&v)[NK], double (&o)[NK]) {
+template <int NK, typename T>
+__device__ __forceinline__ void col_up1(const T (&v)[NK], T (&o)[NK]) {
     const int l = lane_id();
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        double prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : 0.0;
-        double y = __shfl_up(v[c], 1, kWave);
+        T prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : T(0);
+        T y = __shfl_up(v[c], 1, kWave);
         o[c] = (l == 0) ? prev_last : y;
     }
 }
 
 // o_k = v_{k+1}; zero past the last layer (lanes past L hold zeros)
-template <int NK>
-__device__ __forceinline__ void col_down1(const double (&v)[NK], double (&o)[NK]) {
+template <int NK, typename T>
+__device__ __forceinline__ void col_down1(const T (&v)[NK], T (&o)[NK]) {
     const int l = lane_id();
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        double next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : 0.0;
-        double y = __shfl_down(v[c], 1, kWave);
+        T next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : T(0);
+        T y = __shfl_down(v[c], 1, kWave);
         o[c] = (l == kWave - 1) ? next_first : y;
     }
 }
 
-__device__ __forceinline__ double combine(int mode, double b, double x) {
+template <typename T>
+__device__ __forceinline__ T combine(int mode, T b, T x) {
     switch (mode) {
-        case COMB_34: return 0.75 * b + 0.25 * x;
-        case COMB_THIRD: return b / 3.0 + 2.0 * x / 3.0;
-        case COMB_HALF: return 0.5 * (b + x);
+        case COMB_34: return T(0.75) * b + T(0.25) * x;
+        case COMB_THIRD: return b / T(3) + T(2) * x / T(3);
+        case COMB_HALF: return T(0.5) * (b + x);
         default: return x;
     }
 }
@@ -151,8 +160,8 @@ __device__ __forceinline__ double combine(int mode, double b, double x) {
 // ---------------------------------------------------------------------------
 // Baroclinic forward Euler (Algorithm 1): cell pass
 // ---------------------------------------------------------------------------
-template <int NK>
-__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
     const int i = column_id(m.C);
@@ -163,17 +172,18 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             int k = lane + c * kWave;
-            if (k < L) { a.B[base + k] = 0.0; a.Wtop[base + k] = 0.0; }
+            if (k < L) { a.B[base + k] = R(0); a.Wtop[base + k] = R(0); }
         }
         if (lane == 0) a.Kbot[i] = 0.0;
         return;
     }
-    double hi[NK], divhu[NK], divu[NK], K[NK];
+    double hi[NK];
+    R divhu[NK], divu[NK], K[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         int k = lane + c * kWave;
         hi[c] = (k < L) ? a.h[base + k] : 0.0;
-        divhu[c] = divu[c] = K[c] = 0.0;
+        divhu[c] = divu[c] = K[c] = R(0);
     }
     // Padded slots hold a valid index with zero coefficients, so the stencil
     // is unrolled to its full width and all its loads issue together.
@@ -181,45 +191,45 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
     for (int j = 0; j < kMaxEdges; ++j) {
         const int e = m.cell_edges[i * kMaxEdges + j];
         const int nb = m.cell_nbrs[i * kMaxEdges + j];
-        const double cd = m.cell_div[i * kMaxEdges + j];
-        const double ck = m.cell_ke[i * kMaxEdges + j];
-        const double add = a.ubar_add ? a.ubar_add[e] : 0.0;
+        const R cd = (R)m.cell_div[i * kMaxEdges + j];
+        const R ck = (R)m.cell_ke[i * kMaxEdges + j];
+        const R add = a.ubar_add ? (R)a.ubar_add[e] : R(0);
         const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             int k = lane + c * kWave;
             if (k < L) {
-                double u = a.X[eb + k] + add;
-                double he = 0.5 * (hi[c] + a.h[nbb + k]);
+                const R u = a.X[eb + k] + add;
+                const R he = (R)(0.5 * (hi[c] + a.h[nbb + k]));
                 divhu[c] += cd * (he * u);
                 divu[c] += cd * u;
                 K[c] += ck * (u * u);
             }
         }
     }
-    double w[NK];
+    R w[NK];
     if (a.frac) {
         // z-star: T^h_k = -frac_k sum_l div(h u)_l, and w_k - w_{k+1} = -div_k - T^h_k
-        const double tot = col_sum<NK>(divhu);
-        double src[NK];
+        const R tot = col_sum<NK>(divhu);
+        R src[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             int k = lane + c * kWave;
-            double th = (k < L) ? -a.frac[base + k] * tot : 0.0;
-            src[c] = (k < L) ? (-divhu[c] - th) : 0.0;
+            const R th = (k < L) ? -(R)a.frac[base + k] * tot : R(0);
+            src[c] = (k < L) ? (-divhu[c] - th) : R(0);
         }
         col_incl_suffix<NK>(src, w);
     } else {
 #pragma unroll
-        for (int c = 0; c < NK; ++c) w[c] = 0.0;
+        for (int c = 0; c < NK; ++c) w[c] = R(0);
     }
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         int k = lane + c * kWave;
         if (k < L) {
-            a.B[base + k] = K[c] - a.nu_h * divu[c];
+            a.B[base + k] = K[c] - (R)a.nu_h * divu[c];
             a.Wtop[base + k] = w[c];
-            if (k == L - 1) a.Kbot[i] = K[c];
+            if (k == L - 1) a.Kbot[i] = (double)K[c];
         }
     }
 }
@@ -227,21 +237,21 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs a) {
 // ---------------------------------------------------------------------------
 // Baroclinic forward Euler: vertex pass (relative vorticity)
 // ---------------------------------------------------------------------------
-template <int NK>
-__global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs a) {
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs<R> a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
     const int v = column_id(m.V);
     if (v >= m.V) return;
     const int L = a.L;
-    double z[NK];
+    R z[NK];
 #pragma unroll
-    for (int c = 0; c < NK; ++c) z[c] = 0.0;
+    for (int c = 0; c < NK; ++c) z[c] = R(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const int e = m.vert_edges[v * 3 + j];
-        const double cr = m.vert_curl[v * 3 + j];
-        const double add = a.ubar_add ? a.ubar_add[e] : 0.0;
+        const R cr = (R)m.vert_curl[v * 3 + j];
+        const R add = a.ubar_add ? (R)a.ubar_add[e] : R(0);
         const size_t eb = (size_t)e * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
@@ -258,154 +268,114 @@ __global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs a) {
 
 // ---------------------------------------------------------------------------
 // Baroclinic forward Euler: edge pass (Algorithm 1 and the stage combination)
+//
+// The direct-gather and the LDS-staged kernels share everything after the
+// operand loads: fe_edge_finish receives the column values of the edge, its
+// cells and vertices and the accumulated reconstruction sums.
 // ---------------------------------------------------------------------------
-template <int NK>
-__global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
+template <int NK, typename R>
+struct EdgeOperands {
+    R u[NK], ut[NK], za[NK], zb[NK], B1[NK], B2[NK], W1[NK], W2[NK];
+    double h1[NK], h2[NK], r1[NK], r2[NK];
+    R cor[NK], vor[NK];
+};
+
+template <int NK, typename R>
+__device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, int c1, int c2, double idc, double idv,
+                                               const EdgeOperands<NK, R> &o) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int E = m.E;
-    const int e = column_id(E);
-    if (e >= E) return;
     const int L = a.L;
     const size_t base = (size_t)e * L;
-    if (!m.emask[e]) {
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
-            if (k < L) a.out[base + k] = 0.0;
-        }
-        if (lane == 0) {
-            a.G[e] = 0.0;
-            a.sum_h[e] = 0.0;
-            if (a.sum_hu) a.sum_hu[e] = 0.0;
-            if (a.sum_hp) a.sum_hp[e] = 0.0;
-            if (a.Gi) a.Gi[e] = 0.0;
-        }
-        return;
-    }
-    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
-    const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
-    const double idc = m.inv_dc[e], idv = m.inv_dv[e];
-    const double add_e = a.ubar_add ? a.ubar_add[e] : 0.0;
-    const double sub_e = a.ubar_sub ? a.ubar_sub[e] : 0.0;
-    const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
-    const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
-
-    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], za[NK], zb[NK], q[NK];
+    R he[NK];
+    double hed[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        const bool ok = k < L;
-        const double x = ok ? a.X[base + k] : 0.0;
-        u[c] = ok ? x + add_e : 0.0;
-        ut[c] = ok ? x - sub_e : 0.0;
-        h1[c] = ok ? a.h[b1 + k] : 0.0;
-        h2[c] = ok ? a.h[b2 + k] : 0.0;
-        he[c] = 0.5 * (h1[c] + h2[c]);
-        r1[c] = ok ? a.rho[b1 + k] : 0.0;
-        r2[c] = ok ? a.rho[b2 + k] : 0.0;
-        za[c] = ok ? a.Z[bv1 + k] : 0.0;
-        zb[c] = ok ? a.Z[bv2 + k] : 0.0;
-        q[c] = 0.5 * (za[c] + zb[c]);
+        hed[c] = 0.5 * (o.h1[c] + o.h2[c]);
+        he[c] = (R)hed[c];
     }
-
-    // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
-    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
-    // stencil slots point at the edge itself with zero weights, so the loop
-    // runs its full width and its loads issue together.
-    double cor[NK], vor[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) cor[c] = vor[c] = 0.0;
-    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
-#pragma unroll
-    for (int j = 0; j < kMaxEdges2; ++j) {
-        const size_t js = (size_t)j * E + e;
-        const int ep = m.eoe[js];
-        const int2 pv = m.eoe_v[js];
-        const double wj = wp[2 * j], wfj = wp[2 * j + 1];
-        const double padd = a.ubar_add ? a.ubar_add[ep] : 0.0;
-        const double psub = a.ubar_sub ? a.ubar_sub[ep] : 0.0;
-        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv.x * L, pb2 = (size_t)pv.y * L;
+    // Pressure gradient in z-star layers from the column differences, in FP64
+    // in both modes: its two terms cancel down to the density anomaly.
+    double pgf[NK];
+    {
+        double drh[NK], dh[NK], sp[NK], ss[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const int k = lane + c * kWave;
-            if (k < L) {
-                const double xp = a.X[pb + k];
-                const double up = xp + padd, utp = xp - psub;
-                const double qp = 0.5 * (a.Z[pb1 + k] + a.Z[pb2 + k]);
-                cor[c] += wfj * utp;
-                vor[c] += (wj * (0.5 * (q[c] + qp))) * up;
-            }
+            drh[c] = o.r2[c] * o.h2[c] - o.r1[c] * o.h1[c];
+            dh[c] = o.h2[c] - o.h1[c];
+        }
+        col_excl_prefix<NK>(drh, sp);
+        col_excl_suffix<NK>(dh, ss);
+        const double dH = m.H[c2] - m.H[c1];
+        const double pgf_scale = idc / a.rho0;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const double dp = a.g * (sp[c] + 0.5 * drh[c]);
+            const double dz = -dH + ss[c] + 0.5 * dh[c];
+            pgf[c] = -(dp + a.g * (0.5 * (o.r1[c] + o.r2[c])) * dz) * pgf_scale;
         }
     }
-
-    // Pressure gradient in z-star layers from the column differences.
-    double drh[NK], dh[NK], sp[NK], ss[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        drh[c] = r2[c] * h2[c] - r1[c] * h1[c];
-        dh[c] = h2[c] - h1[c];
-    }
-    col_excl_prefix<NK>(drh, sp);
-    col_excl_suffix<NK>(dh, ss);
-    const double dH = m.H[c2] - m.H[c1];
 
     // Vertical advection and vertical viscosity at interior interfaces.
-    double uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
-    col_up1<NK>(u, uu);
+    R uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
+    col_up1<NK>(o.u, uu);
     col_up1<NK>(he, hu);
+    const R nu_v = (R)a.nu_v;
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
         if (k >= 1 && k < L) {
-            const double dzt = (uu[c] - u[c]) * (1.0 / (0.5 * (hu[c] + he[c])));
-            const double we = 0.5 * (a.Wtop[b1 + k] + a.Wtop[b2 + k]);
+            const R dzt = (uu[c] - o.u[c]) * (R(1) / (R(0.5) * (hu[c] + he[c])));
+            const R we = R(0.5) * (o.W1[c] + o.W2[c]);
             at[c] = we * dzt;
-            tau[c] = a.nu_v * dzt;
+            tau[c] = nu_v * dzt;
         } else {
-            at[c] = 0.0;
-            tau[c] = 0.0;
+            at[c] = R(0);
+            tau[c] = R(0);
         }
     }
     col_down1<NK>(at, atn);
     col_down1<NK>(tau, taun);
-    const double speed = sqrt(a.Kbot[c1] + a.Kbot[c2]);
-    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) * idc;
-    const double pgf_scale = idc / a.rho0;
+    const R speed = (R)sqrt(a.Kbot[c1] + a.Kbot[c2]);
+    const R gz = (R)(a.g * (a.zeta[c2] - a.zeta[c1]) * idc);
+    const R dt = (R)a.dt, nu_h = (R)a.nu_h, c_drag = (R)a.c_drag;
+    const R ridc = (R)idc, ridv = (R)idv;
 
-    double ut1[NK], hut1[NK], hu_in[NK];
+    R ut1[NK];
+    double hut1[NK], hu_in[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
         if (k < L) {
-            if (k == L - 1) taun[c] = a.c_drag * speed * u[c];
-            const double dp = a.g * (sp[c] + 0.5 * drh[c]);
-            const double dz = -dH + ss[c] + 0.5 * dh[c];
-            const double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) * pgf_scale;
-            const double gradB = (a.B[b2 + k] - a.B[b1 + k]) * idc;
-            const double curlp = (zb[c] - za[c]) * idv;
-            const double vadv = 0.5 * (at[c] + atn[c]);
-            const double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
-            const double du = (tau[c] - taun[c]) * (1.0 / he[c]);
-            ut1[c] = ut[c] + a.dt * (cor[c] + tu + du + gz);
+            if (k == L - 1) taun[c] = c_drag * speed * o.u[c];
+            const R gradB = (o.B2[c] - o.B1[c]) * ridc;
+            const R curlp = (o.zb[c] - o.za[c]) * ridv;
+            const R vadv = R(0.5) * (at[c] + atn[c]);
+            const R tu = -gradB + o.vor[c] - vadv + (R)pgf[c] - nu_h * curlp;
+            const R du = (tau[c] - taun[c]) * (R(1) / he[c]);
+            ut1[c] = o.ut[c] + dt * (o.cor[c] + tu + du + gz);
         } else {
-            ut1[c] = 0.0;
+            ut1[c] = R(0);
         }
-        hut1[c] = he[c] * ut1[c];
-        hu_in[c] = he[c] * u[c];
+        hut1[c] = hed[c] * (double)ut1[c];
+        hu_in[c] = hed[c] * (double)o.u[c];
     }
-    const double Sh = col_sum<NK>(he);
+    // Column sums that feed the barotropic forcing and the reconciliation are
+    // formed in FP64 in both modes.
+    const double Sh = col_sum<NK>(hed);
     const double G = col_sum<NK>(hut1) / Sh / a.dt;
+    const R dtG = (R)(a.dt * G);
     const double ubn = a.Un ? a.ubar_n[e] : 0.0;
-    double outv[NK], hp[NK];
+    R outv[NK];
+    double hp[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
-        const double x = ut1[c] - a.dt * G;
-        const double utn = (a.Un && k < L) ? a.Un[base + k] - ubn : 0.0;
-        outv[c] = (k < L) ? combine(a.comb, utn, x) : 0.0;
+        const R x = ut1[c] - dtG;
+        const R utn = (a.Un && k < L) ? (R)((double)a.Un[base + k] - ubn) : R(0);
+        outv[c] = (k < L) ? combine<R>(a.comb, utn, x) : R(0);
         if (k < L) a.out[base + k] = outv[c];
-        hp[c] = he[c] * (a.psum_a * utn + a.psum_b * outv[c]);
+        hp[c] = hed[c] * (a.psum_a * (double)utn + a.psum_b * (double)outv[c]);
     }
     double shu = 0.0, shp = 0.0;
     if (a.sum_hu) shu = col_sum<NK>(hu_in);
@@ -422,6 +392,97 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
                 a.Gi[e] = 0.5 * a.Ga[e] + 0.5 * G;
         }
     }
+}
+
+template <int NK, typename R>
+__device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
+    const int lane = lane_id();
+    const size_t base = (size_t)e * a.L;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        if (k < a.L) a.out[base + k] = R(0);
+    }
+    if (lane == 0) {
+        a.G[e] = 0.0;
+        a.sum_h[e] = 0.0;
+        if (a.sum_hu) a.sum_hu[e] = 0.0;
+        if (a.sum_hp) a.sum_hp[e] = 0.0;
+        if (a.Gi) a.Gi[e] = 0.0;
+    }
+}
+
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int E = m.E;
+    const int e = column_id(E);
+    if (e >= E) return;
+    const int L = a.L;
+    const size_t base = (size_t)e * L;
+    if (!m.emask[e]) {
+        fe_edge_dry<NK, R>(a, e);
+        return;
+    }
+    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
+    const double idc = m.inv_dc[e], idv = m.inv_dv[e];
+    const R add_e = a.ubar_add ? (R)a.ubar_add[e] : R(0);
+    const R sub_e = a.ubar_sub ? (R)a.ubar_sub[e] : R(0);
+    const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
+    const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
+
+    EdgeOperands<NK, R> o;
+    R q[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        const bool ok = k < L;
+        const R x = ok ? a.X[base + k] : R(0);
+        o.u[c] = ok ? x + add_e : R(0);
+        o.ut[c] = ok ? x - sub_e : R(0);
+        o.h1[c] = ok ? a.h[b1 + k] : 0.0;
+        o.h2[c] = ok ? a.h[b2 + k] : 0.0;
+        o.r1[c] = ok ? a.rho[b1 + k] : 0.0;
+        o.r2[c] = ok ? a.rho[b2 + k] : 0.0;
+        o.za[c] = ok ? a.Z[bv1 + k] : R(0);
+        o.zb[c] = ok ? a.Z[bv2 + k] : R(0);
+        o.B1[c] = ok ? a.B[b1 + k] : R(0);
+        o.B2[c] = ok ? a.B[b2 + k] : R(0);
+        o.W1[c] = ok ? a.Wtop[b1 + k] : R(0);
+        o.W2[c] = ok ? a.Wtop[b2 + k] : R(0);
+        q[c] = R(0.5) * (o.za[c] + o.zb[c]);
+        o.cor[c] = o.vor[c] = R(0);
+    }
+
+    // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
+    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
+    // stencil slots point at the edge itself with zero weights, so the loop
+    // runs its full width and its loads issue together.
+    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+#pragma unroll
+    for (int j = 0; j < kMaxEdges2; ++j) {
+        const size_t js = (size_t)j * E + e;
+        const int ep = m.eoe[js];
+        const int2 pv = m.eoe_v[js];
+        const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
+        const R padd = a.ubar_add ? (R)a.ubar_add[ep] : R(0);
+        const R psub = a.ubar_sub ? (R)a.ubar_sub[ep] : R(0);
+        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv.x * L, pb2 = (size_t)pv.y * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = lane + c * kWave;
+            if (k < L) {
+                const R xp = a.X[pb + k];
+                const R up = xp + padd, utp = xp - psub;
+                const R qp = R(0.5) * (a.Z[pb1 + k] + a.Z[pb2 + k]);
+                o.cor[c] += wfj * utp;
+                o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
+            }
+        }
+    }
+    fe_edge_finish<NK, R>(a, e, c1, c2, idc, idv, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,9 +495,9 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs a) {
 // On the hexagonal mesh this cuts the column gathers per edge from ~42 to
 // ~12 (T = 8) or ~10 (T = 16).
 // ---------------------------------------------------------------------------
-template <int NK>
-__global__ void __launch_bounds__(1024) fe_edge_tiled_kernel(FEEdgeArgs a, DevTiles t) {
-    extern __shared__ double lds[];
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) fe_edge_tiled_kernel(FEEdgeArgs<R> a, DevTiles t) {
+    extern __shared__ double lds_d[];
     const DevMesh &m = a.m;
     const int tile = xcd_block(t.nT);
     if (tile < 0) return;
@@ -446,228 +507,159 @@ __global__ void __launch_bounds__(1024) fe_edge_tiled_kernel(FEEdgeArgs a, DevTi
     const int ue0 = t.ue_off[tile], nue = t.ue_off[tile + 1] - ue0;
     const int uv0 = t.uv_off[tile], nuv = t.uv_off[tile + 1] - uv0;
     const int uc0 = t.uc_off[tile], nuc = t.uc_off[tile + 1] - uc0;
-    double *sX = lds;
-    double *sZ = sX + (size_t)nue * L;
-    double *sH = sZ + (size_t)nuv * L;
+    // LDS: h | rho | ubar (FP64), then X | Z | B | w (type R)
+    double *sH = lds_d;
     double *sR = sH + (size_t)nuc * L;
-    double *sB = sR + (size_t)nuc * L;
-    double *sW = sB + (size_t)nuc * L;
-    double *sU = sW + (size_t)nuc * L;
+    double *sU = sR + (size_t)nuc * L;
+    R *sX = reinterpret_cast<R *>(sU + nue);
+    R *sZ = sX + (size_t)nue * L;
+    R *sB = sZ + (size_t)nuv * L;
+    R *sW = sB + (size_t)nuc * L;
     const double *ubar_src = a.ubar_add ? a.ubar_add : a.ubar_sub;
 
-    // Stage: every listed column once.  The (column, layer) elements are
+    // Stage every listed column once.  The (column, layer) elements are
     // spread over all threads of the workgroup so that the list reads and the
-    // column reads of one thread are independent of each other and issue
-    // together.
-    const int ncol = nue + nuv + 4 * nuc;
-    const int nelem = ncol * L;
-    for (int i = threadIdx.x; i < nelem; i += blockDim.x) {
-        const int col = i / L, k = i - col * L;
-        const double *src;
-        if (col < nue) {
-            src = a.X + (size_t)t.ue[ue0 + col] * L;
-        } else if (col < nue + nuv) {
-            src = a.Z + (size_t)t.uv[uv0 + (col - nue)] * L;
-        } else {
-            const int r = col - nue - nuv, arr = r / nuc, q = r - arr * nuc;
-            src = (arr == 0 ? a.h : arr == 1 ? a.rho : arr == 2 ? a.B : a.Wtop) + (size_t)t.uc[uc0 + q] * L;
+    // column reads of one thread are independent of each other.
+    {
+        const int nh = 2 * nuc * L;
+        for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+            const int col = i / L, k = i - col * L;
+            const double *src = col < nuc ? a.h : a.rho;
+            sH[i] = src[(size_t)t.uc[uc0 + (col < nuc ? col : col - nuc)] * L + k];
         }
-        lds[i] = src[k];
+        const int nelem = (nue + nuv + 2 * nuc) * L;
+        for (int i = threadIdx.x; i < nelem; i += blockDim.x) {
+            const int col = i / L, k = i - col * L;
+            const R *src;
+            if (col < nue) {
+                src = a.X + (size_t)t.ue[ue0 + col] * L;
+            } else if (col < nue + nuv) {
+                src = a.Z + (size_t)t.uv[uv0 + (col - nue)] * L;
+            } else {
+                const int r = col - nue - nuv, arr = r / nuc, q = r - arr * nuc;
+                src = (arr == 0 ? a.B : a.Wtop) + (size_t)t.uc[uc0 + q] * L;
+            }
+            sX[i] = src[k];
+        }
+        for (int i = threadIdx.x; i < nue; i += blockDim.x) sU[i] = ubar_src ? ubar_src[t.ue[ue0 + i]] : 0.0;
     }
-    for (int i = threadIdx.x; i < nue; i += blockDim.x) sU[i] = ubar_src ? ubar_src[t.ue[ue0 + i]] : 0.0;
     __syncthreads();
 
     const int e = tile * T + wv;
     if (e >= E) return;
-    const size_t base = (size_t)e * L;
     if (!m.emask[e]) {
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const int k = lane + c * kWave;
-            if (k < L) a.out[base + k] = 0.0;
-        }
-        if (lane == 0) {
-            a.G[e] = 0.0;
-            a.sum_h[e] = 0.0;
-            if (a.sum_hu) a.sum_hu[e] = 0.0;
-            if (a.sum_hp) a.sum_hp[e] = 0.0;
-            if (a.Gi) a.Gi[e] = 0.0;
-        }
+        fe_edge_dry<NK, R>(a, e);
         return;
     }
     // 8-bit positions of this edge's operands in the staged lists.
     const uint32_t *lw = reinterpret_cast<const uint32_t *>(t.loc + (size_t)e * kLocPerEdge);
     uint32_t word[kLocPerEdge / 4];
 #pragma unroll
-    for (int q = 0; q < kLocPerEdge / 4; ++q) word[q] = lw[q];
+    for (int qq = 0; qq < kLocPerEdge / 4; ++qq) word[qq] = lw[qq];
     auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
     const int ls = locb(0), lc1 = locb(1), lc2 = locb(2), lv1 = locb(3), lv2 = locb(4);
     const bool is_add = a.ubar_add != nullptr, is_sub = a.ubar_sub != nullptr;
-    const double add_e = is_add ? sU[ls] : 0.0, sub_e = is_sub ? sU[ls] : 0.0;
+    const R add_e = is_add ? (R)sU[ls] : R(0), sub_e = is_sub ? (R)sU[ls] : R(0);
     const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
     const double idc = m.inv_dc[e], idv = m.inv_dv[e];
 
-    double u[NK], ut[NK], he[NK], h1[NK], h2[NK], r1[NK], r2[NK], za[NK], zb[NK], q[NK];
+    EdgeOperands<NK, R> o;
+    R q[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
         const bool ok = k < L;
-        const double x = ok ? sX[(size_t)ls * L + k] : 0.0;
-        u[c] = ok ? x + add_e : 0.0;
-        ut[c] = ok ? x - sub_e : 0.0;
-        h1[c] = ok ? sH[(size_t)lc1 * L + k] : 0.0;
-        h2[c] = ok ? sH[(size_t)lc2 * L + k] : 0.0;
-        he[c] = 0.5 * (h1[c] + h2[c]);
-        r1[c] = ok ? sR[(size_t)lc1 * L + k] : 0.0;
-        r2[c] = ok ? sR[(size_t)lc2 * L + k] : 0.0;
-        za[c] = ok ? sZ[(size_t)lv1 * L + k] : 0.0;
-        zb[c] = ok ? sZ[(size_t)lv2 * L + k] : 0.0;
-        q[c] = 0.5 * (za[c] + zb[c]);
+        const R x = ok ? sX[(size_t)ls * L + k] : R(0);
+        o.u[c] = ok ? x + add_e : R(0);
+        o.ut[c] = ok ? x - sub_e : R(0);
+        o.h1[c] = ok ? sH[(size_t)lc1 * L + k] : 0.0;
+        o.h2[c] = ok ? sH[(size_t)lc2 * L + k] : 0.0;
+        o.r1[c] = ok ? sR[(size_t)lc1 * L + k] : 0.0;
+        o.r2[c] = ok ? sR[(size_t)lc2 * L + k] : 0.0;
+        o.za[c] = ok ? sZ[(size_t)lv1 * L + k] : R(0);
+        o.zb[c] = ok ? sZ[(size_t)lv2 * L + k] : R(0);
+        o.B1[c] = ok ? sB[(size_t)lc1 * L + k] : R(0);
+        o.B2[c] = ok ? sB[(size_t)lc2 * L + k] : R(0);
+        o.W1[c] = ok ? sW[(size_t)lc1 * L + k] : R(0);
+        o.W2[c] = ok ? sW[(size_t)lc2 * L + k] : R(0);
+        q[c] = R(0.5) * (o.za[c] + o.zb[c]);
+        o.cor[c] = o.vor[c] = R(0);
     }
-
-    // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
-    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.
-    double cor[NK], vor[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) cor[c] = vor[c] = 0.0;
     const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
     for (int j = 0; j < kMaxEdges2; ++j) {
-        const double wj = wp[2 * j], wfj = wp[2 * j + 1];
+        const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
         const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
-        const double pu = sU[sl];
-        const double padd = is_add ? pu : 0.0, psub = is_sub ? pu : 0.0;
+        const R pu = (R)sU[sl];
+        const R padd = is_add ? pu : R(0), psub = is_sub ? pu : R(0);
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const int k = lane + c * kWave;
             if (k < L) {
-                const double xp = sX[(size_t)sl * L + k];
-                const double up = xp + padd, utp = xp - psub;
-                const double qp = 0.5 * (sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k]);
-                cor[c] += wfj * utp;
-                vor[c] += (wj * (0.5 * (q[c] + qp))) * up;
+                const R xp = sX[(size_t)sl * L + k];
+                const R up = xp + padd, utp = xp - psub;
+                const R qp = R(0.5) * (sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k]);
+                o.cor[c] += wfj * utp;
+                o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
             }
         }
     }
-
-    // Pressure gradient in z-star layers from the column differences.
-    double drh[NK], dh[NK], sp[NK], ss[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        drh[c] = r2[c] * h2[c] - r1[c] * h1[c];
-        dh[c] = h2[c] - h1[c];
-    }
-    col_excl_prefix<NK>(drh, sp);
-    col_excl_suffix<NK>(dh, ss);
-    const double dH = m.H[c2] - m.H[c1];
-
-    // Vertical advection and vertical viscosity at interior interfaces.
-    double uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
-    col_up1<NK>(u, uu);
-    col_up1<NK>(he, hu);
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        if (k >= 1 && k < L) {
-            const double dzt = (uu[c] - u[c]) * (1.0 / (0.5 * (hu[c] + he[c])));
-            const double we = 0.5 * (sW[(size_t)lc1 * L + k] + sW[(size_t)lc2 * L + k]);
-            at[c] = we * dzt;
-            tau[c] = a.nu_v * dzt;
-        } else {
-            at[c] = 0.0;
-            tau[c] = 0.0;
-        }
-    }
-    col_down1<NK>(at, atn);
-    col_down1<NK>(tau, taun);
-    const double speed = sqrt(a.Kbot[c1] + a.Kbot[c2]);
-    const double gz = a.g * (a.zeta[c2] - a.zeta[c1]) * idc;
-    const double pgf_scale = idc / a.rho0;
-
-    double ut1[NK], hut1[NK], hu_in[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        if (k < L) {
-            if (k == L - 1) taun[c] = a.c_drag * speed * u[c];
-            const double dp = a.g * (sp[c] + 0.5 * drh[c]);
-            const double dz = -dH + ss[c] + 0.5 * dh[c];
-            const double pgf = -(dp + a.g * (0.5 * (r1[c] + r2[c])) * dz) * pgf_scale;
-            const double gradB = (sB[(size_t)lc2 * L + k] - sB[(size_t)lc1 * L + k]) * idc;
-            const double curlp = (zb[c] - za[c]) * idv;
-            const double vadv = 0.5 * (at[c] + atn[c]);
-            const double tu = -gradB + vor[c] - vadv + pgf - a.nu_h * curlp;
-            const double du = (tau[c] - taun[c]) * (1.0 / he[c]);
-            ut1[c] = ut[c] + a.dt * (cor[c] + tu + du + gz);
-        } else {
-            ut1[c] = 0.0;
-        }
-        hut1[c] = he[c] * ut1[c];
-        hu_in[c] = he[c] * u[c];
-    }
-    const double Sh = col_sum<NK>(he);
-    const double G = col_sum<NK>(hut1) / Sh / a.dt;
-    const double ubn = a.Un ? a.ubar_n[e] : 0.0;
-    double outv[NK], hp[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        const double x = ut1[c] - a.dt * G;
-        const double utn = (a.Un && k < L) ? a.Un[base + k] - ubn : 0.0;
-        outv[c] = (k < L) ? combine(a.comb, utn, x) : 0.0;
-        if (k < L) a.out[base + k] = outv[c];
-        hp[c] = he[c] * (a.psum_a * utn + a.psum_b * outv[c]);
-    }
-    double shu = 0.0, shp = 0.0;
-    if (a.sum_hu) shu = col_sum<NK>(hu_in);
-    if (a.sum_hp) shp = col_sum<NK>(hp);
-    if (lane == 0) {
-        a.G[e] = G;
-        a.sum_h[e] = Sh;
-        if (a.sum_hu) a.sum_hu[e] = shu;
-        if (a.sum_hp) a.sum_hp[e] = shp;
-        if (a.Gi) {
-            if (a.interp == 3)
-                a.Gi[e] = a.Ga[e] / 6.0 + a.Gb[e] / 6.0 + 2.0 * G / 3.0;
-            else
-                a.Gi[e] = 0.5 * a.Ga[e] + 0.5 * G;
-        }
-    }
+    fe_edge_finish<NK, R>(a, e, c1, c2, idc, idv, o);
 }
 
 // ---------------------------------------------------------------------------
 // Barotropic forward-Euler evaluation (Algorithms 3 and 4, one stage)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlocks, int nCellBlocks) {
+template <typename R>
+struct BTTables;
+template <>
+struct BTTables<double> {
+    __device__ static const double *wf(const DevMesh &m) { return m.wf; }
+    __device__ static const double *inv_dc(const DevMesh &m) { return m.inv_dc; }
+    __device__ static const double *cdiv(const DevMesh &m) { return m.cell_div_t; }
+    __device__ static const double *H(const DevMesh &m) { return m.H; }
+};
+template <>
+struct BTTables<float> {
+    __device__ static const float *wf(const DevMesh &m) { return m.wf_f; }
+    __device__ static const float *inv_dc(const DevMesh &m) { return m.inv_dc_f; }
+    __device__ static const float *cdiv(const DevMesh &m) { return m.cell_div_t_f; }
+    __device__ static const float *H(const DevMesh &m) { return m.H_f; }
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs<R> a, int nEdgeBlocks, int nCellBlocks) {
     const DevMesh &m = a.m;
     // XCD x owns edge blocks [x * pe, (x + 1) * pe) and cell blocks
     // [x * pc, (x + 1) * pc): one contiguous region of the mesh per L2.
     const int pe = (nEdgeBlocks + kXcd - 1) / kXcd, pc = (nCellBlocks + kXcd - 1) / kXcd;
     const int x = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+    const R tau = (R)a.tau, g = (R)a.g;
     if (local < pe) {
         const int lb = x * pe + local;
         if (lb >= nEdgeBlocks) return;
         const int e = lb * blockDim.x + threadIdx.x;
         if (e >= m.E) return;
         if (!m.emask[e]) {
-            a.uo[e] = 0.0;
+            a.uo[e] = R(0);
             if (a.F && a.zeroF) a.F[e] = 0.0;
             return;
         }
+        const R *__restrict__ wf = BTTables<R>::wf(m);
         const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
-        const double ua = a.ua[e];
-        const double z1 = a.za[c1], z2 = a.za[c2];
+        const R ua = a.ua[e];
+        const R z1 = a.za[c1], z2 = a.za[c2];
         // Padded stencil slots point at the edge itself with zero weight: the
         // loop runs its full width so that all its gathers issue together.
-        double cor = 0.0;
+        R cor = R(0);
 #pragma unroll
-        for (int j = 0; j < kMaxEdges2; ++j)
-            cor += m.wf[(size_t)j * m.E + e] * a.ua[m.eoe[(size_t)j * m.E + e]];
-        const double ru = cor - a.g * (z2 - z1) * m.inv_dc[e] + a.G[e];
-        const double base = a.ub[e];
-        a.uo[e] = combine(a.comb, base, ua + a.tau * ru);
+        for (int j = 0; j < kMaxEdges2; ++j) cor += wf[(size_t)j * m.E + e] * a.ua[m.eoe[(size_t)j * m.E + e]];
+        const R ru = cor - g * (z2 - z1) * BTTables<R>::inv_dc(m)[e] + (R)a.G[e];
+        const R base = a.ub[e];
+        a.uo[e] = combine<R>(a.comb, base, ua + tau * ru);
         if (a.F) {
-            const double flux = ua * (0.5 * ((z1 + m.H[c1]) + (z2 + m.H[c2])));
+            // The transport accumulates in FP64 in both modes.
+            const double flux = (double)ua * (0.5 * (((double)z1 + m.H[c1]) + ((double)z2 + m.H[c2])));
             a.F[e] = (a.zeroF ? 0.0 : a.F[e]) + a.wF * flux;
         }
     } else {
@@ -675,19 +667,21 @@ __global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs a, int nEdgeBlo
         if (lb >= nCellBlocks) return;
         const int i = lb * blockDim.x + threadIdx.x;
         if (i >= m.C) return;
-        if (!m.cmask[i]) { a.zo[i] = 0.0; return; }
-        const double zi = a.za[i] + m.H[i];
-        double div = 0.0;
+        if (!m.cmask[i]) { a.zo[i] = R(0); return; }
+        const R *__restrict__ Ht = BTTables<R>::H(m);
+        const R *__restrict__ cd_t = BTTables<R>::cdiv(m);
+        const R zi = a.za[i] + Ht[i];
+        R div = R(0);
 #pragma unroll
         for (int j = 0; j < kMaxEdges; ++j) {
-            const double cd = m.cell_div_t[(size_t)j * m.C + i];
+            const R cd = cd_t[(size_t)j * m.C + i];
             const int e = m.cell_edges_t[(size_t)j * m.C + i];
             const int nb = m.cell_nbrs_t[(size_t)j * m.C + i];
-            const double zn = a.za[nb] + m.H[nb];
-            div += cd * (a.ua[e] * (0.5 * (zi + zn)));
+            const R zn = a.za[nb] + Ht[nb];
+            div += cd * (a.ua[e] * (R(0.5) * (zi + zn)));
         }
-        const double base = a.zb[i];
-        a.zo[i] = combine(a.comb, base, a.za[i] + a.tau * (-div));
+        const R base = a.zb[i];
+        a.zo[i] = combine<R>(a.comb, base, a.za[i] + tau * (-div));
     }
 }
 
@@ -719,7 +713,7 @@ __global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
             double th = wet ? -a.frac[base + k] * divF : 0.0;
             double x = a.h_in[base + k] + a.dt * th;
             double b = (a.comb != COMB_NONE) ? a.h_n[base + k] : 0.0;
-            hv[c] = combine(a.comb, b, x);
+            hv[c] = combine<double>(a.comb, b, x);
             a.h_out[base + k] = hv[c];
             bad |= !isfinite(hv[c]);
         }
@@ -730,8 +724,8 @@ __global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
 }
 
 // Thickness stage (isopycnal): per-layer flux divergence, w = 0.
-template <int NK>
-__global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs a) {
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs<R> a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
     const int i = column_id(m.C);
@@ -752,14 +746,14 @@ __global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs a) {
             const int e = m.cell_edges[i * kMaxEdges + j];
             const int nb = m.cell_nbrs[i * kMaxEdges + j];
             const double cd = m.cell_div[i * kMaxEdges + j];
-            const double ae = (a.a1 ? a.ca1 * a.a1[e] : 0.0) + (a.a2 ? a.ca2 * a.a2[e] : 0.0) + (a.uA ? a.uA[e] : 0.0);
+            const double ae = (a.a1 ? a.ca1 * a.a1[e] : 0.0) + (a.uA ? a.uA[e] : 0.0);
             const bool ew = m.emask[e] != 0;
             const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
 #pragma unroll
             for (int c = 0; c < NK; ++c) {
                 int k = lane + c * kWave;
                 if (k < L && ew) {
-                    double u = a.c1 * a.X1[eb + k] + (a.X2 ? a.c2 * a.X2[eb + k] : 0.0) + ae;
+                    double u = a.c1 * (double)a.X1[eb + k] + (a.X2 ? a.c2 * (double)a.X2[eb + k] : 0.0) + ae;
                     double he = 0.5 * (hi[c] + a.h_in[nbb + k]);
                     div[c] += cd * (he * u);
                 }
@@ -775,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs a) {
         if (k < L) {
             double x = hi[c] + a.dt * (-div[c]);
             double b = (a.comb != COMB_NONE) ? a.h_n[base + k] : 0.0;
-            hv[c] = combine(a.comb, b, x);
+            hv[c] = combine<double>(a.comb, b, x);
             a.h_out[base + k] = hv[c];
             bad |= !isfinite(hv[c]);
         }
@@ -829,8 +823,8 @@ __global__ void __launch_bounds__(256) recon_kernel(ReconArgs a) {
 // ---------------------------------------------------------------------------
 // u^{n+1} = ubar^{n+1} + ut^{n+1}; split (BBspl) with h^{n+1}
 // ---------------------------------------------------------------------------
-template <int NK>
-__global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs<R> a) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
     const int e = column_id(m.E);
@@ -839,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
     const size_t base = (size_t)e * L;
     const bool wet = m.emask[e] != 0;
     const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
-    const double ub = (a.ubar_bt && wet) ? a.ubar_bt[e] : 0.0;
+    const R ub = (a.ubar_bt && wet) ? (R)a.ubar_bt[e] : R(0);
     double he[NK], hu[NK];
     bool bad = false;
 #pragma unroll
@@ -847,11 +841,11 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs a) {
         int k = lane + c * kWave;
         he[c] = hu[c] = 0.0;
         if (k < L) {
-            double u = wet ? (a.ubar_bt ? ub + a.X[base + k] : a.X[base + k]) : 0.0;
+            const R u = wet ? (a.ubar_bt ? ub + a.X[base + k] : a.X[base + k]) : R(0);
             a.U[base + k] = u;
             he[c] = 0.5 * (a.h[(size_t)c1 * L + k] + a.h[(size_t)c2 * L + k]);
-            hu[c] = he[c] * u;
-            bad |= !isfinite(u);
+            hu[c] = he[c] * (double)u;
+            bad |= !isfinite((double)u);
         }
     }
     const double sh = col_sum<NK>(he);
@@ -876,8 +870,8 @@ __global__ void __launch_bounds__(kBlock) zeta_kernel(DevMesh m, int L, const do
 }
 
 // F_e = sum_k h_e (X_k + uA_e)
-template <int NK>
-__global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const double *X,
+template <int NK, typename R>
+__global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const R *X,
                                                                const double *uA, double *F) {
     const int lane = lane_id();
     const int e = column_id(m.E);
@@ -891,16 +885,17 @@ __global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L,
         f[c] = 0.0;
         if (k < L) {
             double he = 0.5 * (h[(size_t)c1 * L + k] + h[(size_t)c2 * L + k]);
-            f[c] = he * (X[(size_t)e * L + k] + ua);
+            f[c] = he * ((double)X[(size_t)e * L + k] + ua);
         }
     }
     const double s = col_sum<NK>(f);
     if (lane == 0) F[e] = m.emask[e] ? s : 0.0;
 }
 
-__global__ void copy_kernel(const double *src, double *dst, size_t n) {
+template <typename Tin, typename Tout>
+__global__ void convert_kernel(const Tin *src, Tout *dst, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+    if (i < n) dst[i] = (Tout)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -912,59 +907,106 @@ static inline dim3 col_grid(int n) {
 }
 static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
-#define SSE_DISPATCH_NK(L, KERNEL, GRID, ...)                                   \
-    do {                                                                        \
-        if ((L) <= kWave)                                                       \
-            KERNEL<1><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);                     \
-        else                                                                    \
-            KERNEL<2><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);                     \
+// Columns of up to 64 layers use one register chunk per lane, up to 128 two.
+#define SSE_DISPATCH_NK(L, KERNEL, GRID, ...)                         \
+    do {                                                              \
+        if ((L) <= kWave)                                             \
+            KERNEL<1><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);           \
+        else                                                          \
+            KERNEL<2><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);           \
+    } while (0)
+#define SSE_DISPATCH_NK_R(L, KERNEL, GRID, ...)                       \
+    do {                                                              \
+        if ((L) <= kWave)                                             \
+            KERNEL<1, R><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);        \
+        else                                                          \
+            KERNEL<2, R><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);        \
     } while (0)
 
-void launch_fe_cell(const FECellArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_cell_kernel, col_grid(a.m.C), a); }
-void launch_fe_vertex(const FEVertexArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_vertex_kernel, col_grid(a.m.V), a); }
-void launch_fe_edge(const FEEdgeArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, fe_edge_kernel, col_grid(a.m.E), a); }
-
-size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
-    return ((size_t)(t.max_ue + t.max_uv + 4 * t.max_uc) * L + t.max_ue) * sizeof(double);
+template <typename R>
+void launch_fe_cell(const FECellArgs<R> &a, hipStream_t s) {
+    SSE_DISPATCH_NK_R(a.L, fe_cell_kernel, col_grid(a.m.C), a);
+}
+template <typename R>
+void launch_fe_vertex(const FEVertexArgs<R> &a, hipStream_t s) {
+    SSE_DISPATCH_NK_R(a.L, fe_vertex_kernel, col_grid(a.m.V), a);
+}
+template <typename R>
+void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s) {
+    SSE_DISPATCH_NK_R(a.L, fe_edge_kernel, col_grid(a.m.E), a);
 }
 
-void launch_fe_edge_tiled(const FEEdgeArgs &a, const DevTiles &t, hipStream_t s) {
-    const size_t lds = fe_edge_tiled_lds(t, a.L);
+template <typename R>
+size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
+    return ((size_t)2 * t.max_uc * L + t.max_ue) * sizeof(double) +
+           (size_t)(t.max_ue + t.max_uv + 2 * t.max_uc) * L * sizeof(R);
+}
+
+template <typename R>
+void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s) {
+    const size_t lds = fe_edge_tiled_lds<R>(t, a.L);
     const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block(t.T * kWave);
     if (a.L <= kWave)
-        fe_edge_tiled_kernel<1><<<grid, block, lds, s>>>(a, t);
+        fe_edge_tiled_kernel<1, R><<<grid, block, lds, s>>>(a, t);
     else
-        fe_edge_tiled_kernel<2><<<grid, block, lds, s>>>(a, t);
+        fe_edge_tiled_kernel<2, R><<<grid, block, lds, s>>>(a, t);
 }
 
 // Allow the tiled kernels the device's full LDS per workgroup.
 void set_tiled_lds_limit(size_t bytes) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(fe_edge_tiled_kernel<1>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipFuncSetAttribute(reinterpret_cast<const void *>(fe_edge_tiled_kernel<2>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *fns[] = {reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float>)};
+    for (const void *f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+
+template <typename R>
+void launch_bt_eval(const BTEvalArgs<R> &a, hipStream_t s) {
+    const int nEB = (a.m.E + 255) / 256, nCB = (a.m.C + 255) / 256;
+    const int per = (nEB + kXcd - 1) / kXcd + (nCB + kXcd - 1) / kXcd;
+    bt_eval_kernel<R><<<dim3(kXcd * per), 256, 0, s>>>(a, nEB, nCB);
+}
+
 void launch_thickness(const THArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_kernel, col_grid(a.m.C), a); }
-void launch_thickness_iso(const THIsoArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_iso_kernel, col_grid(a.m.C), a); }
-void launch_assemble(const AssembleArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, assemble_kernel, col_grid(a.m.E), a); }
+template <typename R>
+void launch_thickness_iso(const THIsoArgs<R> &a, hipStream_t s) {
+    SSE_DISPATCH_NK_R(a.L, thickness_iso_kernel, col_grid(a.m.C), a);
+}
+template <typename R>
+void launch_assemble(const AssembleArgs<R> &a, hipStream_t s) {
+    SSE_DISPATCH_NK_R(a.L, assemble_kernel, col_grid(a.m.E), a);
+}
 void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s) {
     SSE_DISPATCH_NK(L, zeta_kernel, col_grid(m.C), m, L, h, zeta);
 }
-void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const double *X, const double *uA, double *F,
+template <typename R>
+void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const R *X, const double *uA, double *F,
                           hipStream_t s) {
-    SSE_DISPATCH_NK(L, edge_flux_sum_kernel, col_grid(m.E), m, L, h, X, uA, F);
+    SSE_DISPATCH_NK_R(L, edge_flux_sum_kernel, col_grid(m.E), m, L, h, X, uA, F);
 }
-
-void launch_bt_eval(const BTEvalArgs &a, hipStream_t s) {
-    const int nEB = (a.m.E + 255) / 256, nCB = (a.m.C + 255) / 256;
-    const int per = (nEB + kXcd - 1) / kXcd + (nCB + kXcd - 1) / kXcd;
-    bt_eval_kernel<<<dim3(kXcd * per), 256, 0, s>>>(a, nEB, nCB);
-}
-
 void launch_recon(const ReconArgs &a, hipStream_t s) { recon_kernel<<<flat_grid(a.m.E), 256, 0, s>>>(a); }
 
-void launch_copy(const double *src, double *dst, size_t n, hipStream_t s) {
-    if (n) copy_kernel<<<flat_grid(n), 256, 0, s>>>(src, dst, n);
+template <typename Tin, typename Tout>
+void launch_convert(const Tin *src, Tout *dst, size_t n, hipStream_t s) {
+    if (n) convert_kernel<Tin, Tout><<<flat_grid(n), 256, 0, s>>>(src, dst, n);
 }
+
+#define SSE_INSTANTIATE(R)                                                                                   \
+    template void launch_fe_cell<R>(const FECellArgs<R> &, hipStream_t);                                   \
+    template void launch_fe_vertex<R>(const FEVertexArgs<R> &, hipStream_t);                               \
+    template void launch_fe_edge<R>(const FEEdgeArgs<R> &, hipStream_t);                                   \
+    template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
+    template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
+    template void launch_bt_eval<R>(const BTEvalArgs<R> &, hipStream_t);                                   \
+    template void launch_thickness_iso<R>(const THIsoArgs<R> &, hipStream_t);                              \
+    template void launch_assemble<R>(const AssembleArgs<R> &, hipStream_t);                                \
+    template void launch_edge_flux_sum<R>(const DevMesh &, int, const double *, const R *, const double *, \
+                                          double *, hipStream_t);
+SSE_INSTANTIATE(double)
+SSE_INSTANTIATE(float)
+template void launch_convert<double, double>(const double *, double *, size_t, hipStream_t);
+template void launch_convert<double, float>(const double *, float *, size_t, hipStream_t);
+template void launch_convert<float, double>(const float *, double *, size_t, hipStream_t);
 
 }  // namespace sse

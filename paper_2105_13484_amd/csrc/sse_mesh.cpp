@@ -115,18 +115,25 @@ int validate_desc(const sse_mesh_desc *d, std::string &err) {
     return SSE_OK;
 }
 
+void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
+    const size_t C = C_, E = E_, V = V_;
+    const size_t tab[kMeshTables] = {
+        C * 6 * 4, C * 6 * 4, C * 4, C * 6 * 8, C * 6 * 8,      // cell_edges, cell_nbrs, cell_nedges, cell_div, cell_ke
+        C * 6 * 4, C * 6 * 4, C * 6 * 8, C * 8, C,              // cell_edges_t, cell_nbrs_t, cell_div_t, H, cmask
+        E * 2 * 4, E * 2 * 4, E * 10 * 4, E * 4, E * 10 * 8,    // edge_cells, edge_verts, eoe, neoe, w
+        E * 10 * 8, E * 8, E * 8, E,                            // wf, dc, dv, emask
+        V * 3 * 4, V * 3 * 8,                                   // vert_edges, vert_curl
+        E * 10 * 8, E * 8, E * 8, E * 20 * 8,                   // eoe_v, inv_dc, inv_dv, wpair
+        E * 10 * 4, E * 4, C * 6 * 4, C * 4};                   // wf_f, inv_dc_f, cell_div_t_f, H_f
+    for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
+}
+
 MeshLayout mesh_layout(int C, int E, int V) {
     MeshLayout L;
-    size_t sizes[] = {
-        (size_t)C * 6 * 4, (size_t)C * 6 * 4, (size_t)C * 4, (size_t)C * 6 * 8, (size_t)C * 6 * 8,
-        (size_t)C * 6 * 4, (size_t)C * 6 * 4, (size_t)C * 6 * 8, (size_t)C * 8, (size_t)C,
-        (size_t)E * 2 * 4, (size_t)E * 2 * 4, (size_t)E * 10 * 4, (size_t)E * 4, (size_t)E * 10 * 8,
-        (size_t)E * 10 * 8, (size_t)E * 8, (size_t)E * 8, (size_t)E,
-        (size_t)V * 3 * 4, (size_t)V * 3 * 8,
-        (size_t)E * 10 * 8, (size_t)E * 8, (size_t)E * 8, (size_t)E * 20 * 8};
+    size_t sizes[kMeshTables];
+    mesh_table_sizes(C, E, V, sizes);
     size_t off = 0;
-    int n = sizeof(sizes) / sizeof(sizes[0]);
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < kMeshTables; ++i) {
         L.off[i] = off;
         off += (sizes[i] + kAlign - 1) / kAlign * kAlign;
     }
@@ -227,6 +234,14 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
             double r = (d->vertices_on_edge[2 * e + 1] == v) ? 1.0 : -1.0;
             t.vert_curl[v * 3 + j] = r * d->dc_edge[e] / d->area_triangle[v];
         }
+    auto to_f32 = [](const std::vector<double> &src, std::vector<float> &dst) {
+        dst.resize(src.size());
+        for (size_t i = 0; i < src.size(); ++i) dst[i] = (float)src[i];
+    };
+    to_f32(t.wf, t.wf_f);
+    to_f32(t.inv_dc, t.inv_dc_f);
+    to_f32(t.cell_div_t, t.cell_div_t_f);
+    to_f32(t.H, t.H_f);
 }
 
 bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t) {
