@@ -496,7 +496,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.cell_ke.data(), t.cell_edges_t.data(), t.cell_nbrs_t.data(), t.cell_div_t.data(),
                          t.H.data(), t.cmask.data(), t.edge_cells.data(), t.edge_verts.data(), t.eoe.data(),
                          t.neoe.data(), t.w.data(), t.wf.data(), t.dc.data(), t.dv.data(), t.emask.data(),
-                         t.vert_edges.data(), t.vert_curl.data(), t.eoe_v.data(), t.inv_dc.data(),
+                         t.vert_edges.data(), t.vert_curl.data(), t.erec.data(), t.inv_dc.data(),
                          t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
                          t.cell_div_t_f.data(), t.H_f.data()};
     static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
@@ -538,7 +538,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.emask = (const uint8_t *)P(18);
     dm.vert_edges = (const int32_t *)P(19);
     dm.vert_curl = (const double *)P(20);
-    dm.eoe_v = (const int2 *)P(21);
+    dm.erec = (const int32_t *)P(21);
     dm.inv_dc = (const double *)P(22);
     dm.inv_dv = (const double *)P(23);
     dm.wpair = (const double *)P(24);

@@ -14,6 +14,7 @@ namespace sse {
 
 constexpr int kMaxEdges = 6;    // edges per cell (hexagons / pentagons)
 constexpr int kMaxEdges2 = 10;  // edges in the tangential-reconstruction stencil
+constexpr int kEdgeRec = 32;    // int32 words of one per-edge record (128 bytes)
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kColsPerBlock = 4;
 constexpr int kXcd = 8;           // accelerator complex dies of an MI355X
@@ -42,7 +43,8 @@ struct DevMesh {
     const int32_t *edge_verts = nullptr;    // [E][2]
     const int32_t *eoe = nullptr;           // [10][E]
     const int32_t *neoe = nullptr;          // [E]
-    const int2 *eoe_v = nullptr;            // [10][E] (v1, v2) of each stencil edge
+    const int32_t *erec = nullptr;          // [E][32] per-edge record for the column kernels:
+                                            //   stencil edges [10], their vertices [10][2], cells [2]
     const double *w = nullptr;              // [10][E]  W_{e,j}
     const double *wf = nullptr;             // [10][E]  W_{e,j} (f_e + f_j) / 2
     const double *wpair = nullptr;          // [E][10][2] (W_{e,j}, W_{e,j} (f_e + f_j) / 2), entity-major
@@ -106,7 +108,7 @@ struct HostMeshTables {
     std::vector<int32_t> cell_edges, cell_nbrs, cell_nedges, cell_edges_t, cell_nbrs_t;
     std::vector<double> cell_div, cell_ke, cell_div_t, H;
     std::vector<uint8_t> cmask;
-    std::vector<int32_t> edge_cells, edge_verts, eoe, neoe, eoe_v;
+    std::vector<int32_t> edge_cells, edge_verts, eoe, neoe, erec;
     std::vector<double> w, wf, dc, dv, inv_dc, inv_dv, wpair;
     std::vector<uint8_t> emask;
     std::vector<int32_t> vert_edges;

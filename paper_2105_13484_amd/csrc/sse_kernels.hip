@@ -157,54 +157,68 @@ __device__ __forceinline__ T combine(int mode, T b, T x) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Baroclinic forward Euler (Algorithm 1): cell pass
-// ---------------------------------------------------------------------------
-template <int NK, typename R>
-__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
+// Lane k holds layer k (chunk c: layer k + 64 c).  Lanes past the last layer
+// load layer L - 1 (always in bounds) and zero what they loaded, so loads are
+// never predicated: no branches split the load stream and all loads of a
+// stencil can be in flight together.
+template <int NK>
+__device__ __forceinline__ void lane_layers(int L, int (&kk)[NK], bool (&ok)[NK]) {
     const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        ok[c] = k < L;
+        kk[c] = ok[c] ? k : L - 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Baroclinic forward Euler (Algorithm 1): cell pass.
+// kAdd: the velocity is X + ubar_add (ubar_add non-null), else X itself.
+// ---------------------------------------------------------------------------
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
     const DevMesh &m = a.m;
     const int i = column_id(m.C);
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
     if (!m.cmask[i]) {
 #pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
-            if (k < L) { a.B[base + k] = R(0); a.Wtop[base + k] = R(0); }
-        }
-        if (lane == 0) a.Kbot[i] = 0.0;
+        for (int c = 0; c < NK; ++c)
+            if (ok[c]) { a.B[base + kk[c]] = R(0); a.Wtop[base + kk[c]] = R(0); }
+        if (lane_id() == 0) a.Kbot[i] = 0.0;
         return;
     }
     double hi[NK];
     R divhu[NK], divu[NK], K[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        hi[c] = (k < L) ? a.h[base + k] : 0.0;
+        hi[c] = a.h[base + kk[c]];
         divhu[c] = divu[c] = K[c] = R(0);
     }
     // Padded slots hold a valid index with zero coefficients, so the stencil
-    // is unrolled to its full width and all its loads issue together.
+    // is unrolled to its full width.
 #pragma unroll
     for (int j = 0; j < kMaxEdges; ++j) {
         const int e = m.cell_edges[i * kMaxEdges + j];
         const int nb = m.cell_nbrs[i * kMaxEdges + j];
         const R cd = (R)m.cell_div[i * kMaxEdges + j];
         const R ck = (R)m.cell_ke[i * kMaxEdges + j];
-        const R add = a.ubar_add ? (R)a.ubar_add[e] : R(0);
+        const R add = kAdd ? (R)a.ubar_add[e] : R(0);
         const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
-            if (k < L) {
-                const R u = a.X[eb + k] + add;
-                const R he = (R)(0.5 * (hi[c] + a.h[nbb + k]));
-                divhu[c] += cd * (he * u);
-                divu[c] += cd * u;
-                K[c] += ck * (u * u);
-            }
+            const R x = a.X[eb + kk[c]];
+            const double hn = a.h[nbb + kk[c]];
+            const R u = ok[c] ? x + add : R(0);
+            const R he = (R)(0.5 * (hi[c] + hn));
+            divhu[c] += cd * (he * u);
+            divu[c] += cd * u;
+            K[c] += ck * (u * u);
         }
     }
     R w[NK];
@@ -214,9 +228,8 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
         R src[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
-            const R th = (k < L) ? -(R)a.frac[base + k] * tot : R(0);
-            src[c] = (k < L) ? (-divhu[c] - th) : R(0);
+            const R th = -(R)a.frac[base + kk[c]] * tot;
+            src[c] = ok[c] ? (-divhu[c] - th) : R(0);
         }
         col_incl_suffix<NK>(src, w);
     } else {
@@ -225,25 +238,26 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
     }
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        if (k < L) {
-            a.B[base + k] = K[c] - (R)a.nu_h * divu[c];
-            a.Wtop[base + k] = w[c];
-            if (k == L - 1) a.Kbot[i] = (double)K[c];
+        if (ok[c]) {
+            a.B[base + kk[c]] = K[c] - (R)a.nu_h * divu[c];
+            a.Wtop[base + kk[c]] = w[c];
+            if (kk[c] == L - 1) a.Kbot[i] = (double)K[c];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Baroclinic forward Euler: vertex pass (relative vorticity)
+// Baroclinic forward Euler: vertex pass (relative vorticity of X + ubar_add)
 // ---------------------------------------------------------------------------
-template <int NK, typename R>
+template <int NK, typename R, bool kAdd>
 __global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs<R> a) {
-    const int lane = lane_id();
     const DevMesh &m = a.m;
     const int v = column_id(m.V);
     if (v >= m.V) return;
     const int L = a.L;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
     R z[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) z[c] = R(0);
@@ -251,19 +265,14 @@ __global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs<R> a) {
     for (int j = 0; j < 3; ++j) {
         const int e = m.vert_edges[v * 3 + j];
         const R cr = (R)m.vert_curl[v * 3 + j];
-        const R add = a.ubar_add ? (R)a.ubar_add[e] : R(0);
+        const R add = kAdd ? (R)a.ubar_add[e] : R(0);
         const size_t eb = (size_t)e * L;
 #pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            int k = lane + c * kWave;
-            if (k < L) z[c] += cr * (a.X[eb + k] + add);
-        }
+        for (int c = 0; c < NK; ++c) z[c] += cr * (a.X[eb + kk[c]] + add);
     }
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        if (k < L) a.Z[(size_t)v * L + k] = z[c];
-    }
+    for (int c = 0; c < NK; ++c)
+        if (ok[c]) a.Z[(size_t)v * L + kk[c]] = z[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -412,9 +421,8 @@ __device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
     }
 }
 
-template <int NK, typename R>
+template <int NK, typename R, bool kAdd>
 __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
-    const int lane = lane_id();
     const DevMesh &m = a.m;
     const int E = m.E;
     const int e = column_id(E);
@@ -425,11 +433,16 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
         fe_edge_dry<NK, R>(a, e);
         return;
     }
-    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    // u = X + ubar (kAdd) or ut = X - ubar (otherwise); the other one equals X.
+    const double *ubar = kAdd ? a.ubar_add : a.ubar_sub;
+    const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
+    const int c1 = rec[30], c2 = rec[31];
     const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
     const double idc = m.inv_dc[e], idv = m.inv_dv[e];
-    const R add_e = a.ubar_add ? (R)a.ubar_add[e] : R(0);
-    const R sub_e = a.ubar_sub ? (R)a.ubar_sub[e] : R(0);
+    const R ub_e = (R)ubar[e];
     const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
     const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
 
@@ -437,21 +450,23 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
     R q[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        const bool ok = k < L;
-        const R x = ok ? a.X[base + k] : R(0);
-        o.u[c] = ok ? x + add_e : R(0);
-        o.ut[c] = ok ? x - sub_e : R(0);
-        o.h1[c] = ok ? a.h[b1 + k] : 0.0;
-        o.h2[c] = ok ? a.h[b2 + k] : 0.0;
-        o.r1[c] = ok ? a.rho[b1 + k] : 0.0;
-        o.r2[c] = ok ? a.rho[b2 + k] : 0.0;
-        o.za[c] = ok ? a.Z[bv1 + k] : R(0);
-        o.zb[c] = ok ? a.Z[bv2 + k] : R(0);
-        o.B1[c] = ok ? a.B[b1 + k] : R(0);
-        o.B2[c] = ok ? a.B[b2 + k] : R(0);
-        o.W1[c] = ok ? a.Wtop[b1 + k] : R(0);
-        o.W2[c] = ok ? a.Wtop[b2 + k] : R(0);
+        const int k = kk[c];
+        const R x = a.X[base + k];
+        const double h1 = a.h[b1 + k], h2 = a.h[b2 + k], r1 = a.rho[b1 + k], r2 = a.rho[b2 + k];
+        const R za = a.Z[bv1 + k], zb = a.Z[bv2 + k];
+        const R B1 = a.B[b1 + k], B2 = a.B[b2 + k], W1 = a.Wtop[b1 + k], W2 = a.Wtop[b2 + k];
+        o.u[c] = ok[c] ? (kAdd ? x + ub_e : x) : R(0);
+        o.ut[c] = ok[c] ? (kAdd ? x : x - ub_e) : R(0);
+        o.h1[c] = ok[c] ? h1 : 0.0;
+        o.h2[c] = ok[c] ? h2 : 0.0;
+        o.r1[c] = ok[c] ? r1 : 0.0;
+        o.r2[c] = ok[c] ? r2 : 0.0;
+        o.za[c] = ok[c] ? za : R(0);
+        o.zb[c] = ok[c] ? zb : R(0);
+        o.B1[c] = ok[c] ? B1 : R(0);
+        o.B2[c] = ok[c] ? B2 : R(0);
+        o.W1[c] = ok[c] ? W1 : R(0);
+        o.W2[c] = ok[c] ? W2 : R(0);
         q[c] = R(0.5) * (o.za[c] + o.zb[c]);
         o.cor[c] = o.vor[c] = R(0);
     }
@@ -459,27 +474,21 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
     // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
     // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
     // stencil slots point at the edge itself with zero weights, so the loop
-    // runs its full width and its loads issue together.
+    // runs its full width; its 30 column loads carry no branch between them.
     const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
     for (int j = 0; j < kMaxEdges2; ++j) {
-        const size_t js = (size_t)j * E + e;
-        const int ep = m.eoe[js];
-        const int2 pv = m.eoe_v[js];
+        const int ep = rec[j], pv1 = rec[10 + 2 * j], pv2 = rec[11 + 2 * j];
         const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
-        const R padd = a.ubar_add ? (R)a.ubar_add[ep] : R(0);
-        const R psub = a.ubar_sub ? (R)a.ubar_sub[ep] : R(0);
-        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv.x * L, pb2 = (size_t)pv.y * L;
+        const R ubp = (R)ubar[ep];
+        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv1 * L, pb2 = (size_t)pv2 * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const int k = lane + c * kWave;
-            if (k < L) {
-                const R xp = a.X[pb + k];
-                const R up = xp + padd, utp = xp - psub;
-                const R qp = R(0.5) * (a.Z[pb1 + k] + a.Z[pb2 + k]);
-                o.cor[c] += wfj * utp;
-                o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
-            }
+            const R xp = a.X[pb + kk[c]];
+            const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
+            const R qp = R(0.5) * (a.Z[pb1 + kk[c]] + a.Z[pb2 + kk[c]]);
+            o.cor[c] += wfj * utp;
+            o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
         }
     }
     fe_edge_finish<NK, R>(a, e, c1, c2, idc, idv, o);
@@ -923,17 +932,32 @@ static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n 
             KERNEL<2, R><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);        \
     } while (0)
 
+// The column kernels are instantiated for one or two register chunks
+// (L <= 64 or L <= 128) and for the two velocity forms: u = X + ubar
+// (ubar_add non-null) or u = X (the edge pass then forms ut = X - ubar_sub;
+// exactly one of ubar_add and ubar_sub is non-null there).
+#define SSE_DISPATCH_NK_ADD(L, ADD, KERNEL, GRID, ...)                             \
+    do {                                                                          \
+        if ((L) <= kWave) {                                                       \
+            if (ADD) KERNEL<1, R, true><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);     \
+            else KERNEL<1, R, false><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);       \
+        } else {                                                                  \
+            if (ADD) KERNEL<2, R, true><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);     \
+            else KERNEL<2, R, false><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);       \
+        }                                                                         \
+    } while (0)
+
 template <typename R>
 void launch_fe_cell(const FECellArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_R(a.L, fe_cell_kernel, col_grid(a.m.C), a);
+    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_cell_kernel, col_grid(a.m.C), a);
 }
 template <typename R>
 void launch_fe_vertex(const FEVertexArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_R(a.L, fe_vertex_kernel, col_grid(a.m.V), a);
+    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_vertex_kernel, col_grid(a.m.V), a);
 }
 template <typename R>
 void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_R(a.L, fe_edge_kernel, col_grid(a.m.E), a);
+    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_edge_kernel, col_grid(a.m.E), a);
 }
 
 template <typename R>

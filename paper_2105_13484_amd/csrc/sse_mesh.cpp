@@ -123,7 +123,7 @@ void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
         E * 2 * 4, E * 2 * 4, E * 10 * 4, E * 4, E * 10 * 8,    // edge_cells, edge_verts, eoe, neoe, w
         E * 10 * 8, E * 8, E * 8, E,                            // wf, dc, dv, emask
         V * 3 * 4, V * 3 * 8,                                   // vert_edges, vert_curl
-        E * 10 * 8, E * 8, E * 8, E * 20 * 8,                   // eoe_v, inv_dc, inv_dv, wpair
+        E * 32 * 4, E * 8, E * 8, E * 20 * 8,                   // erec, inv_dc, inv_dv, wpair
         E * 10 * 4, E * 4, C * 6 * 4, C * 4};                   // wf_f, inv_dc_f, cell_div_t_f, H_f
     for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
 }
@@ -214,17 +214,21 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
             t.wpair[(size_t)e * 20 + 2 * j] = t.w[(size_t)j * E + e];
             t.wpair[(size_t)e * 20 + 2 * j + 1] = t.wf[(size_t)j * E + e];
         }
-    t.eoe_v.assign((size_t)E * 10 * 2, 0);
+    t.erec.assign((size_t)E * kEdgeRec, 0);
     t.inv_dc.assign(E, 0.0);
     t.inv_dv.assign(E, 0.0);
     for (int e = 0; e < E; ++e) {
         t.inv_dc[e] = 1.0 / d->dc_edge[e];
         t.inv_dv[e] = 1.0 / d->dv_edge[e];
+        int32_t *r = &t.erec[(size_t)e * kEdgeRec];
         for (int j = 0; j < 10; ++j) {
-            int ep = t.eoe[(size_t)j * E + e];
-            t.eoe_v[((size_t)j * E + e) * 2] = d->vertices_on_edge[2 * ep];
-            t.eoe_v[((size_t)j * E + e) * 2 + 1] = d->vertices_on_edge[2 * ep + 1];
+            const int ep = t.eoe[(size_t)j * E + e];
+            r[j] = ep;
+            r[10 + 2 * j] = d->vertices_on_edge[2 * ep];
+            r[11 + 2 * j] = d->vertices_on_edge[2 * ep + 1];
         }
+        r[30] = d->cells_on_edge[2 * e];
+        r[31] = d->cells_on_edge[2 * e + 1];
     }
     t.vert_edges.assign(d->edges_on_vertex, d->edges_on_vertex + 3 * (size_t)V);
     t.vert_curl.assign((size_t)V * 3, 0.0);
