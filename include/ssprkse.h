@@ -176,6 +176,17 @@ enum { SSE_PROF_FE_EDGE = 0, SSE_PROF_FE_CELL = 1, SSE_PROF_FE_VERTEX = 2,
 int sse_profile_enable(sse_state *s, int class_mask);
 int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
 
+/* Kernel variant of the baroclinic edge pass (results are identical up to
+ * the order of FP64 rounding in no operation: every variant performs the same
+ * arithmetic on the same operands).  variant -1: direct gathers from global
+ * memory; 0, 1, 2: the operands of tiles of 8, 16 or 32 consecutive edges are
+ * first staged in LDS.  SSE_EINVAL if the variant is unknown or does not fit
+ * this mesh (a tile list longer than 255 columns) or the device's LDS for the
+ * state's layer count and precision.  The default is -1.  Applies to
+ * subsequent steps; the autotuner in the Python package calls it. */
+int sse_state_set_edge_variant(sse_state *s, int variant);
+int sse_state_get_edge_variant(const sse_state *s, int *variant);
+
 /*
  * Per-kernel debug entry points (host arrays, caller numbering).  They use
  * the state's stage buffers as scratch and leave its prognostic fields

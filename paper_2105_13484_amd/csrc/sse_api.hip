@@ -122,7 +122,8 @@ struct sse_state {
     size_t rs = 8;           // bytes of the real type R
     bool initialized = false;
     // profiling
-    int edge_variant = -1;   // -1: direct gathers; 0 / 1: LDS tiles of 8 / 16 edges
+    int edge_variant = -1;   // -1: direct gathers; 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
+    size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
     bool prof = false;
     int prof_mask = 0;
     std::vector<hipEvent_t> events;
@@ -485,7 +486,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     int rc = validate_desc(d, err);
     if (rc != SSE_OK) { set_error(err); return rc; }
     MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
-    const size_t need = lay.total + tiles_bytes(d, 8) + tiles_bytes(d, 16);
+    size_t need = lay.total;
+    for (int q = 0; q < kTileVariants; ++q) need += tiles_bytes(d, kTileSizes[q]);
     if (!dev_buf || bytes < need) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
     HostMeshTables t;
@@ -547,13 +549,12 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.cell_div_t_f = (const float *)P(27);
     dm.H_f = (const float *)P(28);
     m->cells_on_edge = t.edge_cells;
-    // Gather lists of the LDS-staged edge pass for tiles of 8 and 16 edges.
+    // Gather lists of the LDS-staged edge pass for tiles of 8, 16 and 32 edges.
     size_t cursor = lay.total;
-    const int Ts[2] = {8, 16};
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < kTileVariants; ++q) {
         HostTiles ht;
         DevTiles &dt = m->tiles[q];
-        if (!build_tiles(d, Ts[q], ht)) { dt.T = 0; continue; }
+        if (!build_tiles(d, kTileSizes[q], ht)) { dt.T = 0; continue; }
         auto put = [&](const void *src, size_t n) -> const void * {
             char *dst = base + cursor;
             if (n) hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
@@ -612,25 +613,31 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->rs = rs;
     s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs);
     s->bytes = bytes;
-    // Edge-pass variant.  Measured on an MI355X at 512x512 cells x 60 layers
-    // (FP64), the direct-gather kernel beats both LDS tilings: at 480 bytes
-    // per column the tiles stay small, their halos triple the staged data,
-    // and the staging runs at L2 speed.  The tiled forms stay selectable
-    // (SSE_EDGE_VARIANT = 0 / 1) for meshes or precisions where they win.
     int dev = 0, lds_max = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_max = 65536;
     set_tiled_lds_limit((size_t)lds_max);
+    s->lds_max = (size_t)lds_max;
     s->edge_variant = -1;
-    if (const char *ev = std::getenv("SSE_EDGE_VARIANT")) {
-        const int v = std::atoi(ev);
-        if (v == 0 || v == 1) {
-            const size_t lds = rs == 4 ? fe_edge_tiled_lds<float>(m->tiles[v], p->n_layers)
-                                       : fe_edge_tiled_lds<double>(m->tiles[v], p->n_layers);
-            if (m->tiles[v].T && lds <= (size_t)lds_max) s->edge_variant = v;
-        }
-    }
     *out = s;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_set_edge_variant(sse_state *s, int variant) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    if (variant == -1) { s->edge_variant = -1; return SSE_OK; }
+    if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -1, 0, 1 or 2"); return SSE_EINVAL; }
+    const DevTiles &t = s->mesh->tiles[variant];
+    if (!t.T) { set_error("edge variant: a tile of this mesh lists more than 255 columns"); return SSE_EINVAL; }
+    const size_t lds = s->rs == 4 ? fe_edge_tiled_lds<float>(t, s->p.n_layers) : fe_edge_tiled_lds<double>(t, s->p.n_layers);
+    if (lds > s->lds_max) { set_error("edge variant: the tile does not fit the device's LDS"); return SSE_EINVAL; }
+    s->edge_variant = variant;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_get_edge_variant(const sse_state *s, int *variant) {
+    if (!s || !variant) { set_error("NULL argument"); return SSE_EINVAL; }
+    *variant = s->edge_variant;
     return SSE_OK;
 }
 

@@ -68,6 +68,8 @@ struct DevMesh {
 // (the tiles' edges and their reconstruction stencils), vertex columns and
 // cell columns it reads are listed once, and every edge stores the 8-bit
 // positions of its operands in those lists.
+constexpr int kTileVariants = 3;
+constexpr int kTileSizes[kTileVariants] = {8, 16, 32};
 constexpr int kLocPerEdge = 36;  // self, c1, c2, v1, v2, stencil[10], stencil vertices[10][2], pad
 struct DevTiles {
     int T = 0, nT = 0;
@@ -84,7 +86,7 @@ struct sse_mesh {
     int C = 0, E = 0, V = 0;
     int n_ocean_cells = 0;
     std::vector<int32_t> cells_on_edge;     // host copy (for debug helpers)
-    sse::DevTiles tiles[2];                 // T = 8 and T = 16
+    sse::DevTiles tiles[sse::kTileVariants];  // T = 8, 16, 32 edges per tile
     void *dev_buf = nullptr;
     size_t dev_bytes = 0;
 };

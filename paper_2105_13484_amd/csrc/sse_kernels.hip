@@ -501,119 +501,218 @@ __global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
 // copies every column the tile reads (stencil edges, their vertices, the
 // edges' cells for h, rho, K - nu div u and w) from global memory into LDS,
 // each column exactly once, then each wavefront evaluates its edge from LDS.
-// On the hexagonal mesh this cuts the column gathers per edge from ~42 to
-// ~12 (T = 8) or ~10 (T = 16).
+// The copy uses 16-byte loads, so one load instruction moves two FP64 (four
+// FP32) layers per lane and several columns per wavefront; the vector-memory
+// address path, which bounds the direct-gather kernel, then handles about a
+// quarter of the instructions.
 // ---------------------------------------------------------------------------
-template <int NK, typename R>
-__global__ void __launch_bounds__(1024) fe_edge_tiled_kernel(FEEdgeArgs<R> a, DevTiles t) {
-    extern __shared__ double lds_d[];
+
+constexpr int kTileWaves = 8;  // wavefronts per workgroup of the tiled edge pass
+
+// One list of columns to stage: column i of the list is the global column
+// src + ids[i] L and goes to dst + i L in LDS.
+template <typename T>
+struct StageSeg {
+    const T *src;
+    const int32_t *ids;
+    int n;
+    T *dst;
+};
+
+// Copy the columns of NS lists (L values of type T each) into LDS with
+// 16-byte loads.  The lists are walked as one: every lane group takes up to
+// 8 columns, loads their ids, then their data, then stores them, so one
+// wavefront has 8 column loads in flight and the whole copy costs two
+// memory round trips.
+template <typename T, int NS>
+__device__ __forceinline__ void stage_columns(const StageSeg<T> (&seg)[NS], int L) {
+    constexpr int V = 16 / sizeof(T);
+    constexpr int B = 8;
+    int start[NS + 1];
+    start[0] = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) start[q + 1] = start[q] + seg[q].n;
+    const int total = start[NS];
+    if (total == 0) return;
+    const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (L % V == 0 && L <= V * kWave) {
+        const int lpc = L / V, cpw = kWave / lpc;  // lanes per column, columns per wavefront
+        const int slot = lane / lpc, part = lane - slot * lpc;
+        const bool lane_on = slot < cpw;
+        const int step = nw * cpw;
+        for (int c0 = wv * cpw + slot; c0 < total + (B - 1) * step; c0 += B * step) {
+            int seg_of[B], pos[B], id[B];
+            bool on[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int c = c0 + u * step;
+                on[u] = lane_on && c < total;
+                const int cs = c < total ? c : total - 1;
+                int q = 0, p0 = cs;
+#pragma unroll
+                for (int r = 1; r < NS; ++r) {
+                    if (cs >= start[r]) {
+                        q = r;
+                        p0 = cs - start[r];
+                    }
+                }
+                seg_of[u] = q;
+                pos[u] = p0;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int32_t *ids = seg[0].ids;
+#pragma unroll
+                for (int r = 1; r < NS; ++r) ids = seg_of[u] == r ? seg[r].ids : ids;
+                id[u] = ids[pos[u]];
+            }
+            uint4 v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const T *src = seg[0].src;
+#pragma unroll
+                for (int r = 1; r < NS; ++r) src = seg_of[u] == r ? seg[r].src : src;
+                v[u] = *reinterpret_cast<const uint4 *>(src + (size_t)id[u] * L + part * V);
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                T *dst = seg[0].dst;
+#pragma unroll
+                for (int r = 1; r < NS; ++r) dst = seg_of[u] == r ? seg[r].dst : dst;
+                if (on[u]) *reinterpret_cast<uint4 *>(dst + (size_t)pos[u] * L + part * V) = v[u];
+            }
+        }
+    } else {
+        // Local arrays are indexed with compile-time indices only (select
+        // chains), so that they stay in registers.
+        for (int c = wv; c < total; c += nw) {
+            int i = c;
+            const int32_t *ids = seg[0].ids;
+            const T *src = seg[0].src;
+            T *dst = seg[0].dst;
+#pragma unroll
+            for (int r = 1; r < NS; ++r) {
+                if (c >= start[r]) {
+                    i = c - start[r];
+                    ids = seg[r].ids;
+                    src = seg[r].src;
+                    dst = seg[r].dst;
+                }
+            }
+            const T *col = src + (size_t)ids[i] * L;
+            for (int k = lane; k < L; k += kWave) dst[(size_t)i * L + k] = col[k];
+        }
+    }
+}
+
+template <typename R>
+size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
+    const size_t nd = (size_t)2 * t.max_uc * L;                              // h, rho (FP64)
+    const size_t nr = (size_t)(t.max_ue + t.max_uv + 2 * t.max_uc) * L;      // X, Z, B, w (type R)
+    return nd * sizeof(double) + nr * sizeof(R);
+}
+
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdgeArgs<R> a, DevTiles t) {
+    extern __shared__ __align__(16) double lds_d[];
     const DevMesh &m = a.m;
     const int tile = xcd_block(t.nT);
     if (tile < 0) return;
     const int T = t.T, L = a.L, E = m.E;
-    const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ue0 = t.ue_off[tile], nue = t.ue_off[tile + 1] - ue0;
     const int uv0 = t.uv_off[tile], nuv = t.uv_off[tile + 1] - uv0;
     const int uc0 = t.uc_off[tile], nuc = t.uc_off[tile + 1] - uc0;
-    // LDS: h | rho | ubar (FP64), then X | Z | B | w (type R)
+    // LDS: h | rho (FP64) | X | Z | B | w (type R).  With L even every column
+    // starts on a 16-byte boundary, as the 16-byte copies need.
     double *sH = lds_d;
     double *sR = sH + (size_t)nuc * L;
-    double *sU = sR + (size_t)nuc * L;
-    R *sX = reinterpret_cast<R *>(sU + nue);
+    R *sX = reinterpret_cast<R *>(sR + (size_t)nuc * L);
     R *sZ = sX + (size_t)nue * L;
     R *sB = sZ + (size_t)nuv * L;
     R *sW = sB + (size_t)nuc * L;
-    const double *ubar_src = a.ubar_add ? a.ubar_add : a.ubar_sub;
-
-    // Stage every listed column once.  The (column, layer) elements are
-    // spread over all threads of the workgroup so that the list reads and the
-    // column reads of one thread are independent of each other.
-    {
-        const int nh = 2 * nuc * L;
-        for (int i = threadIdx.x; i < nh; i += blockDim.x) {
-            const int col = i / L, k = i - col * L;
-            const double *src = col < nuc ? a.h : a.rho;
-            sH[i] = src[(size_t)t.uc[uc0 + (col < nuc ? col : col - nuc)] * L + k];
-        }
-        const int nelem = (nue + nuv + 2 * nuc) * L;
-        for (int i = threadIdx.x; i < nelem; i += blockDim.x) {
-            const int col = i / L, k = i - col * L;
-            const R *src;
-            if (col < nue) {
-                src = a.X + (size_t)t.ue[ue0 + col] * L;
-            } else if (col < nue + nuv) {
-                src = a.Z + (size_t)t.uv[uv0 + (col - nue)] * L;
-            } else {
-                const int r = col - nue - nuv, arr = r / nuc, q = r - arr * nuc;
-                src = (arr == 0 ? a.B : a.Wtop) + (size_t)t.uc[uc0 + q] * L;
-            }
-            sX[i] = src[k];
-        }
-        for (int i = threadIdx.x; i < nue; i += blockDim.x) sU[i] = ubar_src ? ubar_src[t.ue[ue0 + i]] : 0.0;
+    const double *ubar = kAdd ? a.ubar_add : a.ubar_sub;
+    const int32_t *lc = t.uc + uc0, *le = t.ue + ue0, *lv = t.uv + uv0;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        const StageSeg<R> seg[6] = {{reinterpret_cast<const R *>(a.h), lc, nuc, reinterpret_cast<R *>(sH)},
+                                    {reinterpret_cast<const R *>(a.rho), lc, nuc, reinterpret_cast<R *>(sR)},
+                                    {a.X, le, nue, sX},
+                                    {a.Z, lv, nuv, sZ},
+                                    {a.B, lc, nuc, sB},
+                                    {a.Wtop, lc, nuc, sW}};
+        stage_columns<R, 6>(seg, L);
+    } else {
+        const StageSeg<double> segd[2] = {{a.h, lc, nuc, sH}, {a.rho, lc, nuc, sR}};
+        const StageSeg<R> segr[4] = {{a.X, le, nue, sX}, {a.Z, lv, nuv, sZ}, {a.B, lc, nuc, sB}, {a.Wtop, lc, nuc, sW}};
+        stage_columns<double, 2>(segd, L);
+        stage_columns<R, 4>(segr, L);
     }
     __syncthreads();
 
-    const int e = tile * T + wv;
-    if (e >= E) return;
-    if (!m.emask[e]) {
-        fe_edge_dry<NK, R>(a, e);
-        return;
-    }
-    // 8-bit positions of this edge's operands in the staged lists.
-    const uint32_t *lw = reinterpret_cast<const uint32_t *>(t.loc + (size_t)e * kLocPerEdge);
-    uint32_t word[kLocPerEdge / 4];
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    // A workgroup has at most kTileWaves wavefronts (a 256-register budget per
+    // lane, no spills); with larger tiles each wavefront evaluates several edges.
+    const int nw = blockDim.x >> 6;
+    for (int el = wv; el < T; el += nw) {
+        const int e = tile * T + el;
+        if (e >= E) break;
+        if (!m.emask[e]) {
+            fe_edge_dry<NK, R>(a, e);
+            continue;
+        }
+        // 8-bit positions of this edge's operands in the staged lists.
+        const uint32_t *lw = reinterpret_cast<const uint32_t *>(t.loc + (size_t)e * kLocPerEdge);
+        uint32_t word[kLocPerEdge / 4];
 #pragma unroll
-    for (int qq = 0; qq < kLocPerEdge / 4; ++qq) word[qq] = lw[qq];
-    auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
-    const int ls = locb(0), lc1 = locb(1), lc2 = locb(2), lv1 = locb(3), lv2 = locb(4);
-    const bool is_add = a.ubar_add != nullptr, is_sub = a.ubar_sub != nullptr;
-    const R add_e = is_add ? (R)sU[ls] : R(0), sub_e = is_sub ? (R)sU[ls] : R(0);
-    const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
-    const double idc = m.inv_dc[e], idv = m.inv_dv[e];
+        for (int qq = 0; qq < kLocPerEdge / 4; ++qq) word[qq] = lw[qq];
+        auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
+        const int ls = locb(0), lc1 = locb(1), lc2 = locb(2), lv1 = locb(3), lv2 = locb(4);
+        const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
+        const R ub_e = (R)ubar[e];
+        const int c1 = rec[30], c2 = rec[31];
+        const double idcv = m.inv_dc[e], idvv = m.inv_dv[e];
 
-    EdgeOperands<NK, R> o;
-    R q[NK];
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        const int k = lane + c * kWave;
-        const bool ok = k < L;
-        const R x = ok ? sX[(size_t)ls * L + k] : R(0);
-        o.u[c] = ok ? x + add_e : R(0);
-        o.ut[c] = ok ? x - sub_e : R(0);
-        o.h1[c] = ok ? sH[(size_t)lc1 * L + k] : 0.0;
-        o.h2[c] = ok ? sH[(size_t)lc2 * L + k] : 0.0;
-        o.r1[c] = ok ? sR[(size_t)lc1 * L + k] : 0.0;
-        o.r2[c] = ok ? sR[(size_t)lc2 * L + k] : 0.0;
-        o.za[c] = ok ? sZ[(size_t)lv1 * L + k] : R(0);
-        o.zb[c] = ok ? sZ[(size_t)lv2 * L + k] : R(0);
-        o.B1[c] = ok ? sB[(size_t)lc1 * L + k] : R(0);
-        o.B2[c] = ok ? sB[(size_t)lc2 * L + k] : R(0);
-        o.W1[c] = ok ? sW[(size_t)lc1 * L + k] : R(0);
-        o.W2[c] = ok ? sW[(size_t)lc2 * L + k] : R(0);
-        q[c] = R(0.5) * (o.za[c] + o.zb[c]);
-        o.cor[c] = o.vor[c] = R(0);
-    }
-    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
-#pragma unroll
-    for (int j = 0; j < kMaxEdges2; ++j) {
-        const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
-        const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
-        const R pu = (R)sU[sl];
-        const R padd = is_add ? pu : R(0), psub = is_sub ? pu : R(0);
+        EdgeOperands<NK, R> o;
+        R q[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const int k = lane + c * kWave;
-            if (k < L) {
+            const int k = kk[c];
+            const R x = sX[(size_t)ls * L + k];
+            o.u[c] = ok[c] ? (kAdd ? x + ub_e : x) : R(0);
+            o.ut[c] = ok[c] ? (kAdd ? x : x - ub_e) : R(0);
+            o.h1[c] = ok[c] ? sH[(size_t)lc1 * L + k] : 0.0;
+            o.h2[c] = ok[c] ? sH[(size_t)lc2 * L + k] : 0.0;
+            o.r1[c] = ok[c] ? sR[(size_t)lc1 * L + k] : 0.0;
+            o.r2[c] = ok[c] ? sR[(size_t)lc2 * L + k] : 0.0;
+            o.za[c] = ok[c] ? sZ[(size_t)lv1 * L + k] : R(0);
+            o.zb[c] = ok[c] ? sZ[(size_t)lv2 * L + k] : R(0);
+            o.B1[c] = ok[c] ? sB[(size_t)lc1 * L + k] : R(0);
+            o.B2[c] = ok[c] ? sB[(size_t)lc2 * L + k] : R(0);
+            o.W1[c] = ok[c] ? sW[(size_t)lc1 * L + k] : R(0);
+            o.W2[c] = ok[c] ? sW[(size_t)lc2 * L + k] : R(0);
+            q[c] = R(0.5) * (o.za[c] + o.zb[c]);
+            o.cor[c] = o.vor[c] = R(0);
+        }
+        const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+#pragma unroll
+        for (int j = 0; j < kMaxEdges2; ++j) {
+            const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
+            const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
+            const R ubp = (R)ubar[rec[j]];
+#pragma unroll
+            for (int c = 0; c < NK; ++c) {
+                const int k = kk[c];
                 const R xp = sX[(size_t)sl * L + k];
-                const R up = xp + padd, utp = xp - psub;
+                const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
                 const R qp = R(0.5) * (sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k]);
                 o.cor[c] += wfj * utp;
                 o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
             }
         }
+        fe_edge_finish<NK, R>(a, e, c1, c2, idcv, idvv, o);
     }
-    fe_edge_finish<NK, R>(a, e, c1, c2, idc, idv, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -961,28 +1060,30 @@ void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s) {
 }
 
 template <typename R>
-size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
-    return ((size_t)2 * t.max_uc * L + t.max_ue) * sizeof(double) +
-           (size_t)(t.max_ue + t.max_uv + 2 * t.max_uc) * L * sizeof(R);
-}
-
-template <typename R>
 void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s) {
     const size_t lds = fe_edge_tiled_lds<R>(t, a.L);
-    const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block(t.T * kWave);
-    if (a.L <= kWave)
-        fe_edge_tiled_kernel<1, R><<<grid, block, lds, s>>>(a, t);
-    else
-        fe_edge_tiled_kernel<2, R><<<grid, block, lds, s>>>(a, t);
+    const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block((t.T < kTileWaves ? t.T : kTileWaves) * kWave);
+    const bool add = a.ubar_add != nullptr;
+    if (a.L <= kWave) {
+        if (add) fe_edge_tiled_kernel<1, R, true><<<grid, block, lds, s>>>(a, t);
+        else fe_edge_tiled_kernel<1, R, false><<<grid, block, lds, s>>>(a, t);
+    } else {
+        if (add) fe_edge_tiled_kernel<2, R, true><<<grid, block, lds, s>>>(a, t);
+        else fe_edge_tiled_kernel<2, R, false><<<grid, block, lds, s>>>(a, t);
+    }
 }
 
 // Allow the tiled kernels the device's full LDS per workgroup.
 void set_tiled_lds_limit(size_t bytes) {
-    const void *fns[] = {reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float>)};
-    for (const void *f : fns) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *fns[] = {reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double, true>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double, false>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double, true>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double, false>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float, true>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float, false>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float, true>),
+                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float, false>)};
+    for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 template <typename R>

@@ -321,7 +321,7 @@ extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
 extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
     if (!d || !bytes) { sse::set_error("NULL argument"); return SSE_EINVAL; }
     if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { sse::set_error("mesh counts must be positive"); return SSE_EINVAL; }
-    *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total + sse::tiles_bytes(d, 8) +
-             sse::tiles_bytes(d, 16);
+    *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
+    for (int q = 0; q < sse::kTileVariants; ++q) *bytes += sse::tiles_bytes(d, sse::kTileSizes[q]);
     return SSE_OK;
 }

@@ -27,7 +27,11 @@ EXPORTED = (
     "sse_mesh_destroy", "sse_state_workspace_bytes", "sse_state_create", "sse_state_destroy", "sse_state_init",
     "sse_step", "sse_step_async", "sse_sync", "sse_read_state", "sse_profile_enable", "sse_profile_read",
     "sse_debug_baroclinic_feuler", "sse_debug_barotropic_substep", "sse_debug_thickness_stage",
+    "sse_state_set_edge_variant", "sse_state_get_edge_variant",
 )
+
+# Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
+EDGE_VARIANTS = (-1, 0, 1, 2)
 
 
 class SSEError(RuntimeError):
@@ -93,6 +97,8 @@ def load():
         "sse_debug_baroclinic_feuler": (c_int, [P, dp, dp, dp, dp, c_double, dp, dp]),
         "sse_debug_barotropic_substep": (c_int, [P, c_int32, c_int32, c_double, dp, dp, dp, dp, dp, dp]),
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
+        "sse_state_set_edge_variant": (c_int, [P, c_int]),
+        "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +256,21 @@ class DeviceState:
         for c in classes:
             mask |= 1 << PROF_CLASSES.index(c)
         _check(load().sse_profile_enable(self.handle, mask))
+
+    @property
+    def edge_variant(self) -> int:
+        v = c_int(0)
+        _check(load().sse_state_get_edge_variant(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    @edge_variant.setter
+    def edge_variant(self, variant: int):
+        _check(load().sse_state_set_edge_variant(self.handle, int(variant)))
+
+    def try_edge_variant(self, variant: int) -> bool:
+        """Select an edge-pass variant; False (and no change) if it does not fit."""
+        rc = load().sse_state_set_edge_variant(self.handle, int(variant))
+        return rc == 0
 
     def profile_read(self):
         n = (c_int32 * len(PROF_CLASSES))()

@@ -276,3 +276,39 @@ def test_nonfinite_input_rejected(dev):
     with pytest.raises(dev.SSEError) as ei:
         st.init(h, case.u, case.rho, case.h_ref)
     assert ei.value.code == dev.SSE_ENONFINITE
+
+
+# ---------------------------------------------------------------------------
+# edge-pass variants (direct gathers, LDS tiles of 8 / 16 / 32 edges)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["hex12_L64", "hex8_L100", "sphere3_land_L7"])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_edge_variant_feuler_parity(dev, name, variant):
+    case = KERNEL_CASES[name]()
+    st_o = Setup.from_case(case)
+    u, h = _noisy_state(case, steps=1)
+    ubar, _ = S.split(u, h, st_o)
+    zeta = S.ssh(h, st_o)
+    ut1, G = S.baroclinic_feuler(u, u - ubar[:, None], zeta, h, case.params.dt, st_o)
+    _, st = dev.state_from_case(case)
+    if not st.try_edge_variant(variant):
+        pytest.skip(f"variant {variant} does not fit: {dev.last_error()}")
+    g_ut1, g_G = st.debug_baroclinic_feuler(u, ubar, zeta, h, case.params.dt)
+    errs = {"ut1": rel_l2(g_ut1, ut1), "G": rel_l2(g_G, G)}
+    _report(f"feuler variant={variant} {name}", errs)
+    assert max(errs.values()) < TOL
+
+
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
+def test_edge_variants_bitwise_equal(dev, variant):
+    """Every variant performs the same arithmetic on the same operands: whole
+    steps agree bit for bit with the direct-gather kernel."""
+    case = cases.c1(n=16, L=60, steps=3)
+    out = {}
+    for v in (-1, variant):
+        _, st = dev.state_from_case(case)
+        assert st.try_edge_variant(v), dev.last_error()
+        assert st.step(3) == 0
+        out[v] = st.read()
+    for k in out[-1]:
+        assert np.array_equal(out[-1][k], out[variant][k]), k
