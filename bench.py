@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the SSPRK3-SE step on one MI355X.
 
-Workload (default): 512 x 512 doubly periodic hexagonal TRiSK mesh (262,144
-cells, 786,432 edges), 60 z-star layers, bathymetry 1000 +- 100 m, linear-EOS
-density front, SSPRK3-SE with M = 20 barotropic substeps, dt = 300 s, FP64.
-Inputs are synthetic and seeded and resident in HBM before timing starts.
+Workload (the headline line): 512 x 512 doubly periodic hexagonal TRiSK mesh
+(262,144 cells, 786,432 edges), 60 z-star layers, bathymetry 1000 +- 100 m,
+linear-EOS density front, SSPRK3-SE with M = 20 barotropic substeps,
+dt = 300 s, FP64.  Inputs are synthetic and seeded and resident in HBM before
+timing starts.
 
 Prints ONE JSON line on stdout: cell-layer updates/s over the timed steps,
-the roofline of the dominant kernel (algorithmic bytes / HIP-event time of
-that kernel in a second timed region) and the FP64 CPU oracle timed on a
-bounded sample of the same recipe.  Progress goes to stderr.
+the roofline of the dominant kernel class (algorithmic bytes / HIP-event time
+of that class in a second timed region), the same workload in mixed
+precision, the level-7 sphere (C2 recipe) in FP64 and mixed precision, and
+the FP64 CPU oracle timed on a bounded sample of the headline recipe.
+Progress goes to stderr.
+
+--copy-probe runs only a plain device copy of a known size (for scaling the
+FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 run) and exits.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,29 +32,54 @@ HBM_PEAK_GBS = 8000.0
 # every 3D array read once and written once per pass (13 edge-array and 14
 # cell-array touches, E = 3C): (13*3 + 14) * 8.
 STEP_BYTES_PER_CELL_LAYER = 424.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2105_13484_amd", "csrc", "sse_kernels.hip")
+COPY_PROBE_BYTES = 1 << 30
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(cls, C, E, V, L, launches_by_stage=None):
-    """Algorithmic bytes of one launch of a kernel class (FP64, state arrays only)."""
-    b = 8.0
+def kernel_bytes(cls, C, E, V, L, b=8.0):
+    """Algorithmic bytes of one launch of a kernel class (state arrays only,
+    each read once and written once; mesh tables excluded)."""
     if cls == "fe_edge":
         # X, h, rho, B, w, Z read; out written; u^n read by 2 of the 3 stages
         return b * L * (2 * E + 4 * C + V + (2.0 / 3.0) * E)
     if cls == "fe_cell":
-        return b * L * (E + 4 * C)
+        return b * L * (E + 4 * C)          # X, h, frac read; B, w written
     if cls == "fe_vertex":
-        return b * L * (E + V)
+        return b * L * (E + V)              # X read; Z written
     if cls == "bt_eval":
-        return b * (5 * E + 4 * C)
+        # edges: stage input, combination base, G, F read; output, F written.
+        # cells: stage input, base read; output written.
+        return b * (6 * E + 3 * C)
     if cls == "thickness":
-        return b * L * C * (3 + 2.0 / 3.0)
+        return b * L * C * (3 + 2.0 / 3.0)  # h_in, frac, h_out (+ h^n in 2 of 3)
     if cls == "other":
-        return b * L * (2 * E + C)
+        return b * L * (2 * E + C)          # assembly: X read, u written, h read
     raise KeyError(cls)
+
+
+def source_sha256(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(dom):
+    """HBM bytes per launch of the dominant class from the committed rocprofv3
+    counter summary, or None when it is missing, covers another kernel class
+    or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    c = t.get("classes", {}).get(dom)
+    if c is None or t.get("kernel_source_sha256") != source_sha256(KERNEL_SOURCE):
+        return None
+    return float(c["fetch_bytes_per_launch"]) + float(c["write_bytes_per_launch"])
 
 
 def cpu_baseline(n=128, steps=2):
@@ -70,6 +102,30 @@ def cpu_baseline(n=128, steps=2):
             "cores_available": len(os.sched_getaffinity(0))}
 
 
+def timed_steps(torch, st, steps):
+    """ms per step of `steps` steps, HIP events on the state's stream."""
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    st.step_async(steps)
+    ev1.record(stream)
+    rc = st.sync()
+    torch.cuda.synchronize()
+    assert rc == 0, f"timed steps returned {rc}"
+    return ev0.elapsed_time(ev1) / steps
+
+
+def copy_probe():
+    import torch
+    a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: {COPY_PROBE_BYTES} bytes read and written once")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +135,8 @@ def main():
     ap.add_argument("--layers", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing")
+    ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
+    ap.add_argument("--copy-probe", action="store_true", help="run only a plain device copy and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -87,6 +145,9 @@ def main():
               "(the step would shard by horizontal domain decomposition; see the design notes).",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import numpy as np
     import torch
@@ -99,11 +160,10 @@ def main():
     C, E, V, L = case.mesh.nCells, case.mesh.nEdges, case.mesh.nVertices, args.layers
     cell_layers = case.active_cell_layers
     dm, st = ssprkse.state_from_case(case, device="cuda:0")
-    stream = torch.cuda.current_stream()
-    log(f"[bench] uploaded: mesh {dm.nbytes / 1e9:.3f} GB, state {st.nbytes / 1e9:.3f} GB")
+    log(f"[bench] uploaded: mesh {dm.nbytes / 1e9:.3f} GB, state {st.nbytes / 1e9:.3f} GB, "
+        f"edge variant {st.edge_variant}")
 
-    rc = st.step(args.warmup)
-    assert rc == 0, f"warmup returned {rc}"
+    assert st.step(args.warmup) == 0, "warmup failed"
 
     # per-class timing over a few steps: which kernel class dominates
     st.profile(ssprkse.PROF_CLASSES)
@@ -111,23 +171,15 @@ def main():
     prof = st.profile_read()
     st.profile(())
     dom = max(prof, key=lambda k: prof[k][1])
-    log(f"[bench] per-class ms over 3 steps: " + ", ".join(f"{k}={v[1]:.3f}({v[0]})" for k, v in prof.items()))
+    log("[bench] per-class ms over 3 steps: " + ", ".join(f"{k}={v[1]:.3f}({v[0]})" for k, v in prof.items()))
 
     # timed region 1: clean
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    st.step_async(args.steps)
-    ev1.record(stream)
-    rc = st.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    assert rc == 0, f"timed steps returned {rc}"
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (events), wall {wall * 1e3 / args.steps:.3f} ms/step")
+    ms_step = timed_steps(torch, st, args.steps)
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (events), wall {wall:.3f} ms/step")
 
-    # timed region 2: the same steps with HIP events around the dominant kernel only
+    # timed region 2: the same steps with HIP events around the dominant class only
     st.profile((dom,))
     torch.cuda.synchronize()
     assert st.step(args.steps) == 0
@@ -136,28 +188,43 @@ def main():
     avg_ms = ms_dom / max(n_dom, 1)
     kb = kernel_bytes(dom, C, E, V, L)
     achieved = kb / (avg_ms * 1e-3) / 1e9
-    log(f"[bench] dominant kernel {dom}: {n_dom} launches, {avg_ms * 1e3:.1f} us avg, {achieved:.0f} GB/s algorithmic")
+    traffic = measured_traffic(dom)
+    log(f"[bench] dominant class {dom}: {n_dom} launches, {avg_ms * 1e3:.1f} us avg, "
+        f"{achieved:.0f} GB/s algorithmic, measured traffic per launch {traffic}")
+    final = st.read()
+    assert np.isfinite(final["u"]).all() and np.isfinite(final["h"]).all()
+    del st
 
     # the same workload in mixed precision (FP32 tendencies and substeps)
     ms_mixed = None
     if not args.no_mixed:
-        dm_m, st_m = ssprkse.state_from_case(cases.with_params(case, precision=1), device="cuda:0")
+        _, st_m = ssprkse.state_from_case(cases.with_params(case, precision=1), device="cuda:0")
         assert st_m.step(args.warmup) == 0
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        st_m.step_async(args.steps)
-        ev1.record(stream)
-        assert st_m.sync() == 0
-        torch.cuda.synchronize()
-        ms_mixed = ev0.elapsed_time(ev1) / args.steps
-        log(f"[bench] mixed precision: {ms_mixed:.3f} ms/step")
-        del st_m, dm_m
+        ms_mixed = timed_steps(torch, st_m, args.steps)
+        log(f"[bench] C1 mixed precision: {ms_mixed:.3f} ms/step")
+        del st_m
+    del dm
+
+    # C2 recipe: level-7 sphere, 60 layers, 30% land, M = 30, dt = 1800 s
+    c2 = None
+    if not args.no_c2:
+        log("[bench] building the level-7 sphere (C2 recipe)")
+        case2 = cases.c2()
+        c2 = {"workload": "C2: SSPRK3-SE on an icosahedral level-7 sphere (163,842 cells, 491,520 edges), "
+                          "60 z-star layers, 30% land, M=30, dt=1800 s",
+              "active_cell_layers": case2.active_cell_layers}
+        for prec, key in ((0, "fp64"), (1, "mixed")):
+            dm2, st2 = ssprkse.state_from_case(cases.with_params(case2, precision=prec), device="cuda:0")
+            assert st2.step(2) == 0
+            ms2 = timed_steps(torch, st2, 20)
+            c2[f"{key}_ms_per_step"] = ms2
+            c2[f"{key}_cell_layer_updates_per_s"] = case2.active_cell_layers / (ms2 * 1e-3)
+            log(f"[bench] C2 {key}: {ms2:.3f} ms/step")
+            del st2, dm2
+        c2["mixed_vs_fp64_speedup"] = c2["fp64_ms_per_step"] / c2["mixed_ms_per_step"]
 
     value = cell_layers / (ms_step * 1e-3)
     step_gbs = STEP_BYTES_PER_CELL_LAYER * cell_layers / (ms_step * 1e-3) / 1e9
-    final = st.read()
-    assert np.isfinite(final["u"]).all() and np.isfinite(final["h"]).all()
-
     out = {
         "metric": "cell-layer updates/s per SSPRK3-SE step; % HBM peak; mixed vs FP64 speedup",
         "value": value,
@@ -180,8 +247,9 @@ def main():
         "mixed_ms_per_step": ms_mixed,
         "per_class_ms_per_step": {k: v[1] / 3.0 for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": kb},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": kb, "launch_ms": avg_ms},
+        "c2": c2,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
