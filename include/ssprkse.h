@@ -187,6 +187,60 @@ int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
 int sse_state_set_edge_variant(sse_state *s, int variant);
 int sse_state_get_edge_variant(const sse_state *s, int *variant);
 
+/* Launch geometry of the state's kernels; results do not depend on it.
+ * cols_per_block: wavefronts per workgroup of the column kernels (one
+ * wavefront per vertical column), 1, 2, 4, 8 or 16; block_2d: threads per
+ * workgroup of the 2D kernels (barotropic evaluations, reconciliation), a
+ * multiple of 64 in [64, 1024].  Defaults 4 and 256.  SSE_EINVAL otherwise. */
+int sse_state_set_geometry(sse_state *s, int cols_per_block, int block_2d);
+
+/* enable != 0: the next sse_step / sse_step_async captures the launches of one
+ * step on the state's stream into a HIP graph and every step then replays
+ * it (one graph launch per step).  The stream must not be the null stream
+ * (SSE_EINVAL).  Changing the geometry, the edge variant or this flag drops the
+ * graph.  Per-class profiling does not apply to graph replays. */
+int sse_state_use_graph(sse_state *s, int enable);
+
+/*
+ * Batched ensembles (many independent states advanced together).
+ *
+ * A batch advances its member states by whole SSPRK-SE steps with one kernel
+ * launch per phase of the step across all members: the launch sequence of
+ * one step (Sections 3.2 / 3.3; the barotropic loops of Algorithms 3 / 4 run
+ * max M substeps, a member with a smaller M taking part in its first M) is
+ * recorded for every member and equal launches are merged.  Members keep
+ * their own mesh, parameters (L, M, dt, ...) and workspace, and produce
+ * bit-for-bit the results they produce alone.  They must share precision,
+ * scheme and vertical coordinate and have been created on the batch's
+ * stream.  Batched launches use the direct-gather edge pass and the batch's
+ * geometry.  The library allocates nothing: sse_batch_program_bytes gives
+ * the size of the device buffer that sse_batch_compile fills with the
+ * merged argument blocks and workgroup tables (256-byte aligned; the caller
+ * owns it and keeps it alive while the batch steps).  Adding or removing a
+ * member, or changing the geometry, invalidates the compiled program.  A
+ * member must not be stepped on its own while the batch runs.
+ */
+typedef struct sse_batch sse_batch;
+int sse_batch_create(void *hip_stream, sse_batch **out);
+int sse_batch_destroy(sse_batch *b);
+int sse_batch_add(sse_batch *b, sse_state *s);
+int sse_batch_remove(sse_batch *b, sse_state *s);
+int sse_batch_size(const sse_batch *b, int32_t *n);
+int sse_batch_set_geometry(sse_batch *b, int cols_per_block, int block_2d);
+int sse_batch_program_bytes(sse_batch *b, size_t *bytes);
+int sse_batch_compile(sse_batch *b, void *dev_buf, size_t bytes);
+/* Number of batched launches in one step of the compiled program. */
+int sse_batch_launches_per_step(sse_batch *b, int32_t *n);
+/* enable != 0: one step of the batch is captured into a HIP graph on first
+ * use and replayed (non-null stream required). */
+int sse_batch_use_graph(sse_batch *b, int enable);
+/* Enqueue n steps of every member / wait and check every member's
+ * non-finite flag (SSE_ENONFINITE if any member blew up; sse_sync on a
+ * member tells which). */
+int sse_batch_step_async(sse_batch *b, int32_t n);
+int sse_batch_sync(sse_batch *b);
+int sse_batch_step(sse_batch *b, int32_t n);
+
 /*
  * Per-kernel debug entry points (host arrays, caller numbering).  They use
  * the state's stage buffers as scratch and leave its prognostic fields

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -111,6 +112,28 @@ bool all_finite(const double *x, size_t n) {
     return true;
 }
 
+// Launch recording.  While a batch compiles its program, the building blocks
+// below do not launch: they append their argument block under a structural
+// key (seq = launch site in step order; j = substep evaluation inside a
+// barotropic loop), so that the same launch of every member can be merged
+// into one batched launch.
+enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD };
+
+struct RecEntry {
+    Kind kind;
+    int seq, j;
+    int nk;
+    bool add;
+    int blocks;
+    std::vector<uint8_t> args;
+};
+
+struct Recorder {
+    int seq = 0;
+    int loop_seq = -1;
+    std::vector<RecEntry> entries;
+};
+
 }  // namespace
 
 struct sse_state {
@@ -121,9 +144,15 @@ struct sse_state {
     size_t bytes = 0;
     size_t rs = 8;           // bytes of the real type R
     bool initialized = false;
-    // profiling
+    Geom geom{};             // launch geometry (autotuner knob)
     int edge_variant = -1;   // -1: direct gathers; 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
     size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
+    Recorder *rec = nullptr; // non-null while a batch records this state's step
+    sse_batch *batch = nullptr;
+    // single-state step captured as a HIP graph
+    bool use_graph = false;
+    hipGraphExec_t graph_exec = nullptr;
+    // profiling
     bool prof = false;
     int prof_mask = 0;
     std::vector<hipEvent_t> events;
@@ -138,7 +167,7 @@ namespace {
 // ---- per-class event timing ------------------------------------------------
 void prof_flush(sse_state *s) {
     if (s->ev_used == 0) return;
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
     for (size_t i = 0; i < s->ev_used / 2; ++i) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, s->events[2 * i], s->events[2 * i + 1]) == hipSuccess) {
@@ -155,18 +184,35 @@ struct ProfScope {
     int cls;
     bool active;
     ProfScope(sse_state *st, int c)
-        : s(st), cls(c), active(st->prof && !st->events.empty() && ((st->prof_mask >> c) & 1)) {
+        : s(st), cls(c),
+          active(st->prof && !st->rec && !st->events.empty() && ((st->prof_mask >> c) & 1)) {
         if (!active) return;
         if (s->ev_used + 2 > s->events.size()) prof_flush(s);
-        hipEventRecord(s->events[s->ev_used], s->stream);
+        (void)hipEventRecord(s->events[s->ev_used], s->stream);
     }
     ~ProfScope() {
         if (!active) return;
-        hipEventRecord(s->events[s->ev_used + 1], s->stream);
+        (void)hipEventRecord(s->events[s->ev_used + 1], s->stream);
         s->ev_used += 2;
         s->rec_class.push_back(cls);
     }
 };
+
+template <typename A>
+void record(sse_state *s, Kind kind, const A &a, int nk, bool add, int blocks, int j = -1) {
+    Recorder &r = *s->rec;
+    RecEntry e;
+    e.kind = kind;
+    e.j = j;
+    e.seq = j >= 0 ? r.loop_seq : r.seq++;
+    e.nk = nk;
+    e.add = add;
+    e.blocks = blocks;
+    e.args.assign(reinterpret_cast<const uint8_t *>(&a), reinterpret_cast<const uint8_t *>(&a) + sizeof(A));
+    r.entries.push_back(std::move(e));
+}
+
+int nk_of(int L) { return L <= kWave ? 1 : 2; }
 
 // ---- building blocks -------------------------------------------------------
 template <typename R>
@@ -177,15 +223,18 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
     const sse_params &p = s->p;
     Work &w = s->w;
     const bool zstar = p.vcoord == SSE_ZSTAR;
+    const int nk = nk_of(p.n_layers);
     {
         ProfScope ps(s, SSE_PROF_FE_CELL);
         FECellArgs<R> a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, p.nu_h, rp<R>(w.B), rp<R>(w.Wt), w.Kbot};
-        launch_fe_cell<R>(a, s->stream);
+        if (s->rec) record(s, Kind::FE_CELL, a, nk, add != nullptr, col_blocks(m.C, s->geom));
+        else launch_fe_cell<R>(a, s->geom, s->stream);
     }
     {
         ProfScope ps(s, SSE_PROF_FE_VERTEX);
         FEVertexArgs<R> a{m, p.n_layers, X, add, rp<R>(w.Z)};
-        launch_fe_vertex<R>(a, s->stream);
+        if (s->rec) record(s, Kind::FE_VERTEX, a, nk, add != nullptr, col_blocks(m.V, s->geom));
+        else launch_fe_vertex<R>(a, s->geom, s->stream);
     }
     {
         ProfScope ps(s, SSE_PROF_FE_EDGE);
@@ -222,11 +271,23 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         a.nu_h = p.nu_h;
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
-        if (s->edge_variant >= 0)
+        if (s->rec)
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom));
+        else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
-            launch_fe_edge<R>(a, s->stream);
+            launch_fe_edge<R>(a, s->geom, s->stream);
     }
+}
+
+template <typename Tin, typename Tout>
+void convert(sse_state *s, const Tin *src, Tout *dst, size_t n) {
+    ProfScope ps(s, SSE_PROF_OTHER);
+    ConvArgs<Tin, Tout> a{src, dst, n};
+    if (s->rec)
+        record(s, std::is_same<Tin, double>::value ? Kind::CONV_DF : Kind::CONV_FD, a, 1, false, flat_blocks(n, s->geom));
+    else
+        launch_convert<Tin, Tout>(a, s->geom, s->stream);
 }
 
 // Algorithm 3 (scheme 2) / Algorithm 4 (scheme 3): M substeps of dt / M with
@@ -248,49 +309,50 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         ou = out_u;
         oz = out_z;
     } else {
-        ProfScope ps(s, SSE_PROF_OTHER);
-        launch_convert<double, R>(in_u, rp<R>(w.bt_ua), m.E, s->stream);
-        launch_convert<double, R>(in_z, rp<R>(w.bt_za), m.C, s->stream);
+        convert<double, R>(s, in_u, rp<R>(w.bt_ua), m.E);
+        convert<double, R>(s, in_z, rp<R>(w.bt_za), m.C);
         iu = rp<R>(w.bt_ua);
         iz = rp<R>(w.bt_za);
         ou = rp<R>(w.bt_uo);
         oz = rp<R>(w.bt_zo);
     }
     R *u1 = rp<R>(w.bt_u1), *uh = rp<R>(w.bt_uh), *z1 = rp<R>(w.bt_z1), *zh = rp<R>(w.bt_zh);
+    if (s->rec) s->rec->loop_seq = s->rec->seq++;
+    const int nblk = bt_blocks(m.E, m.C, s->geom);
     BTEvalArgs<R> a{};
     a.m = m;
     a.G = G;
     a.F = F;
     a.tau = dt / M;
     a.g = s->p.gravity;
-    for (int j = 0; j < M; ++j) {
-        const R *bu = j == 0 ? iu : ou;
-        const R *bz = j == 0 ? iz : oz;
+    int j = 0;
+    auto eval = [&]() {
+        ProfScope ps(s, SSE_PROF_BT_EVAL);
+        if (s->rec) record(s, Kind::BT_EVAL, a, 1, false, nblk, j++);
+        else launch_bt_eval<R>(a, s->geom, s->stream);
+    };
+    for (int sub = 0; sub < M; ++sub) {
+        const R *bu = sub == 0 ? iu : ou;
+        const R *bz = sub == 0 ? iz : oz;
         if (scheme == SSE_SCHEME_SSPRK3) {
             const double w1 = 1.0 / (6.0 * M), w3 = 2.0 / (3.0 * M);
-            { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
-              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval<R>(a, s->stream); }
-            { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = uh; a.zo = zh;
-              a.wF = w1; a.zeroF = 0; a.comb = COMB_34; launch_bt_eval<R>(a, s->stream); }
-            { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = uh; a.za = zh; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
-              a.wF = w3; a.zeroF = 0; a.comb = COMB_THIRD; launch_bt_eval<R>(a, s->stream); }
+            a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
+            a.wF = w1; a.zeroF = (sub == 0); a.comb = COMB_NONE; eval();
+            a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = uh; a.zo = zh;
+            a.wF = w1; a.zeroF = 0; a.comb = COMB_34; eval();
+            a.ua = uh; a.za = zh; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
+            a.wF = w3; a.zeroF = 0; a.comb = COMB_THIRD; eval();
         } else {
             const double w1 = 1.0 / (2.0 * M);
-            { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
-              a.wF = w1; a.zeroF = (j == 0); a.comb = COMB_NONE; launch_bt_eval<R>(a, s->stream); }
-            { ProfScope ps(s, SSE_PROF_BT_EVAL);
-              a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
-              a.wF = w1; a.zeroF = 0; a.comb = COMB_HALF; launch_bt_eval<R>(a, s->stream); }
+            a.ua = bu; a.za = bz; a.ub = bu; a.zb = bz; a.uo = u1; a.zo = z1;
+            a.wF = w1; a.zeroF = (sub == 0); a.comb = COMB_NONE; eval();
+            a.ua = u1; a.za = z1; a.ub = bu; a.zb = bz; a.uo = ou; a.zo = oz;
+            a.wF = w1; a.zeroF = 0; a.comb = COMB_HALF; eval();
         }
     }
     if constexpr (!std::is_same<R, double>::value) {
-        ProfScope ps(s, SSE_PROF_OTHER);
-        launch_convert<R, double>(ou, out_u, m.E, s->stream);
-        launch_convert<R, double>(oz, out_z, m.C, s->stream);
+        convert<R, double>(s, ou, out_u, m.E);
+        convert<R, double>(s, oz, out_z, m.C);
     }
 }
 
@@ -316,7 +378,8 @@ void recon(sse_state *s, int mode, const double *Fz, const double *Fh, const dou
     a.uA = w.uA;
     a.ub2 = ub2;
     a.ub_half = ub_half;
-    launch_recon(a, s->stream);
+    if (s->rec) record(s, Kind::RECON, a, 1, false, flat_blocks(a.m.E, s->geom));
+    else launch_recon(a, s->geom, s->stream);
 }
 
 // Thickness stage.  z-star uses the 2D total flux w.Ftot; isopycnal rebuilds
@@ -326,9 +389,11 @@ void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, do
                const R *X1, double c1, const R *X2, double c2, const double *a1, double ca1, double dt) {
     ProfScope ps(s, SSE_PROF_THICKNESS);
     Work &w = s->w;
+    const int nk = nk_of(s->p.n_layers), nb = col_blocks(s->mesh->d.C, s->geom);
     if (s->p.vcoord == SSE_ZSTAR) {
         THArgs a{s->mesh->d, s->p.n_layers, h_in, h_n, w.frac, w.Ftot, comb, dt, h_out, zeta_out, w.flag};
-        launch_thickness(a, s->stream);
+        if (s->rec) record(s, Kind::THICK, a, nk, false, nb);
+        else launch_thickness(a, s->geom, s->stream);
     } else {
         THIsoArgs<R> a{};
         a.m = s->mesh->d;
@@ -347,7 +412,8 @@ void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, do
         a.h_out = h_out;
         a.zeta_out = zeta_out;
         a.nonfinite = w.flag;
-        launch_thickness_iso<R>(a, s->stream);
+        if (s->rec) record(s, Kind::THICK_ISO, a, nk, false, nb);
+        else launch_thickness_iso<R>(a, s->geom, s->stream);
     }
 }
 
@@ -356,7 +422,8 @@ void assemble(sse_state *s, const R *X, const double *ubar_bt) {
     ProfScope ps(s, SSE_PROF_OTHER);
     Work &w = s->w;
     AssembleArgs<R> a{s->mesh->d, s->p.n_layers, X, ubar_bt, w.Hs, rp<R>(w.U), w.ubar_n, w.flag};
-    launch_assemble<R>(a, s->stream);
+    if (s->rec) record(s, Kind::ASSEMBLE, a, nk_of(s->p.n_layers), false, col_blocks(a.m.E, s->geom));
+    else launch_assemble<R>(a, s->geom, s->stream);
 }
 
 template <typename R>
@@ -625,13 +692,20 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
 
 extern "C" int sse_state_set_edge_variant(sse_state *s, int variant) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
-    if (variant == -1) { s->edge_variant = -1; return SSE_OK; }
+    if (variant == -1) {
+        s->edge_variant = -1;
+        if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+        return SSE_OK;
+    }
     if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -1, 0, 1 or 2"); return SSE_EINVAL; }
     const DevTiles &t = s->mesh->tiles[variant];
     if (!t.T) { set_error("edge variant: a tile of this mesh lists more than 255 columns"); return SSE_EINVAL; }
     const size_t lds = s->rs == 4 ? fe_edge_tiled_lds<float>(t, s->p.n_layers) : fe_edge_tiled_lds<double>(t, s->p.n_layers);
     if (lds > s->lds_max) { set_error("edge variant: the tile does not fit the device's LDS"); return SSE_EINVAL; }
     s->edge_variant = variant;
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    s->graph_exec = nullptr;
     return SSE_OK;
 }
 
@@ -643,7 +717,9 @@ extern "C" int sse_state_get_edge_variant(const sse_state *s, int *variant) {
 
 extern "C" int sse_state_destroy(sse_state *s) {
     if (!s) return SSE_OK;
-    for (auto e : s->events) hipEventDestroy(e);
+    if (s->batch) (void)sse_batch_remove(s->batch, s);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    for (auto e : s->events) (void)hipEventDestroy(e);
     delete s;
     return SSE_OK;
 }
@@ -683,10 +759,10 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
     launch_zeta_from_h(m->d, L, w.Hs, w.zeta_n, s->stream);
     if (s->rs == 4) {
         AssembleArgs<float> a{m->d, L, rp<float>(w.U), nullptr, w.Hs, rp<float>(w.U), w.ubar_n, w.flag};
-        launch_assemble<float>(a, s->stream);
+        launch_assemble<float>(a, s->geom, s->stream);
     } else {
         AssembleArgs<double> a{m->d, L, rp<double>(w.U), nullptr, w.Hs, rp<double>(w.U), w.ubar_n, w.flag};
-        launch_assemble<double>(a, s->stream);
+        launch_assemble<double>(a, s->geom, s->stream);
     }
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipStreamSynchronize(s->stream));
@@ -694,21 +770,74 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
     return SSE_OK;
 }
 
+namespace {
+
+void drop_graph(sse_state *s) {
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    s->graph_exec = nullptr;
+}
+
+void enqueue_step(sse_state *s) {
+    if (s->rs == 4)
+        step_one<float>(s);
+    else
+        step_one<double>(s);
+}
+
+// Capture one step of launches on `stream` into an executable graph.
+template <typename F>
+int capture(hipStream_t stream, F &&enqueue, hipGraphExec_t *out) {
+    if (!stream) { set_error("HIP graphs need a non-default stream"); return SSE_EINVAL; }
+    SSE_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    const hipError_t e2 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
+    return SSE_OK;
+}
+
+void batch_invalidate(sse_batch *b);
+
+}  // namespace
+
 extern "C" int sse_step_async(sse_state *s, int32_t n) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
     if (n < 0) { set_error("n must be >= 0"); return SSE_EINVAL; }
+    if (s->use_graph) {
+        if (!s->graph_exec) {
+            int rc = capture(s->stream, [&] { enqueue_step(s); }, &s->graph_exec);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < n; ++i) SSE_HIP(hipGraphLaunch(s->graph_exec, s->stream));
+        return SSE_OK;
+    }
     if (s->prof && s->events.empty()) {
         s->events.resize(8192);
         for (auto &e : s->events) SSE_HIP(hipEventCreate(&e));
     }
-    for (int i = 0; i < n; ++i) {
-        if (s->rs == 4)
-            step_one<float>(s);
-        else
-            step_one<double>(s);
-    }
+    for (int i = 0; i < n; ++i) enqueue_step(s);
     SSE_HIP(hipGetLastError());
+    return SSE_OK;
+}
+
+extern "C" int sse_state_set_geometry(sse_state *s, int cols_per_block, int block_2d) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    Geom g{cols_per_block, block_2d};
+    if (!geom_valid(g)) { set_error("geometry: cols_per_block in {1,2,4,8,16}, block_2d a multiple of 64 in [64, 1024]"); return SSE_EINVAL; }
+    s->geom = g;
+    drop_graph(s);
+    return SSE_OK;
+}
+
+extern "C" int sse_state_use_graph(sse_state *s, int enable) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    if (enable && !s->stream) { set_error("HIP graphs need a non-default stream"); return SSE_EINVAL; }
+    s->use_graph = enable != 0;
+    drop_graph(s);
     return SSE_OK;
 }
 
@@ -838,4 +967,275 @@ extern "C" int sse_debug_thickness_stage(sse_state *s, const double *h_in, const
     SSE_HIP(hipMemcpyAsync(zeta_out, w.z_half, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
     return SSE_OK;
+}
+
+// ===========================================================================
+// Batched ensembles
+// ===========================================================================
+namespace {
+
+struct BatchOp {
+    Kind kind;
+    int nk;
+    bool add;
+    int blocks;
+    size_t args_off, table_off;
+};
+
+}  // namespace
+
+struct sse_batch {
+    hipStream_t stream = nullptr;
+    std::vector<sse_state *> members;
+    Geom geom{};
+    bool recorded = false;
+    std::vector<BatchOp> prog;
+    std::vector<uint8_t> image;   // argument blocks and block tables, device layout
+    void *dev = nullptr;
+    bool compiled = false;
+    bool use_graph = false;
+    hipGraphExec_t graph_exec = nullptr;
+    size_t launches_per_step = 0;
+};
+
+namespace {
+
+void batch_invalidate(sse_batch *b) {
+    if (!b) return;
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+    b->recorded = b->compiled = false;
+    b->prog.clear();
+    b->image.clear();
+    b->dev = nullptr;
+}
+
+// Record one step of every member and merge equal launches into batched ones.
+int batch_record(sse_batch *b) {
+    if (b->recorded) return SSE_OK;
+    if (b->members.empty()) { set_error("batch has no members"); return SSE_ESTATE; }
+    const sse_state *s0 = b->members[0];
+    struct Key {
+        int seq, j, nk;
+        bool operator<(const Key &o) const {
+            if (seq != o.seq) return seq < o.seq;
+            if (j != o.j) return j < o.j;
+            return nk < o.nk;
+        }
+    };
+    std::map<Key, std::vector<std::pair<int, RecEntry>>> groups;
+    for (size_t mi = 0; mi < b->members.size(); ++mi) {
+        sse_state *s = b->members[mi];
+        if (s->rs != s0->rs || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
+            set_error("batch members must share precision, scheme and vertical coordinate");
+            return SSE_EINVAL;
+        }
+        Recorder r;
+        const Geom saved = s->geom;
+        s->geom = b->geom;
+        s->rec = &r;
+        enqueue_step(s);
+        s->rec = nullptr;
+        s->geom = saved;
+        for (auto &e : r.entries) groups[Key{e.seq, e.j, e.nk}].emplace_back((int)mi, std::move(e));
+    }
+    auto align = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
+    b->prog.clear();
+    b->image.clear();
+    size_t off = 0;
+    for (auto &kv : groups) {
+        auto &v = kv.second;
+        BatchOp op{v[0].second.kind, v[0].second.nk, v[0].second.add, 0, 0, 0};
+        const size_t asz = v[0].second.args.size();
+        std::vector<int2> table;
+        for (size_t q = 0; q < v.size(); ++q) {
+            if (v[q].second.kind != op.kind || v[q].second.add != op.add || v[q].second.args.size() != asz) {
+                set_error("internal: batch members recorded different step structures");
+                return SSE_EINVAL;
+            }
+            for (int blk = 0; blk < v[q].second.blocks; ++blk) table.push_back(int2{(int)q, blk});
+        }
+        op.blocks = (int)table.size();
+        op.args_off = off;
+        off = align(off + asz * v.size());
+        op.table_off = off;
+        off = align(off + table.size() * sizeof(int2));
+        b->image.resize(off, 0);
+        for (size_t q = 0; q < v.size(); ++q)
+            std::memcpy(b->image.data() + op.args_off + q * asz, v[q].second.args.data(), asz);
+        std::memcpy(b->image.data() + op.table_off, table.data(), table.size() * sizeof(int2));
+        b->prog.push_back(op);
+    }
+    b->launches_per_step = b->prog.size();
+    b->recorded = true;
+    return SSE_OK;
+}
+
+template <typename A>
+BatchLaunch<A> bl(const sse_batch *b, const BatchOp &op) {
+    const char *base = static_cast<const char *>(b->dev);
+    return BatchLaunch<A>{reinterpret_cast<const A *>(base + op.args_off),
+                          reinterpret_cast<const int2 *>(base + op.table_off), op.blocks};
+}
+
+template <typename R>
+void batch_enqueue(const sse_batch *b) {
+    const Geom &g = b->geom;
+    hipStream_t st = b->stream;
+    for (const BatchOp &op : b->prog) {
+        switch (op.kind) {
+            case Kind::FE_CELL: launch_fe_cell_batch<R>(bl<FECellArgs<R>>(b, op), op.nk, op.add, g, st); break;
+            case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
+            case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, g, st); break;
+            case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), g, st); break;
+            case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
+            case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;
+            case Kind::RECON: launch_recon_batch(bl<ReconArgs>(b, op), g, st); break;
+            case Kind::ASSEMBLE: launch_assemble_batch<R>(bl<AssembleArgs<R>>(b, op), op.nk, g, st); break;
+            case Kind::CONV_DF: launch_convert_batch<double, float>(bl<ConvArgs<double, float>>(b, op), g, st); break;
+            case Kind::CONV_FD: launch_convert_batch<float, double>(bl<ConvArgs<float, double>>(b, op), g, st); break;
+        }
+    }
+}
+
+void batch_enqueue_any(const sse_batch *b) {
+    if (b->members[0]->rs == 4)
+        batch_enqueue<float>(b);
+    else
+        batch_enqueue<double>(b);
+}
+
+}  // namespace
+
+extern "C" int sse_batch_create(void *stream, sse_batch **out) {
+    if (!out) { set_error("out is NULL"); return SSE_EINVAL; }
+    sse_batch *b = new sse_batch();
+    b->stream = static_cast<hipStream_t>(stream);
+    *out = b;
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_destroy(sse_batch *b) {
+    if (!b) return SSE_OK;
+    for (sse_state *s : b->members) s->batch = nullptr;
+    batch_invalidate(b);
+    delete b;
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_add(sse_batch *b, sse_state *s) {
+    if (!b || !s) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (!s->initialized) { set_error("batch members must be initialised"); return SSE_ESTATE; }
+    if (s->batch) { set_error("state already belongs to a batch"); return SSE_ESTATE; }
+    if (s->stream != b->stream) { set_error("batch members must use the batch's stream"); return SSE_EINVAL; }
+    if (!b->members.empty()) {
+        const sse_state *s0 = b->members[0];
+        if (s->rs != s0->rs || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
+            set_error("batch members must share precision, scheme and vertical coordinate");
+            return SSE_EINVAL;
+        }
+    }
+    b->members.push_back(s);
+    s->batch = b;
+    batch_invalidate(b);
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_remove(sse_batch *b, sse_state *s) {
+    if (!b || !s) { set_error("NULL argument"); return SSE_EINVAL; }
+    auto it = std::find(b->members.begin(), b->members.end(), s);
+    if (it == b->members.end()) { set_error("state is not a member of this batch"); return SSE_EINVAL; }
+    b->members.erase(it);
+    s->batch = nullptr;
+    batch_invalidate(b);
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_size(const sse_batch *b, int32_t *n) {
+    if (!b || !n) { set_error("NULL argument"); return SSE_EINVAL; }
+    *n = (int32_t)b->members.size();
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_set_geometry(sse_batch *b, int cols_per_block, int block_2d) {
+    if (!b) { set_error("NULL batch"); return SSE_EINVAL; }
+    Geom g{cols_per_block, block_2d};
+    if (!geom_valid(g)) { set_error("geometry: cols_per_block in {1,2,4,8,16}, block_2d a multiple of 64 in [64, 1024]"); return SSE_EINVAL; }
+    b->geom = g;
+    batch_invalidate(b);
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_program_bytes(sse_batch *b, size_t *bytes) {
+    if (!b || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
+    int rc = batch_record(b);
+    if (rc) return rc;
+    *bytes = b->image.size();
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_compile(sse_batch *b, void *dev_buf, size_t bytes) {
+    if (!b) { set_error("NULL batch"); return SSE_EINVAL; }
+    int rc = batch_record(b);
+    if (rc) return rc;
+    if (!dev_buf || bytes < b->image.size()) { set_error("batch program buffer too small"); return SSE_ENOMEM; }
+    if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("batch program buffer must be 256-byte aligned"); return SSE_EINVAL; }
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+    SSE_HIP(hipMemcpyAsync(dev_buf, b->image.data(), b->image.size(), hipMemcpyHostToDevice, b->stream));
+    SSE_HIP(hipStreamSynchronize(b->stream));
+    b->dev = dev_buf;
+    b->compiled = true;
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_use_graph(sse_batch *b, int enable) {
+    if (!b) { set_error("NULL batch"); return SSE_EINVAL; }
+    if (enable && !b->stream) { set_error("HIP graphs need a non-default stream"); return SSE_EINVAL; }
+    b->use_graph = enable != 0;
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_launches_per_step(sse_batch *b, int32_t *n) {
+    if (!b || !n) { set_error("NULL argument"); return SSE_EINVAL; }
+    int rc = batch_record(b);
+    if (rc) return rc;
+    *n = (int32_t)b->launches_per_step;
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_step_async(sse_batch *b, int32_t n) {
+    if (!b) { set_error("NULL batch"); return SSE_EINVAL; }
+    if (n < 0) { set_error("n must be >= 0"); return SSE_EINVAL; }
+    if (!b->compiled) { set_error("batch program not compiled (sse_batch_compile)"); return SSE_ESTATE; }
+    if (b->use_graph) {
+        if (!b->graph_exec) {
+            int rc = capture(b->stream, [&] { batch_enqueue_any(b); }, &b->graph_exec);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < n; ++i) SSE_HIP(hipGraphLaunch(b->graph_exec, b->stream));
+        return SSE_OK;
+    }
+    for (int i = 0; i < n; ++i) batch_enqueue_any(b);
+    SSE_HIP(hipGetLastError());
+    return SSE_OK;
+}
+
+extern "C" int sse_batch_sync(sse_batch *b) {
+    if (!b) { set_error("NULL batch"); return SSE_EINVAL; }
+    SSE_HIP(hipStreamSynchronize(b->stream));
+    int worst = SSE_OK;
+    for (sse_state *s : b->members) {
+        int rc = read_flag(s);
+        if (rc && !worst) worst = rc;
+    }
+    return worst;
+}
+
+extern "C" int sse_batch_step(sse_batch *b, int32_t n) {
+    int rc = sse_batch_step_async(b, n);
+    if (rc) return rc;
+    return sse_batch_sync(b);
 }

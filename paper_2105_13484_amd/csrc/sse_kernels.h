@@ -147,22 +147,69 @@ struct AssembleArgs {
     int *nonfinite;
 };
 
-template <typename R> void launch_fe_cell(const FECellArgs<R> &a, hipStream_t s);
-template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, hipStream_t s);
-template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s);
+// Element-wise type conversion dst[i] = src[i], i < n.
+template <typename Tin, typename Tout>
+struct ConvArgs {
+    const Tin *src;
+    Tout *dst;
+    size_t n;
+};
+
+// Launch geometry: wavefronts (= columns) per workgroup of the column kernels
+// and threads per workgroup of the 2D kernels.  The autotuner picks them.
+struct Geom {
+    int cols_per_block = 4;   // 1, 2, 4, 8 or 16
+    int block_2d = 256;       // 64 .. 1024, a multiple of 64
+};
+bool geom_valid(const Geom &g);
+
+// Workgroups of a column kernel over n columns, and of a 2D kernel over n
+// entities (bt_eval: edge blocks, then cell blocks).
+int col_blocks(int n, const Geom &g);
+int flat_blocks(size_t n, const Geom &g);
+int bt_blocks(int E, int C, const Geom &g);
+
+// Single-state launches.  The column kernels take NK from a.L and the velocity
+// form from whether ubar_add is non-null.
+template <typename R> void launch_fe_cell(const FECellArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s);
 // LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
 template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
 template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
 void set_tiled_lds_limit(size_t bytes);
-template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, hipStream_t s);
-template <typename R> void launch_thickness_iso(const THIsoArgs<R> &a, hipStream_t s);
-template <typename R> void launch_assemble(const AssembleArgs<R> &a, hipStream_t s);
+template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_thickness_iso(const THIsoArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_assemble(const AssembleArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R>
 void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const R *X, const double *uA, double *F,
                           hipStream_t s);
-template <typename Tin, typename Tout> void launch_convert(const Tin *src, Tout *dst, size_t n, hipStream_t s);
-void launch_thickness(const THArgs &a, hipStream_t s);
-void launch_recon(const ReconArgs &a, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_convert(const ConvArgs<Tin, Tout> &a, const Geom &g, hipStream_t s);
+void launch_thickness(const THArgs &a, const Geom &g, hipStream_t s);
+void launch_recon(const ReconArgs &a, const Geom &g, hipStream_t s);
 void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s);
+
+// Batched launches: one kernel launch over the blocks of several states.
+// table[b] = (member index into args, that member's block index) for the
+// b-th of `blocks` workgroups, in member order; args and table live in
+// device memory.  nk and add select the template instance (all members of
+// one batched launch share them).
+template <typename A>
+struct BatchLaunch {
+    const A *args;
+    const int2 *table;
+    int blocks;
+};
+template <typename R> void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
+template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
+template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
+template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, const Geom &g, hipStream_t s);
+template <typename R> void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
+template <typename R> void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom &g, hipStream_t s);
+void launch_thickness_batch(const BatchLaunch<THArgs> &b, int nk, const Geom &g, hipStream_t s);
+void launch_recon_batch(const BatchLaunch<ReconArgs> &b, const Geom &g, hipStream_t s);
 
 }  // namespace sse

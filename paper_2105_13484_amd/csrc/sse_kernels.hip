@@ -34,13 +34,15 @@ __device__ __forceinline__ int xcd_block(int nb) {
     return logical < nb ? logical : -1;
 }
 
-// Index of the column owned by this wavefront among n columns (n: none).
+// Index of the column owned by this wavefront among n columns (n: none); a
+// workgroup of w wavefronts owns w consecutive columns.
 // readfirstlane tells the compiler the value is wave-uniform, so mesh-table
 // reads that depend on it become scalar loads instead of 64 identical vector
 // loads.
 __device__ __forceinline__ int column_id(int n) {
-    const int lb = xcd_block((n + kColsPerBlock - 1) / kColsPerBlock);
-    const int col = lb * kColsPerBlock + (threadIdx.x >> 6);
+    const int cpb = blockDim.x >> 6;
+    const int lb = xcd_block((n + cpb - 1) / cpb);
+    const int col = lb * cpb + (threadIdx.x >> 6);
     return __builtin_amdgcn_readfirstlane(lb < 0 ? n : col);
 }
 
@@ -177,9 +179,9 @@ __device__ __forceinline__ void lane_layers(int L, int (&kk)[NK], bool (&ok)[NK]
 // kAdd: the velocity is X + ubar_add (ubar_add non-null), else X itself.
 // ---------------------------------------------------------------------------
 template <int NK, typename R, bool kAdd>
-__global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
+__device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
     const DevMesh &m = a.m;
-    const int i = column_id(m.C);
+    const int i = col;
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -250,9 +252,9 @@ __global__ void __launch_bounds__(kBlock) fe_cell_kernel(FECellArgs<R> a) {
 // Baroclinic forward Euler: vertex pass (relative vorticity of X + ubar_add)
 // ---------------------------------------------------------------------------
 template <int NK, typename R, bool kAdd>
-__global__ void __launch_bounds__(kBlock) fe_vertex_kernel(FEVertexArgs<R> a) {
+__device__ __forceinline__ void fe_vertex_body(const FEVertexArgs<R> &a, int col) {
     const DevMesh &m = a.m;
-    const int v = column_id(m.V);
+    const int v = col;
     if (v >= m.V) return;
     const int L = a.L;
     int kk[NK];
@@ -422,10 +424,10 @@ __device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
 }
 
 template <int NK, typename R, bool kAdd>
-__global__ void __launch_bounds__(kBlock) fe_edge_kernel(FEEdgeArgs<R> a) {
+__device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     const DevMesh &m = a.m;
     const int E = m.E;
-    const int e = column_id(E);
+    const int e = col;
     if (e >= E) return;
     const int L = a.L;
     const size_t base = (size_t)e * L;
@@ -735,17 +737,12 @@ struct BTTables<float> {
     __device__ static const float *H(const DevMesh &m) { return m.H_f; }
 };
 
+// One block of edges (edge_part) or of cells of one evaluation.
 template <typename R>
-__global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs<R> a, int nEdgeBlocks, int nCellBlocks) {
+__device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_part, int lb) {
     const DevMesh &m = a.m;
-    // XCD x owns edge blocks [x * pe, (x + 1) * pe) and cell blocks
-    // [x * pc, (x + 1) * pc): one contiguous region of the mesh per L2.
-    const int pe = (nEdgeBlocks + kXcd - 1) / kXcd, pc = (nCellBlocks + kXcd - 1) / kXcd;
-    const int x = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
     const R tau = (R)a.tau, g = (R)a.g;
-    if (local < pe) {
-        const int lb = x * pe + local;
-        if (lb >= nEdgeBlocks) return;
+    if (edge_part) {
         const int e = lb * blockDim.x + threadIdx.x;
         if (e >= m.E) return;
         if (!m.emask[e]) {
@@ -771,8 +768,6 @@ __global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs<R> a, int nEdge
             a.F[e] = (a.zeroF ? 0.0 : a.F[e]) + a.wF * flux;
         }
     } else {
-        const int lb = x * pc + (local - pe);
-        if (lb >= nCellBlocks) return;
         const int i = lb * blockDim.x + threadIdx.x;
         if (i >= m.C) return;
         if (!m.cmask[i]) { a.zo[i] = R(0); return; }
@@ -797,10 +792,10 @@ __global__ void __launch_bounds__(256) bt_eval_kernel(BTEvalArgs<R> a, int nEdge
 // Thickness stage (z-star): h_out = comb(h_n, h_in + dt T^h), zeta = sum h - H
 // ---------------------------------------------------------------------------
 template <int NK>
-__global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
+__device__ __forceinline__ void thickness_body(const THArgs &a, int col) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int i = column_id(m.C);
+    const int i = col;
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -833,10 +828,10 @@ __global__ void __launch_bounds__(kBlock) thickness_kernel(THArgs a) {
 
 // Thickness stage (isopycnal): per-layer flux divergence, w = 0.
 template <int NK, typename R>
-__global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs<R> a) {
+__device__ __forceinline__ void thickness_iso_body(const THIsoArgs<R> &a, int col) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int i = column_id(m.C);
+    const int i = col;
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
@@ -890,9 +885,9 @@ __global__ void __launch_bounds__(kBlock) thickness_iso_kernel(THIsoArgs<R> a) {
 // ---------------------------------------------------------------------------
 // Reconciliation deficits D^e and adjusted total fluxes (Section 3.4)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) recon_kernel(ReconArgs a) {
+__device__ __forceinline__ void recon_body(const ReconArgs &a, int lb) {
     const DevMesh &m = a.m;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = lb * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
     if (a.ub_half) a.ub_half[e] = 0.75 * a.ub_n[e] + 0.25 * a.ub2[e];
     if (!m.emask[e]) {
@@ -932,10 +927,10 @@ __global__ void __launch_bounds__(256) recon_kernel(ReconArgs a) {
 // u^{n+1} = ubar^{n+1} + ut^{n+1}; split (BBspl) with h^{n+1}
 // ---------------------------------------------------------------------------
 template <int NK, typename R>
-__global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs<R> a) {
+__device__ __forceinline__ void assemble_body(const AssembleArgs<R> &a, int col) {
     const int lane = lane_id();
     const DevMesh &m = a.m;
-    const int e = column_id(m.E);
+    const int e = col;
     if (e >= m.E) return;
     const int L = a.L;
     const size_t base = (size_t)e * L;
@@ -963,7 +958,7 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(AssembleArgs<R> a) {
 }
 
 template <int NK>
-__global__ void __launch_bounds__(kBlock) zeta_kernel(DevMesh m, int L, const double *h, double *zeta) {
+__global__ void __launch_bounds__(1024) zeta_kernel(DevMesh m, int L, const double *h, double *zeta) {
     const int lane = lane_id();
     const int i = column_id(m.C);
     if (i >= m.C) return;
@@ -979,7 +974,7 @@ __global__ void __launch_bounds__(kBlock) zeta_kernel(DevMesh m, int L, const do
 
 // F_e = sum_k h_e (X_k + uA_e)
 template <int NK, typename R>
-__global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const R *X,
+__global__ void __launch_bounds__(1024) edge_flux_sum_kernel(DevMesh m, int L, const double *h, const R *X,
                                                                const double *uA, double *F) {
     const int lane = lane_id();
     const int e = column_id(m.E);
@@ -1001,62 +996,177 @@ __global__ void __launch_bounds__(kBlock) edge_flux_sum_kernel(DevMesh m, int L,
 }
 
 template <typename Tin, typename Tout>
-__global__ void convert_kernel(const Tin *src, Tout *dst, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (Tout)src[i];
+__device__ __forceinline__ void convert_body(const ConvArgs<Tin, Tout> &a, int lb) {
+    const size_t i = (size_t)lb * blockDim.x + threadIdx.x;
+    if (i < a.n) a.dst[i] = (Tout)a.src[i];
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Entry points.  Every kernel body above runs either from a single-state
+// wrapper (the kernel arguments hold the state's argument block) or from a
+// batched wrapper: one launch over the workgroups of several states, where
+// each workgroup reads its (member, block) pair from a device table and the
+// member's argument block from device memory.
 // ---------------------------------------------------------------------------
-static inline dim3 col_grid(int n) {
-    const int nb = (n + kColsPerBlock - 1) / kColsPerBlock;
-    return dim3((unsigned)(kXcd * ((nb + kXcd - 1) / kXcd)));
-}
-static inline dim3 flat_grid(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
-// Columns of up to 64 layers use one register chunk per lane, up to 128 two.
-#define SSE_DISPATCH_NK(L, KERNEL, GRID, ...)                         \
-    do {                                                              \
-        if ((L) <= kWave)                                             \
-            KERNEL<1><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);           \
-        else                                                          \
-            KERNEL<2><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);           \
-    } while (0)
-#define SSE_DISPATCH_NK_R(L, KERNEL, GRID, ...)                       \
-    do {                                                              \
-        if ((L) <= kWave)                                             \
-            KERNEL<1, R><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);        \
-        else                                                          \
-            KERNEL<2, R><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);        \
-    } while (0)
+// (member, member-local block) of this workgroup in a batched launch, with
+// the same XCD renumbering as the single-state launches.
+__device__ __forceinline__ bool batch_entry(const int2 *table, int blocks, int2 &ent) {
+    const int lb = xcd_block(blocks);
+    if (lb < 0) return false;
+    const int2 t = table[lb];
+    ent.x = __builtin_amdgcn_readfirstlane(t.x);
+    ent.y = __builtin_amdgcn_readfirstlane(t.y);
+    return true;
+}
+
+__device__ __forceinline__ int batch_column(int local_block) {
+    return __builtin_amdgcn_readfirstlane(local_block * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
+}
+
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_cell_kernel(FECellArgs<R> a) { fe_cell_body<NK, R, kAdd>(a, column_id(a.m.C)); }
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_cell_batch(BatchLaunch<FECellArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) fe_cell_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_vertex_kernel(FEVertexArgs<R> a) { fe_vertex_body<NK, R, kAdd>(a, column_id(a.m.V)); }
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) fe_vertex_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_edge_kernel(FEEdgeArgs<R> a) { fe_edge_body<NK, R, kAdd>(a, column_id(a.m.E)); }
+template <int NK, typename R, bool kAdd>
+__global__ void __launch_bounds__(1024) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK>
+__global__ void __launch_bounds__(1024) thickness_kernel(THArgs a) { thickness_body<NK>(a, column_id(a.m.C)); }
+template <int NK>
+__global__ void __launch_bounds__(1024) thickness_batch(BatchLaunch<THArgs> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) thickness_body<NK>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) thickness_iso_kernel(THIsoArgs<R> a) { thickness_iso_body<NK, R>(a, column_id(a.m.C)); }
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) thickness_iso_batch(BatchLaunch<THIsoArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) thickness_iso_body<NK, R>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) assemble_kernel(AssembleArgs<R> a) { assemble_body<NK, R>(a, column_id(a.m.E)); }
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) assemble_batch(BatchLaunch<AssembleArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) assemble_body<NK, R>(b.args[t.x], batch_column(t.y));
+}
+
+// Barotropic evaluation: XCD x owns edge blocks [x pe, (x + 1) pe) and cell
+// blocks [x pc, (x + 1) pc), one contiguous region of the mesh per L2.
+template <typename R>
+__global__ void __launch_bounds__(1024) bt_eval_kernel(BTEvalArgs<R> a, int nEdgeBlocks, int nCellBlocks) {
+    const int pe = (nEdgeBlocks + kXcd - 1) / kXcd, pc = (nCellBlocks + kXcd - 1) / kXcd;
+    const int x = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+    if (local < pe) {
+        const int lb = x * pe + local;
+        if (lb < nEdgeBlocks) bt_eval_body<R>(a, true, lb);
+    } else {
+        const int lb = x * pc + (local - pe);
+        if (lb < nCellBlocks) bt_eval_body<R>(a, false, lb);
+    }
+}
+template <typename R>
+__global__ void __launch_bounds__(1024) bt_eval_batch(BatchLaunch<BTEvalArgs<R>> b) {
+    int2 t;
+    if (!batch_entry(b.table, b.blocks, t)) return;
+    const BTEvalArgs<R> &a = b.args[t.x];
+    const int nEB = (a.m.E + (int)blockDim.x - 1) / (int)blockDim.x;
+    if (t.y < nEB)
+        bt_eval_body<R>(a, true, t.y);
+    else
+        bt_eval_body<R>(a, false, t.y - nEB);
+}
+
+__global__ void __launch_bounds__(1024) recon_kernel(ReconArgs a) { recon_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(1024) recon_batch(BatchLaunch<ReconArgs> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) recon_body(b.args[t.x], t.y);
+}
+
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(1024) convert_kernel(ConvArgs<Tin, Tout> a) { convert_body<Tin, Tout>(a, blockIdx.x); }
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(1024) convert_batch(BatchLaunch<ConvArgs<Tin, Tout>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) convert_body<Tin, Tout>(b.args[t.x], t.y);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+bool geom_valid(const Geom &g) {
+    const int c = g.cols_per_block;
+    return (c == 1 || c == 2 || c == 4 || c == 8 || c == 16) && g.block_2d >= 64 && g.block_2d <= 1024 &&
+           g.block_2d % 64 == 0;
+}
+int col_blocks(int n, const Geom &g) { return (n + g.cols_per_block - 1) / g.cols_per_block; }
+int flat_blocks(size_t n, const Geom &g) { return (int)((n + g.block_2d - 1) / g.block_2d); }
+int bt_blocks(int E, int C, const Geom &g) { return flat_blocks(E, g) + flat_blocks(C, g); }
+
+// Grids are rounded up to a multiple of the 8 XCDs; the kernels renumber the
+// workgroups and the padding workgroups exit.
+static inline dim3 xcd_grid(int nb) { return dim3((unsigned)(kXcd * ((nb + kXcd - 1) / kXcd))); }
+static inline dim3 col_block(const Geom &g) { return dim3((unsigned)(kWave * g.cols_per_block)); }
 
 // The column kernels are instantiated for one or two register chunks
 // (L <= 64 or L <= 128) and for the two velocity forms: u = X + ubar
 // (ubar_add non-null) or u = X (the edge pass then forms ut = X - ubar_sub;
 // exactly one of ubar_add and ubar_sub is non-null there).
-#define SSE_DISPATCH_NK_ADD(L, ADD, KERNEL, GRID, ...)                             \
-    do {                                                                          \
-        if ((L) <= kWave) {                                                       \
-            if (ADD) KERNEL<1, R, true><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);     \
-            else KERNEL<1, R, false><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);       \
-        } else {                                                                  \
-            if (ADD) KERNEL<2, R, true><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);     \
-            else KERNEL<2, R, false><<<GRID, kBlock, 0, s>>>(__VA_ARGS__);       \
-        }                                                                         \
+#define SSE_NK_ADD(NK2, ADD, KERNEL, GRID, BLOCK, ARG)                                  \
+    do {                                                                               \
+        if (!(NK2)) {                                                                  \
+            if (ADD) KERNEL<1, R, true><<<GRID, BLOCK, 0, s>>>(ARG);                   \
+            else KERNEL<1, R, false><<<GRID, BLOCK, 0, s>>>(ARG);                      \
+        } else {                                                                       \
+            if (ADD) KERNEL<2, R, true><<<GRID, BLOCK, 0, s>>>(ARG);                   \
+            else KERNEL<2, R, false><<<GRID, BLOCK, 0, s>>>(ARG);                      \
+        }                                                                              \
     } while (0)
 
 template <typename R>
-void launch_fe_cell(const FECellArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_cell_kernel, col_grid(a.m.C), a);
+void launch_fe_cell(const FECellArgs<R> &a, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_cell_kernel, xcd_grid(col_blocks(a.m.C, g)), col_block(g), a);
 }
 template <typename R>
-void launch_fe_vertex(const FEVertexArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_vertex_kernel, col_grid(a.m.V), a);
+void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_vertex_kernel, xcd_grid(col_blocks(a.m.V, g)), col_block(g), a);
 }
 template <typename R>
-void launch_fe_edge(const FEEdgeArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_ADD(a.L, a.ubar_add != nullptr, fe_edge_kernel, col_grid(a.m.E), a);
+void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_edge_kernel, xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
+}
+template <typename R>
+void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(nk == 2, add, fe_cell_batch, xcd_grid(b.blocks), col_block(g), b);
+}
+template <typename R>
+void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(nk == 2, add, fe_vertex_batch, xcd_grid(b.blocks), col_block(g), b);
+}
+template <typename R>
+void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
+    SSE_NK_ADD(nk == 2, add, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
 }
 
 template <typename R>
@@ -1087,51 +1197,103 @@ void set_tiled_lds_limit(size_t bytes) {
 }
 
 template <typename R>
-void launch_bt_eval(const BTEvalArgs<R> &a, hipStream_t s) {
-    const int nEB = (a.m.E + 255) / 256, nCB = (a.m.C + 255) / 256;
+void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s) {
+    const int nEB = flat_blocks(a.m.E, g), nCB = flat_blocks(a.m.C, g);
     const int per = (nEB + kXcd - 1) / kXcd + (nCB + kXcd - 1) / kXcd;
-    bt_eval_kernel<R><<<dim3(kXcd * per), 256, 0, s>>>(a, nEB, nCB);
+    bt_eval_kernel<R><<<dim3(kXcd * per), g.block_2d, 0, s>>>(a, nEB, nCB);
+}
+template <typename R>
+void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, const Geom &g, hipStream_t s) {
+    bt_eval_batch<R><<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
 }
 
-void launch_thickness(const THArgs &a, hipStream_t s) { SSE_DISPATCH_NK(a.L, thickness_kernel, col_grid(a.m.C), a); }
-template <typename R>
-void launch_thickness_iso(const THIsoArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_R(a.L, thickness_iso_kernel, col_grid(a.m.C), a);
+void launch_thickness(const THArgs &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.C, g));
+    if (a.L <= kWave) thickness_kernel<1><<<grid, col_block(g), 0, s>>>(a);
+    else thickness_kernel<2><<<grid, col_block(g), 0, s>>>(a);
+}
+void launch_thickness_batch(const BatchLaunch<THArgs> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) thickness_batch<1><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else thickness_batch<2><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
 }
 template <typename R>
-void launch_assemble(const AssembleArgs<R> &a, hipStream_t s) {
-    SSE_DISPATCH_NK_R(a.L, assemble_kernel, col_grid(a.m.E), a);
+void launch_thickness_iso(const THIsoArgs<R> &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.C, g));
+    if (a.L <= kWave) thickness_iso_kernel<1, R><<<grid, col_block(g), 0, s>>>(a);
+    else thickness_iso_kernel<2, R><<<grid, col_block(g), 0, s>>>(a);
+}
+template <typename R>
+void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) thickness_iso_batch<1, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else thickness_iso_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+}
+template <typename R>
+void launch_assemble(const AssembleArgs<R> &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.E, g));
+    if (a.L <= kWave) assemble_kernel<1, R><<<grid, col_block(g), 0, s>>>(a);
+    else assemble_kernel<2, R><<<grid, col_block(g), 0, s>>>(a);
+}
+template <typename R>
+void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) assemble_batch<1, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else assemble_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
 }
 void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s) {
-    SSE_DISPATCH_NK(L, zeta_kernel, col_grid(m.C), m, L, h, zeta);
+    const dim3 grid = xcd_grid((m.C + 3) / 4);
+    if (L <= kWave) zeta_kernel<1><<<grid, 256, 0, s>>>(m, L, h, zeta);
+    else zeta_kernel<2><<<grid, 256, 0, s>>>(m, L, h, zeta);
 }
 template <typename R>
 void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const R *X, const double *uA, double *F,
                           hipStream_t s) {
-    SSE_DISPATCH_NK_R(L, edge_flux_sum_kernel, col_grid(m.E), m, L, h, X, uA, F);
+    const dim3 grid = xcd_grid((m.E + 3) / 4);
+    if (L <= kWave) edge_flux_sum_kernel<1, R><<<grid, 256, 0, s>>>(m, L, h, X, uA, F);
+    else edge_flux_sum_kernel<2, R><<<grid, 256, 0, s>>>(m, L, h, X, uA, F);
 }
-void launch_recon(const ReconArgs &a, hipStream_t s) { recon_kernel<<<flat_grid(a.m.E), 256, 0, s>>>(a); }
-
+void launch_recon(const ReconArgs &a, const Geom &g, hipStream_t s) {
+    recon_kernel<<<flat_blocks(a.m.E, g), g.block_2d, 0, s>>>(a);
+}
+void launch_recon_batch(const BatchLaunch<ReconArgs> &b, const Geom &g, hipStream_t s) {
+    recon_batch<<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
+}
 template <typename Tin, typename Tout>
-void launch_convert(const Tin *src, Tout *dst, size_t n, hipStream_t s) {
-    if (n) convert_kernel<Tin, Tout><<<flat_grid(n), 256, 0, s>>>(src, dst, n);
+void launch_convert(const ConvArgs<Tin, Tout> &a, const Geom &g, hipStream_t s) {
+    if (a.n) convert_kernel<Tin, Tout><<<flat_blocks(a.n, g), g.block_2d, 0, s>>>(a);
+}
+template <typename Tin, typename Tout>
+void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom &g, hipStream_t s) {
+    convert_batch<Tin, Tout><<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
 }
 
 #define SSE_INSTANTIATE(R)                                                                                   \
-    template void launch_fe_cell<R>(const FECellArgs<R> &, hipStream_t);                                   \
-    template void launch_fe_vertex<R>(const FEVertexArgs<R> &, hipStream_t);                               \
-    template void launch_fe_edge<R>(const FEEdgeArgs<R> &, hipStream_t);                                   \
+    template void launch_fe_cell<R>(const FECellArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_fe_vertex<R>(const FEVertexArgs<R> &, const Geom &, hipStream_t);                 \
+    template void launch_fe_edge<R>(const FEEdgeArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_fe_cell_batch<R>(const BatchLaunch<FECellArgs<R>> &, int, bool, const Geom &,     \
+                                          hipStream_t);                                                    \
+    template void launch_fe_vertex_batch<R>(const BatchLaunch<FEVertexArgs<R>> &, int, bool, const Geom &, \
+                                            hipStream_t);                                                  \
+    template void launch_fe_edge_batch<R>(const BatchLaunch<FEEdgeArgs<R>> &, int, bool, const Geom &,     \
+                                          hipStream_t);                                                    \
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
-    template void launch_bt_eval<R>(const BTEvalArgs<R> &, hipStream_t);                                   \
-    template void launch_thickness_iso<R>(const THIsoArgs<R> &, hipStream_t);                              \
-    template void launch_assemble<R>(const AssembleArgs<R> &, hipStream_t);                                \
+    template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, const Geom &, hipStream_t);  \
+    template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \
+    template void launch_thickness_iso_batch<R>(const BatchLaunch<THIsoArgs<R>> &, int, const Geom &,      \
+                                                hipStream_t);                                              \
+    template void launch_assemble<R>(const AssembleArgs<R> &, const Geom &, hipStream_t);                  \
+    template void launch_assemble_batch<R>(const BatchLaunch<AssembleArgs<R>> &, int, const Geom &,        \
+                                           hipStream_t);                                                   \
     template void launch_edge_flux_sum<R>(const DevMesh &, int, const double *, const R *, const double *, \
                                           double *, hipStream_t);
 SSE_INSTANTIATE(double)
 SSE_INSTANTIATE(float)
-template void launch_convert<double, double>(const double *, double *, size_t, hipStream_t);
-template void launch_convert<double, float>(const double *, float *, size_t, hipStream_t);
-template void launch_convert<float, double>(const float *, double *, size_t, hipStream_t);
+template void launch_convert<double, float>(const ConvArgs<double, float> &, const Geom &, hipStream_t);
+template void launch_convert<float, double>(const ConvArgs<float, double> &, const Geom &, hipStream_t);
+template void launch_convert_batch<double, float>(const BatchLaunch<ConvArgs<double, float>> &, const Geom &,
+                                                  hipStream_t);
+template void launch_convert_batch<float, double>(const BatchLaunch<ConvArgs<float, double>> &, const Geom &,
+                                                  hipStream_t);
 
 }  // namespace sse

@@ -27,7 +27,10 @@ EXPORTED = (
     "sse_mesh_destroy", "sse_state_workspace_bytes", "sse_state_create", "sse_state_destroy", "sse_state_init",
     "sse_step", "sse_step_async", "sse_sync", "sse_read_state", "sse_profile_enable", "sse_profile_read",
     "sse_debug_baroclinic_feuler", "sse_debug_barotropic_substep", "sse_debug_thickness_stage",
-    "sse_state_set_edge_variant", "sse_state_get_edge_variant",
+    "sse_state_set_edge_variant", "sse_state_get_edge_variant", "sse_state_set_geometry", "sse_state_use_graph",
+    "sse_batch_create", "sse_batch_destroy", "sse_batch_add", "sse_batch_remove", "sse_batch_size",
+    "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
+    "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -99,6 +102,21 @@ def load():
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
+        "sse_state_set_geometry": (c_int, [P, c_int, c_int]),
+        "sse_state_use_graph": (c_int, [P, c_int]),
+        "sse_batch_create": (c_int, [P, POINTER(P)]),
+        "sse_batch_destroy": (c_int, [P]),
+        "sse_batch_add": (c_int, [P, P]),
+        "sse_batch_remove": (c_int, [P, P]),
+        "sse_batch_size": (c_int, [P, POINTER(c_int32)]),
+        "sse_batch_set_geometry": (c_int, [P, c_int, c_int]),
+        "sse_batch_program_bytes": (c_int, [P, POINTER(c_size_t)]),
+        "sse_batch_compile": (c_int, [P, P, c_size_t]),
+        "sse_batch_launches_per_step": (c_int, [P, POINTER(c_int32)]),
+        "sse_batch_use_graph": (c_int, [P, c_int]),
+        "sse_batch_step_async": (c_int, [P, c_int32]),
+        "sse_batch_sync": (c_int, [P]),
+        "sse_batch_step": (c_int, [P, c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +285,14 @@ class DeviceState:
     def edge_variant(self, variant: int):
         _check(load().sse_state_set_edge_variant(self.handle, int(variant)))
 
+    def set_geometry(self, cols_per_block: int = 4, block_2d: int = 256):
+        """Launch geometry (wavefronts per column-kernel workgroup, threads per 2D workgroup)."""
+        _check(load().sse_state_set_geometry(self.handle, int(cols_per_block), int(block_2d)))
+
+    def use_graph(self, enable: bool = True):
+        """Replay each step as one captured HIP graph (needs a non-default stream)."""
+        _check(load().sse_state_use_graph(self.handle, int(bool(enable))))
+
     def try_edge_variant(self, variant: int) -> bool:
         """Select an edge-pass variant; False (and no change) if it does not fit."""
         rc = load().sse_state_set_edge_variant(self.handle, int(variant))
@@ -321,3 +347,77 @@ def state_from_case(case, device="cuda", stream=None, params=None):
     st = DeviceState(dm, params if params is not None else case.params, device=device, stream=stream)
     st.init(case.h, case.u, case.rho, case.h_ref)
     return dm, st
+
+
+class Batch:
+    """Several DeviceStates advanced together, one launch per step phase.
+
+    Members must share precision, scheme and vertical coordinate and must have
+    been created on the batch's stream.  ``compile()`` allocates the device
+    buffer for the merged launch program (a torch tensor) and uploads it.
+    """
+
+    def __init__(self, stream=None):
+        self.stream = stream
+        self.handle = c_void_p()
+        _check(load().sse_batch_create(_stream_ptr(stream), byref(self.handle)))
+        self.members = []
+        self.buf = None
+
+    def add(self, state: "DeviceState"):
+        _check(load().sse_batch_add(self.handle, state.handle))
+        self.members.append(state)
+        self.buf = None
+
+    def remove(self, state: "DeviceState"):
+        _check(load().sse_batch_remove(self.handle, state.handle))
+        self.members = [m for m in self.members if m is not state]
+        self.buf = None
+
+    def __len__(self):
+        return len(self.members)
+
+    def set_geometry(self, cols_per_block: int = 4, block_2d: int = 256):
+        _check(load().sse_batch_set_geometry(self.handle, int(cols_per_block), int(block_2d)))
+        self.buf = None
+
+    def compile(self, device="cuda"):
+        lib = load()
+        nbytes = c_size_t()
+        _check(lib.sse_batch_program_bytes(self.handle, byref(nbytes)))
+        self.buf, ptr = _aligned_buffer(max(nbytes.value, 256), device)
+        _check(lib.sse_batch_compile(self.handle, c_void_p(ptr), nbytes.value))
+        return nbytes.value
+
+    def launches_per_step(self) -> int:
+        n = c_int32()
+        _check(load().sse_batch_launches_per_step(self.handle, byref(n)))
+        return int(n.value)
+
+    def use_graph(self, enable: bool = True):
+        _check(load().sse_batch_use_graph(self.handle, int(bool(enable))))
+
+    def step(self, n: int = 1) -> int:
+        if self.buf is None:
+            self.compile()
+        return _check(load().sse_batch_step(self.handle, int(n)), allow=(SSE_ENONFINITE,))
+
+    def step_async(self, n: int = 1):
+        if self.buf is None:
+            self.compile()
+        _check(load().sse_batch_step_async(self.handle, int(n)))
+
+    def sync(self) -> int:
+        return _check(load().sse_batch_sync(self.handle), allow=(SSE_ENONFINITE,))
+
+    def close(self):
+        if self.handle:
+            load().sse_batch_destroy(self.handle)
+            self.handle = c_void_p()
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
