@@ -82,7 +82,7 @@ def measured_traffic(dom):
     return float(c["fetch_bytes_per_launch"]) + float(c["write_bytes_per_launch"])
 
 
-def cpu_baseline(n=128, steps=2):
+def cpu_baseline(n=128, steps=6):
     """The FP64 oracle on the same recipe at n x n cells (same L, M, dt)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import ssprk_se
@@ -116,6 +116,96 @@ def timed_steps(torch, st, steps):
     return ev0.elapsed_time(ev1) / steps
 
 
+def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
+    """C3: a 64-member ensemble of uneven planar members in mixed precision,
+    per-member loop vs one batch (autotuned launch geometry, HIP graph)."""
+    from paper_2105_13484_amd import autotune
+    stream = torch.cuda.Stream()
+    log(f"[bench] ensemble: building {members} members")
+    cs = [cases.c3_member(i) for i in range(members)]
+    keep = [ssprkse.state_from_case(c, device="cuda:0", stream=stream) for c in cs]
+    sts = [st for _, st in keep]
+    cl = sum(c.active_cell_layers for c in cs)
+
+    def loop(n):
+        for _ in range(n):
+            for st in sts:
+                st.step_async(1)
+
+    for st in sts:
+        assert st.step(1) == 0
+    ms_loop = autotune._time_steps(torch, stream, loop, steps)
+    log(f"[bench] ensemble per-member loop: {ms_loop:.2f} ms/step")
+    b = ssprkse.Batch(stream=stream)
+    for st in sts:
+        b.add(st)
+    b.compile()
+    assert b.step(1) == 0
+    ms_plain = autotune._time_steps(torch, stream, lambda n: b.step_async(n), steps)
+    tuned = autotune.tune_batch(b, steps=2)
+    b.use_graph(True)
+    assert b.step(1) == 0
+    ms_batch = autotune._time_steps(torch, stream, lambda n: b.step_async(n), steps)
+    assert b.sync() == 0
+    log(f"[bench] ensemble batch: {ms_plain:.2f} ms/step default geometry, {ms_batch:.2f} ms/step tuned + graph "
+        f"({tuned['best']})")
+    out = {"workload": f"C3: {members} planar hex members, n in {{64,128,192,256}}, L in {{20,40,60}}, "
+                       "M in [10,30], mixed precision",
+           "cell_layers_per_step": cl, "per_member_loop_ms_per_step": ms_loop,
+           "batch_default_geometry_ms_per_step": ms_plain, "batch_tuned_graph_ms_per_step": ms_batch,
+           "per_member_loop_cell_layer_updates_per_s": cl / (ms_loop * 1e-3),
+           "batch_cell_layer_updates_per_s": cl / (ms_batch * 1e-3),
+           "speedup_vs_per_member_loop": ms_loop / ms_batch, "tuned": tuned["best"],
+           "tuning_trials": len(tuned["trials"]), "launches_per_step": b.launches_per_step()}
+    b.close()
+    return out
+
+
+def serve_leg(torch, ssprkse, cases, n_requests=24, load=0.8, full=False):
+    """C4: Poisson arrivals of sphere requests, continuous batching under an HBM
+    budget.  Capacity is measured first with every request queued at t = 0;
+    arrivals then come at `load` x that capacity.  The default mix is the
+    served recipe at reduced size (levels 4-6, 10-40 steps); full=True uses
+    levels 5-8 and 50-500 steps."""
+    import numpy as np
+    from paper_2105_13484_amd.serve import Engine, Request, poisson_arrivals
+
+    def make(i):
+        rng = np.random.default_rng(cases.SEED_BASE + 400 + i)
+        if full:
+            c = cases.c4_request(i)
+            return c, int(c.steps)
+        level = int(rng.integers(4, 7))
+        L = int(rng.integers(16, 101))
+        steps = int(rng.integers(10, 41))
+        c = cases.sphere_case(level, L, cases.SEED_BASE + 400 + i, substeps=30, dt_btr=cases.served_dt_btr(level))
+        c = cases.with_params(c, precision=int(rng.integers(0, 2)))
+        return c, steps
+
+    log(f"[bench] serving: building {n_requests} requests")
+    made = [make(i) for i in range(n_requests)]
+
+    def requests(arrivals):
+        return [Request(rid=i, case=c, steps=s, arrival=a) for i, ((c, s), a) in enumerate(zip(made, arrivals))]
+
+    eng = Engine(budget_bytes=200 << 30, chunk_steps=10, keep_results=False)
+    closed = eng.run(requests([0.0] * n_requests))
+    cap = n_requests / closed["wall_s"]
+    log(f"[bench] serving capacity (all queued at t=0): {cap:.2f} requests/s, "
+        f"{closed['cell_layer_updates_per_s']:.3g} cell-layer updates/s")
+    arr = poisson_arrivals(n_requests, load * cap, cases.SEED_BASE + 499)
+    opened = eng.run(requests(arr))
+    eng.close()
+    log(f"[bench] serving at {load:.1f}x capacity: p50 {opened['p50_s']:.3f} s, p99 {opened['p99_s']:.3f} s")
+    return {"workload": ("C4 served recipe: icosahedral levels 5-8, L 16-100, 50-500 steps" if full else
+                         "C4 served recipe at reduced size: icosahedral levels 4-6, L 16-100, 10-40 steps") +
+                        ", FP64 or mixed at random, M = 30, HBM budget 200 GB",
+            "requests": n_requests, "capacity_requests_per_s": cap,
+            "closed_loop_cell_layer_updates_per_s": closed["cell_layer_updates_per_s"],
+            "load": load, "p50_s": opened["p50_s"], "p99_s": opened["p99_s"],
+            "cell_layer_updates_per_s": opened["cell_layer_updates_per_s"], "failed": opened["failed"]}
+
+
 def copy_probe():
     import torch
     a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
@@ -136,6 +226,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing")
     ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-full", action="store_true", help="serving leg with the full request recipe")
     ap.add_argument("--copy-probe", action="store_true", help="run only a plain device copy and exit")
     args = ap.parse_args()
 
@@ -223,6 +316,9 @@ def main():
             del st2, dm2
         c2["mixed_vs_fp64_speedup"] = c2["fp64_ms_per_step"] / c2["mixed_ms_per_step"]
 
+    ensemble = None if args.no_ensemble else ensemble_leg(torch, ssprkse, cases)
+    serving = None if args.no_serve else serve_leg(torch, ssprkse, cases, full=args.serve_full)
+
     value = cell_layers / (ms_step * 1e-3)
     step_gbs = STEP_BYTES_PER_CELL_LAYER * cell_layers / (ms_step * 1e-3) / 1e9
     out = {
@@ -250,6 +346,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kb, "launch_ms": avg_ms},
         "c2": c2,
+        "ensemble": ensemble,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -187,6 +187,12 @@ int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
 int sse_state_set_edge_variant(sse_state *s, int variant);
 int sse_state_get_edge_variant(const sse_state *s, int *variant);
 
+/* Device bytes one state of these parameters on this mesh needs in total:
+ * the mesh image (sse_mesh_device_bytes) plus the workspace
+ * (sse_state_workspace_bytes).  Reads only the counts in d; allocates
+ * nothing.  For admission control by a device-memory budget. */
+int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, size_t *bytes);
+
 /* Launch geometry of the state's kernels; results do not depend on it.
  * cols_per_block: wavefronts per workgroup of the column kernels (one
  * wavefront per vertical column), 1, 2, 4, 8 or 16; block_2d: threads per

@@ -663,6 +663,17 @@ extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p,
     return SSE_OK;
 }
 
+extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, size_t *bytes) {
+    if (!d || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { set_error("mesh counts must be positive"); return SSE_EINVAL; }
+    size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
+    for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
+    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision));
+    return SSE_OK;
+}
+
 extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *dev_workspace, size_t bytes,
                                 void *stream, sse_state **out) {
     if (!m || !out) { set_error("NULL argument"); return SSE_EINVAL; }

@@ -30,7 +30,7 @@ EXPORTED = (
     "sse_state_set_edge_variant", "sse_state_get_edge_variant", "sse_state_set_geometry", "sse_state_use_graph",
     "sse_batch_create", "sse_batch_destroy", "sse_batch_add", "sse_batch_remove", "sse_batch_size",
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
-    "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step",
+    "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -117,6 +117,7 @@ def load():
         "sse_batch_step_async": (c_int, [P, c_int32]),
         "sse_batch_sync": (c_int, [P]),
         "sse_batch_step": (c_int, [P, c_int32]),
+        "sse_footprint_bytes": (c_int, [POINTER(sse_mesh_desc), POINTER(sse_params), POINTER(c_size_t)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +180,17 @@ def make_params(p) -> sse_params:
     for name, _ in sse_params._fields_:
         setattr(out, name, getattr(p, name))
     return out
+
+
+def footprint_bytes(mesh, params) -> int:
+    """Device bytes (mesh image + workspace) of one state of `params` on `mesh`."""
+    C, E, V = mesh.nCells, mesh.nEdges, mesh.nVertices
+    d = sse_mesh_desc()
+    d.n_cells, d.n_edges, d.n_vertices = C, E, V
+    p = make_params(params)
+    n = c_size_t()
+    _check(load().sse_footprint_bytes(byref(d), byref(p), byref(n)))
+    return int(n.value)
 
 
 def sse_mesh_validate(mesh, bottom_depth, cell_mask) -> int:

@@ -208,6 +208,14 @@ def c3_member(member: int) -> Case:
                 np.ones(C, np.uint8), 100, seed, meta={"n": n, "kfront": kfront})
 
 
+def served_dt_btr(level: int) -> float:
+    """Barotropic substep of a served request: 60 s at level 7, halved per finer
+    level; coarser levels keep 60 s (dt = 1800 s with M = 30), since with
+    dt of several hours the explicit bottom drag on thin bottom layers is
+    unstable."""
+    return 60.0 * 2.0 ** min(0, 7 - level)
+
+
 def c4_request(i: int, max_level: int = 8) -> Case:
     seed = SEED_BASE + 400 + i
     rng = np.random.default_rng(seed)
@@ -215,7 +223,7 @@ def c4_request(i: int, max_level: int = 8) -> Case:
     L = int(rng.integers(16, 101))
     steps = int(rng.integers(50, 501))
     mixed = bool(rng.integers(0, 2))
-    case = sphere_case(level, L, seed, substeps=30, dt_btr=60.0 * 2.0 ** (7 - level), name=f"c4[{i}]")
+    case = sphere_case(level, L, seed, substeps=30, dt_btr=served_dt_btr(level), name=f"c4[{i}]")
     case.params.precision = 1 if mixed else 0
     case.steps = steps
     return case
