@@ -95,6 +95,48 @@ Work carve(void *buf, int C, int E, int V, int L, size_t rs) {
 template <typename R>
 R *rp(void *p) { return static_cast<R *>(p); }
 
+constexpr int kPatchCells = 512;  // cells per locality patch of the internal numbering
+constexpr int kLocalSpan = 1024;  // index distance below which two cells count as near
+
+// Share of edges whose two cells are at most kLocalSpan apart in a numbering
+// (the caller's if o is null).
+double local_share(const sse_mesh_desc *d, const MeshOrder *o) {
+    long near = 0;
+    for (int e = 0; e < d->n_edges; ++e) {
+        int a = d->cells_on_edge[2 * (size_t)e], b = d->cells_on_edge[2 * (size_t)e + 1];
+        if (a < 0 || b < 0) continue;
+        if (o) { a = o->cell_new[a]; b = o->cell_new[b]; }
+        near += std::abs(a - b) <= kLocalSpan;
+    }
+    return d->n_edges ? (double)near / d->n_edges : 1.0;
+}
+
+void identity_order(const sse_mesh_desc *d, MeshOrder &o) {
+    auto iota = [](std::vector<int32_t> &v, int n) {
+        v.resize(n);
+        for (int i = 0; i < n; ++i) v[i] = i;
+    };
+    iota(o.cell_old, d->n_cells);
+    iota(o.cell_new, d->n_cells);
+    iota(o.edge_old, d->n_edges);
+    iota(o.edge_new, d->n_edges);
+    iota(o.vert_old, d->n_vertices);
+    iota(o.vert_new, d->n_vertices);
+}
+
+// Rows of a host array between the caller's numbering and the internal one
+// (old_of_new[i] = caller index of internal entity i).
+template <typename T>
+void rows_to_internal(const T *user, T *internal, const std::vector<int32_t> &old_of_new, size_t row) {
+    for (size_t i = 0; i < old_of_new.size(); ++i)
+        std::memcpy(internal + i * row, user + (size_t)old_of_new[i] * row, row * sizeof(T));
+}
+template <typename T>
+void rows_to_user(const T *internal, T *user, const std::vector<int32_t> &old_of_new, size_t row) {
+    for (size_t i = 0; i < old_of_new.size(); ++i)
+        std::memcpy(user + (size_t)old_of_new[i] * row, internal + i * row, row * sizeof(T));
+}
+
 int hip_fail(hipError_t e, const char *what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return SSE_EDEVICE;
@@ -552,6 +594,20 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     std::string err;
     int rc = validate_desc(d, err);
     if (rc != SSE_OK) { set_error(err); return rc; }
+    // Renumber for locality: cells in compact patches, edges and vertices
+    // after their cells.  Every table below is built in the new numbering;
+    // the host-side state I/O translates at the boundary.
+    // The caller's numbering is kept when it is already at least as local
+    // (share of edges whose two cells lie within kLocalSpan indices).
+    MeshOrder ord;
+    locality_order(d, kPatchCells, ord);
+    PermutedDesc pd;
+    if (local_share(d, nullptr) >= local_share(d, &ord)) {
+        identity_order(d, ord);
+    } else {
+        permute_desc(d, ord, pd);
+        d = &pd.d;
+    }
     MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
     size_t need = lay.total;
     for (int q = 0; q < kTileVariants; ++q) need += tiles_bytes(d, kTileSizes[q]);
@@ -616,6 +672,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.cell_div_t_f = (const float *)P(27);
     dm.H_f = (const float *)P(28);
     m->cells_on_edge = t.edge_cells;
+    m->cell_old = ord.cell_old;
+    m->edge_old = ord.edge_old;
     // Gather lists of the LDS-staged edge pass for tiles of 8, 16 and 32 edges.
     size_t cursor = lay.total;
     for (int q = 0; q < kTileVariants; ++q) {
@@ -745,7 +803,15 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
         set_error("non-finite value in the initial state");
         return SSE_ENONFINITE;
     }
-    std::vector<double> frac(CL, 0.0), um(u, u + EL);
+    // caller numbering -> internal numbering
+    std::vector<double> hi(CL), ri(CL), hri, um(EL), frac(CL, 0.0);
+    rows_to_internal(h, hi.data(), m->cell_old, L);
+    rows_to_internal(rho, ri.data(), m->cell_old, L);
+    rows_to_internal(u, um.data(), m->edge_old, L);
+    if (h_ref) {
+        hri.resize(CL);
+        rows_to_internal(h_ref, hri.data(), m->cell_old, L);
+    }
     std::vector<uint8_t> cmask(m->C);
     SSE_HIP(hipMemcpy(cmask.data(), m->d.cmask, m->C, hipMemcpyDeviceToHost));
     for (int e = 0; e < m->E; ++e) {
@@ -756,15 +822,15 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
         for (int i = 0; i < m->C; ++i) {
             if (!cmask[i]) continue;
             double tot = 0.0;
-            for (int k = 0; k < L; ++k) tot += h_ref[(size_t)i * L + k];
+            for (int k = 0; k < L; ++k) tot += hri[(size_t)i * L + k];
             if (!(tot > 0)) { set_error("h_ref must have a positive column sum on ocean cells"); return SSE_EINVAL; }
-            for (int k = 0; k < L; ++k) frac[(size_t)i * L + k] = h_ref[(size_t)i * L + k] / tot;
+            for (int k = 0; k < L; ++k) frac[(size_t)i * L + k] = hri[(size_t)i * L + k] / tot;
         }
     }
     Work &w = s->w;
-    SSE_HIP(hipMemcpyAsync(w.Hs, h, CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(w.Hs, hi.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_TRY(upload_real(s, w.U, um.data(), EL));
-    SSE_HIP(hipMemcpyAsync(w.rho, rho, CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(w.rho, ri.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_HIP(hipMemcpyAsync(w.frac, frac.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s->stream));
     launch_zeta_from_h(m->d, L, w.Hs, w.zeta_n, s->stream);
@@ -867,14 +933,19 @@ extern "C" int sse_read_state(const sse_state *cs, double *h, double *u, double 
     if (!cs) { set_error("NULL state"); return SSE_EINVAL; }
     if (!cs->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
     const sse_mesh *m = cs->mesh;
-    const int L = cs->p.n_layers;
+    const size_t L = cs->p.n_layers;
     const Work &w = cs->w;
     hipStream_t st = cs->stream;
-    if (h) SSE_HIP(hipMemcpyAsync(h, w.Hs, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
-    if (u) SSE_TRY(download_real(cs, u, w.U, (size_t)m->E * L));
-    if (zeta) SSE_HIP(hipMemcpyAsync(zeta, w.zeta_n, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
-    if (ubar) SSE_HIP(hipMemcpyAsync(ubar, w.ubar_n, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    std::vector<double> hi(h ? m->C * L : 0), ui(u ? m->E * L : 0), zi(zeta ? m->C : 0), bi(ubar ? m->E : 0);
+    if (h) SSE_HIP(hipMemcpyAsync(hi.data(), w.Hs, hi.size() * 8, hipMemcpyDeviceToHost, st));
+    if (u) SSE_TRY(download_real(cs, ui.data(), w.U, ui.size()));
+    if (zeta) SSE_HIP(hipMemcpyAsync(zi.data(), w.zeta_n, zi.size() * 8, hipMemcpyDeviceToHost, st));
+    if (ubar) SSE_HIP(hipMemcpyAsync(bi.data(), w.ubar_n, bi.size() * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
+    if (h) rows_to_user(hi.data(), h, m->cell_old, L);
+    if (u) rows_to_user(ui.data(), u, m->edge_old, L);
+    if (zeta) rows_to_user(zi.data(), zeta, m->cell_old, 1);
+    if (ubar) rows_to_user(bi.data(), ubar, m->edge_old, 1);
     return SSE_OK;
 }
 
@@ -906,13 +977,18 @@ extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const 
     if (!s || !u || !ubar || !zeta || !h || !ut1 || !G) { set_error("NULL argument"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("state not initialised (rho and h_ref are needed)"); return SSE_ESTATE; }
     const sse_mesh *m = s->mesh;
-    const int L = s->p.n_layers;
+    const size_t L = s->p.n_layers, C = m->C, E = m->E;
     Work &w = s->w;
     hipStream_t st = s->stream;
-    SSE_TRY(upload_real(s, w.T2, u, (size_t)m->E * L));
-    SSE_HIP(hipMemcpyAsync(w.ub2, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
-    SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
-    SSE_HIP(hipMemcpyAsync(w.H1, h, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
+    std::vector<double> ui(E * L), bi(E), zi(C), hi(C * L), oi(E * L), gi(E);
+    rows_to_internal(u, ui.data(), m->edge_old, L);
+    rows_to_internal(ubar, bi.data(), m->edge_old, 1);
+    rows_to_internal(zeta, zi.data(), m->cell_old, 1);
+    rows_to_internal(h, hi.data(), m->cell_old, L);
+    SSE_TRY(upload_real(s, w.T2, ui.data(), E * L));
+    SSE_HIP(hipMemcpyAsync(w.ub2, bi.data(), E * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.z1, zi.data(), C * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.H1, hi.data(), C * L * 8, hipMemcpyHostToDevice, st));
     const double saved = s->p.dt;
     s->p.dt = dt;
     if (s->rs == 4)
@@ -923,9 +999,11 @@ extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const 
                         w.Sh1, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, 0);
     s->p.dt = saved;
     SSE_HIP(hipGetLastError());
-    SSE_TRY(download_real(s, ut1, w.T1, (size_t)m->E * L));
-    SSE_HIP(hipMemcpyAsync(G, w.G0, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_TRY(download_real(s, oi.data(), w.T1, E * L));
+    SSE_HIP(hipMemcpyAsync(gi.data(), w.G0, E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
+    rows_to_user(oi.data(), ut1, m->edge_old, L);
+    rows_to_user(gi.data(), G, m->edge_old, 1);
     return SSE_OK;
 }
 
@@ -936,20 +1014,28 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
     if (scheme != 2 && scheme != 3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
     if (M < 1 || !(dt > 0)) { set_error("M must be >= 1 and dt > 0"); return SSE_EINVAL; }
     const sse_mesh *m = s->mesh;
+    const size_t C = m->C, E = m->E;
     Work &w = s->w;
     hipStream_t st = s->stream;
-    SSE_HIP(hipMemcpyAsync(w.ub1, ubar, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
-    SSE_HIP(hipMemcpyAsync(w.z1, zeta, (size_t)m->C * 8, hipMemcpyHostToDevice, st));
-    SSE_HIP(hipMemcpyAsync(w.G0, G, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    std::vector<double> bi(E), zi(C), gi(E), bo(E), zo(C), fo(E);
+    rows_to_internal(ubar, bi.data(), m->edge_old, 1);
+    rows_to_internal(zeta, zi.data(), m->cell_old, 1);
+    rows_to_internal(G, gi.data(), m->edge_old, 1);
+    SSE_HIP(hipMemcpyAsync(w.ub1, bi.data(), E * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.z1, zi.data(), C * 8, hipMemcpyHostToDevice, st));
+    SSE_HIP(hipMemcpyAsync(w.G0, gi.data(), E * 8, hipMemcpyHostToDevice, st));
     if (s->rs == 4)
         bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
     else
         bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
     SSE_HIP(hipGetLastError());
-    SSE_HIP(hipMemcpyAsync(ubar1, w.ub2, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
-    SSE_HIP(hipMemcpyAsync(zeta1, w.bt_zout, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
-    SSE_HIP(hipMemcpyAsync(Fzeta, w.Fz1, (size_t)m->E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(bo.data(), w.ub2, E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(zo.data(), w.bt_zout, C * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(fo.data(), w.Fz1, E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
+    rows_to_user(bo.data(), ubar1, m->edge_old, 1);
+    rows_to_user(zo.data(), zeta1, m->cell_old, 1);
+    rows_to_user(fo.data(), Fzeta, m->edge_old, 1);
     return SSE_OK;
 }
 
@@ -958,25 +1044,32 @@ extern "C" int sse_debug_thickness_stage(sse_state *s, const double *h_in, const
     if (!s || !h_in || !u || !uA || !h_out || !zeta_out) { set_error("NULL argument"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("state not initialised (h_ref is needed)"); return SSE_ESTATE; }
     const sse_mesh *m = s->mesh;
-    const int L = s->p.n_layers;
+    const size_t L = s->p.n_layers, C = m->C, E = m->E;
     Work &w = s->w;
     hipStream_t st = s->stream;
-    SSE_HIP(hipMemcpyAsync(w.H1, h_in, (size_t)m->C * L * 8, hipMemcpyHostToDevice, st));
-    SSE_TRY(upload_real(s, w.T2, u, (size_t)m->E * L));
-    SSE_HIP(hipMemcpyAsync(w.uA, uA, (size_t)m->E * 8, hipMemcpyHostToDevice, st));
+    std::vector<double> hi(C * L), ui(E * L), ai(E), ho(C * L), zo(C);
+    rows_to_internal(h_in, hi.data(), m->cell_old, L);
+    rows_to_internal(u, ui.data(), m->edge_old, L);
+    rows_to_internal(uA, ai.data(), m->edge_old, 1);
+    SSE_HIP(hipMemcpyAsync(w.H1, hi.data(), C * L * 8, hipMemcpyHostToDevice, st));
+    SSE_TRY(upload_real(s, w.T2, ui.data(), E * L));
+    SSE_HIP(hipMemcpyAsync(w.uA, ai.data(), E * 8, hipMemcpyHostToDevice, st));
+    const int Li = (int)L;
     if (s->rs == 4) {
-        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<float>(m->d, L, w.H1, rp<float>(w.T2), w.uA, w.Ftot, st);
+        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<float>(m->d, Li, w.H1, rp<float>(w.T2), w.uA, w.Ftot, st);
         thickness<float>(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, rp<float>(w.T2), 1.0, nullptr, 0.0, nullptr,
                          0.0, dt);
     } else {
-        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<double>(m->d, L, w.H1, rp<double>(w.T2), w.uA, w.Ftot, st);
+        if (s->p.vcoord == SSE_ZSTAR) launch_edge_flux_sum<double>(m->d, Li, w.H1, rp<double>(w.T2), w.uA, w.Ftot, st);
         thickness<double>(s, w.H1, nullptr, COMB_NONE, w.H2, w.z_half, rp<double>(w.T2), 1.0, nullptr, 0.0,
                           nullptr, 0.0, dt);
     }
     SSE_HIP(hipGetLastError());
-    SSE_HIP(hipMemcpyAsync(h_out, w.H2, (size_t)m->C * L * 8, hipMemcpyDeviceToHost, st));
-    SSE_HIP(hipMemcpyAsync(zeta_out, w.z_half, (size_t)m->C * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(ho.data(), w.H2, C * L * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(zo.data(), w.z_half, C * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
+    rows_to_user(ho.data(), h_out, m->cell_old, L);
+    rows_to_user(zo.data(), zeta_out, m->cell_old, 1);
     return SSE_OK;
 }
 

@@ -85,6 +85,9 @@ struct sse_mesh {
     sse::DevMesh d;
     int C = 0, E = 0, V = 0;
     int n_ocean_cells = 0;
+    // Internal (locality) numbering: entity i of the device arrays is entity
+    // cell_old[i] / edge_old[i] of the caller's numbering.
+    std::vector<int32_t> cell_old, edge_old;
     std::vector<int32_t> cells_on_edge;     // host copy (for debug helpers)
     sse::DevTiles tiles[sse::kTileVariants];  // T = 8, 16, 32 edges per tile
     void *dev_buf = nullptr;
@@ -128,6 +131,25 @@ struct HostTiles {
 // Returns false if a tile needs more than 255 entries in one list.
 bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t);
 size_t tiles_bytes(const sse_mesh_desc *d, int T);
+
+// Locality order of a mesh (new -> old and old -> new numbering): cells in
+// compact breadth-first patches of `patch` cells, edges following the first
+// cell that lists them, vertices following the first edge that lists them.
+struct MeshOrder {
+    std::vector<int32_t> cell_old, edge_old, vert_old;
+    std::vector<int32_t> cell_new, edge_new, vert_new;
+};
+void locality_order(const sse_mesh_desc *d, int patch, MeshOrder &o);
+
+// A copy of a mesh description renumbered by `o` (same conventions; the
+// stencil order inside every row is kept, so results do not change).
+struct PermutedDesc {
+    sse_mesh_desc d{};
+    std::vector<int32_t> coe, eoc, neoc, voe, eov, eoe, neoe;
+    std::vector<double> w, dc, dv, f, area, H, tri;
+    std::vector<uint8_t> mask;
+};
+void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p);
 
 void set_error(const std::string &msg);
 

@@ -509,7 +509,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 // quarter of the instructions.
 // ---------------------------------------------------------------------------
 
-constexpr int kTileWaves = 8;  // wavefronts per workgroup of the tiled edge pass
+constexpr int kTileWaves = 4;  // wavefronts per workgroup of the tiled edge pass
 
 // One list of columns to stage: column i of the list is the global column
 // src + ids[i] L and goes to dst + i L in LDS.
@@ -609,9 +609,7 @@ __device__ __forceinline__ void stage_columns(const StageSeg<T> (&seg)[NS], int 
 
 template <typename R>
 size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
-    const size_t nd = (size_t)2 * t.max_uc * L;                              // h, rho (FP64)
-    const size_t nr = (size_t)(t.max_ue + t.max_uv + 2 * t.max_uc) * L;      // X, Z, B, w (type R)
-    return nd * sizeof(double) + nr * sizeof(R);
+    return (size_t)(t.max_ue + t.max_uv) * L * sizeof(R);   // X and Z columns
 }
 
 template <int NK, typename R, bool kAdd>
@@ -625,30 +623,18 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
     const int ue0 = t.ue_off[tile], nue = t.ue_off[tile + 1] - ue0;
     const int uv0 = t.uv_off[tile], nuv = t.uv_off[tile + 1] - uv0;
     const int uc0 = t.uc_off[tile], nuc = t.uc_off[tile + 1] - uc0;
-    // LDS: h | rho (FP64) | X | Z | B | w (type R).  With L even every column
-    // starts on a 16-byte boundary, as the 16-byte copies need.
-    double *sH = lds_d;
-    double *sR = sH + (size_t)nuc * L;
-    R *sX = reinterpret_cast<R *>(sR + (size_t)nuc * L);
+    // LDS holds the reused stencil operands only: the X columns of the tile's
+    // edges and stencil edges, then the vorticity columns of their vertices.
+    // The cell operands (h, rho, K - nu div u, w: two columns each, little
+    // reuse across the tile) are read from global memory per edge.
+    R *sX = reinterpret_cast<R *>(lds_d);
     R *sZ = sX + (size_t)nue * L;
-    R *sB = sZ + (size_t)nuv * L;
-    R *sW = sB + (size_t)nuc * L;
     const double *ubar = kAdd ? a.ubar_add : a.ubar_sub;
-    const int32_t *lc = t.uc + uc0, *le = t.ue + ue0, *lv = t.uv + uv0;
-    if constexpr (sizeof(R) == sizeof(double)) {
-        const StageSeg<R> seg[6] = {{reinterpret_cast<const R *>(a.h), lc, nuc, reinterpret_cast<R *>(sH)},
-                                    {reinterpret_cast<const R *>(a.rho), lc, nuc, reinterpret_cast<R *>(sR)},
-                                    {a.X, le, nue, sX},
-                                    {a.Z, lv, nuv, sZ},
-                                    {a.B, lc, nuc, sB},
-                                    {a.Wtop, lc, nuc, sW}};
-        stage_columns<R, 6>(seg, L);
-    } else {
-        const StageSeg<double> segd[2] = {{a.h, lc, nuc, sH}, {a.rho, lc, nuc, sR}};
-        const StageSeg<R> segr[4] = {{a.X, le, nue, sX}, {a.Z, lv, nuv, sZ}, {a.B, lc, nuc, sB}, {a.Wtop, lc, nuc, sW}};
-        stage_columns<double, 2>(segd, L);
-        stage_columns<R, 4>(segr, L);
-    }
+    const int32_t *le = t.ue + ue0, *lv = t.uv + uv0;
+    (void)uc0;
+    (void)nuc;
+    const StageSeg<R> seg[2] = {{a.X, le, nue, sX}, {a.Z, lv, nuv, sZ}};
+    stage_columns<R, 2>(seg, L);
     __syncthreads();
 
     int kk[NK];
@@ -670,30 +656,33 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
 #pragma unroll
         for (int qq = 0; qq < kLocPerEdge / 4; ++qq) word[qq] = lw[qq];
         auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
-        const int ls = locb(0), lc1 = locb(1), lc2 = locb(2), lv1 = locb(3), lv2 = locb(4);
+        const int ls = locb(0), lv1 = locb(3), lv2 = locb(4);
         const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
         const R ub_e = (R)ubar[e];
         const int c1 = rec[30], c2 = rec[31];
         const double idcv = m.inv_dc[e], idvv = m.inv_dv[e];
 
+        const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
         EdgeOperands<NK, R> o;
         R q[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const int k = kk[c];
+            const double h1 = a.h[b1 + k], h2 = a.h[b2 + k], r1 = a.rho[b1 + k], r2 = a.rho[b2 + k];
+            const R B1 = a.B[b1 + k], B2 = a.B[b2 + k], W1 = a.Wtop[b1 + k], W2 = a.Wtop[b2 + k];
             const R x = sX[(size_t)ls * L + k];
             o.u[c] = ok[c] ? (kAdd ? x + ub_e : x) : R(0);
             o.ut[c] = ok[c] ? (kAdd ? x : x - ub_e) : R(0);
-            o.h1[c] = ok[c] ? sH[(size_t)lc1 * L + k] : 0.0;
-            o.h2[c] = ok[c] ? sH[(size_t)lc2 * L + k] : 0.0;
-            o.r1[c] = ok[c] ? sR[(size_t)lc1 * L + k] : 0.0;
-            o.r2[c] = ok[c] ? sR[(size_t)lc2 * L + k] : 0.0;
+            o.h1[c] = ok[c] ? h1 : 0.0;
+            o.h2[c] = ok[c] ? h2 : 0.0;
+            o.r1[c] = ok[c] ? r1 : 0.0;
+            o.r2[c] = ok[c] ? r2 : 0.0;
             o.za[c] = ok[c] ? sZ[(size_t)lv1 * L + k] : R(0);
             o.zb[c] = ok[c] ? sZ[(size_t)lv2 * L + k] : R(0);
-            o.B1[c] = ok[c] ? sB[(size_t)lc1 * L + k] : R(0);
-            o.B2[c] = ok[c] ? sB[(size_t)lc2 * L + k] : R(0);
-            o.W1[c] = ok[c] ? sW[(size_t)lc1 * L + k] : R(0);
-            o.W2[c] = ok[c] ? sW[(size_t)lc2 * L + k] : R(0);
+            o.B1[c] = ok[c] ? B1 : R(0);
+            o.B2[c] = ok[c] ? B2 : R(0);
+            o.W1[c] = ok[c] ? W1 : R(0);
+            o.W2[c] = ok[c] ? W2 : R(0);
             q[c] = R(0.5) * (o.za[c] + o.zb[c]);
             o.cor[c] = o.vor[c] = R(0);
         }

@@ -11,6 +11,7 @@
 // vertex is the edge's second vertex.
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -307,6 +308,162 @@ size_t tiles_bytes(const sse_mesh_desc *d, int T) {
     auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     return 3 * al((nT + 1) * 4) + al(nT * T * 11 * 4) + al(nT * T * 22 * 4) + al(nT * T * 2 * 4) +
            al(E * kLocPerEdge);
+}
+
+
+// ---------------------------------------------------------------------------
+// Locality ordering
+// ---------------------------------------------------------------------------
+void locality_order(const sse_mesh_desc *d, int patch, MeshOrder &o) {
+    const int C = d->n_cells, E = d->n_edges, V = d->n_vertices, me = d->max_edges;
+    o.cell_old.clear();
+    o.cell_old.reserve(C);
+    std::vector<char> taken(C, 0);
+    std::deque<int> front, q;
+    int scan = 0;
+    auto neighbours = [&](int c, auto &&f) {
+        for (int j = 0; j < d->n_edges_on_cell[c]; ++j) {
+            const int e = d->edges_on_cell[(size_t)c * me + j];
+            if (e < 0) continue;
+            const int a = d->cells_on_edge[2 * (size_t)e], b = d->cells_on_edge[2 * (size_t)e + 1];
+            const int nb = a == c ? b : a;
+            if (nb >= 0 && nb != c) f(nb);
+        }
+    };
+    while ((int)o.cell_old.size() < C) {
+        int seed = -1;
+        while (!front.empty()) {
+            const int c = front.front();
+            front.pop_front();
+            if (!taken[c]) { seed = c; break; }
+        }
+        if (seed < 0) {
+            while (taken[scan]) ++scan;
+            seed = scan;
+        }
+        // grow one patch breadth-first from the seed
+        int count = 0;
+        q.clear();
+        q.push_back(seed);
+        taken[seed] = 1;
+        while (!q.empty()) {
+            const int c = q.front();
+            q.pop_front();
+            o.cell_old.push_back(c);
+            ++count;
+            neighbours(c, [&](int nb) {
+                if (taken[nb]) return;
+                if (count + (int)q.size() < patch) {
+                    taken[nb] = 1;
+                    q.push_back(nb);
+                } else {
+                    front.push_back(nb);
+                }
+            });
+        }
+    }
+    o.cell_new.assign(C, -1);
+    for (int i = 0; i < C; ++i) o.cell_new[o.cell_old[i]] = i;
+    o.edge_new.assign(E, -1);
+    o.edge_old.clear();
+    o.edge_old.reserve(E);
+    for (int i = 0; i < C; ++i) {
+        const int c = o.cell_old[i];
+        for (int j = 0; j < d->n_edges_on_cell[c]; ++j) {
+            const int e = d->edges_on_cell[(size_t)c * me + j];
+            if (e >= 0 && o.edge_new[e] < 0) {
+                o.edge_new[e] = (int)o.edge_old.size();
+                o.edge_old.push_back(e);
+            }
+        }
+    }
+    for (int e = 0; e < E; ++e)
+        if (o.edge_new[e] < 0) {
+            o.edge_new[e] = (int)o.edge_old.size();
+            o.edge_old.push_back(e);
+        }
+    o.vert_new.assign(V, -1);
+    o.vert_old.clear();
+    o.vert_old.reserve(V);
+    for (int i = 0; i < E; ++i) {
+        const int e = o.edge_old[i];
+        for (int k = 0; k < 2; ++k) {
+            const int v = d->vertices_on_edge[2 * (size_t)e + k];
+            if (v >= 0 && o.vert_new[v] < 0) {
+                o.vert_new[v] = (int)o.vert_old.size();
+                o.vert_old.push_back(v);
+            }
+        }
+    }
+    for (int v = 0; v < V; ++v)
+        if (o.vert_new[v] < 0) {
+            o.vert_new[v] = (int)o.vert_old.size();
+            o.vert_old.push_back(v);
+        }
+}
+
+void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p) {
+    const int C = d->n_cells, E = d->n_edges, V = d->n_vertices, me = d->max_edges, me2 = d->max_edges2;
+    auto map = [](const std::vector<int32_t> &nw, int x) { return x < 0 ? x : nw[x]; };
+    p.coe.resize((size_t)E * 2);
+    p.voe.resize((size_t)E * 2);
+    p.eoe.resize((size_t)E * me2);
+    p.neoe.resize(E);
+    p.w.resize((size_t)E * me2);
+    p.dc.resize(E);
+    p.dv.resize(E);
+    p.f.resize(E);
+    for (int i = 0; i < E; ++i) {
+        const int e = o.edge_old[i];
+        for (int k = 0; k < 2; ++k) {
+            p.coe[2 * (size_t)i + k] = map(o.cell_new, d->cells_on_edge[2 * (size_t)e + k]);
+            p.voe[2 * (size_t)i + k] = map(o.vert_new, d->vertices_on_edge[2 * (size_t)e + k]);
+        }
+        for (int j = 0; j < me2; ++j) {
+            p.eoe[(size_t)i * me2 + j] = map(o.edge_new, d->edges_on_edge[(size_t)e * me2 + j]);
+            p.w[(size_t)i * me2 + j] = d->weights_on_edge[(size_t)e * me2 + j];
+        }
+        p.neoe[i] = d->n_edges_on_edge[e];
+        p.dc[i] = d->dc_edge[e];
+        p.dv[i] = d->dv_edge[e];
+        p.f[i] = d->f_edge[e];
+    }
+    p.eoc.resize((size_t)C * me);
+    p.neoc.resize(C);
+    p.area.resize(C);
+    p.H.resize(C);
+    p.mask.resize(C);
+    for (int i = 0; i < C; ++i) {
+        const int c = o.cell_old[i];
+        for (int j = 0; j < me; ++j) p.eoc[(size_t)i * me + j] = map(o.edge_new, d->edges_on_cell[(size_t)c * me + j]);
+        p.neoc[i] = d->n_edges_on_cell[c];
+        p.area[i] = d->area_cell[c];
+        p.H[i] = d->bottom_depth[c];
+        p.mask[i] = d->cell_mask ? d->cell_mask[c] : 1;
+    }
+    p.eov.resize((size_t)V * 3);
+    p.tri.resize(V);
+    for (int i = 0; i < V; ++i) {
+        const int v = o.vert_old[i];
+        for (int k = 0; k < 3; ++k) p.eov[(size_t)i * 3 + k] = map(o.edge_new, d->edges_on_vertex[(size_t)v * 3 + k]);
+        p.tri[i] = d->area_triangle[v];
+    }
+    p.d = *d;
+    p.d.cells_on_edge = p.coe.data();
+    p.d.edges_on_cell = p.eoc.data();
+    p.d.n_edges_on_cell = p.neoc.data();
+    p.d.vertices_on_edge = p.voe.data();
+    p.d.edges_on_vertex = p.eov.data();
+    p.d.edges_on_edge = p.eoe.data();
+    p.d.n_edges_on_edge = p.neoe.data();
+    p.d.weights_on_edge = p.w.data();
+    p.d.dc_edge = p.dc.data();
+    p.d.dv_edge = p.dv.data();
+    p.d.f_edge = p.f.data();
+    p.d.area_cell = p.area.data();
+    p.d.bottom_depth = p.H.data();
+    p.d.area_triangle = p.tri.data();
+    p.d.cell_mask = p.mask.data();
 }
 
 }  // namespace sse
