@@ -165,6 +165,7 @@ struct RecEntry {
     Kind kind;
     int seq, j;
     int nk;
+    int var;      // kernel variant flag that must match within a batched launch
     bool add;
     int blocks;
     std::vector<uint8_t> args;
@@ -241,13 +242,14 @@ struct ProfScope {
 };
 
 template <typename A>
-void record(sse_state *s, Kind kind, const A &a, int nk, bool add, int blocks, int j = -1) {
+void record(sse_state *s, Kind kind, const A &a, int nk, bool add, int blocks, int j = -1, int var = 0) {
     Recorder &r = *s->rec;
     RecEntry e;
     e.kind = kind;
     e.j = j;
     e.seq = j >= 0 ? r.loop_seq : r.seq++;
     e.nk = nk;
+    e.var = var;
     e.add = add;
     e.blocks = blocks;
     e.args.assign(reinterpret_cast<const uint8_t *>(&a), reinterpret_cast<const uint8_t *>(&a) + sizeof(A));
@@ -314,7 +316,7 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
         if (s->rec)
-            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom));
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, m.chain);
         else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
@@ -601,19 +603,21 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     // (share of edges whose two cells lie within kLocalSpan indices).
     MeshOrder ord;
     locality_order(d, kPatchCells, ord);
+    if (local_share(d, nullptr) >= local_share(d, &ord)) identity_order(d, ord);
     PermutedDesc pd;
-    if (local_share(d, nullptr) >= local_share(d, &ord)) {
-        identity_order(d, ord);
-    } else {
-        permute_desc(d, ord, pd);
-        d = &pd.d;
-    }
+    permute_desc(d, ord, pd);
+    // Reconstruction stencils in canonical two-cell order when the mesh
+    // allows it (the edge pass then gathers 10 vertex columns, not 20).
+    std::vector<int32_t> chain;
+    const bool canonical = canonical_stencils(pd, chain);
+    d = &pd.d;
     MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
     size_t need = lay.total;
     for (int q = 0; q < kTileVariants; ++q) need += tiles_bytes(d, kTileSizes[q]);
     if (!dev_buf || bytes < need) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
     HostMeshTables t;
+    if (canonical) t.chain.swap(chain);
     build_tables(d, t);
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(dev_buf);
@@ -667,6 +671,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.inv_dc = (const double *)P(22);
     dm.inv_dv = (const double *)P(23);
     dm.wpair = (const double *)P(24);
+    dm.chain = t.chain.empty() ? 0 : 1;
     dm.wf_f = (const float *)P(25);
     dm.inv_dc_f = (const float *)P(26);
     dm.cell_div_t_f = (const float *)P(27);
@@ -1081,6 +1086,7 @@ namespace {
 struct BatchOp {
     Kind kind;
     int nk;
+    int var;
     bool add;
     int blocks;
     size_t args_off, table_off;
@@ -1120,11 +1126,12 @@ int batch_record(sse_batch *b) {
     if (b->members.empty()) { set_error("batch has no members"); return SSE_ESTATE; }
     const sse_state *s0 = b->members[0];
     struct Key {
-        int seq, j, nk;
+        int seq, j, nk, var;
         bool operator<(const Key &o) const {
             if (seq != o.seq) return seq < o.seq;
             if (j != o.j) return j < o.j;
-            return nk < o.nk;
+            if (nk != o.nk) return nk < o.nk;
+            return var < o.var;
         }
     };
     std::map<Key, std::vector<std::pair<int, RecEntry>>> groups;
@@ -1141,7 +1148,7 @@ int batch_record(sse_batch *b) {
         enqueue_step(s);
         s->rec = nullptr;
         s->geom = saved;
-        for (auto &e : r.entries) groups[Key{e.seq, e.j, e.nk}].emplace_back((int)mi, std::move(e));
+        for (auto &e : r.entries) groups[Key{e.seq, e.j, e.nk, e.var}].emplace_back((int)mi, std::move(e));
     }
     auto align = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     b->prog.clear();
@@ -1149,7 +1156,7 @@ int batch_record(sse_batch *b) {
     size_t off = 0;
     for (auto &kv : groups) {
         auto &v = kv.second;
-        BatchOp op{v[0].second.kind, v[0].second.nk, v[0].second.add, 0, 0, 0};
+        BatchOp op{v[0].second.kind, v[0].second.nk, v[0].second.var, v[0].second.add, 0, 0, 0};
         const size_t asz = v[0].second.args.size();
         std::vector<int2> table;
         for (size_t q = 0; q < v.size(); ++q) {
@@ -1190,7 +1197,7 @@ void batch_enqueue(const sse_batch *b) {
         switch (op.kind) {
             case Kind::FE_CELL: launch_fe_cell_batch<R>(bl<FECellArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
-            case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, g, st); break;
+            case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var != 0, g, st); break;
             case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), g, st); break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;

@@ -44,7 +44,10 @@ struct DevMesh {
     const int32_t *eoe = nullptr;           // [10][E]
     const int32_t *neoe = nullptr;          // [E]
     const int32_t *erec = nullptr;          // [E][32] per-edge record for the column kernels:
-                                            //   stencil edges [10], their vertices [10][2], cells [2]
+                                            //   stencil edges [10], cells [2] at 30/31, and either
+                                            //   the stencil edges' vertices [10][2] (generic) or the
+                                            //   vertex chains of the two cells (chain == 1)
+    int chain = 0;                          // 1: stencils in canonical two-cell order (see sse_mesh.cpp)
     const double *w = nullptr;              // [10][E]  W_{e,j}
     const double *wf = nullptr;             // [10][E]  W_{e,j} (f_e + f_j) / 2
     const double *wpair = nullptr;          // [E][10][2] (W_{e,j}, W_{e,j} (f_e + f_j) / 2), entity-major
@@ -120,6 +123,8 @@ struct HostMeshTables {
     std::vector<double> vert_curl;
     std::vector<float> wf_f, inv_dc_f, cell_div_t_f, H_f;
     int n_ocean_cells = 0;
+    // [E][kChainWords] vertex chains of canonical stencils (empty: generic)
+    std::vector<int32_t> chain;
 };
 void build_tables(const sse_mesh_desc *d, HostMeshTables &t);
 
@@ -150,6 +155,13 @@ struct PermutedDesc {
     std::vector<uint8_t> mask;
 };
 void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p);
+
+// Rewrites every reconstruction stencil of p in the canonical two-cell order
+// and returns the vertex chains ([E][kChainWords]), or returns false and
+// leaves p unchanged when some stencil is not "the other edges of the two
+// cells of e" (then the generic tables are used).
+constexpr int kChainWords = 11;  // A0..A5, B0..B3, flag (A0 is vertex 0 of the edge)
+bool canonical_stencils(PermutedDesc &p, std::vector<int32_t> &chain);
 
 void set_error(const std::string &msg);
 

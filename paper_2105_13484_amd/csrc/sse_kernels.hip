@@ -423,7 +423,11 @@ __device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
     }
 }
 
-template <int NK, typename R, bool kAdd>
+// kChain: the stencil is in canonical two-cell order (sse_mesh.cpp) and the
+// edge record holds the two cells' vertex chains, so the vorticity of the 10
+// distinct vertices is read once instead of at both ends of every stencil
+// edge; otherwise every stencil edge carries its own two vertices.
+template <int NK, typename R, bool kAdd, bool kChain>
 __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     const DevMesh &m = a.m;
     const int E = m.E;
@@ -442,21 +446,52 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     const double *ubar = kAdd ? a.ubar_add : a.ubar_sub;
     const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
     const int c1 = rec[30], c2 = rec[31];
-    const int v1 = m.edge_verts[2 * e], v2 = m.edge_verts[2 * e + 1];
     const double idc = m.inv_dc[e], idv = m.inv_dv[e];
     const R ub_e = (R)ubar[e];
     const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
-    const size_t bv1 = (size_t)v1 * L, bv2 = (size_t)v2 * L;
 
     EdgeOperands<NK, R> o;
     R q[NK];
+    // vertex vorticity: chain A0..A5 around c1 (A0, A5 the end points of e),
+    // B0..B3 the inner vertices of the chain around c2
+    R zA[6][NK], zB[4][NK];
+    if constexpr (kChain) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const size_t vb = (size_t)rec[10 + i] * L;
+#pragma unroll
+            for (int c = 0; c < NK; ++c) {
+                const R z = a.Z[vb + kk[c]];
+                zA[i][c] = ok[c] ? z : R(0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const size_t vb = (size_t)rec[16 + i] * L;
+#pragma unroll
+            for (int c = 0; c < NK; ++c) {
+                const R z = a.Z[vb + kk[c]];
+                zB[i][c] = ok[c] ? z : R(0);
+            }
+        }
+    }
+    const bool a0_is_v1 = kChain ? rec[20] != 0 : false;
+    const size_t bv1 = kChain ? 0 : (size_t)m.edge_verts[2 * e] * L;
+    const size_t bv2 = kChain ? 0 : (size_t)m.edge_verts[2 * e + 1] * L;
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = kk[c];
         const R x = a.X[base + k];
         const double h1 = a.h[b1 + k], h2 = a.h[b2 + k], r1 = a.rho[b1 + k], r2 = a.rho[b2 + k];
-        const R za = a.Z[bv1 + k], zb = a.Z[bv2 + k];
         const R B1 = a.B[b1 + k], B2 = a.B[b2 + k], W1 = a.Wtop[b1 + k], W2 = a.Wtop[b2 + k];
+        R za, zb;
+        if constexpr (kChain) {
+            za = a0_is_v1 ? zA[0][c] : zA[5][c];
+            zb = a0_is_v1 ? zA[5][c] : zA[0][c];
+        } else {
+            za = a.Z[bv1 + k];
+            zb = a.Z[bv2 + k];
+        }
         o.u[c] = ok[c] ? (kAdd ? x + ub_e : x) : R(0);
         o.ut[c] = ok[c] ? (kAdd ? x : x - ub_e) : R(0);
         o.h1[c] = ok[c] ? h1 : 0.0;
@@ -476,19 +511,30 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
     // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
     // stencil slots point at the edge itself with zero weights, so the loop
-    // runs its full width; its 30 column loads carry no branch between them.
+    // runs its full width; its column loads carry no branch between them.
     const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
     for (int j = 0; j < kMaxEdges2; ++j) {
-        const int ep = rec[j], pv1 = rec[10 + 2 * j], pv2 = rec[11 + 2 * j];
+        const int ep = rec[j];
         const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
         const R ubp = (R)ubar[ep];
-        const size_t pb = (size_t)ep * L, pb1 = (size_t)pv1 * L, pb2 = (size_t)pv2 * L;
+        const size_t pb = (size_t)ep * L;
+        const size_t pb1 = kChain ? 0 : (size_t)rec[10 + 2 * j] * L;
+        const size_t pb2 = kChain ? 0 : (size_t)rec[11 + 2 * j] * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const R xp = a.X[pb + kk[c]];
             const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
-            const R qp = R(0.5) * (a.Z[pb1 + kk[c]] + a.Z[pb2 + kk[c]]);
+            R qp;
+            if constexpr (kChain) {
+                // chain of c1: A_j, A_{j+1}; chain of c2: A5, B0, B1, B2, B3, A0
+                const int s = j - 5;
+                const R za_ = j < 5 ? zA[j < 5 ? j : 0][c] : (s == 0 ? zA[5][c] : zB[s > 0 ? s - 1 : 0][c]);
+                const R zb_ = j < 5 ? zA[j < 5 ? j + 1 : 0][c] : (s == 4 ? zA[0][c] : zB[s < 4 && s >= 0 ? s : 0][c]);
+                qp = R(0.5) * (za_ + zb_);
+            } else {
+                qp = R(0.5) * (a.Z[pb1 + kk[c]] + a.Z[pb2 + kk[c]]);
+            }
             o.cor[c] += wfj * utp;
             o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
         }
@@ -1029,12 +1075,14 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
     if (batch_entry(b.table, b.blocks, t)) fe_vertex_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
 }
 
-template <int NK, typename R, bool kAdd>
-__global__ void __launch_bounds__(1024) fe_edge_kernel(FEEdgeArgs<R> a) { fe_edge_body<NK, R, kAdd>(a, column_id(a.m.E)); }
-template <int NK, typename R, bool kAdd>
+template <int NK, typename R, bool kAdd, bool kChain>
+__global__ void __launch_bounds__(1024) fe_edge_kernel(FEEdgeArgs<R> a) {
+    fe_edge_body<NK, R, kAdd, kChain>(a, column_id(a.m.E));
+}
+template <int NK, typename R, bool kAdd, bool kChain>
 __global__ void __launch_bounds__(1024) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kChain>(b.args[t.x], batch_column(t.y));
 }
 
 template <int NK>
@@ -1141,9 +1189,33 @@ template <typename R>
 void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
     SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_vertex_kernel, xcd_grid(col_blocks(a.m.V, g)), col_block(g), a);
 }
+// The edge pass has a fourth template flag: canonical stencils with vertex
+// chains (the mesh's chain flag; every member of a batched launch shares it).
+#define SSE_NK_ADD_CHAIN(NK2, ADD, CHAIN, KERNEL, GRID, BLOCK, ARG)                     \
+    do {                                                                               \
+        if (CHAIN) {                                                                   \
+            if (!(NK2)) {                                                              \
+                if (ADD) KERNEL<1, R, true, true><<<GRID, BLOCK, 0, s>>>(ARG);         \
+                else KERNEL<1, R, false, true><<<GRID, BLOCK, 0, s>>>(ARG);            \
+            } else {                                                                   \
+                if (ADD) KERNEL<2, R, true, true><<<GRID, BLOCK, 0, s>>>(ARG);         \
+                else KERNEL<2, R, false, true><<<GRID, BLOCK, 0, s>>>(ARG);            \
+            }                                                                          \
+        } else {                                                                       \
+            if (!(NK2)) {                                                              \
+                if (ADD) KERNEL<1, R, true, false><<<GRID, BLOCK, 0, s>>>(ARG);        \
+                else KERNEL<1, R, false, false><<<GRID, BLOCK, 0, s>>>(ARG);           \
+            } else {                                                                   \
+                if (ADD) KERNEL<2, R, true, false><<<GRID, BLOCK, 0, s>>>(ARG);        \
+                else KERNEL<2, R, false, false><<<GRID, BLOCK, 0, s>>>(ARG);           \
+            }                                                                          \
+        }                                                                              \
+    } while (0)
+
 template <typename R>
 void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_edge_kernel, xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
+    SSE_NK_ADD_CHAIN(a.L > kWave, a.ubar_add != nullptr, a.m.chain != 0, fe_edge_kernel,
+                     xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
 }
 template <typename R>
 void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
@@ -1154,8 +1226,9 @@ void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool 
     SSE_NK_ADD(nk == 2, add, fe_vertex_batch, xcd_grid(b.blocks), col_block(g), b);
 }
 template <typename R>
-void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD(nk == 2, add, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
+void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, bool chain, const Geom &g,
+                          hipStream_t s) {
+    SSE_NK_ADD_CHAIN(nk == 2, add, chain, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
 }
 
 template <typename R>
@@ -1262,7 +1335,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
                                           hipStream_t);                                                    \
     template void launch_fe_vertex_batch<R>(const BatchLaunch<FEVertexArgs<R>> &, int, bool, const Geom &, \
                                             hipStream_t);                                                  \
-    template void launch_fe_edge_batch<R>(const BatchLaunch<FEEdgeArgs<R>> &, int, bool, const Geom &,     \
+    template void launch_fe_edge_batch<R>(const BatchLaunch<FEEdgeArgs<R>> &, int, bool, bool, const Geom &, \
                                           hipStream_t);                                                    \
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \

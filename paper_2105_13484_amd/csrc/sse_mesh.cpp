@@ -198,8 +198,8 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
         int n = d->n_edges_on_edge[e];
         t.neoe[e] = n;
         for (int j = 0; j < 10; ++j) {
-            if (j < n) {
-                int ep = d->edges_on_edge[e * me2 + j];
+            const int ep = j < n ? d->edges_on_edge[e * me2 + j] : -1;
+            if (ep >= 0) {
                 double wj = d->weights_on_edge[e * me2 + j];
                 t.eoe[(size_t)j * E + e] = ep;
                 t.w[(size_t)j * E + e] = wj;
@@ -225,9 +225,13 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
         for (int j = 0; j < 10; ++j) {
             const int ep = t.eoe[(size_t)j * E + e];
             r[j] = ep;
-            r[10 + 2 * j] = d->vertices_on_edge[2 * ep];
-            r[11 + 2 * j] = d->vertices_on_edge[2 * ep + 1];
+            if (t.chain.empty()) {
+                r[10 + 2 * j] = d->vertices_on_edge[2 * ep];
+                r[11 + 2 * j] = d->vertices_on_edge[2 * ep + 1];
+            }
         }
+        if (!t.chain.empty())
+            for (int q = 0; q < kChainWords; ++q) r[10 + q] = t.chain[(size_t)e * kChainWords + q];
         r[30] = d->cells_on_edge[2 * e];
         r[31] = d->cells_on_edge[2 * e + 1];
     }
@@ -464,6 +468,98 @@ void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p) {
     p.d.bottom_depth = p.H.data();
     p.d.area_triangle = p.tri.data();
     p.d.cell_mask = p.mask.data();
+}
+
+
+// ---------------------------------------------------------------------------
+// Canonical two-cell stencils
+//
+// On a TRiSK C-grid the tangential reconstruction at edge e combines the
+// other edges of its two cells (Thuburn et al. 2009).  Listed in the order of
+// the cells' own counter-clockwise edge lists, starting after e, the stencil
+// edges of one cell follow the chain of the cell's vertices: stencil edge k
+// of cell c1 joins chain vertices A_k and A_{k+1} (A_0 and A_5 are the end
+// points of e; a pentagon repeats A_4), and on c2 the chain runs
+// A_5, B_0 .. B_3, A_0 back (a pentagon repeats A_0 as B_3).  The edge pass
+// then needs the vorticity of these 10 vertices instead of 2 per stencil
+// edge.  Slots: 0-4 the edges of c1, 5-9 those of c2 (unused: -1, weight 0).
+// ---------------------------------------------------------------------------
+bool canonical_stencils(PermutedDesc &p, std::vector<int32_t> &chain) {
+    const sse_mesh_desc &d = p.d;
+    const int E = d.n_edges, me = d.max_edges, me2 = d.max_edges2;
+    if (me2 != 10 || me > 6) return false;
+    auto common_vertex = [&](int ea, int eb) -> int {
+        const int a0 = d.vertices_on_edge[2 * (size_t)ea], a1 = d.vertices_on_edge[2 * (size_t)ea + 1];
+        const int b0 = d.vertices_on_edge[2 * (size_t)eb], b1 = d.vertices_on_edge[2 * (size_t)eb + 1];
+        if (a0 >= 0 && (a0 == b0 || a0 == b1)) return a0;
+        if (a1 >= 0 && (a1 == b0 || a1 == b1)) return a1;
+        return -1;
+    };
+    std::vector<int32_t> eoe((size_t)E * 10, -1), ch((size_t)E * kChainWords, 0);
+    std::vector<double> w((size_t)E * 10, 0.0);
+    for (int e = 0; e < E; ++e) {
+        int cv[2][6], slot[2][5], n[2];
+        for (int s = 0; s < 2; ++s) {
+            const int c = d.cells_on_edge[2 * (size_t)e + s];
+            if (c < 0) return false;
+            n[s] = d.n_edges_on_cell[c];
+            if (n[s] < 5 || n[s] > 6) return false;
+            const int32_t *ec = d.edges_on_cell + (size_t)c * me;
+            int m = -1;
+            for (int j = 0; j < n[s]; ++j)
+                if (ec[j] == e) m = j;
+            if (m < 0) return false;
+            for (int k = 0; k < n[s]; ++k) {
+                cv[s][k] = common_vertex(ec[(m + k) % n[s]], ec[(m + k + 1) % n[s]]);
+                if (cv[s][k] < 0) return false;
+            }
+            if (n[s] == 5) cv[s][5] = cv[s][4];
+            for (int k = 0; k < 5; ++k) slot[s][k] = k < n[s] - 1 ? ec[(m + 1 + k) % n[s]] : -1;
+        }
+        const int first = cv[0][0], last = cv[0][n[0] - 1];
+        if (cv[1][0] != last || cv[1][n[1] - 1] != first) return false;
+        const int v1 = d.vertices_on_edge[2 * (size_t)e], v2 = d.vertices_on_edge[2 * (size_t)e + 1];
+        if (!((first == v1 && last == v2) || (first == v2 && last == v1))) return false;
+        // weights of the canonical slots from the caller's row; every entry of
+        // the caller's row with a nonzero weight must be one of them
+        const int nr = d.n_edges_on_edge[e];
+        const int32_t *ue = d.edges_on_edge + (size_t)e * me2;
+        const double *uw = d.weights_on_edge + (size_t)e * me2;
+        int used = 0;
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < 5; ++k) {
+                const int ep = slot[s][k];
+                const size_t o = (size_t)e * 10 + s * 5 + k;
+                if (ep < 0) continue;
+                int jj = -1;
+                for (int j = 0; j < nr; ++j)
+                    if (ue[j] == ep) jj = j;
+                if (jj < 0) return false;
+                eoe[o] = ep;
+                w[o] = uw[jj];
+                ++used;
+            }
+        for (int j = 0; j < nr; ++j) {
+            if (ue[j] < 0 || uw[j] == 0.0) continue;
+            bool found = false;
+            for (int q = 0; q < 10; ++q) found |= eoe[(size_t)e * 10 + q] == ue[j];
+            if (!found) return false;
+        }
+        (void)used;
+        int32_t *r = &ch[(size_t)e * kChainWords];
+        for (int k = 0; k < 5; ++k) r[k] = cv[0][k];
+        r[5] = last;
+        for (int k = 0; k < 4; ++k) r[6 + k] = k + 1 < n[1] - 1 ? cv[1][k + 1] : first;
+        r[10] = first == v1 ? 1 : 0;
+    }
+    p.eoe.swap(eoe);
+    p.w.swap(w);
+    for (int e = 0; e < E; ++e) p.neoe[e] = 10;
+    p.d.edges_on_edge = p.eoe.data();
+    p.d.weights_on_edge = p.w.data();
+    p.d.n_edges_on_edge = p.neoe.data();
+    chain.swap(ch);
+    return true;
 }
 
 }  // namespace sse
