@@ -372,7 +372,7 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
     int j = 0;
     auto eval = [&]() {
         ProfScope ps(s, SSE_PROF_BT_EVAL);
-        if (s->rec) record(s, Kind::BT_EVAL, a, 1, false, nblk, j++);
+        if (s->rec) record(s, Kind::BT_EVAL, a, 1, false, nblk, j++, m.delta16);
         else launch_bt_eval<R>(a, s->geom, s->stream);
     };
     for (int sub = 0; sub < M; ++sub) {
@@ -627,7 +627,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.neoe.data(), t.w.data(), t.wf.data(), t.dc.data(), t.dv.data(), t.emask.data(),
                          t.vert_edges.data(), t.vert_curl.data(), t.erec.data(), t.inv_dc.data(),
                          t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
-                         t.cell_div_t_f.data(), t.H_f.data()};
+                         t.cell_div_t_f.data(), t.H_f.data(), t.eoe16.data(), t.ecells16.data(),
+                         t.cedges16.data(), t.cnbrs16.data()};
     static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
     size_t nb[kMeshTables];
     mesh_table_sizes(d->n_cells, d->n_edges, d->n_vertices, nb);
@@ -676,6 +677,13 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.inv_dc_f = (const float *)P(26);
     dm.cell_div_t_f = (const float *)P(27);
     dm.H_f = (const float *)P(28);
+    dm.eoe16 = (const int16_t *)P(29);
+    dm.ecells16 = (const int32_t *)P(30);
+    dm.cedges16 = (const int16_t *)P(31);
+    dm.cnbrs16 = (const int16_t *)P(32);
+    dm.delta16 = t.delta16;
+    dm.ratio_ce = t.ratio_ce;
+    dm.ratio_ec = t.ratio_ec;
     m->cells_on_edge = t.edge_cells;
     m->cell_old = ord.cell_old;
     m->edge_old = ord.edge_old;
@@ -1198,7 +1206,7 @@ void batch_enqueue(const sse_batch *b) {
             case Kind::FE_CELL: launch_fe_cell_batch<R>(bl<FECellArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var != 0, g, st); break;
-            case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), g, st); break;
+            case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), op.var != 0, g, st); break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;
             case Kind::RECON: launch_recon_batch(bl<ReconArgs>(b, op), g, st); break;

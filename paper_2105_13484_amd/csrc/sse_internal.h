@@ -64,7 +64,23 @@ struct DevMesh {
     const float *inv_dc_f = nullptr;        // [E]
     const float *cell_div_t_f = nullptr;    // [6][C]
     const float *H_f = nullptr;             // [C]
+    // 16-bit index tables of the barotropic evaluation (delta16 == 1 when every
+    // offset fits): stencil edges as e + eoe16[j][e]; the cells of edge e as
+    // bc(e) + low / high half of ecells16[e]; the edges and neighbours of cell
+    // i as be(i) + cedges16[j][i] and i + cnbrs16[j][i], with the fixed-point
+    // bases bc(e) = (e ratio_ce) >> 16 and be(i) = (i ratio_ec) >> 16.
+    int delta16 = 0;
+    uint32_t ratio_ce = 0, ratio_ec = 0;
+    const int16_t *eoe16 = nullptr;         // [10][E]
+    const int32_t *ecells16 = nullptr;      // [E]
+    const int16_t *cedges16 = nullptr;      // [6][C]
+    const int16_t *cnbrs16 = nullptr;       // [6][C]
 };
+
+// Fixed-point base of the 16-bit offsets (see DevMesh).
+__host__ __device__ inline int delta_base(int x, uint32_t ratio) {
+    return (int)(((unsigned long long)x * ratio) >> 16);
+}
 
 // Gather lists of the LDS-staged baroclinic edge pass.  The edges are cut
 // into tiles of T consecutive edges; for every tile the unique edge columns
@@ -101,7 +117,7 @@ namespace sse {
 
 // Sizes of the device mesh image (bytes) and the offsets of its tables, in
 // the order in which mesh_create uploads them.
-constexpr int kMeshTables = 29;
+constexpr int kMeshTables = 33;
 void mesh_table_sizes(int C, int E, int V, size_t (&sizes)[kMeshTables]);
 struct MeshLayout {
     size_t off[kMeshTables] = {};
@@ -122,6 +138,10 @@ struct HostMeshTables {
     std::vector<int32_t> vert_edges;
     std::vector<double> vert_curl;
     std::vector<float> wf_f, inv_dc_f, cell_div_t_f, H_f;
+    std::vector<int16_t> eoe16, cedges16, cnbrs16;
+    std::vector<int32_t> ecells16;
+    int delta16 = 0;
+    uint32_t ratio_ce = 0, ratio_ec = 0;
     int n_ocean_cells = 0;
     // [E][kChainWords] vertex chains of canonical stencils (empty: generic)
     std::vector<int32_t> chain;

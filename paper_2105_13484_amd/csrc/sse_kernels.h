@@ -204,7 +204,7 @@ struct BatchLaunch {
 template <typename R> void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, bool chain, const Geom &g, hipStream_t s);
-template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, const Geom &g, hipStream_t s);
+template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
 template <typename R> void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename Tin, typename Tout>

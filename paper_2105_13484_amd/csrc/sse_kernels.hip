@@ -772,8 +772,9 @@ struct BTTables<float> {
     __device__ static const float *H(const DevMesh &m) { return m.H_f; }
 };
 
-// One block of edges (edge_part) or of cells of one evaluation.
-template <typename R>
+// One block of edges (edge_part) or of cells of one evaluation.  kD16: the
+// index tables are read as 16-bit offsets (half the index bytes).
+template <typename R, bool kD16>
 __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_part, int lb) {
     const DevMesh &m = a.m;
     const R tau = (R)a.tau, g = (R)a.g;
@@ -786,16 +787,28 @@ __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_p
             return;
         }
         const R *__restrict__ wf = BTTables<R>::wf(m);
-        const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
+        int c1, c2;
+        if constexpr (kD16) {
+            const int pk = m.ecells16[e], bc = delta_base(e, m.ratio_ce);
+            c1 = bc + (int)(int16_t)(pk & 0xffff);
+            c2 = bc + (int)(int16_t)((unsigned)pk >> 16);
+        } else {
+            c1 = m.edge_cells[2 * e];
+            c2 = m.edge_cells[2 * e + 1];
+        }
         const R ua = a.ua[e];
         const R z1 = a.za[c1], z2 = a.za[c2];
         // Padded stencil slots point at the edge itself with zero weight: the
         // loop runs its full width so that all its gathers issue together.
         R cor = R(0);
 #pragma unroll
-        for (int j = 0; j < kMaxEdges2; ++j) cor += wf[(size_t)j * m.E + e] * a.ua[m.eoe[(size_t)j * m.E + e]];
+        for (int j = 0; j < kMaxEdges2; ++j) {
+            const int ep = kD16 ? e + (int)m.eoe16[(size_t)j * m.E + e] : m.eoe[(size_t)j * m.E + e];
+            cor += wf[(size_t)j * m.E + e] * a.ua[ep];
+        }
         const R ru = cor - g * (z2 - z1) * BTTables<R>::inv_dc(m)[e] + (R)a.G[e];
-        const R base = a.ub[e];
+        // the first stage of a substep combines with nothing: no base read
+        const R base = a.comb != COMB_NONE ? a.ub[e] : R(0);
         a.uo[e] = combine<R>(a.comb, base, ua + tau * ru);
         if (a.F) {
             // The transport accumulates in FP64 in both modes.
@@ -810,15 +823,16 @@ __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_p
         const R *__restrict__ cd_t = BTTables<R>::cdiv(m);
         const R zi = a.za[i] + Ht[i];
         R div = R(0);
+        const int be = kD16 ? delta_base(i, m.ratio_ec) : 0;
 #pragma unroll
         for (int j = 0; j < kMaxEdges; ++j) {
             const R cd = cd_t[(size_t)j * m.C + i];
-            const int e = m.cell_edges_t[(size_t)j * m.C + i];
-            const int nb = m.cell_nbrs_t[(size_t)j * m.C + i];
+            const int e = kD16 ? be + (int)m.cedges16[(size_t)j * m.C + i] : m.cell_edges_t[(size_t)j * m.C + i];
+            const int nb = kD16 ? i + (int)m.cnbrs16[(size_t)j * m.C + i] : m.cell_nbrs_t[(size_t)j * m.C + i];
             const R zn = a.za[nb] + Ht[nb];
             div += cd * (a.ua[e] * (R(0.5) * (zi + zn)));
         }
-        const R base = a.zb[i];
+        const R base = a.comb != COMB_NONE ? a.zb[i] : R(0);
         a.zo[i] = combine<R>(a.comb, base, a.za[i] + tau * (-div));
     }
 }
@@ -1111,28 +1125,28 @@ __global__ void __launch_bounds__(1024) assemble_batch(BatchLaunch<AssembleArgs<
 
 // Barotropic evaluation: XCD x owns edge blocks [x pe, (x + 1) pe) and cell
 // blocks [x pc, (x + 1) pc), one contiguous region of the mesh per L2.
-template <typename R>
+template <typename R, bool kD16>
 __global__ void __launch_bounds__(1024) bt_eval_kernel(BTEvalArgs<R> a, int nEdgeBlocks, int nCellBlocks) {
     const int pe = (nEdgeBlocks + kXcd - 1) / kXcd, pc = (nCellBlocks + kXcd - 1) / kXcd;
     const int x = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
     if (local < pe) {
         const int lb = x * pe + local;
-        if (lb < nEdgeBlocks) bt_eval_body<R>(a, true, lb);
+        if (lb < nEdgeBlocks) bt_eval_body<R, kD16>(a, true, lb);
     } else {
         const int lb = x * pc + (local - pe);
-        if (lb < nCellBlocks) bt_eval_body<R>(a, false, lb);
+        if (lb < nCellBlocks) bt_eval_body<R, kD16>(a, false, lb);
     }
 }
-template <typename R>
+template <typename R, bool kD16>
 __global__ void __launch_bounds__(1024) bt_eval_batch(BatchLaunch<BTEvalArgs<R>> b) {
     int2 t;
     if (!batch_entry(b.table, b.blocks, t)) return;
     const BTEvalArgs<R> &a = b.args[t.x];
     const int nEB = (a.m.E + (int)blockDim.x - 1) / (int)blockDim.x;
     if (t.y < nEB)
-        bt_eval_body<R>(a, true, t.y);
+        bt_eval_body<R, kD16>(a, true, t.y);
     else
-        bt_eval_body<R>(a, false, t.y - nEB);
+        bt_eval_body<R, kD16>(a, false, t.y - nEB);
 }
 
 __global__ void __launch_bounds__(1024) recon_kernel(ReconArgs a) { recon_body(a, blockIdx.x); }
@@ -1262,11 +1276,17 @@ template <typename R>
 void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s) {
     const int nEB = flat_blocks(a.m.E, g), nCB = flat_blocks(a.m.C, g);
     const int per = (nEB + kXcd - 1) / kXcd + (nCB + kXcd - 1) / kXcd;
-    bt_eval_kernel<R><<<dim3(kXcd * per), g.block_2d, 0, s>>>(a, nEB, nCB);
+    if (a.m.delta16)
+        bt_eval_kernel<R, true><<<dim3(kXcd * per), g.block_2d, 0, s>>>(a, nEB, nCB);
+    else
+        bt_eval_kernel<R, false><<<dim3(kXcd * per), g.block_2d, 0, s>>>(a, nEB, nCB);
 }
 template <typename R>
-void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, const Geom &g, hipStream_t s) {
-    bt_eval_batch<R><<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
+void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s) {
+    if (delta16)
+        bt_eval_batch<R, true><<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
+    else
+        bt_eval_batch<R, false><<<xcd_grid(b.blocks), g.block_2d, 0, s>>>(b);
 }
 
 void launch_thickness(const THArgs &a, const Geom &g, hipStream_t s) {
@@ -1340,7 +1360,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
-    template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, const Geom &, hipStream_t);  \
+    template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, bool, const Geom &, hipStream_t); \
     template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \
     template void launch_thickness_iso_batch<R>(const BatchLaunch<THIsoArgs<R>> &, int, const Geom &,      \
                                                 hipStream_t);                                              \

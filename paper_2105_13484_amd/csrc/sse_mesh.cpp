@@ -125,7 +125,8 @@ void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
         E * 10 * 8, E * 8, E * 8, E,                            // wf, dc, dv, emask
         V * 3 * 4, V * 3 * 8,                                   // vert_edges, vert_curl
         E * 32 * 4, E * 8, E * 8, E * 20 * 8,                   // erec, inv_dc, inv_dv, wpair
-        E * 10 * 4, E * 4, C * 6 * 4, C * 4};                   // wf_f, inv_dc_f, cell_div_t_f, H_f
+        E * 10 * 4, E * 4, C * 6 * 4, C * 4,                    // wf_f, inv_dc_f, cell_div_t_f, H_f
+        E * 10 * 2, E * 4, C * 6 * 2, C * 6 * 2};               // eoe16, ecells16, cedges16, cnbrs16
     for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
 }
 
@@ -243,6 +244,33 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
             double r = (d->vertices_on_edge[2 * e + 1] == v) ? 1.0 : -1.0;
             t.vert_curl[v * 3 + j] = r * d->dc_edge[e] / d->area_triangle[v];
         }
+    // 16-bit offsets of the barotropic index tables, if every one fits
+    t.ratio_ce = (uint32_t)std::lround(65536.0 * C / E);
+    t.ratio_ec = (uint32_t)std::lround(65536.0 * E / C);
+    t.eoe16.assign((size_t)E * 10, 0);
+    t.ecells16.assign(E, 0);
+    t.cedges16.assign((size_t)C * 6, 0);
+    t.cnbrs16.assign((size_t)C * 6, 0);
+    bool fits = true;
+    auto put16 = [&](long v) -> int16_t {
+        if (v < -32767 || v > 32767) fits = false;
+        return (int16_t)(fits ? v : 0);
+    };
+    for (int e = 0; e < E && fits; ++e) {
+        for (int j = 0; j < 10; ++j) t.eoe16[(size_t)j * E + e] = put16((long)t.eoe[(size_t)j * E + e] - e);
+        const int bc = delta_base(e, t.ratio_ce);
+        const int16_t a = put16((long)t.edge_cells[2 * (size_t)e] - bc);
+        const int16_t b = put16((long)t.edge_cells[2 * (size_t)e + 1] - bc);
+        t.ecells16[e] = (int32_t)(((uint32_t)(uint16_t)b << 16) | (uint16_t)a);
+    }
+    for (int i = 0; i < C && fits; ++i) {
+        const int be = delta_base(i, t.ratio_ec);
+        for (int j = 0; j < 6; ++j) {
+            t.cedges16[(size_t)j * C + i] = put16((long)t.cell_edges_t[(size_t)j * C + i] - be);
+            t.cnbrs16[(size_t)j * C + i] = put16((long)t.cell_nbrs_t[(size_t)j * C + i] - i);
+        }
+    }
+    t.delta16 = fits ? 1 : 0;
     auto to_f32 = [](const std::vector<double> &src, std::vector<float> &dst) {
         dst.resize(src.size());
         for (size_t i = 0; i < src.size(); ++i) dst[i] = (float)src[i];
