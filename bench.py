@@ -10,8 +10,10 @@ timing starts.
 Prints ONE JSON line on stdout: cell-layer updates/s over the timed steps,
 the roofline of the dominant kernel class (algorithmic bytes / HIP-event time
 of that class in a second timed region), the same workload in mixed
-precision, the level-7 sphere (C2 recipe) in FP64 and mixed precision, and
-the FP64 CPU oracle timed on a bounded sample of the headline recipe.
+precision, the runtime to a fixed simulated time as the number of substeps
+M varies (both schemes), the level-7 sphere (C2 recipe) in FP64 and mixed
+precision, a batched ensemble, a served request stream, and the FP64 CPU
+oracle timed on a bounded sample of the headline recipe.
 Progress goes to stderr.
 
 --copy-probe runs only a plain device copy of a known size (for scaling the
@@ -114,6 +116,49 @@ def timed_steps(torch, st, steps):
     torch.cuda.synchronize()
     assert rc == 0, f"timed steps returned {rc}"
     return ev0.elapsed_time(ev1) / steps
+
+
+def m_sweep_leg(torch, ssprkse, dm, case, T=1920.0, dt_btr=15.0, ms=(1, 2, 4, 8, 16, 32)):
+    """Runtime to a fixed simulated time T at a fixed barotropic step dt_btr
+    as the number of substeps M varies (dt = M dt_btr, T / dt steps), for
+    both schemes on the same mesh and initial state (the cost study of
+    Sec. 5: T = 1920 s, dt_btr = 15 s, M = 1 .. 32).  When the 3D work
+    dominates, runtime falls like 1/M, and the SSPRK3-SE / SSPRK2-SE cost
+    per step sits between 1.5 (3D-dominated) and 2.25 (2D-dominated)."""
+    import math
+    from dataclasses import replace
+    rows = []
+    for scheme in (3, 2):
+        for M in ms:
+            steps = int(round(T / (M * dt_btr)))
+            p = replace(case.params, scheme=scheme, substeps=M, dt=M * dt_btr)
+            st = ssprkse.DeviceState(dm, p, device="cuda:0")
+            st.init(case.h, case.u, case.rho, case.h_ref)
+            assert st.step(1) == 0
+            st.init(case.h, case.u, case.rho, case.h_ref)
+            ms_step = timed_steps(torch, st, steps)
+            rows.append({"scheme": scheme, "M": M, "dt": M * dt_btr, "steps": steps,
+                         "ms_per_step": ms_step, "runtime_ms": ms_step * steps})
+            log(f"[bench] M sweep: SSPRK{scheme}-SE M={M:2d} dt={M * dt_btr:.0f} s: "
+                f"{steps:3d} steps x {ms_step:.3f} ms = {ms_step * steps:.1f} ms")
+            st.close()
+            del st
+    out = {"T_s": T, "dt_btr_s": dt_btr, "rows": rows}
+    for scheme in (3, 2):
+        r = [x for x in rows if x["scheme"] == scheme]
+        # least-squares slope of log(runtime) against log(M)
+        xs = [math.log(x["M"]) for x in r]
+        ys = [math.log(x["runtime_ms"]) for x in r]
+        mx, my = sum(xs) / len(xs), sum(ys) / len(ys)
+        out[f"ssprk{scheme}_loglog_slope"] = (sum((a - mx) * (b - my) for a, b in zip(xs, ys))
+                                              / sum((a - mx) ** 2 for a in xs))
+    out["ssprk3_over_ssprk2_per_step"] = {
+        str(M): next(x["ms_per_step"] for x in rows if x["scheme"] == 3 and x["M"] == M)
+        / next(x["ms_per_step"] for x in rows if x["scheme"] == 2 and x["M"] == M) for M in ms}
+    log(f"[bench] M sweep slopes: SSPRK3-SE {out['ssprk3_loglog_slope']:.3f}, "
+        f"SSPRK2-SE {out['ssprk2_loglog_slope']:.3f}; cost ratio per step "
+        + ", ".join(f"M={k}: {v:.2f}" for k, v in out["ssprk3_over_ssprk2_per_step"].items()))
+    return out
 
 
 def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
@@ -226,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing")
     ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
+    ap.add_argument("--no-m-sweep", action="store_true", help="skip the runtime-vs-M sweep")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-full", action="store_true", help="serving leg with the full request recipe")
@@ -296,6 +342,9 @@ def main():
         ms_mixed = timed_steps(torch, st_m, args.steps)
         log(f"[bench] C1 mixed precision: {ms_mixed:.3f} ms/step")
         del st_m
+
+    # runtime vs the number of substeps at fixed T and dt_btr, both schemes
+    m_sweep = None if args.no_m_sweep else m_sweep_leg(torch, ssprkse, dm, case)
     del dm
 
     # C2 recipe: level-7 sphere, 60 layers, 30% land, M = 30, dt = 1800 s
@@ -346,6 +395,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kb, "launch_ms": avg_ms},
         "c2": c2,
+        "m_sweep": m_sweep,
         "ensemble": ensemble,
         "serving": serving,
     }

@@ -21,7 +21,10 @@ Readings of what the paper leaves to MPAS (each stated where it is used):
   from the thickness equation upwards from w_{L} = 0; isopycnal: w = 0;
 * vertical boundary conditions: w = 0 at the surface and the bottom, no
   surface stress, bottom stress c_drag |u| u at the lowest layer (the drag
-  condition of Section 5), with |u|^2 = K_c1 + K_c2 of the bottom layer.
+  condition of Section 5), with |u|^2 = K_c1 + K_c2 of the bottom layer;
+* implicit vertical diffusion (Algorithm 2): the same operator with the drag
+  speed |u| taken from the stage input and frozen, so that the solve is
+  linear; the velocity multiplying c_drag |u| is the new one.
 """
 from __future__ import annotations
 
@@ -187,15 +190,78 @@ def T_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
     return mask_edges(tu, st)
 
 
-def D_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
-    """D^u_k(u) = D_{z^m}(nu_v D_{z^t}(u))_k with no surface stress and bottom drag."""
+def bottom_speed(u: np.ndarray, st: Setup) -> np.ndarray:
+    """|u| of the lowest layer at edges, sqrt(K_c1 + K_c2) of that layer (drag)."""
+    m = st.mesh
+    kb = trisk.kinetic_energy(u, m)[:, -1]
+    return np.sqrt(kb[m.cellsOnEdge[:, 0]] + kb[m.cellsOnEdge[:, 1]])
+
+
+def D_u(u: np.ndarray, h: np.ndarray, st: Setup, speed: np.ndarray | None = None) -> np.ndarray:
+    """D^u_k(u) = D_{z^m}(nu_v D_{z^t}(u))_k with no surface stress and bottom drag.
+
+    The drag speed is that of u itself unless ``speed`` is given (the
+    linearised form whose implicit solve is ``vertical_diffusion_solve``).
+    """
     m, p = st.mesh, st.params
     he = trisk.cell_to_edge(h, m)
     tau = p.nu_v * D_zt(u, he)
-    K = trisk.kinetic_energy(u, m)
-    kb = K[:, -1]
-    speed = np.sqrt(kb[m.cellsOnEdge[:, 0]] + kb[m.cellsOnEdge[:, 1]])
+    if speed is None:
+        speed = bottom_speed(u, st)
     tau[:, 0] = 0.0
     tau[:, -1] = p.c_drag * speed * u[:, -1]
     du = safe_ratio(tau[:, :-1] - tau[:, 1:], he, st.edge_mask[:, None])
     return mask_edges(du, st)
+
+
+def thomas(a: np.ndarray, b: np.ndarray, c: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """Solves a_k x_{k-1} + b_k x_k + c_k x_{k+1} = d_k, k = 0 .. L-1, for every row
+    of the (N, L) arrays (a_0 and c_{L-1} unused): Gaussian elimination
+    without pivoting of a tridiagonal matrix, forward sweep then back
+    substitution (Golub and Van Loan, the tridiagonal LU).  Stable for the
+    diagonally dominant systems of implicit vertical diffusion."""
+    N, L = d.shape
+    cp = np.zeros((N, L))
+    dp = np.zeros((N, L))
+    cp[:, 0] = c[:, 0] / b[:, 0]
+    dp[:, 0] = d[:, 0] / b[:, 0]
+    for k in range(1, L):
+        piv = b[:, k] - a[:, k] * cp[:, k - 1]
+        cp[:, k] = c[:, k] / piv
+        dp[:, k] = (d[:, k] - a[:, k] * dp[:, k - 1]) / piv
+    x = np.zeros((N, L))
+    x[:, L - 1] = dp[:, L - 1]
+    for k in range(L - 2, -1, -1):
+        x[:, k] = dp[:, k] - cp[:, k] * x[:, k + 1]
+    return x
+
+
+def vertical_diffusion_solve(r: np.ndarray, h: np.ndarray, speed: np.ndarray, dt: float,
+                             st: Setup) -> np.ndarray:
+    """The vertical diffusion solve of Algorithm 2: u with u - dt D^u(u) = r.
+
+    D^u is the operator of ``D_u`` with the bottom-drag speed frozen at
+    ``speed`` (the stage input's), which makes the system linear and
+    tridiagonal in each edge column: with A_k = nu_v / hbar^t_k at the
+    interior interfaces, A_0 = 0 (no surface stress) and A_L = c_drag |u|,
+
+        -dt A_k / h_k u_{k-1} + (1 + dt (A_k + A_{k+1}) / h_k) u_k
+            - dt A_{k+1} / h_k u_{k+1} = r_k.
+
+    Dry edges return 0.
+    """
+    m, p = st.mesh, st.params
+    he = trisk.cell_to_edge(h, m)
+    N, L = r.shape
+    wet = st.edge_mask
+    hs = np.where(wet[:, None], he, 1.0)
+    A = np.zeros((N, L + 1))
+    hbar_t = 0.5 * (hs[:, :-1] + hs[:, 1:])
+    A[:, 1:L] = p.nu_v / hbar_t
+    A[:, L] = p.c_drag * np.where(wet, speed, 0.0)
+    a = -dt * A[:, :L] / hs
+    c = -dt * A[:, 1:] / hs
+    b = 1.0 + dt * (A[:, :L] + A[:, 1:]) / hs
+    a[:, 0] = 0.0
+    c[:, L - 1] = 0.0
+    return mask_edges(thomas(a, b, c, np.where(wet[:, None], r, 0.0)), st)

@@ -4,6 +4,9 @@ Follows Section 3 of the paper:
 
 * ``split``                       -- barotropic/baroclinic split (BBspl)
 * ``baroclinic_feuler``           -- Algorithm 1 (Baroclinic_FEuler)
+* ``baroclinic_feuler_mixing``    -- Algorithm 2 (Baroclinic_FEuler_Mixing), used
+                                     in every stage instead of Algorithm 1 when
+                                     ``params.vmix`` is set
 * ``barotropic_ssprk2_substep``   -- Algorithm 3, with the accumulated flux F^zeta
                                      of the SSPRK2-SE reconciliation paragraph
 * ``barotropic_ssprk3_substep``   -- Algorithm 4, with F^zeta of the SSPRK3-SE
@@ -29,7 +32,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import trisk
-from .layered import Setup, T_h, T_u, D_u, colsum, mask_edges, safe_ratio
+from .layered import (Setup, T_h, T_u, D_u, bottom_speed, colsum, mask_edges, safe_ratio,
+                      vertical_diffusion_solve)
 
 
 def split(u: np.ndarray, h: np.ndarray, st: Setup):
@@ -53,6 +57,34 @@ def baroclinic_feuler(u, ut, zeta, h, dt, st: Setup):
     G = safe_ratio(colsum(he * ut1), colsum(he), st.edge_mask) / dt
     ut1 = mask_edges(ut1 - dt * G[:, None], st)
     return ut1, G
+
+
+def baroclinic_feuler_mixing(u, ut, ubar, zeta, h, dt, st: Setup):
+    """Algorithm 2: Algorithm 1 without D^u, then the implicit vertical
+    diffusion of the whole velocity.
+
+    ut1 = ut + dt(-f ut^perp + T^u(u) + g grad zeta);  G from ut1 as in
+    Algorithm 1;  ut1 -= dt G;  u1 - dt D^u(u1) = ut1 + ubar;  ut1 = u1 - ubar.
+    ubar is the barotropic velocity of the stage input (u = ubar + ut); the
+    drag speed of D^u is the input's.  G is the one formed before the solve.
+    """
+    m, p = st.mesh, st.params
+    coriolis = trisk.tangential_flux(m.fEdge, ut, m)
+    rhs = coriolis + T_u(u, h, st) + p.gravity * trisk.gradient(zeta, m)[:, None]
+    ut1 = mask_edges(ut + dt * rhs, st)
+    he = trisk.cell_to_edge(h, m)
+    G = safe_ratio(colsum(he * ut1), colsum(he), st.edge_mask) / dt
+    ut1 = mask_edges(ut1 - dt * G[:, None], st)
+    u1 = vertical_diffusion_solve(ut1 + ubar[:, None], h, bottom_speed(u, st), dt, st)
+    return mask_edges(u1 - ubar[:, None], st), G
+
+
+def bfe(u, ut, ubar, zeta, h, dt, st: Setup):
+    """The stage's baroclinic forward Euler: Algorithm 2 when params.vmix is
+    set (implicit vertical mixing), else Algorithm 1 (explicit D^u)."""
+    if getattr(st.params, "vmix", 0):
+        return baroclinic_feuler_mixing(u, ut, ubar, zeta, h, dt, st)
+    return baroclinic_feuler(u, ut, zeta, h, dt, st)
 
 
 def barotropic_rhs(ubar, zeta, G, st: Setup):
@@ -133,7 +165,7 @@ def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None):
     zeta = ssh(h, st)
     ubar, ut = split(u, h, st)
     # Step 1, stage 1
-    ut1, G0 = baroclinic_feuler(u, ut, zeta, h, dt, st)
+    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, st)
     ub1, zb1, Fz1 = barotropic_ssprk2_substep(ubar, zeta, G0, dt, M, st)
     u1 = mask_edges(ub1[:, None] + ut1, st)
     Fh1, S1 = _edge_sum(h, u, st)
@@ -141,7 +173,7 @@ def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None):
     h1 = thickness_stage(h, u, uA1, dt, st)
     z1 = ssh(h1, st)
     # Step 1, stage 2
-    ut2, G1 = baroclinic_feuler(u1, ut1, z1, h1, dt, st)
+    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, st)
     ut_new = 0.5 * (ut + ut2)
     # Step 2
     ub_new, zb2, Fz2 = barotropic_ssprk2_substep(ubar, zeta, interp2(G0, G1), dt, M, st)
@@ -170,7 +202,7 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
     ubar, ut = split(u, h, st)
     zero = np.zeros_like(ubar)
     # Step 1, stage 1
-    ut1, G0 = baroclinic_feuler(u, ut, zeta, h, dt, st)
+    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, st)
     ub1, zb1, Fz1 = barotropic_ssprk3_substep(ubar, zeta, G0, dt, M, st)
     u1 = mask_edges(ub1[:, None] + ut1, st)
     Fh1, S1 = _edge_sum(h, u, st)
@@ -178,7 +210,7 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
     h1 = thickness_stage(h, u, uA1, dt, st)
     z1 = ssh(h1, st)
     # Step 1, stage 2
-    ut2, G1 = baroclinic_feuler(u1, ut1, z1, h1, dt, st)
+    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, st)
     ut_half = 0.75 * ut + 0.25 * ut2
     ub2, zb2, Fz2 = barotropic_ssprk3_substep(ub1, z1, G1, dt, M, st)
     ub_half = 0.75 * ubar + 0.25 * ub2
@@ -189,7 +221,7 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
     h_half = 0.75 * h + 0.25 * h2
     z_half = ssh(h_half, st)
     # Step 1, stage 3
-    ut3, G_half = baroclinic_feuler(u_half, ut_half, z_half, h_half, dt, st)
+    ut3, G_half = bfe(u_half, ut_half, ub_half, z_half, h_half, dt, st)
     ut_new = ut / 3.0 + 2.0 * ut3 / 3.0
     # Step 2
     ub_new, zb3, Fz3 = barotropic_ssprk3_substep(ubar, zeta, interp3(G0, G1, G_half), dt, M, st)

@@ -53,6 +53,7 @@ class Params:
     nu_h: float = 10.0
     nu_v: float = 1.0e-4
     c_drag: float = 1.0e-3
+    vmix: int = 0              # 1 = implicit vertical mixing (Algorithm 2)
 
 
 @dataclass
