@@ -10,7 +10,7 @@ timing starts.
 Prints ONE JSON line on stdout: cell-layer updates/s over the timed steps,
 the roofline of the dominant kernel class (algorithmic bytes / HIP-event time
 of that class in a second timed region), the same workload in mixed
-precision, the runtime to a fixed simulated time as the number of substeps
+precision and with implicit vertical mixing, the runtime to a fixed simulated time as the number of substeps
 M varies (both schemes), the level-7 sphere (C2 recipe) in FP64 and mixed
 precision, a batched ensemble, a served request stream, and the FP64 CPU
 oracle timed on a bounded sample of the headline recipe.
@@ -271,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing")
     ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
+    ap.add_argument("--no-vmix", action="store_true", help="skip the implicit-vertical-mixing timing")
     ap.add_argument("--no-m-sweep", action="store_true", help="skip the runtime-vs-M sweep")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -343,6 +344,15 @@ def main():
         log(f"[bench] C1 mixed precision: {ms_mixed:.3f} ms/step")
         del st_m
 
+    # the same workload with implicit vertical mixing (Algorithm 2 in every stage)
+    ms_vmix = None
+    if not args.no_vmix:
+        _, st_v = ssprkse.state_from_case(cases.with_params(case, vmix=1), device="cuda:0")
+        assert st_v.step(args.warmup) == 0
+        ms_vmix = timed_steps(torch, st_v, args.steps)
+        log(f"[bench] C1 with implicit vertical mixing: {ms_vmix:.3f} ms/step")
+        del st_v
+
     # runtime vs the number of substeps at fixed T and dt_btr, both schemes
     m_sweep = None if args.no_m_sweep else m_sweep_leg(torch, ssprkse, dm, case)
     del dm
@@ -390,6 +400,7 @@ def main():
         "hbm_frac_step": step_gbs / HBM_PEAK_GBS,
         "mixed_vs_fp64_speedup": (ms_step / ms_mixed) if ms_mixed else None,
         "mixed_ms_per_step": ms_mixed,
+        "vmix_ms_per_step": ms_vmix,
         "per_class_ms_per_step": {k: v[1] / 3.0 for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -56,6 +56,14 @@ enum { SSE_ZSTAR = 0, SSE_ISOPYCNAL = 1 };
  * SSH at every stage; LITERAL uses the printed F^h_2 (SSPRK2-SE) and F^h_3
  * (SSPRK3-SE). */
 enum { SSE_RECONCILE_OFF = 0, SSE_RECONCILE_EXACT = 1, SSE_RECONCILE_LITERAL = 2 };
+/* Vertical viscosity and bottom drag D^u (Section 3.1): EXPLICIT adds them to
+ * the forward-Euler tendency of every baroclinic stage (Algorithm 1);
+ * IMPLICIT leaves them out of the tendency and applies them afterwards to
+ * the whole velocity by a backward-Euler solve, one tridiagonal system per
+ * edge column (Algorithm 2, "vertical mixing").  The implicit solve freezes
+ * the drag speed |u| at the stage input's; G-bar is the one formed before
+ * the solve. */
+enum { SSE_VMIX_EXPLICIT = 0, SSE_VMIX_IMPLICIT = 1 };
 
 /*
  * Mesh description (host memory, caller numbering; copied by
@@ -94,12 +102,13 @@ typedef struct {
  *   n_layers L (1..128); scheme SSE_SCHEME_SSPRK2 | SSE_SCHEME_SSPRK3;
  *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 | SSE_MIXED;
  *   vcoord SSE_ZSTAR | SSE_ISOPYCNAL (Section 2, vertical coordinate);
- *   reconcile SSE_RECONCILE_*; dt > 0 (s); gravity g; rho0 (Boussinesq
- *   reference density); nu_h, nu_v (Laplacian horizontal and vertical
- *   viscosity, m^2/s); c_drag (bottom drag of Section 5, dimensionless).
+ *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; dt > 0 (s); gravity g;
+ *   rho0 (Boussinesq reference density); nu_h, nu_v (Laplacian horizontal
+ *   and vertical viscosity, m^2/s); c_drag (bottom drag of Section 5,
+ *   dimensionless).
  */
 typedef struct {
-    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile;
+    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile, vmix;
     double dt, gravity, rho0, nu_h, nu_v, c_drag;
 } sse_params;
 

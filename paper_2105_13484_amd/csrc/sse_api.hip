@@ -315,8 +315,9 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         a.nu_h = p.nu_h;
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
+        a.vmix = p.vmix;
         if (s->rec)
-            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, m.chain);
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, fe_edge_variant(m, p.vmix));
         else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
@@ -536,6 +537,7 @@ int check_params(const sse_params *p) {
     if (p->precision != SSE_FP64 && p->precision != SSE_MIXED) { set_error("precision must be SSE_FP64 or SSE_MIXED"); return SSE_EINVAL; }
     if (p->vcoord != SSE_ZSTAR && p->vcoord != SSE_ISOPYCNAL) { set_error("vcoord must be ZSTAR or ISOPYCNAL"); return SSE_EINVAL; }
     if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
+    if (p->vmix != SSE_VMIX_EXPLICIT && p->vmix != SSE_VMIX_IMPLICIT) { set_error("vmix must be SSE_VMIX_EXPLICIT or SSE_VMIX_IMPLICIT"); return SSE_EINVAL; }
     const double v[] = {p->dt, p->gravity, p->rho0};
     for (double x : v)
         if (!(x > 0) || !std::isfinite(x)) { set_error("dt, gravity and rho0 must be positive"); return SSE_EINVAL; }
@@ -1205,7 +1207,7 @@ void batch_enqueue(const sse_batch *b) {
         switch (op.kind) {
             case Kind::FE_CELL: launch_fe_cell_batch<R>(bl<FECellArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
-            case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var != 0, g, st); break;
+            case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var, g, st); break;
             case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), op.var != 0, g, st); break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;

@@ -70,6 +70,7 @@ struct FEEdgeArgs {
     double *Gi;               // [E] interpolated forcing, nullable
     const double *Ga, *Gb;
     int interp;               // 2: Ga/2 + G/2; 3: Ga/6 + Gb/6 + 2G/3
+    int vmix;                 // 1: D^u by the implicit column solve (Algorithm 2)
     double dt, g, rho0, nu_h, nu_v, c_drag;
 };
 
@@ -203,7 +204,10 @@ struct BatchLaunch {
 };
 template <typename R> void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
-template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, bool chain, const Geom &g, hipStream_t s);
+// Template variant of the edge pass: bit 0 canonical stencils with vertex
+// chains (mesh), bit 1 implicit vertical mixing (parameters).
+int fe_edge_variant(const DevMesh &m, int vmix);
+template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g, hipStream_t s);
 template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
 template <typename R> void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s);

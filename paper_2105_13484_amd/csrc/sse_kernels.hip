@@ -149,6 +149,80 @@ __device__ __forceinline__ void col_down1(const T (&v)[NK], T (&o)[NK]) {
     }
 }
 
+// o_k = v_{k-s} (fill where k < s), 1 <= s <= 64, k = lane + 64 c
+template <int NK, typename T>
+__device__ __forceinline__ void col_shift_up(const T (&v)[NK], int s, T fill, T (&o)[NK]) {
+    const int l = lane_id();
+    if (s >= kWave) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) o[c] = c > 0 ? v[c > 0 ? c - 1 : 0] : fill;
+        return;
+    }
+    const int src = (l - s) & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const T a = __shfl(v[c], src, kWave);
+        const T b = c > 0 ? __shfl(v[c > 0 ? c - 1 : 0], src, kWave) : fill;
+        o[c] = l >= s ? a : b;
+    }
+}
+
+// o_k = v_{k+s} (fill past the last register chunk), 1 <= s <= 64
+template <int NK, typename T>
+__device__ __forceinline__ void col_shift_down(const T (&v)[NK], int s, T fill, T (&o)[NK]) {
+    const int l = lane_id();
+    if (s >= kWave) {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) o[c] = c < NK - 1 ? v[c < NK - 1 ? c + 1 : c] : fill;
+        return;
+    }
+    const int src = (l + s) & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const T a = __shfl(v[c], src, kWave);
+        const T b = c < NK - 1 ? __shfl(v[c < NK - 1 ? c + 1 : c], src, kWave) : fill;
+        o[c] = l + s < kWave ? a : b;
+    }
+}
+
+// Solves lo_k x_{k-1} + di_k x_k + up_k x_{k+1} = d_k over the layers of a
+// column, x returned in d.  Rows past the last layer must be the identity
+// (lo = up = 0, di = 1, d = 0) and the first and last rows must not couple
+// outwards (lo_0 = up_{L-1} = 0).  Parallel cyclic reduction (Hockney): in
+// round r every row eliminates its couplings to the rows s = 2^r above and
+// below with those rows' equations, so after ceil(log2 L) rounds each row
+// holds one unknown.  Every lane works in every round, the cross-lane reads
+// are register shuffles, and for the diagonally dominant systems of implicit
+// diffusion no pivoting is needed.
+template <int NK, typename T>
+__device__ __forceinline__ void col_tridiag_solve(int L, T (&lo)[NK], T (&di)[NK], T (&up)[NK], T (&d)[NK]) {
+    for (int s = 1; s < L; s <<= 1) {
+        T rdi[NK];
+#pragma unroll
+        for (int c = 0; c < NK; ++c) rdi[c] = T(1) / di[c];
+        T loA[NK], upA[NK], dA[NK], rA[NK], loB[NK], upB[NK], dB[NK], rB[NK];
+        col_shift_up<NK>(lo, s, T(0), loA);
+        col_shift_up<NK>(up, s, T(0), upA);
+        col_shift_up<NK>(d, s, T(0), dA);
+        col_shift_up<NK>(rdi, s, T(1), rA);
+        col_shift_down<NK>(lo, s, T(0), loB);
+        col_shift_down<NK>(up, s, T(0), upB);
+        col_shift_down<NK>(d, s, T(0), dB);
+        col_shift_down<NK>(rdi, s, T(1), rB);
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const T al = -lo[c] * rA[c];
+            const T ga = -up[c] * rB[c];
+            di[c] = di[c] + al * upA[c] + ga * loB[c];
+            d[c] = d[c] + al * dA[c] + ga * dB[c];
+            lo[c] = al * loA[c];
+            up[c] = ga * upB[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NK; ++c) d[c] = d[c] / di[c];
+}
+
 template <typename T>
 __device__ __forceinline__ T combine(int mode, T b, T x) {
     switch (mode) {
@@ -291,7 +365,9 @@ struct EdgeOperands {
     R cor[NK], vor[NK];
 };
 
-template <int NK, typename R>
+// kMix: D^u is left out of the tendency and applied by the implicit column
+// solve of Algorithm 2 (the vertical-mixing form of the stage).
+template <int NK, typename R, bool kMix>
 __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, int c1, int c2, double idc, double idv,
                                                const EdgeOperands<NK, R> &o) {
     const int lane = lane_id();
@@ -363,7 +439,7 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
             const R curlp = (o.zb[c] - o.za[c]) * ridv;
             const R vadv = R(0.5) * (at[c] + atn[c]);
             const R tu = -gradB + o.vor[c] - vadv + (R)pgf[c] - nu_h * curlp;
-            const R du = (tau[c] - taun[c]) * (R(1) / he[c]);
+            const R du = kMix ? R(0) : (tau[c] - taun[c]) * (R(1) / he[c]);
             ut1[c] = o.ut[c] + dt * (o.cor[c] + tu + du + gz);
         } else {
             ut1[c] = R(0);
@@ -376,15 +452,42 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
     const double Sh = col_sum<NK>(hed);
     const double G = col_sum<NK>(hut1) / Sh / a.dt;
     const R dtG = (R)(a.dt * G);
+    R x[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) x[c] = (lane + c * kWave < L) ? ut1[c] - dtG : R(0);
+    if constexpr (kMix) {
+        // Algorithm 2: u1 - dt D^u(u1) = ut1 + ubar with the drag speed of the
+        // input, then ut1 = u1 - ubar (ubar: the input's barotropic velocity).
+        const R ubin = (R)((a.ubar_add ? a.ubar_add[e] : 0.0) + (a.ubar_sub ? a.ubar_sub[e] : 0.0));
+        R Aup[NK], Adn[NK], lo[NK], di[NK], up[NK];
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = lane + c * kWave;
+            Aup[c] = (k >= 1 && k < L) ? nu_v / (R(0.5) * (hu[c] + he[c])) : R(0);
+        }
+        col_down1<NK>(Aup, Adn);
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = lane + c * kWave;
+            if (k == L - 1) Adn[c] = c_drag * speed;
+            const bool in = k < L;
+            lo[c] = in ? -dt * Aup[c] / he[c] : R(0);
+            up[c] = (in && k < L - 1) ? -dt * Adn[c] / he[c] : R(0);
+            di[c] = in ? R(1) + dt * (Aup[c] + Adn[c]) / he[c] : R(1);
+            x[c] = in ? x[c] + ubin : R(0);
+        }
+        col_tridiag_solve<NK, R>(L, lo, di, up, x);
+#pragma unroll
+        for (int c = 0; c < NK; ++c) x[c] = (lane + c * kWave < L) ? x[c] - ubin : R(0);
+    }
     const double ubn = a.Un ? a.ubar_n[e] : 0.0;
     R outv[NK];
     double hp[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
-        const R x = ut1[c] - dtG;
         const R utn = (a.Un && k < L) ? (R)((double)a.Un[base + k] - ubn) : R(0);
-        outv[c] = (k < L) ? combine<R>(a.comb, utn, x) : R(0);
+        outv[c] = (k < L) ? combine<R>(a.comb, utn, x[c]) : R(0);
         if (k < L) a.out[base + k] = outv[c];
         hp[c] = hed[c] * (a.psum_a * (double)utn + a.psum_b * (double)outv[c]);
     }
@@ -427,8 +530,11 @@ __device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
 // edge record holds the two cells' vertex chains, so the vorticity of the 10
 // distinct vertices is read once instead of at both ends of every stencil
 // edge; otherwise every stencil edge carries its own two vertices.
-template <int NK, typename R, bool kAdd, bool kChain>
+// kVar bit 0: kChain; bit 1: kMix (see fe_edge_finish).
+template <int NK, typename R, bool kAdd, int kVar>
 __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
+    constexpr bool kChain = (kVar & 1) != 0;
+    constexpr bool kMix = (kVar & 2) != 0;
     const DevMesh &m = a.m;
     const int E = m.E;
     const int e = col;
@@ -539,7 +645,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
             o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
         }
     }
-    fe_edge_finish<NK, R>(a, e, c1, c2, idc, idv, o);
+    fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idc, idv, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -658,7 +764,7 @@ size_t fe_edge_tiled_lds(const DevTiles &t, int L) {
     return (size_t)(t.max_ue + t.max_uv) * L * sizeof(R);   // X and Z columns
 }
 
-template <int NK, typename R, bool kAdd>
+template <int NK, typename R, bool kAdd, bool kMix>
 __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdgeArgs<R> a, DevTiles t) {
     extern __shared__ __align__(16) double lds_d[];
     const DevMesh &m = a.m;
@@ -748,7 +854,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
                 o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
             }
         }
-        fe_edge_finish<NK, R>(a, e, c1, c2, idcv, idvv, o);
+        fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idcv, idvv, o);
     }
 }
 
@@ -1089,14 +1195,14 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
     if (batch_entry(b.table, b.blocks, t)) fe_vertex_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
 }
 
-template <int NK, typename R, bool kAdd, bool kChain>
+template <int NK, typename R, bool kAdd, int kVar>
 __global__ void __launch_bounds__(1024) fe_edge_kernel(FEEdgeArgs<R> a) {
-    fe_edge_body<NK, R, kAdd, kChain>(a, column_id(a.m.E));
+    fe_edge_body<NK, R, kAdd, kVar>(a, column_id(a.m.E));
 }
-template <int NK, typename R, bool kAdd, bool kChain>
+template <int NK, typename R, bool kAdd, int kVar>
 __global__ void __launch_bounds__(1024) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kChain>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kVar>(b.args[t.x], batch_column(t.y));
 }
 
 template <int NK>
@@ -1203,33 +1309,36 @@ template <typename R>
 void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
     SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_vertex_kernel, xcd_grid(col_blocks(a.m.V, g)), col_block(g), a);
 }
-// The edge pass has a fourth template flag: canonical stencils with vertex
-// chains (the mesh's chain flag; every member of a batched launch shares it).
-#define SSE_NK_ADD_CHAIN(NK2, ADD, CHAIN, KERNEL, GRID, BLOCK, ARG)                     \
+// The edge pass has a fourth template parameter, the variant: bit 0 for
+// canonical stencils with vertex chains (the mesh's chain flag), bit 1 for
+// implicit vertical mixing (the state's vmix parameter).  Every member of a
+// batched launch shares it.
+#define SSE_NK_ADD_V(NK2, ADD, V, KERNEL, GRID, BLOCK, ARG)                             \
     do {                                                                               \
-        if (CHAIN) {                                                                   \
-            if (!(NK2)) {                                                              \
-                if (ADD) KERNEL<1, R, true, true><<<GRID, BLOCK, 0, s>>>(ARG);         \
-                else KERNEL<1, R, false, true><<<GRID, BLOCK, 0, s>>>(ARG);            \
-            } else {                                                                   \
-                if (ADD) KERNEL<2, R, true, true><<<GRID, BLOCK, 0, s>>>(ARG);         \
-                else KERNEL<2, R, false, true><<<GRID, BLOCK, 0, s>>>(ARG);            \
-            }                                                                          \
+        if (!(NK2)) {                                                                  \
+            if (ADD) KERNEL<1, R, true, V><<<GRID, BLOCK, 0, s>>>(ARG);                \
+            else KERNEL<1, R, false, V><<<GRID, BLOCK, 0, s>>>(ARG);                   \
         } else {                                                                       \
-            if (!(NK2)) {                                                              \
-                if (ADD) KERNEL<1, R, true, false><<<GRID, BLOCK, 0, s>>>(ARG);        \
-                else KERNEL<1, R, false, false><<<GRID, BLOCK, 0, s>>>(ARG);           \
-            } else {                                                                   \
-                if (ADD) KERNEL<2, R, true, false><<<GRID, BLOCK, 0, s>>>(ARG);        \
-                else KERNEL<2, R, false, false><<<GRID, BLOCK, 0, s>>>(ARG);           \
-            }                                                                          \
+            if (ADD) KERNEL<2, R, true, V><<<GRID, BLOCK, 0, s>>>(ARG);                \
+            else KERNEL<2, R, false, V><<<GRID, BLOCK, 0, s>>>(ARG);                   \
+        }                                                                              \
+    } while (0)
+#define SSE_NK_ADD_VAR(NK2, ADD, VAR, KERNEL, GRID, BLOCK, ARG)                         \
+    do {                                                                               \
+        switch (VAR) {                                                                 \
+            case 0: SSE_NK_ADD_V(NK2, ADD, 0, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 1: SSE_NK_ADD_V(NK2, ADD, 1, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 2: SSE_NK_ADD_V(NK2, ADD, 2, KERNEL, GRID, BLOCK, ARG); break;        \
+            default: SSE_NK_ADD_V(NK2, ADD, 3, KERNEL, GRID, BLOCK, ARG); break;       \
         }                                                                              \
     } while (0)
 
+int fe_edge_variant(const DevMesh &m, int vmix) { return (m.chain ? 1 : 0) | (vmix ? 2 : 0); }
+
 template <typename R>
 void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD_CHAIN(a.L > kWave, a.ubar_add != nullptr, a.m.chain != 0, fe_edge_kernel,
-                     xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
+    SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, fe_edge_variant(a.m, a.vmix), fe_edge_kernel,
+                   xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
 }
 template <typename R>
 void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
@@ -1240,9 +1349,9 @@ void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool 
     SSE_NK_ADD(nk == 2, add, fe_vertex_batch, xcd_grid(b.blocks), col_block(g), b);
 }
 template <typename R>
-void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, bool chain, const Geom &g,
+void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g,
                           hipStream_t s) {
-    SSE_NK_ADD_CHAIN(nk == 2, add, chain, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
+    SSE_NK_ADD_VAR(nk == 2, add, var, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
 }
 
 template <typename R>
@@ -1250,25 +1359,28 @@ void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t
     const size_t lds = fe_edge_tiled_lds<R>(t, a.L);
     const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block((t.T < kTileWaves ? t.T : kTileWaves) * kWave);
     const bool add = a.ubar_add != nullptr;
+    const int v = a.vmix ? 1 : 0;
+#define SSE_TILED(NK_, ADD_, MIX_) fe_edge_tiled_kernel<NK_, R, ADD_, MIX_><<<grid, block, lds, s>>>(a, t)
     if (a.L <= kWave) {
-        if (add) fe_edge_tiled_kernel<1, R, true><<<grid, block, lds, s>>>(a, t);
-        else fe_edge_tiled_kernel<1, R, false><<<grid, block, lds, s>>>(a, t);
+        if (add) { if (v) SSE_TILED(1, true, true); else SSE_TILED(1, true, false); }
+        else { if (v) SSE_TILED(1, false, true); else SSE_TILED(1, false, false); }
     } else {
-        if (add) fe_edge_tiled_kernel<2, R, true><<<grid, block, lds, s>>>(a, t);
-        else fe_edge_tiled_kernel<2, R, false><<<grid, block, lds, s>>>(a, t);
+        if (add) { if (v) SSE_TILED(2, true, true); else SSE_TILED(2, true, false); }
+        else { if (v) SSE_TILED(2, false, true); else SSE_TILED(2, false, false); }
     }
+#undef SSE_TILED
 }
 
 // Allow the tiled kernels the device's full LDS per workgroup.
 void set_tiled_lds_limit(size_t bytes) {
-    const void *fns[] = {reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double, true>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, double, false>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double, true>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, double, false>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float, true>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<1, float, false>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float, true>),
-                         reinterpret_cast<const void *>(fe_edge_tiled_kernel<2, float, false>)};
+#define SSE_TILED_FN(NK_, R_, ADD_, MIX_) reinterpret_cast<const void *>(fe_edge_tiled_kernel<NK_, R_, ADD_, MIX_>)
+#define SSE_TILED_FNS(R_, MIX_)                                                                            \
+    SSE_TILED_FN(1, R_, true, MIX_), SSE_TILED_FN(1, R_, false, MIX_), SSE_TILED_FN(2, R_, true, MIX_), \
+        SSE_TILED_FN(2, R_, false, MIX_)
+    const void *fns[] = {SSE_TILED_FNS(double, false), SSE_TILED_FNS(double, true), SSE_TILED_FNS(float, false),
+                         SSE_TILED_FNS(float, true)};
+#undef SSE_TILED_FNS
+#undef SSE_TILED_FN
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -1355,7 +1467,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
                                           hipStream_t);                                                    \
     template void launch_fe_vertex_batch<R>(const BatchLaunch<FEVertexArgs<R>> &, int, bool, const Geom &, \
                                             hipStream_t);                                                  \
-    template void launch_fe_edge_batch<R>(const BatchLaunch<FEEdgeArgs<R>> &, int, bool, bool, const Geom &, \
+    template void launch_fe_edge_batch<R>(const BatchLaunch<FEEdgeArgs<R>> &, int, bool, int, const Geom &, \
                                           hipStream_t);                                                    \
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
