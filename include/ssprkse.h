@@ -127,7 +127,9 @@ const char *sse_version(void);
  * term energy neutral.  Touches no GPU.  SSE_EINVAL on the first violation. */
 int sse_mesh_validate(const sse_mesh_desc *d);
 
-/* Device bytes a mesh occupies (for the caller's allocation). */
+/* Device bytes a mesh occupies (for the caller's allocation).  Validates d
+ * as sse_mesh_validate does (SSE_EINVAL on a malformed mesh): the size of the
+ * barotropic patch tables depends on the cell-edge topology. */
 int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes);
 
 /* Validate, lay out and upload a mesh into dev_buf (>= sse_mesh_device_bytes,
@@ -196,10 +198,23 @@ int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
 int sse_state_set_edge_variant(sse_state *s, int variant);
 int sse_state_get_edge_variant(const sse_state *s, int *variant);
 
+/* Kernel layout of the barotropic substep loops (Algorithms 3 and 4); the
+ * results are bitwise the same.  0: one launch per forward-Euler evaluation
+ * (3M per SSPRK3 loop, 2M per SSPRK2 loop).  1: one launch per substep: the
+ * mesh is cut into patches of a few hundred cells, and one workgroup carries
+ * its patch, extended by the halo rings the substep's evaluations read,
+ * through all evaluations of the substep in LDS.  The default is 1 when the
+ * mesh has such patches (sse_mesh_create builds them when every patch's halo
+ * region fits a workgroup and every reconstruction stencil stays within the
+ * two cells of its edge) and they fit the device's LDS, else 0.  SSE_EINVAL
+ * for 1 otherwise.  Batched steps use variant 0. */
+int sse_state_set_bt_variant(sse_state *s, int variant);
+int sse_state_get_bt_variant(const sse_state *s, int *variant);
+
 /* Device bytes one state of these parameters on this mesh needs in total:
- * the mesh image (sse_mesh_device_bytes) plus the workspace
- * (sse_state_workspace_bytes).  Reads only the counts in d; allocates
- * nothing.  For admission control by a device-memory budget. */
+ * the mesh image (sse_mesh_device_bytes, which validates d) plus the
+ * workspace (sse_state_workspace_bytes).  Host only; allocates nothing.  For
+ * admission control by a device-memory budget. */
 int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, size_t *bytes);
 
 /* Launch geometry of the state's kernels; results do not depend on it.

@@ -189,6 +189,7 @@ struct sse_state {
     bool initialized = false;
     Geom geom{};             // launch geometry (autotuner knob)
     int edge_variant = -1;   // -1: direct gathers; 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
+    int bt_variant = 0;      // 0: one launch per barotropic evaluation; 1: one per substep (patches)
     size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
     Recorder *rec = nullptr; // non-null while a batch records this state's step
     sse_batch *batch = nullptr;
@@ -257,6 +258,13 @@ void record(sse_state *s, Kind kind, const A &a, int nk, bool add, int blocks, i
 }
 
 int nk_of(int L) { return L <= kWave ? 1 : 2; }
+
+// The tiled barotropic substep kernel is usable: the mesh has patches and
+// the largest patch's LDS fits the device.
+bool bt_tiles_fit(const sse_state *s) {
+    const DevBtTiles &t = s->mesh->bt;
+    return t.nP > 0 && (s->rs == 8 ? t.lds_d : t.lds_f) <= s->lds_max;
+}
 
 // ---- building blocks -------------------------------------------------------
 template <typename R>
@@ -362,6 +370,40 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         oz = rp<R>(w.bt_zo);
     }
     R *u1 = rp<R>(w.bt_u1), *uh = rp<R>(w.bt_uh), *z1 = rp<R>(w.bt_z1), *zh = rp<R>(w.bt_zh);
+    if (!s->rec && s->bt_variant == 1) {
+        // one launch per substep; outputs alternate between the loop's
+        // output and a scratch pair so that no launch reads what another
+        // workgroup of the same launch writes, ending in the output
+        BTTileArgs<R> a{};
+        a.t = s->mesh->bt;
+        a.G = G;
+        a.F = F;
+        a.tau = dt / M;
+        a.g = s->p.gravity;
+        a.w1 = scheme == SSE_SCHEME_SSPRK3 ? 1.0 / (6.0 * M) : 1.0 / (2.0 * M);
+        a.w3 = scheme == SSE_SCHEME_SSPRK3 ? 2.0 / (3.0 * M) : 0.0;
+        const R *pu = iu, *pz = iz;
+        for (int sub = 0; sub < M; ++sub) {
+            const bool to_out = (M - 1 - sub) % 2 == 0;
+            R *tu = to_out ? ou : u1, *tz = to_out ? oz : z1;
+            a.ua = pu;
+            a.za = pz;
+            a.uo = tu;
+            a.zo = tz;
+            a.zeroF = sub == 0;
+            {
+                ProfScope ps(s, SSE_PROF_BT_EVAL);
+                launch_bt_substep<R>(a, scheme, s->stream);
+            }
+            pu = tu;
+            pz = tz;
+        }
+        if constexpr (!std::is_same<R, double>::value) {
+            convert<R, double>(s, ou, out_u, m.E);
+            convert<R, double>(s, oz, out_z, m.C);
+        }
+        return;
+    }
     if (s->rec) s->rec->loop_seq = s->rec->seq++;
     const int nblk = bt_blocks(m.E, m.C, s->geom);
     BTEvalArgs<R> a{};
@@ -603,6 +645,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     // the host-side state I/O translates at the boundary.
     // The caller's numbering is kept when it is already at least as local
     // (share of edges whose two cells lie within kLocalSpan indices).
+    const sse_mesh_desc *d0 = d;  // the caller's numbering
     MeshOrder ord;
     locality_order(d, kPatchCells, ord);
     if (local_share(d, nullptr) >= local_share(d, &ord)) identity_order(d, ord);
@@ -616,6 +659,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     MeshLayout lay = mesh_layout(d->n_cells, d->n_edges, d->n_vertices);
     size_t need = lay.total;
     for (int q = 0; q < kTileVariants; ++q) need += tiles_bytes(d, kTileSizes[q]);
+    need += bt_tiles_bytes(d0);
     if (!dev_buf || bytes < need) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
     HostMeshTables t;
@@ -715,6 +759,46 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
         dt.loc = (const uint8_t *)put(ht.loc.data(), ht.loc.size());
         SSE_HIP(hipStreamSynchronize(s));
     }
+    // Patches of the tiled barotropic substeps (partitioned in the caller's
+    // numbering, the same partition the device-bytes query sizes).
+    {
+        std::vector<int32_t> pid0, pid;
+        int nP = 0;
+        HostBtTiles hb;
+        if (bt_partition(d0, pid0, nP)) {
+            pid.resize(d->n_cells);
+            for (int i = 0; i < d->n_cells; ++i) pid[i] = pid0[ord.cell_old[i]];
+            if (build_bt_tiles(d, pid, nP, &t, hb)) {
+                auto put = [&](const void *src, size_t n) -> const void * {
+                    char *dst = base + cursor;
+                    if (n) hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+                    cursor += (n + kAlign - 1) / kAlign * kAlign;
+                    return dst;
+                };
+                DevBtTiles &b = m->bt;
+                b.patch = (const int32_t *)put(hb.patch.data(), hb.patch.size() * 4);
+                b.eid = (const int32_t *)put(hb.eid.data(), hb.eid.size() * 4);
+                b.cid = (const int32_t *)put(hb.cid.data(), hb.cid.size() * 4);
+                b.cH = (const double *)put(hb.cH.data(), hb.cH.size() * 8);
+                b.cH_f = (const float *)put(hb.cH_f.data(), hb.cH_f.size() * 4);
+                b.ec = (const uint32_t *)put(hb.ec.data(), hb.ec.size() * 4);
+                b.enb = (const uint32_t *)put(hb.enb.data(), hb.enb.size() * 4);
+                b.ew = (const double *)put(hb.ew.data(), hb.ew.size() * 8);
+                b.ew_f = (const float *)put(hb.ew_f.data(), hb.ew_f.size() * 4);
+                b.eidc = (const double *)put(hb.eidc.data(), hb.eidc.size() * 8);
+                b.eidc_f = (const float *)put(hb.eidc_f.data(), hb.eidc_f.size() * 4);
+                b.cen = (const uint32_t *)put(hb.cen.data(), hb.cen.size() * 4);
+                b.ccd = (const double *)put(hb.ccd.data(), hb.ccd.size() * 8);
+                b.ccd_f = (const float *)put(hb.ccd_f.data(), hb.ccd_f.size() * 4);
+                b.cwet = (const uint8_t *)put(hb.cwet.data(), hb.cwet.size());
+                SSE_HIP(hipStreamSynchronize(s));
+                b.nP = hb.nP;
+                b.ks = hb.ks;
+                b.lds_d = hb.lds_d;
+                b.lds_f = hb.lds_f;
+            }
+        }
+    }
     if (cursor > need) { delete m; set_error("internal: tile tables overflow the mesh buffer"); return SSE_EINVAL; }
     *out = m;
     return SSE_OK;
@@ -740,9 +824,12 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     if (!d || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
     int rc = check_params(p);
     if (rc) return rc;
-    if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { set_error("mesh counts must be positive"); return SSE_EINVAL; }
+    std::string err;
+    rc = validate_desc(d, err);
+    if (rc != SSE_OK) { set_error(err); return rc; }
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
+    mb += bt_tiles_bytes(d);
     *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision));
     return SSE_OK;
 }
@@ -770,7 +857,27 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     set_tiled_lds_limit((size_t)lds_max);
     s->lds_max = (size_t)lds_max;
     s->edge_variant = -1;
+    s->bt_variant = bt_tiles_fit(s) ? 1 : 0;
     *out = s;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_set_bt_variant(sse_state *s, int variant) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    if (variant != 0 && variant != 1) { set_error("barotropic variant must be 0 or 1"); return SSE_EINVAL; }
+    if (variant == 1 && !bt_tiles_fit(s)) {
+        set_error("barotropic variant 1: the mesh has no patches that fit a workgroup");
+        return SSE_EINVAL;
+    }
+    s->bt_variant = variant;
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    s->graph_exec = nullptr;
+    return SSE_OK;
+}
+
+extern "C" int sse_state_get_bt_variant(const sse_state *s, int *variant) {
+    if (!s || !variant) { set_error("NULL argument"); return SSE_EINVAL; }
+    *variant = s->bt_variant;
     return SSE_OK;
 }
 

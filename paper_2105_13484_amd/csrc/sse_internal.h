@@ -100,6 +100,49 @@ struct DevTiles {
 
 }  // namespace sse
 
+namespace sse {
+// Tiled barotropic substeps.  The cells are cut into compact patches; a patch
+// with its halo rings is everything one SSPRK3 substep (three evaluations)
+// of its own cells and edges reads, so one workgroup advances its patch a
+// whole substep with the state in LDS and the stencil tables in registers,
+// and the launches per barotropic loop drop from 3M to M.
+//
+// Region of a patch, by level k = 0..3: cells R_k (R_0 the patch, R_{k+1} =
+// R_k and its neighbours) and edges E_k (E_0 the owned edges, those whose
+// first cell is in the patch; E_k = all edges of R_k for k >= 1), listed
+// level by level, so a level-k set is a prefix of the region lists.  The
+// evaluation that produces level k reads level k + 1.
+constexpr int kBtThreads = 1024;   // threads per workgroup
+constexpr int kBtPatch = 384;      // target cells per patch
+constexpr int kBtEdgeSlots = 2;    // edges of level 2 per thread (at most)
+constexpr int kBtRec = 12;         // ints per patch record
+struct DevBtTiles {
+    int nP = 0;                    // patches (0: tiling not available)
+    int ks = 0;                    // edge slots per thread needed (1 or 2)
+    size_t lds_d = 0, lds_f = 0;   // dynamic LDS bytes for R = double / float
+    // per patch: e0, es0, c0, cs0, ne[4], nc[4] (offsets into the region
+    // lists / the stencil tables, prefix counts per level)
+    const int32_t *patch = nullptr;
+    const int32_t *eid = nullptr;     // [sum ne3] global edge of each region edge
+    const int32_t *cid = nullptr;     // [sum nc3] global cell of each region cell
+    const double *cH = nullptr;       // [sum nc3] H of region cells
+    const float *cH_f = nullptr;
+    // stencil tables of the edges of levels 0..2 (es0 + le), per patch slot-major
+    // with stride ne2: entry (j, le) at es0 * J + j * ne2 + le
+    const uint32_t *ec = nullptr;     // [sum ne2] local c1 | c2 << 15 | wet << 30
+    const uint32_t *enb = nullptr;    // [5][..] local stencil edges, two 16-bit indices per word
+    const double *ew = nullptr;       // [10][..] W (f_e + f_j) / 2
+    const float *ew_f = nullptr;
+    const double *eidc = nullptr;     // [..] 1 / d_e
+    const float *eidc_f = nullptr;
+    // cell tables of the cells of levels 0..2 (cs0 + lc), stride nc2
+    const uint32_t *cen = nullptr;    // [6][..] local edge | local neighbour << 16
+    const double *ccd = nullptr;      // [6][..] s l / A
+    const float *ccd_f = nullptr;
+    const uint8_t *cwet = nullptr;    // [..]
+};
+}  // namespace sse
+
 struct sse_mesh {
     sse::DevMesh d;
     int C = 0, E = 0, V = 0;
@@ -109,6 +152,7 @@ struct sse_mesh {
     std::vector<int32_t> cell_old, edge_old;
     std::vector<int32_t> cells_on_edge;     // host copy (for debug helpers)
     sse::DevTiles tiles[sse::kTileVariants];  // T = 8, 16, 32 edges per tile
+    sse::DevBtTiles bt;                       // patches of the tiled barotropic substeps
     void *dev_buf = nullptr;
     size_t dev_bytes = 0;
 };
@@ -182,6 +226,30 @@ void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p);
 // cells of e" (then the generic tables are used).
 constexpr int kChainWords = 11;  // A0..A5, B0..B3, flag (A0 is vertex 0 of the edge)
 bool canonical_stencils(PermutedDesc &p, std::vector<int32_t> &chain);
+
+// Patches of the tiled barotropic substeps, computed in the numbering of d:
+// breadth-first patches of about kBtPatch cells, split in two (in their
+// breadth-first order) until every patch's level-2 region fits the
+// workgroup (kBtEdgeSlots edges and one cell per thread).  pid[c] = patch of
+// cell c.  Returns false if no such partition exists.
+bool bt_partition(const sse_mesh_desc *d, std::vector<int32_t> &pid, int &nP);
+
+struct HostBtTiles {
+    int nP = 0, ks = 0;
+    size_t lds_d = 0, lds_f = 0;
+    std::vector<int32_t> patch, eid, cid;
+    std::vector<double> cH, ew, eidc, ccd;
+    std::vector<float> cH_f, ew_f, eidc_f, ccd_f;
+    std::vector<uint32_t> ec, enb, cen;
+    std::vector<uint8_t> cwet;
+};
+// Region lists and tables of the partition pid (numbering of d, the same
+// numbering as the tables t).  With t == nullptr only the sizes are filled
+// (patch records, list lengths), which is what the device-bytes query needs.
+bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int nP, const HostMeshTables *t,
+                    HostBtTiles &bt);
+// Device bytes of the tiled barotropic tables of d (0 if d cannot be tiled).
+size_t bt_tiles_bytes(const sse_mesh_desc *d);
 
 void set_error(const std::string &msg);
 

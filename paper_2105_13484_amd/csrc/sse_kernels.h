@@ -90,6 +90,20 @@ struct BTEvalArgs {
     double tau, g;
 };
 
+// One whole barotropic substep of every patch (tiled kernel): input (ua, za)
+// is also the combination base; output (uo, zo) must not alias the input.
+template <typename R>
+struct BTTileArgs {
+    DevBtTiles t;
+    const R *ua, *za;
+    R *uo, *zo;
+    const double *G;
+    double *F;                // nullable
+    int zeroF;
+    double tau, g;
+    double w1, w3;            // flux weights: SSPRK3 w1, w1, w3; SSPRK2 w1, w1
+};
+
 // Thickness stage with the z-star distribution of a 2D total flux.
 struct THArgs {
     DevMesh m;
@@ -180,6 +194,8 @@ template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
 template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
 void set_tiled_lds_limit(size_t bytes);
 template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
+// scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit).
+template <typename R> void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s);
 template <typename R> void launch_thickness_iso(const THIsoArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble(const AssembleArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R>

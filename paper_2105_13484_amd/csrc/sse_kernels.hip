@@ -223,10 +223,16 @@ __device__ __forceinline__ void col_tridiag_solve(int L, T (&lo)[NK], T (&di)[NK
     for (int c = 0; c < NK; ++c) d[c] = d[c] / di[c];
 }
 
+// a b + c rounded once
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The 3/4 combination is one fused multiply-add with an explicit operand
+// order (1/4 x is exact), so every kernel that forms it rounds alike.
 template <typename T>
 __device__ __forceinline__ T combine(int mode, T b, T x) {
     switch (mode) {
-        case COMB_34: return T(0.75) * b + T(0.25) * x;
+        case COMB_34: return fmadd(T(0.75), b, T(0.25) * x);
         case COMB_THIRD: return b / T(3) + T(2) * x / T(3);
         case COMB_HALF: return T(0.5) * (b + x);
         default: return x;
@@ -880,8 +886,12 @@ struct BTTables<float> {
 
 // One block of edges (edge_part) or of cells of one evaluation.  kD16: the
 // index tables are read as 16-bit offsets (half the index bytes).
+// The barotropic kernels (one evaluation / one tiled substep) spell every
+// fused multiply-add out and contract nothing else, so that the two forms
+// give the same bits whatever the compiler would fuse in either context.
 template <typename R, bool kD16>
 __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_part, int lb) {
+#pragma clang fp contract(off)
     const DevMesh &m = a.m;
     const R tau = (R)a.tau, g = (R)a.g;
     if (edge_part) {
@@ -910,16 +920,16 @@ __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_p
 #pragma unroll
         for (int j = 0; j < kMaxEdges2; ++j) {
             const int ep = kD16 ? e + (int)m.eoe16[(size_t)j * m.E + e] : m.eoe[(size_t)j * m.E + e];
-            cor += wf[(size_t)j * m.E + e] * a.ua[ep];
+            cor = fmadd(wf[(size_t)j * m.E + e], a.ua[ep], cor);
         }
-        const R ru = cor - g * (z2 - z1) * BTTables<R>::inv_dc(m)[e] + (R)a.G[e];
+        const R ru = fmadd(-(g * (z2 - z1)), BTTables<R>::inv_dc(m)[e], cor) + (R)a.G[e];
         // the first stage of a substep combines with nothing: no base read
         const R base = a.comb != COMB_NONE ? a.ub[e] : R(0);
-        a.uo[e] = combine<R>(a.comb, base, ua + tau * ru);
+        a.uo[e] = combine<R>(a.comb, base, fmadd(tau, ru, ua));
         if (a.F) {
             // The transport accumulates in FP64 in both modes.
             const double flux = (double)ua * (0.5 * (((double)z1 + m.H[c1]) + ((double)z2 + m.H[c2])));
-            a.F[e] = (a.zeroF ? 0.0 : a.F[e]) + a.wF * flux;
+            a.F[e] = fmadd(a.wF, flux, a.zeroF ? 0.0 : a.F[e]);
         }
     } else {
         const int i = lb * blockDim.x + threadIdx.x;
@@ -936,10 +946,182 @@ __device__ __forceinline__ void bt_eval_body(const BTEvalArgs<R> &a, bool edge_p
             const int e = kD16 ? be + (int)m.cedges16[(size_t)j * m.C + i] : m.cell_edges_t[(size_t)j * m.C + i];
             const int nb = kD16 ? i + (int)m.cnbrs16[(size_t)j * m.C + i] : m.cell_nbrs_t[(size_t)j * m.C + i];
             const R zn = a.za[nb] + Ht[nb];
-            div += cd * (a.ua[e] * (R(0.5) * (zi + zn)));
+            div = fmadd(cd, a.ua[e] * (R(0.5) * (zi + zn)), div);
         }
         const R base = a.comb != COMB_NONE ? a.zb[i] : R(0);
-        a.zo[i] = combine<R>(a.comb, base, a.za[i] + tau * (-div));
+        a.zo[i] = combine<R>(a.comb, base, fmadd(tau, -div, a.za[i]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled barotropic substep: one workgroup advances one cell patch (with its
+// halo rings) through a whole SSPRK3 (three evaluations) or SSPRK2 (two)
+// substep.  The substep input and every stage live in LDS; each thread holds
+// the stencil tables of its edges (at most KS) and of its cell in registers
+// for all evaluations, so the tables are read once per substep instead of
+// once per evaluation.  Evaluation k computes the region level that the next
+// one reads (level 2, then 1, then 0 = the patch's own cells and edges) with
+// exactly the arithmetic of the one-evaluation kernel, so both paths give the
+// same bits.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct BtTab;
+template <>
+struct BtTab<double> {
+    __device__ static const double *w(const DevBtTiles &t) { return t.ew; }
+    __device__ static const double *idc(const DevBtTiles &t) { return t.eidc; }
+    __device__ static const double *cd(const DevBtTiles &t) { return t.ccd; }
+};
+template <>
+struct BtTab<float> {
+    __device__ static const float *w(const DevBtTiles &t) { return t.ew_f; }
+    __device__ static const float *idc(const DevBtTiles &t) { return t.eidc_f; }
+    __device__ static const float *cd(const DevBtTiles &t) { return t.ccd_f; }
+};
+
+template <typename R, int kScheme, int KS>
+__global__ void __launch_bounds__(kBtThreads) bt_substep_kernel(BTTileArgs<R> a) {
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) double lds_d[];
+    const DevBtTiles &T = a.t;
+    const int p = xcd_block(T.nP);
+    if (p < 0) return;
+    const int tid = threadIdx.x;
+    const int32_t *rec = T.patch + (size_t)p * kBtRec;
+    const int e0 = rec[0], es0 = rec[1], c0 = rec[2], cs0 = rec[3];
+    int ne[4], nc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ne[k] = rec[4 + k];
+        nc[k] = rec[8 + k];
+    }
+    constexpr int kIn = kScheme == 3 ? 3 : 2;  // level of the substep input
+    const int nEin = ne[kIn], nCin = nc[kIn];
+    const int nE1 = ne[kIn - 1], nC1 = nc[kIn - 1];  // level of the first evaluation
+    const int se = ne[2], sc = nc[2];                // strides of the stencil tables
+
+    // LDS: H (double) | U0 U1 U2 | Z0 Z1 Z2 | H in R (FP32 state only)
+    double *H64 = lds_d;
+    R *U0 = reinterpret_cast<R *>(H64 + nc[3]);
+    R *U1 = U0 + ne[3];
+    R *U2 = U1 + ne[2];
+    R *Z0 = U2 + ne[1];
+    R *Z1 = Z0 + nc[3];
+    R *Z2 = Z1 + nc[2];
+    const R *Hr;
+    if constexpr (sizeof(R) == 8) {
+        Hr = reinterpret_cast<const R *>(H64);
+    } else {
+        R *h = Z2 + nc[1];
+        for (int lc = tid; lc < nCin; lc += kBtThreads) h[lc] = T.cH_f[c0 + lc];
+        Hr = h;
+    }
+    for (int le = tid; le < nEin; le += kBtThreads) U0[le] = a.ua[T.eid[e0 + le]];
+    for (int lc = tid; lc < nCin; lc += kBtThreads) {
+        Z0[lc] = a.za[T.cid[c0 + lc]];
+        H64[lc] = T.cH[c0 + lc];
+    }
+
+    // this thread's edges (le = s kBtThreads + tid) and cell (lc = tid)
+    const R *__restrict__ wt = BtTab<R>::w(T);
+    R w[KS][kMaxEdges2], idc[KS], Gv[KS];
+    uint32_t nbw[KS][kMaxEdges2 / 2], ecw[KS];
+    double Fa[KS];
+    int ge[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int le = s * kBtThreads + tid;
+        const bool on = le < nE1;
+        const int q = on ? le : 0;
+        ecw[s] = on ? T.ec[es0 + q] : 0u;
+        ge[s] = T.eid[e0 + q];
+        idc[s] = BtTab<R>::idc(T)[es0 + q];
+        Gv[s] = (R)a.G[ge[s]];
+#pragma unroll
+        for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = wt[(size_t)kMaxEdges2 * es0 + (size_t)j * se + q];
+#pragma unroll
+        for (int i = 0; i < kMaxEdges2 / 2; ++i) nbw[s][i] = T.enb[(size_t)(kMaxEdges2 / 2) * es0 + (size_t)i * se + q];
+        Fa[s] = (a.F && le < ne[0]) ? (a.zeroF ? 0.0 : a.F[ge[s]]) : 0.0;
+    }
+    const bool con = tid < nC1;
+    const int qc = con ? tid : 0;
+    const bool cwet = con && T.cwet[cs0 + qc] != 0;
+    const int gc = T.cid[c0 + qc];
+    R cd[kMaxEdges];
+    uint32_t cen[kMaxEdges];
+#pragma unroll
+    for (int j = 0; j < kMaxEdges; ++j) {
+        cd[j] = BtTab<R>::cd(T)[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
+        cen[j] = T.cen[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
+    }
+    __syncthreads();
+
+    const R tau = (R)a.tau, g = (R)a.g;
+    // One evaluation producing level lvl from (Ui, Zi); the last one writes the
+    // substep output to global memory.
+    auto evaluate = [&](const R *Ui, const R *Zi, int lvl, int comb, double wF, R *Uo, R *Zo, bool last) {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int le = s * kBtThreads + tid;
+            if (le < ne[lvl]) {
+                const uint32_t c = ecw[s];
+                R out = R(0);
+                if ((c >> 30) & 1u) {
+                    const int l1 = (int)(c & 0x7fffu), l2 = (int)((c >> 15) & 0x7fffu);
+                    const R ua = Ui[le];
+                    const R z1 = Zi[l1], z2 = Zi[l2];
+                    R cor = R(0);
+#pragma unroll
+                    for (int j = 0; j < kMaxEdges2; ++j) {
+                        const int lj = (int)((nbw[s][j >> 1] >> (16 * (j & 1))) & 0xffffu);
+                        cor = fmadd(w[s][j], Ui[lj], cor);
+                    }
+                    const R ru = fmadd(-(g * (z2 - z1)), idc[s], cor) + Gv[s];
+                    const R base = comb != COMB_NONE ? U0[le] : R(0);
+                    out = combine<R>(comb, base, fmadd(tau, ru, ua));
+                    if (a.F && le < ne[0]) {
+                        const double flux = (double)ua * (0.5 * (((double)z1 + H64[l1]) + ((double)z2 + H64[l2])));
+                        Fa[s] = fmadd(wF, flux, Fa[s]);
+                    }
+                }
+                if (last) a.uo[ge[s]] = out;
+                else Uo[le] = out;
+            }
+        }
+        if (tid < nc[lvl]) {
+            R out = R(0);
+            if (cwet) {
+                const R zi = Zi[tid] + Hr[tid];
+                R div = R(0);
+#pragma unroll
+                for (int j = 0; j < kMaxEdges; ++j) {
+                    const int le = (int)(cen[j] & 0xffffu), ln = (int)(cen[j] >> 16);
+                    const R zn = Zi[ln] + Hr[ln];
+                    div = fmadd(cd[j], Ui[le] * (R(0.5) * (zi + zn)), div);
+                }
+                const R base = comb != COMB_NONE ? Z0[tid] : R(0);
+                out = combine<R>(comb, base, fmadd(tau, -div, Zi[tid]));
+            }
+            if (last) a.zo[gc] = out;
+            else Zo[tid] = out;
+        }
+    };
+    if constexpr (kScheme == 3) {
+        evaluate(U0, Z0, 2, COMB_NONE, a.w1, U1, Z1, false);
+        __syncthreads();
+        evaluate(U1, Z1, 1, COMB_34, a.w1, U2, Z2, false);
+        __syncthreads();
+        evaluate(U2, Z2, 0, COMB_THIRD, a.w3, nullptr, nullptr, true);
+    } else {
+        evaluate(U0, Z0, 1, COMB_NONE, a.w1, U1, Z1, false);
+        __syncthreads();
+        evaluate(U1, Z1, 0, COMB_HALF, a.w1, nullptr, nullptr, true);
+    }
+    if (a.F) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (s * kBtThreads + tid < ne[0]) a.F[ge[s]] = Fa[s];
     }
 }
 
@@ -1381,7 +1563,29 @@ void set_tiled_lds_limit(size_t bytes) {
                          SSE_TILED_FNS(float, true)};
 #undef SSE_TILED_FNS
 #undef SSE_TILED_FN
+    const void *bt[] = {reinterpret_cast<const void *>(bt_substep_kernel<double, 3, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 3, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 2, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 2, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 3, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 3, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 2>)};
+    for (const void *f : bt) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename R>
+void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s) {
+    const dim3 grid = xcd_grid(a.t.nP), block(kBtThreads);
+    const size_t lds = sizeof(R) == 8 ? a.t.lds_d : a.t.lds_f;
+    if (scheme == 3) {
+        if (a.t.ks == 1) bt_substep_kernel<R, 3, 1><<<grid, block, lds, s>>>(a);
+        else bt_substep_kernel<R, 3, 2><<<grid, block, lds, s>>>(a);
+    } else {
+        if (a.t.ks == 1) bt_substep_kernel<R, 2, 1><<<grid, block, lds, s>>>(a);
+        else bt_substep_kernel<R, 2, 2><<<grid, block, lds, s>>>(a);
+    }
 }
 
 template <typename R>
@@ -1472,6 +1676,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_bt_substep<R>(const BTTileArgs<R> &, int, hipStream_t);                           \
     template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, bool, const Geom &, hipStream_t); \
     template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \
     template void launch_thickness_iso_batch<R>(const BatchLaunch<THIsoArgs<R>> &, int, const Geom &,      \

@@ -590,6 +590,257 @@ bool canonical_stencils(PermutedDesc &p, std::vector<int32_t> &chain) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Patches of the tiled barotropic substeps
+// ---------------------------------------------------------------------------
+namespace {
+
+// Cells adjacent to c across its edges.
+template <typename F>
+void for_each_neighbour(const sse_mesh_desc *d, int c, F &&f) {
+    const int me = d->max_edges;
+    for (int j = 0; j < d->n_edges_on_cell[c]; ++j) {
+        const int e = d->edges_on_cell[(size_t)c * me + j];
+        if (e < 0) continue;
+        const int a = d->cells_on_edge[2 * (size_t)e], b = d->cells_on_edge[2 * (size_t)e + 1];
+        const int nb = a == c ? b : a;
+        if (nb >= 0 && nb != c) f(nb);
+    }
+}
+
+// Region of one patch: cells and edges by level (see DevBtTiles).  Stamps
+// mark membership without clearing between patches; loc holds the local
+// index of every member.
+struct RegionBuilder {
+    const sse_mesh_desc *d;
+    std::vector<int32_t> cst, est, cloc, eloc;
+    int stamp = 0;
+    std::vector<int32_t> cells, edges;
+    int nc[4] = {}, ne[4] = {};
+
+    explicit RegionBuilder(const sse_mesh_desc *d_)
+        : d(d_), cst(d_->n_cells, 0), est(d_->n_edges, 0), cloc(d_->n_cells, -1), eloc(d_->n_edges, -1) {}
+
+    void add_cell(int c) { cst[c] = stamp; cloc[c] = (int)cells.size(); cells.push_back(c); }
+    void add_edge(int e) { est[e] = stamp; eloc[e] = (int)edges.size(); edges.push_back(e); }
+
+    // own: the patch's cells; pid/p decide edge ownership (first cell).
+    void build(const std::vector<int32_t> &own, const std::vector<int32_t> &pid, int p) {
+        ++stamp;
+        cells.clear();
+        edges.clear();
+        std::vector<int32_t> lvl(own);
+        std::sort(lvl.begin(), lvl.end());
+        for (int c : lvl) add_cell(c);
+        nc[0] = (int)cells.size();
+        const int me = d->max_edges;
+        // level-0 edges: owned (first cell in the patch)
+        std::vector<int32_t> tmp;
+        for (int c : own)
+            for (int j = 0; j < d->n_edges_on_cell[c]; ++j) {
+                const int e = d->edges_on_cell[(size_t)c * me + j];
+                if (e >= 0 && pid[d->cells_on_edge[2 * (size_t)e]] == p) tmp.push_back(e);
+            }
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        for (int e : tmp) add_edge(e);
+        ne[0] = (int)edges.size();
+        for (int k = 1; k <= 3; ++k) {
+            tmp.clear();
+            for (int i = 0; i < nc[k - 1]; ++i)
+                for_each_neighbour(d, cells[i], [&](int nb) {
+                    if (cst[nb] != stamp) { cst[nb] = stamp; tmp.push_back(nb); }
+                });
+            std::sort(tmp.begin(), tmp.end());
+            for (int c : tmp) { cst[c] = 0; add_cell(c); }
+            nc[k] = (int)cells.size();
+            // edges of level k: every edge of R_k not listed yet
+            tmp.clear();
+            for (int i = 0; i < nc[k]; ++i) {
+                const int c = cells[i];
+                for (int j = 0; j < d->n_edges_on_cell[c]; ++j) {
+                    const int e = d->edges_on_cell[(size_t)c * me + j];
+                    if (e >= 0 && est[e] != stamp) { est[e] = stamp; tmp.push_back(e); }
+                }
+            }
+            std::sort(tmp.begin(), tmp.end());
+            for (int e : tmp) { est[e] = 0; add_edge(e); }
+            ne[k] = (int)edges.size();
+        }
+    }
+    bool fits() const {
+        return ne[2] <= kBtEdgeSlots * kBtThreads && nc[2] <= kBtThreads && nc[3] < (1 << 15) && ne[3] < (1 << 16);
+    }
+};
+
+template <typename R>
+size_t bt_lds_bytes(const int (&ne)[4], const int (&nc)[4]) {
+    // U0, U1, U2, Z0, Z1, Z2 (R), H (double), and H in R for FP32 state
+    size_t b = sizeof(R) * ((size_t)ne[3] + ne[2] + ne[1] + nc[3] + nc[2] + nc[1]) + 8 * (size_t)nc[3];
+    if (sizeof(R) != 8) b += sizeof(R) * (size_t)nc[3];
+    return b;
+}
+
+constexpr size_t kBtLdsMax = 160 * 1024;
+
+}  // namespace
+
+bool bt_partition(const sse_mesh_desc *d, std::vector<int32_t> &pid, int &nP) {
+    const int C = d->n_cells;
+    pid.assign(C, -1);
+    std::vector<std::vector<int32_t>> patches;
+    // breadth-first patches, seeded from the previous patches' frontier
+    std::vector<char> taken(C, 0);
+    std::deque<int> front, q;
+    int scan = 0, done = 0;
+    while (done < C) {
+        int seed = -1;
+        while (!front.empty()) {
+            const int c = front.front();
+            front.pop_front();
+            if (!taken[c]) { seed = c; break; }
+        }
+        if (seed < 0) {
+            while (taken[scan]) ++scan;
+            seed = scan;
+        }
+        std::vector<int32_t> cells;
+        q.clear();
+        q.push_back(seed);
+        taken[seed] = 1;
+        while (!q.empty()) {
+            const int c = q.front();
+            q.pop_front();
+            cells.push_back(c);
+            for_each_neighbour(d, c, [&](int nb) {
+                if (taken[nb]) return;
+                if ((int)(cells.size() + q.size()) < kBtPatch) {
+                    taken[nb] = 1;
+                    q.push_back(nb);
+                } else {
+                    front.push_back(nb);
+                }
+            });
+        }
+        done += (int)cells.size();
+        for (int c : cells) pid[c] = (int)patches.size();
+        patches.push_back(std::move(cells));
+    }
+    // split patches whose region does not fit, in their breadth-first order
+    RegionBuilder rb(d);
+    for (size_t p = 0; p < patches.size(); ++p) {
+        for (;;) {
+            rb.build(patches[p], pid, (int)p);
+            if (rb.fits() && bt_lds_bytes<double>(rb.ne, rb.nc) <= kBtLdsMax) break;
+            if (patches[p].size() < 2) return false;
+            const size_t half = patches[p].size() / 2;
+            std::vector<int32_t> tail(patches[p].begin() + half, patches[p].end());
+            patches[p].resize(half);
+            for (int c : tail) pid[c] = (int)patches.size();
+            patches.push_back(std::move(tail));
+        }
+    }
+    nP = (int)patches.size();
+    return true;
+}
+
+bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int nP, const HostMeshTables *t,
+                    HostBtTiles &bt) {
+    const int C = d->n_cells, E = d->n_edges;
+    std::vector<std::vector<int32_t>> own(nP);
+    for (int c = 0; c < C; ++c) own[pid[c]].push_back(c);
+    RegionBuilder rb(d);
+    bt = HostBtTiles();
+    bt.nP = nP;
+    bt.patch.assign((size_t)nP * kBtRec, 0);
+    int e0 = 0, es0 = 0, c0 = 0, cs0 = 0, max_ne2 = 0;
+    for (int p = 0; p < nP; ++p) {
+        rb.build(own[p], pid, p);
+        if (!rb.fits()) return false;
+        int32_t *r = &bt.patch[(size_t)p * kBtRec];
+        r[0] = e0; r[1] = es0; r[2] = c0; r[3] = cs0;
+        for (int k = 0; k < 4; ++k) { r[4 + k] = rb.ne[k]; r[8 + k] = rb.nc[k]; }
+        max_ne2 = std::max(max_ne2, rb.ne[2]);
+        bt.lds_d = std::max(bt.lds_d, bt_lds_bytes<double>(rb.ne, rb.nc));
+        bt.lds_f = std::max(bt.lds_f, bt_lds_bytes<float>(rb.ne, rb.nc));
+        if (t) {
+            const int ne2 = rb.ne[2], nc2 = rb.nc[2];
+            bt.eid.insert(bt.eid.end(), rb.edges.begin(), rb.edges.end());
+            bt.cid.insert(bt.cid.end(), rb.cells.begin(), rb.cells.end());
+            for (int c : rb.cells) { bt.cH.push_back(t->H[c]); bt.cH_f.push_back(t->H_f[c]); }
+            const size_t b = bt.ec.size();
+            bt.ec.resize(b + ne2);
+            bt.eidc.resize(b + ne2);
+            bt.eidc_f.resize(b + ne2);
+            bt.enb.resize(5 * (b + ne2));
+            bt.ew.resize(10 * (b + ne2));
+            bt.ew_f.resize(10 * (b + ne2));
+            auto in_c = [&](int c) { return c >= 0 && rb.cst[c] == rb.stamp; };
+            auto in_e = [&](int e) { return e >= 0 && rb.est[e] == rb.stamp; };
+            for (int le = 0; le < ne2; ++le) {
+                const int e = rb.edges[le];
+                const int g1 = t->edge_cells[2 * (size_t)e], g2 = t->edge_cells[2 * (size_t)e + 1];
+                if (!in_c(g1) || !in_c(g2)) return false;
+                const int c1 = rb.cloc[g1], c2 = rb.cloc[g2];
+                bt.ec[b + le] = (uint32_t)c1 | ((uint32_t)c2 << 15) | ((uint32_t)(t->emask[e] ? 1 : 0) << 30);
+                bt.eidc[b + le] = t->inv_dc[e];
+                bt.eidc_f[b + le] = t->inv_dc_f[e];
+                uint32_t lj[10];
+                for (int j = 0; j < 10; ++j) {
+                    const int ep = t->eoe[(size_t)j * E + e];
+                    if (!in_e(ep)) return false;  // a stencil reaching past the two cells
+                    lj[j] = (uint32_t)rb.eloc[ep];
+                    bt.ew[10 * b + (size_t)j * ne2 + le] = t->wf[(size_t)j * E + e];
+                    bt.ew_f[10 * b + (size_t)j * ne2 + le] = t->wf_f[(size_t)j * E + e];
+                }
+                for (int i = 0; i < 5; ++i) bt.enb[5 * b + (size_t)i * ne2 + le] = lj[2 * i] | (lj[2 * i + 1] << 16);
+            }
+            const size_t cb = bt.cwet.size();
+            bt.cwet.resize(cb + nc2);
+            bt.cen.resize(6 * (cb + nc2));
+            bt.ccd.resize(6 * (cb + nc2));
+            bt.ccd_f.resize(6 * (cb + nc2));
+            for (int lc = 0; lc < nc2; ++lc) {
+                const int i = rb.cells[lc];
+                bt.cwet[cb + lc] = t->cmask[i] ? 1 : 0;
+                for (int j = 0; j < 6; ++j) {
+                    const int e = t->cell_edges_t[(size_t)j * C + i], nb = t->cell_nbrs_t[(size_t)j * C + i];
+                    if (!in_e(e) || !in_c(nb)) return false;
+                    bt.cen[6 * cb + (size_t)j * nc2 + lc] = (uint32_t)rb.eloc[e] | ((uint32_t)rb.cloc[nb] << 16);
+                    bt.ccd[6 * cb + (size_t)j * nc2 + lc] = t->cell_div_t[(size_t)j * C + i];
+                    bt.ccd_f[6 * cb + (size_t)j * nc2 + lc] = t->cell_div_t_f[(size_t)j * C + i];
+                }
+            }
+        }
+        e0 += rb.ne[3];
+        es0 += rb.ne[2];
+        c0 += rb.nc[3];
+        cs0 += rb.nc[2];
+    }
+    bt.ks = (max_ne2 + kBtThreads - 1) / kBtThreads;
+    if (!t) {
+        // sizes only
+        bt.eid.resize(e0);
+        bt.cid.resize(c0);
+        bt.ec.resize(es0);
+        bt.cwet.resize(cs0);
+    }
+    return bt.ks >= 1 && bt.ks <= kBtEdgeSlots;
+}
+
+size_t bt_tiles_bytes(const sse_mesh_desc *d) {
+    std::vector<int32_t> pid;
+    int nP = 0;
+    if (!bt_partition(d, pid, nP)) return 0;
+    HostBtTiles bt;
+    if (!build_bt_tiles(d, pid, nP, nullptr, bt)) return 0;
+    auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
+    const size_t TE = bt.eid.size(), TC = bt.cid.size(), SE = bt.ec.size(), SC = bt.cwet.size();
+    return al(bt.patch.size() * 4) + al(TE * 4) + al(TC * 4) + al(TC * 8) + al(TC * 4) + al(SE * 4) +
+           al(SE * 5 * 4) + al(SE * 10 * 8) + al(SE * 10 * 4) + al(SE * 8) + al(SE * 4) + al(SC * 6 * 4) +
+           al(SC * 6 * 8) + al(SC * 6 * 4) + al(SC);
+}
+
 }  // namespace sse
 
 extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
@@ -601,8 +852,11 @@ extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
 
 extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
     if (!d || !bytes) { sse::set_error("NULL argument"); return SSE_EINVAL; }
-    if (d->n_cells <= 0 || d->n_edges <= 0 || d->n_vertices <= 0) { sse::set_error("mesh counts must be positive"); return SSE_EINVAL; }
+    std::string err;
+    const int rc = sse::validate_desc(d, err);
+    if (rc != SSE_OK) { sse::set_error(err); return rc; }
     *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < sse::kTileVariants; ++q) *bytes += sse::tiles_bytes(d, sse::kTileSizes[q]);
+    *bytes += sse::bt_tiles_bytes(d);
     return SSE_OK;
 }

@@ -32,6 +32,7 @@ EXPORTED = (
     "sse_batch_create", "sse_batch_destroy", "sse_batch_add", "sse_batch_remove", "sse_batch_size",
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
     "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
+    "sse_state_set_bt_variant", "sse_state_get_bt_variant",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -103,6 +104,8 @@ def load():
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
+        "sse_state_set_bt_variant": (c_int, [P, c_int]),
+        "sse_state_get_bt_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_geometry": (c_int, [P, c_int, c_int]),
         "sse_state_use_graph": (c_int, [P, c_int]),
         "sse_batch_create": (c_int, [P, POINTER(P)]),
@@ -184,13 +187,13 @@ def make_params(p) -> sse_params:
 
 
 def footprint_bytes(mesh, params) -> int:
-    """Device bytes (mesh image + workspace) of one state of `params` on `mesh`."""
-    C, E, V = mesh.nCells, mesh.nEdges, mesh.nVertices
-    d = sse_mesh_desc()
-    d.n_cells, d.n_edges, d.n_vertices = C, E, V
+    """Device bytes (mesh image + workspace) of one state of `params` on `mesh`
+    (sized from the mesh topology; depths and the land mask do not matter)."""
+    d, keep = mesh_desc(mesh, np.ones(mesh.nCells), np.ones(mesh.nCells, np.uint8))
     p = make_params(params)
     n = c_size_t()
     _check(load().sse_footprint_bytes(byref(d), byref(p), byref(n)))
+    del keep
     return int(n.value)
 
 
@@ -305,6 +308,21 @@ class DeviceState:
     def use_graph(self, enable: bool = True):
         """Replay each step as one captured HIP graph (needs a non-default stream)."""
         _check(load().sse_state_use_graph(self.handle, int(bool(enable))))
+
+    @property
+    def bt_variant(self) -> int:
+        """Barotropic loop kernels: 0 one launch per evaluation, 1 one per substep."""
+        v = c_int(0)
+        _check(load().sse_state_get_bt_variant(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    @bt_variant.setter
+    def bt_variant(self, variant: int):
+        _check(load().sse_state_set_bt_variant(self.handle, int(variant)))
+
+    def try_bt_variant(self, variant: int) -> bool:
+        """Select a barotropic loop variant; False (and no change) if unavailable."""
+        return load().sse_state_set_bt_variant(self.handle, int(variant)) == 0
 
     def try_edge_variant(self, variant: int) -> bool:
         """Select an edge-pass variant; False (and no change) if it does not fit."""

@@ -312,3 +312,52 @@ def test_edge_variants_bitwise_equal(dev, variant):
         out[v] = st.read()
     for k in out[-1]:
         assert np.array_equal(out[-1][k], out[variant][k]), k
+
+
+# ---------------------------------------------------------------------------
+# barotropic loop variants (one launch per evaluation, one per substep)
+# ---------------------------------------------------------------------------
+BT_CASES = {
+    "c0_one_patch": lambda: cases.c0(),
+    "hex32_L60": lambda: cases.c1(n=32, L=60, steps=3),
+    "sphere3_land_L7": lambda: cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0),
+    "sphere4_land_L9": lambda: cases.sphere_case(4, 9, 78, substeps=6, dt_btr=120.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BT_CASES))
+@pytest.mark.parametrize("scheme", [2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bt_variants_bitwise_equal(dev, name, scheme, precision):
+    """The per-substep (patch) kernel performs the per-evaluation kernel's
+    arithmetic on the same operands: whole steps agree bit for bit."""
+    case = cases.with_params(BT_CASES[name](), scheme=scheme, precision=precision)
+    out = {}
+    for v in (0, 1):
+        _, st = dev.state_from_case(case)
+        assert st.try_bt_variant(v), dev.last_error()
+        assert st.bt_variant == v
+        assert st.step(2) == 0
+        out[v] = st.read()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("scheme", [2, 3])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_barotropic_substep_variants_parity(dev, scheme, variant):
+    case = KERNEL_CASES["sphere3_land_L7"]()
+    st_o = Setup.from_case(case)
+    rng = np.random.default_rng(15)
+    ubar = np.where(st_o.edge_mask, rng.normal(0, 0.05, case.mesh.nEdges), 0.0)
+    zeta = np.where(st_o.cell_mask, rng.normal(0, 0.05, case.mesh.nCells), 0.0)
+    G = np.where(st_o.edge_mask, rng.normal(0, 1e-5, case.mesh.nEdges), 0.0)
+    M, dt = 8, case.params.dt
+    sub = S.barotropic_ssprk2_substep if scheme == 2 else S.barotropic_ssprk3_substep
+    u1, z1, F = sub(ubar, zeta, G, dt, M, st_o)
+    _, st = dev.state_from_case(case)
+    assert st.try_bt_variant(variant), dev.last_error()
+    g_u1, g_z1, g_F = st.debug_barotropic_substep(scheme, M, dt, ubar, zeta, G)
+    errs = {"ubar": rel_l2(g_u1, u1), "zeta": rel_l2(g_z1, z1), "Fzeta": rel_l2(g_F, F)}
+    _report(f"bt{scheme} variant={variant}", errs)
+    assert max(errs.values()) < TOL
