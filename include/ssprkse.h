@@ -127,9 +127,11 @@ const char *sse_version(void);
  * term energy neutral.  Touches no GPU.  SSE_EINVAL on the first violation. */
 int sse_mesh_validate(const sse_mesh_desc *d);
 
-/* Device bytes a mesh occupies (for the caller's allocation).  Validates d
- * as sse_mesh_validate does (SSE_EINVAL on a malformed mesh): the size of the
- * barotropic patch tables depends on the cell-edge topology. */
+/* Device bytes a mesh occupies (for the caller's allocation).  The size of
+ * the barotropic patch tables depends on the cell-edge topology, so the call
+ * reads cells_on_edge, edges_on_cell and n_edges_on_cell (SSE_EINVAL if they
+ * are NULL or out of range; sse_mesh_create validates everything).  The
+ * partition is cached by a hash of those tables. */
 int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes);
 
 /* Validate, lay out and upload a mesh into dev_buf (>= sse_mesh_device_bytes,
@@ -193,8 +195,11 @@ int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
  * memory; 0, 1, 2: the operands of tiles of 8, 16 or 32 consecutive edges are
  * first staged in LDS.  SSE_EINVAL if the variant is unknown or does not fit
  * this mesh (a tile list longer than 255 columns) or the device's LDS for the
- * state's layer count and precision.  The default is -1.  Applies to
- * subsequent steps; the autotuner in the Python package calls it. */
+ * state's layer count and precision.  The default is -1.  The first
+ * selection of a tiled variant on a mesh builds its gather lists on the host
+ * and uploads them (on the state's stream, synchronously) into space the
+ * mesh buffer reserves for them.  Applies to subsequent steps; the autotuner
+ * in the Python package calls it. */
 int sse_state_set_edge_variant(sse_state *s, int variant);
 int sse_state_get_edge_variant(const sse_state *s, int *variant);
 
@@ -207,12 +212,12 @@ int sse_state_get_edge_variant(const sse_state *s, int *variant);
  * mesh has such patches (sse_mesh_create builds them when every patch's halo
  * region fits a workgroup and every reconstruction stencil stays within the
  * two cells of its edge) and they fit the device's LDS, else 0.  SSE_EINVAL
- * for 1 otherwise.  Batched steps use variant 0. */
+ * for 1 otherwise.  Each member of a batch uses its own variant. */
 int sse_state_set_bt_variant(sse_state *s, int variant);
 int sse_state_get_bt_variant(const sse_state *s, int *variant);
 
 /* Device bytes one state of these parameters on this mesh needs in total:
- * the mesh image (sse_mesh_device_bytes, which validates d) plus the
+ * the mesh image (sse_mesh_device_bytes, with its topology checks) plus the
  * workspace (sse_state_workspace_bytes).  Host only; allocates nothing.  For
  * admission control by a device-memory budget. */
 int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, size_t *bytes);

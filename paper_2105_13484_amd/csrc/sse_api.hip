@@ -159,7 +159,7 @@ bool all_finite(const double *x, size_t n) {
 // key (seq = launch site in step order; j = substep evaluation inside a
 // barotropic loop), so that the same launch of every member can be merged
 // into one batched launch.
-enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD };
+enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, BT_TILE, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD };
 
 struct RecEntry {
     Kind kind;
@@ -168,6 +168,7 @@ struct RecEntry {
     int var;      // kernel variant flag that must match within a batched launch
     bool add;
     int blocks;
+    size_t lds = 0;   // dynamic LDS bytes the launch needs (tiled substeps)
     std::vector<uint8_t> args;
 };
 
@@ -370,7 +371,7 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         oz = rp<R>(w.bt_zo);
     }
     R *u1 = rp<R>(w.bt_u1), *uh = rp<R>(w.bt_uh), *z1 = rp<R>(w.bt_z1), *zh = rp<R>(w.bt_zh);
-    if (!s->rec && s->bt_variant == 1) {
+    if (s->bt_variant == 1) {
         // one launch per substep; outputs alternate between the loop's
         // output and a scratch pair so that no launch reads what another
         // workgroup of the same launch writes, ending in the output
@@ -383,6 +384,7 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         a.w1 = scheme == SSE_SCHEME_SSPRK3 ? 1.0 / (6.0 * M) : 1.0 / (2.0 * M);
         a.w3 = scheme == SSE_SCHEME_SSPRK3 ? 2.0 / (3.0 * M) : 0.0;
         const R *pu = iu, *pz = iz;
+        if (s->rec) s->rec->loop_seq = s->rec->seq++;
         for (int sub = 0; sub < M; ++sub) {
             const bool to_out = (M - 1 - sub) % 2 == 0;
             R *tu = to_out ? ou : u1, *tz = to_out ? oz : z1;
@@ -391,7 +393,10 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
             a.uo = tu;
             a.zo = tz;
             a.zeroF = sub == 0;
-            {
+            if (s->rec) {
+                record(s, Kind::BT_TILE, a, 1, false, a.t.nP, sub, a.t.ks);
+                s->rec->entries.back().lds = s->rs == 8 ? a.t.lds_d : a.t.lds_f;
+            } else {
                 ProfScope ps(s, SSE_PROF_BT_EVAL);
                 launch_bt_substep<R>(a, scheme, s->stream);
             }
@@ -733,31 +738,15 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     m->cells_on_edge = t.edge_cells;
     m->cell_old = ord.cell_old;
     m->edge_old = ord.edge_old;
-    // Gather lists of the LDS-staged edge pass for tiles of 8, 16 and 32 edges.
+    // Gather lists of the LDS-staged edge pass for tiles of 8, 16 and 32
+    // edges: space is reserved here, the lists are built when a state first
+    // selects the variant (most runs never do).
     size_t cursor = lay.total;
     for (int q = 0; q < kTileVariants; ++q) {
-        HostTiles ht;
-        DevTiles &dt = m->tiles[q];
-        if (!build_tiles(d, kTileSizes[q], ht)) { dt.T = 0; continue; }
-        auto put = [&](const void *src, size_t n) -> const void * {
-            char *dst = base + cursor;
-            if (n) hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
-            cursor += (n + kAlign - 1) / kAlign * kAlign;
-            return dst;
-        };
-        dt.T = ht.T;
-        dt.nT = ht.nT;
-        dt.max_ue = ht.max_ue;
-        dt.max_uv = ht.max_uv;
-        dt.max_uc = ht.max_uc;
-        dt.ue_off = (const int32_t *)put(ht.ue_off.data(), ht.ue_off.size() * 4);
-        dt.uv_off = (const int32_t *)put(ht.uv_off.data(), ht.uv_off.size() * 4);
-        dt.uc_off = (const int32_t *)put(ht.uc_off.data(), ht.uc_off.size() * 4);
-        dt.ue = (const int32_t *)put(ht.ue.data(), ht.ue.size() * 4);
-        dt.uv = (const int32_t *)put(ht.uv.data(), ht.uv.size() * 4);
-        dt.uc = (const int32_t *)put(ht.uc.data(), ht.uc.size() * 4);
-        dt.loc = (const uint8_t *)put(ht.loc.data(), ht.loc.size());
-        SSE_HIP(hipStreamSynchronize(s));
+        m->tile_off[q] = cursor;
+        m->tile_state[q] = 0;
+        m->tiles[q].T = 0;
+        cursor += tiles_bytes(d, kTileSizes[q]);
     }
     // Patches of the tiled barotropic substeps (partitioned in the caller's
     // numbering, the same partition the device-bytes query sizes).
@@ -765,7 +754,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
         std::vector<int32_t> pid0, pid;
         int nP = 0;
         HostBtTiles hb;
-        if (bt_partition(d0, pid0, nP)) {
+        if (bt_cached_partition(d0, pid0, nP)) {
             pid.resize(d->n_cells);
             for (int i = 0; i < d->n_cells; ++i) pid[i] = pid0[ord.cell_old[i]];
             if (build_bt_tiles(d, pid, nP, &t, hb)) {
@@ -800,9 +789,56 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
         }
     }
     if (cursor > need) { delete m; set_error("internal: tile tables overflow the mesh buffer"); return SSE_EINVAL; }
+    m->host_desc.reset(new PermutedDesc(std::move(pd)));
     *out = m;
     return SSE_OK;
 }
+
+namespace {
+
+// Builds and uploads the gather lists of edge-pass variant q on first use.
+int ensure_tiles(const sse_mesh *cm, int q, hipStream_t s) {
+    sse_mesh *m = const_cast<sse_mesh *>(cm);
+    std::lock_guard<std::mutex> g(m->tile_mu);
+    if (m->tile_state[q] != 0) return SSE_OK;
+    HostTiles ht;
+    const sse_mesh_desc *d = &m->host_desc->d;
+    if (!build_tiles(d, kTileSizes[q], ht)) {
+        m->tile_state[q] = -1;
+        return SSE_OK;
+    }
+    char *base = static_cast<char *>(m->dev_buf);
+    size_t cursor = m->tile_off[q];
+    auto put = [&](const void *src, size_t n) -> const void * {
+        char *dst = base + cursor;
+        if (n) (void)hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+        cursor += (n + kAlign - 1) / kAlign * kAlign;
+        return dst;
+    };
+    DevTiles &dt = m->tiles[q];
+    dt.nT = ht.nT;
+    dt.max_ue = ht.max_ue;
+    dt.max_uv = ht.max_uv;
+    dt.max_uc = ht.max_uc;
+    dt.ue_off = (const int32_t *)put(ht.ue_off.data(), ht.ue_off.size() * 4);
+    dt.uv_off = (const int32_t *)put(ht.uv_off.data(), ht.uv_off.size() * 4);
+    dt.uc_off = (const int32_t *)put(ht.uc_off.data(), ht.uc_off.size() * 4);
+    dt.ue = (const int32_t *)put(ht.ue.data(), ht.ue.size() * 4);
+    dt.uv = (const int32_t *)put(ht.uv.data(), ht.uv.size() * 4);
+    dt.uc = (const int32_t *)put(ht.uc.data(), ht.uc.size() * 4);
+    dt.loc = (const uint8_t *)put(ht.loc.data(), ht.loc.size());
+    SSE_HIP(hipStreamSynchronize(s));
+    if (cursor > m->tile_off[q] + tiles_bytes(d, kTileSizes[q])) {
+        set_error("internal: tile lists overflow their reserved space");
+        m->tile_state[q] = -1;
+        return SSE_EINVAL;
+    }
+    dt.T = ht.T;
+    m->tile_state[q] = 1;
+    return SSE_OK;
+}
+
+}  // namespace
 
 extern "C" int sse_mesh_destroy(sse_mesh *m) {
     delete m;
@@ -825,7 +861,7 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     int rc = check_params(p);
     if (rc) return rc;
     std::string err;
-    rc = validate_desc(d, err);
+    rc = check_topology(d, err);
     if (rc != SSE_OK) { set_error(err); return rc; }
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
@@ -890,6 +926,8 @@ extern "C" int sse_state_set_edge_variant(sse_state *s, int variant) {
         return SSE_OK;
     }
     if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -1, 0, 1 or 2"); return SSE_EINVAL; }
+    const int rc = ensure_tiles(s->mesh, variant, s->stream);
+    if (rc) return rc;
     const DevTiles &t = s->mesh->tiles[variant];
     if (!t.T) { set_error("edge variant: a tile of this mesh lists more than 255 columns"); return SSE_EINVAL; }
     const size_t lds = s->rs == 4 ? fe_edge_tiled_lds<float>(t, s->p.n_layers) : fe_edge_tiled_lds<double>(t, s->p.n_layers);
@@ -1207,6 +1245,7 @@ struct BatchOp {
     bool add;
     int blocks;
     size_t args_off, table_off;
+    size_t lds;
 };
 
 }  // namespace
@@ -1243,10 +1282,11 @@ int batch_record(sse_batch *b) {
     if (b->members.empty()) { set_error("batch has no members"); return SSE_ESTATE; }
     const sse_state *s0 = b->members[0];
     struct Key {
-        int seq, j, nk, var;
+        int seq, j, kind, nk, var;
         bool operator<(const Key &o) const {
             if (seq != o.seq) return seq < o.seq;
             if (j != o.j) return j < o.j;
+            if (kind != o.kind) return kind < o.kind;
             if (nk != o.nk) return nk < o.nk;
             return var < o.var;
         }
@@ -1265,7 +1305,7 @@ int batch_record(sse_batch *b) {
         enqueue_step(s);
         s->rec = nullptr;
         s->geom = saved;
-        for (auto &e : r.entries) groups[Key{e.seq, e.j, e.nk, e.var}].emplace_back((int)mi, std::move(e));
+        for (auto &e : r.entries) groups[Key{e.seq, e.j, (int)e.kind, e.nk, e.var}].emplace_back((int)mi, std::move(e));
     }
     auto align = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     b->prog.clear();
@@ -1273,7 +1313,7 @@ int batch_record(sse_batch *b) {
     size_t off = 0;
     for (auto &kv : groups) {
         auto &v = kv.second;
-        BatchOp op{v[0].second.kind, v[0].second.nk, v[0].second.var, v[0].second.add, 0, 0, 0};
+        BatchOp op{v[0].second.kind, v[0].second.nk, v[0].second.var, v[0].second.add, 0, 0, 0, 0};
         const size_t asz = v[0].second.args.size();
         std::vector<int2> table;
         for (size_t q = 0; q < v.size(); ++q) {
@@ -1282,6 +1322,7 @@ int batch_record(sse_batch *b) {
                 return SSE_EINVAL;
             }
             for (int blk = 0; blk < v[q].second.blocks; ++blk) table.push_back(int2{(int)q, blk});
+            op.lds = std::max(op.lds, v[q].second.lds);
         }
         op.blocks = (int)table.size();
         op.args_off = off;
@@ -1316,6 +1357,9 @@ void batch_enqueue(const sse_batch *b) {
             case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var, g, st); break;
             case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), op.var != 0, g, st); break;
+            case Kind::BT_TILE:
+                launch_bt_substep_batch<R>(bl<BTTileArgs<R>>(b, op), b->members[0]->p.scheme, op.var, op.lds, st);
+                break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;
             case Kind::RECON: launch_recon_batch(bl<ReconArgs>(b, op), g, st); break;

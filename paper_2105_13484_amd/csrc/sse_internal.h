@@ -5,6 +5,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -143,6 +145,10 @@ struct DevBtTiles {
 };
 }  // namespace sse
 
+namespace sse {
+struct PermutedDesc;
+}
+
 struct sse_mesh {
     sse::DevMesh d;
     int C = 0, E = 0, V = 0;
@@ -151,7 +157,14 @@ struct sse_mesh {
     // cell_old[i] / edge_old[i] of the caller's numbering.
     std::vector<int32_t> cell_old, edge_old;
     std::vector<int32_t> cells_on_edge;     // host copy (for debug helpers)
-    sse::DevTiles tiles[sse::kTileVariants];  // T = 8, 16, 32 edges per tile
+    // Gather lists of the LDS-staged edge pass (T = 8, 16, 32 edges per
+    // tile), built and uploaded into their reserved part of the mesh buffer
+    // the first time a state selects the variant (ensure_tiles).
+    sse::DevTiles tiles[sse::kTileVariants];
+    size_t tile_off[sse::kTileVariants] = {};
+    int tile_state[sse::kTileVariants] = {};  // 0 not built, 1 built, -1 not possible
+    std::mutex tile_mu;
+    std::unique_ptr<sse::PermutedDesc> host_desc;  // internal numbering, for building the lists
     sse::DevBtTiles bt;                       // patches of the tiled barotropic substeps
     void *dev_buf = nullptr;
     size_t dev_bytes = 0;
@@ -248,8 +261,12 @@ struct HostBtTiles {
 // (patch records, list lengths), which is what the device-bytes query needs.
 bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int nP, const HostMeshTables *t,
                     HostBtTiles &bt);
-// Device bytes of the tiled barotropic tables of d (0 if d cannot be tiled).
+// Device bytes of the tiled barotropic tables of d (0 if d cannot be tiled),
+// and the partition itself; both come from a cache keyed by the topology.
 size_t bt_tiles_bytes(const sse_mesh_desc *d);
+bool bt_cached_partition(const sse_mesh_desc *d, std::vector<int32_t> &pid, int &nP);
+// Range checks of the topology tables the size queries read.
+int check_topology(const sse_mesh_desc *d, std::string &err);
 
 void set_error(const std::string &msg);
 

@@ -225,6 +225,9 @@ template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs
 int fe_edge_variant(const DevMesh &m, int vmix);
 template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g, hipStream_t s);
 template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
+// table entries (member, patch); ks and lds: the largest over the members
+template <typename R>
+void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, size_t lds, hipStream_t s);
 template <typename R> void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename Tin, typename Tout>

@@ -980,12 +980,10 @@ struct BtTab<float> {
 };
 
 template <typename R, int kScheme, int KS>
-__global__ void __launch_bounds__(kBtThreads) bt_substep_kernel(BTTileArgs<R> a) {
+__device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
 #pragma clang fp contract(off)
     extern __shared__ __align__(16) double lds_d[];
     const DevBtTiles &T = a.t;
-    const int p = xcd_block(T.nP);
-    if (p < 0) return;
     const int tid = threadIdx.x;
     const int32_t *rec = T.patch + (size_t)p * kBtRec;
     const int e0 = rec[0], es0 = rec[1], c0 = rec[2], cs0 = rec[3];
@@ -1124,6 +1122,7 @@ __global__ void __launch_bounds__(kBtThreads) bt_substep_kernel(BTTileArgs<R> a)
             if (s * kBtThreads + tid < ne[0]) a.F[ge[s]] = Fa[s];
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Thickness stage (z-star): h_out = comb(h_n, h_in + dt T^h), zeta = sum h - H
@@ -1437,6 +1436,19 @@ __global__ void __launch_bounds__(1024) bt_eval_batch(BatchLaunch<BTEvalArgs<R>>
         bt_eval_body<R, kD16>(a, false, t.y - nEB);
 }
 
+template <typename R, int kScheme, int KS>
+__global__ void __launch_bounds__(kBtThreads) bt_substep_kernel(BTTileArgs<R> a) {
+    const int p = xcd_block(a.t.nP);
+    if (p >= 0) bt_substep_body<R, kScheme, KS>(a, p);
+}
+// Batched: one workgroup per (member, patch); the dynamic LDS is the
+// largest member's.
+template <typename R, int kScheme, int KS>
+__global__ void __launch_bounds__(kBtThreads) bt_substep_batch(BatchLaunch<BTTileArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) bt_substep_body<R, kScheme, KS>(b.args[t.x], t.y);
+}
+
 __global__ void __launch_bounds__(1024) recon_kernel(ReconArgs a) { recon_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(1024) recon_batch(BatchLaunch<ReconArgs> b) {
     int2 t;
@@ -1572,6 +1584,15 @@ void set_tiled_lds_limit(size_t bytes) {
                         reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 1>),
                         reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 2>)};
     for (const void *f : bt) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *btb[] = {reinterpret_cast<const void *>(bt_substep_batch<double, 3, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 3, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 2, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 2, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 3, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 3, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 2, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 2, 2>)};
+    for (const void *f : btb) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -1585,6 +1606,18 @@ void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s) {
     } else {
         if (a.t.ks == 1) bt_substep_kernel<R, 2, 1><<<grid, block, lds, s>>>(a);
         else bt_substep_kernel<R, 2, 2><<<grid, block, lds, s>>>(a);
+    }
+}
+
+template <typename R>
+void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, size_t lds, hipStream_t s) {
+    const dim3 grid = xcd_grid(b.blocks), block(kBtThreads);
+    if (scheme == 3) {
+        if (ks == 1) bt_substep_batch<R, 3, 1><<<grid, block, lds, s>>>(b);
+        else bt_substep_batch<R, 3, 2><<<grid, block, lds, s>>>(b);
+    } else {
+        if (ks == 1) bt_substep_batch<R, 2, 1><<<grid, block, lds, s>>>(b);
+        else bt_substep_batch<R, 2, 2><<<grid, block, lds, s>>>(b);
     }
 }
 
@@ -1677,6 +1710,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_bt_substep<R>(const BTTileArgs<R> &, int, hipStream_t);                           \
+    template void launch_bt_substep_batch<R>(const BatchLaunch<BTTileArgs<R>> &, int, int, size_t, hipStream_t); \
     template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, bool, const Geom &, hipStream_t); \
     template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \
     template void launch_thickness_iso_batch<R>(const BatchLaunch<THIsoArgs<R>> &, int, const Geom &,      \

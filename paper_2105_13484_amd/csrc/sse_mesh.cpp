@@ -13,6 +13,7 @@
 #include <cmath>
 #include <deque>
 #include <cstdio>
+#include <mutex>
 #include <cstring>
 #include <string>
 
@@ -828,17 +829,104 @@ bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int
     return bt.ks >= 1 && bt.ks <= kBtEdgeSlots;
 }
 
-size_t bt_tiles_bytes(const sse_mesh_desc *d) {
+namespace {
+
+// The partition depends on the cell-edge topology only; meshes that share it
+// (every request on the same icosahedral level, the size query before the
+// creation of a mesh) reuse it from a small cache keyed by a hash of the
+// topology tables.
+uint64_t topology_hash(const sse_mesh_desc *d) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    const int32_t cnt[5] = {d->n_cells, d->n_edges, d->n_vertices, d->max_edges, d->max_edges2};
+    mix(cnt, sizeof(cnt));
+    mix(d->cells_on_edge, 2 * (size_t)d->n_edges * 4);
+    mix(d->edges_on_cell, (size_t)d->n_cells * d->max_edges * 4);
+    mix(d->n_edges_on_cell, (size_t)d->n_cells * 4);
+    return h;
+}
+
+struct PartitionEntry {
+    uint64_t key;
+    bool ok;
+    int nP;
     std::vector<int32_t> pid;
-    int nP = 0;
-    if (!bt_partition(d, pid, nP)) return 0;
-    HostBtTiles bt;
-    if (!build_bt_tiles(d, pid, nP, nullptr, bt)) return 0;
+    size_t bytes;
+};
+std::mutex g_part_mu;
+std::deque<PartitionEntry> g_part_cache;  // most recent first
+constexpr size_t kPartCache = 8;
+
+size_t bt_bytes_of(const HostBtTiles &bt) {
     auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     const size_t TE = bt.eid.size(), TC = bt.cid.size(), SE = bt.ec.size(), SC = bt.cwet.size();
     return al(bt.patch.size() * 4) + al(TE * 4) + al(TC * 4) + al(TC * 8) + al(TC * 4) + al(SE * 4) +
            al(SE * 5 * 4) + al(SE * 10 * 8) + al(SE * 10 * 4) + al(SE * 8) + al(SE * 4) + al(SC * 6 * 4) +
            al(SC * 6 * 8) + al(SC * 6 * 4) + al(SC);
+}
+
+// Partition of d with its table bytes (0 if d cannot be tiled), cached.
+PartitionEntry cached_partition(const sse_mesh_desc *d) {
+    const uint64_t key = topology_hash(d);
+    {
+        std::lock_guard<std::mutex> g(g_part_mu);
+        for (auto it = g_part_cache.begin(); it != g_part_cache.end(); ++it)
+            if (it->key == key) {
+                PartitionEntry e = *it;
+                g_part_cache.erase(it);
+                g_part_cache.push_front(e);
+                return e;
+            }
+    }
+    PartitionEntry e{key, false, 0, {}, 0};
+    if (bt_partition(d, e.pid, e.nP)) {
+        HostBtTiles bt;
+        if (build_bt_tiles(d, e.pid, e.nP, nullptr, bt)) {
+            e.ok = true;
+            e.bytes = bt_bytes_of(bt);
+        }
+    }
+    std::lock_guard<std::mutex> g(g_part_mu);
+    g_part_cache.push_front(e);
+    if (g_part_cache.size() > kPartCache) g_part_cache.pop_back();
+    return e;
+}
+
+}  // namespace
+
+size_t bt_tiles_bytes(const sse_mesh_desc *d) { return cached_partition(d).bytes; }
+
+bool bt_cached_partition(const sse_mesh_desc *d, std::vector<int32_t> &pid, int &nP) {
+    PartitionEntry e = cached_partition(d);
+    if (!e.ok) return false;
+    pid.swap(e.pid);
+    nP = e.nP;
+    return true;
+}
+
+int check_topology(const sse_mesh_desc *d, std::string &err) {
+    if (!d) { err = "mesh description is NULL"; return SSE_EINVAL; }
+    const int C = d->n_cells, E = d->n_edges;
+    if (C <= 0 || E <= 0 || d->n_vertices <= 0) { err = "mesh counts must be positive"; return SSE_EINVAL; }
+    if (d->max_edges < 1 || d->max_edges > 6 || d->max_edges2 < 1 || d->max_edges2 > 10) {
+        err = "max_edges must be in [1, 6] and max_edges2 in [1, 10]";
+        return SSE_EINVAL;
+    }
+    if (!d->cells_on_edge || !d->edges_on_cell || !d->n_edges_on_cell) { err = "topology tables are NULL"; return SSE_EINVAL; }
+    for (size_t i = 0; i < 2 * (size_t)E; ++i)
+        if (d->cells_on_edge[i] < 0 || d->cells_on_edge[i] >= C) { err = "cells_on_edge out of range"; return SSE_EINVAL; }
+    for (int c = 0; c < C; ++c) {
+        const int n = d->n_edges_on_cell[c];
+        if (n < 1 || n > d->max_edges) { err = "n_edges_on_cell out of range"; return SSE_EINVAL; }
+        for (int j = 0; j < n; ++j) {
+            const int e = d->edges_on_cell[(size_t)c * d->max_edges + j];
+            if (e < -1 || e >= E) { err = "edges_on_cell out of range"; return SSE_EINVAL; }
+        }
+    }
+    return SSE_OK;
 }
 
 }  // namespace sse
@@ -853,7 +941,7 @@ extern "C" int sse_mesh_validate(const sse_mesh_desc *d) {
 extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
     if (!d || !bytes) { sse::set_error("NULL argument"); return SSE_EINVAL; }
     std::string err;
-    const int rc = sse::validate_desc(d, err);
+    const int rc = sse::check_topology(d, err);
     if (rc != SSE_OK) { sse::set_error(err); return rc; }
     *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < sse::kTileVariants; ++q) *bytes += sse::tiles_bytes(d, sse::kTileSizes[q]);

@@ -127,3 +127,22 @@ def test_graph_replays_equal_eager(dev, stream, precision):
         torch.cuda.synchronize()
         assert g.step(1) == 0
         assert_same(g.read(), eager.read(), f"replay {k}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_members_with_either_barotropic_variant(dev, stream, precision):
+    """Members running the per-evaluation and the per-substep barotropic
+    kernels share one batch and compute what they compute alone."""
+    cs = member_cases(precision)
+    alone = [run_alone(dev, c, 3, stream) for c in cs]
+    keep, b = [], dev.Batch(stream=stream)
+    for i, c in enumerate(cs):
+        dm, st = dev.state_from_case(c, stream=stream)
+        keep.append(dm)
+        if i % 2:
+            assert st.try_bt_variant(0)
+        b.add(st)
+    b.compile()
+    assert b.step(3) == 0
+    for i, st in enumerate(b.members):
+        assert_same(st.read(), alone[i], f"member {i}")
