@@ -1376,12 +1376,20 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
     if (batch_entry(b.table, b.blocks, t)) fe_vertex_body<NK, R, kAdd>(b.args[t.x], batch_column(t.y));
 }
 
+// Minimum waves per SIMD requested for the one-register-chunk edge pass.
+// Left alone the compiler settles at 79-81 VGPRs (5-6 waves); the
+// gather-bound pass runs faster with more loads in flight.  Measured on C1
+// (edge-pass time over 3 steps, FP64 / mixed): no request 12.1 / -, 5: 11.2,
+// 6: 11.6, 7: 10.8, 8: 11.4 ms in FP64; mixed steps are fastest at 5-6.
+template <int NK, typename R>
+constexpr int edge_min_waves() { return NK != 1 ? 1 : (sizeof(R) == 8 ? 7 : 6); }
+
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(1024) fe_edge_kernel(FEEdgeArgs<R> a) {
+__global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_kernel(FEEdgeArgs<R> a) {
     fe_edge_body<NK, R, kAdd, kVar>(a, column_id(a.m.E));
 }
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(1024) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
+__global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
     int2 t;
     if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kVar>(b.args[t.x], batch_column(t.y));
 }
