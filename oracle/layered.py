@@ -22,6 +22,8 @@ Readings of what the paper leaves to MPAS (each stated where it is used):
 * vertical boundary conditions: w = 0 at the surface and the bottom, no
   surface stress, bottom stress c_drag |u| u at the lowest layer (the drag
   condition of Section 5), with |u|^2 = K_c1 + K_c2 of the bottom layer;
+* horizontal viscosity nu_h lap u, or the biharmonic -nu_h lap(lap u) with the
+  inner Laplacian zeroed on coast edges;
 * implicit vertical diffusion (Algorithm 2): the same operator with the drag
   speed |u| taken from the stage input and frozen, so that the solve is
   linear; the velocity multiplying c_drag |u| is the new one.
@@ -185,9 +187,20 @@ def T_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
     w_e[:, -1] = 0.0
     wdz = w_e * D_zt(u, he)
     vadv = 0.5 * (wdz[:, :-1] + wdz[:, 1:])
-    tu = (-trisk.gradient(K, m) + vort - vadv + pressure_gradient_force(h, st)
-          + p.nu_h * trisk.laplacian(u, m))
+    tu = -trisk.gradient(K, m) + vort - vadv + pressure_gradient_force(h, st) + horizontal_viscosity(u, st)
     return mask_edges(tu, st)
+
+
+def horizontal_viscosity(u: np.ndarray, st: Setup) -> np.ndarray:
+    """nu_h lap u (hdiff = 0), or the hyperviscosity -nu_h lap(lap u) that the
+    remark of Section 2 puts in its place for global runs (hdiff = 1).  The
+    inner Laplacian is a velocity-like edge field and, like u, is zero on
+    coast edges before the outer one is taken."""
+    m, p = st.mesh, st.params
+    lap = trisk.laplacian(u, m)
+    if getattr(p, "hdiff", 0) == 1:
+        return -p.nu_h * trisk.laplacian(mask_edges(lap, st), m)
+    return p.nu_h * lap
 
 
 def bottom_speed(u: np.ndarray, st: Setup) -> np.ndarray:

@@ -54,6 +54,7 @@ class Params:
     nu_v: float = 1.0e-4
     c_drag: float = 1.0e-3
     vmix: int = 0              # 1 = implicit vertical mixing (Algorithm 2)
+    hdiff: int = 0             # 0 = nu_h lap u (m^2/s), 1 = -nu_h lap(lap u) (m^4/s)
 
 
 @dataclass

@@ -10,7 +10,7 @@ from synthetic.mesh import Mesh, planar_hex
 def uniform_case(L: int = 4, U=None, h_layers=None, rho_layers=None, f0: float = 1.0e-4,
                  scheme: int = 3, M: int = 4, dt: float = 600.0, nu_h: float = 10.0,
                  nu_v: float = 0.0, c_drag: float = 0.0, reconcile: int = 1, n: int = 8,
-                 mesh: Mesh | None = None, vmix: int = 0) -> Case:
+                 mesh: Mesh | None = None, vmix: int = 0, hdiff: int = 0) -> Case:
     """Horizontally uniform layers on a regular hex: u_{e,k} = U_k . n_e."""
     mesh = mesh if mesh is not None else planar_hex(n, n, 1.0e4, f0=f0)
     C, E = mesh.nCells, mesh.nEdges
@@ -25,7 +25,7 @@ def uniform_case(L: int = 4, U=None, h_layers=None, rho_layers=None, f0: float =
     rho = np.tile(np.asarray(rho_layers, float), (C, 1))
     u = mesh.normalEdge[:, :2] @ np.asarray(U, float).T
     params = Params(n_layers=L, scheme=scheme, substeps=M, dt=dt, nu_h=nu_h, nu_v=nu_v,
-                    c_drag=c_drag, reconcile=reconcile, vmix=vmix)
+                    c_drag=c_drag, reconcile=reconcile, vmix=vmix, hdiff=hdiff)
     return Case("uniform", mesh, params, H, h.copy(), rho, h, u, np.ones(C, np.uint8), 1, 0)
 
 
