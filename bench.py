@@ -10,7 +10,7 @@ timing starts.
 Prints ONE JSON line on stdout: cell-layer updates/s over the timed steps,
 the roofline of the dominant kernel class (algorithmic bytes / HIP-event time
 of that class in a second timed region), the same workload in mixed
-precision and with implicit vertical mixing, the runtime to a fixed simulated time as the number of substeps
+precision, with implicit vertical mixing and with biharmonic viscosity, the runtime to a fixed simulated time as the number of substeps
 M varies (both schemes), the level-7 sphere (C2 recipe) in FP64 and mixed
 precision, a batched ensemble, a served request stream, and the FP64 CPU
 oracle timed on a bounded sample of the headline recipe.
@@ -278,6 +278,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timing")
     ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
     ap.add_argument("--no-vmix", action="store_true", help="skip the implicit-vertical-mixing timing")
+    ap.add_argument("--no-del4", action="store_true", help="skip the biharmonic-viscosity timing")
     ap.add_argument("--no-m-sweep", action="store_true", help="skip the runtime-vs-M sweep")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -359,6 +360,16 @@ def main():
         log(f"[bench] C1 with implicit vertical mixing: {ms_vmix:.3f} ms/step")
         del st_v
 
+    # the same workload with the biharmonic viscosity in place of the Laplacian
+    # (nu_h = 1e9 m^4/s, about the paper's global value scaled to 5 km cells)
+    ms_del4 = None
+    if not args.no_del4:
+        _, st_d = ssprkse.state_from_case(cases.with_params(case, hdiff=1, nu_h=1.0e9), device="cuda:0")
+        assert st_d.step(args.warmup) == 0
+        ms_del4 = timed_steps(torch, st_d, args.steps)
+        log(f"[bench] C1 with biharmonic viscosity: {ms_del4:.3f} ms/step")
+        del st_d
+
     # runtime vs the number of substeps at fixed T and dt_btr, both schemes
     m_sweep = None if args.no_m_sweep else m_sweep_leg(torch, ssprkse, dm, case)
     del dm
@@ -407,6 +418,7 @@ def main():
         "mixed_vs_fp64_speedup": (ms_step / ms_mixed) if ms_mixed else None,
         "mixed_ms_per_step": ms_mixed,
         "vmix_ms_per_step": ms_vmix,
+        "del4_ms_per_step": ms_del4,
         "per_class_ms_per_step": {k: v[1] / 3.0 for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

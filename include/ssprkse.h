@@ -64,6 +64,13 @@ enum { SSE_RECONCILE_OFF = 0, SSE_RECONCILE_EXACT = 1, SSE_RECONCILE_LITERAL = 2
  * the drag speed |u| at the stage input's; G-bar is the one formed before
  * the solve. */
 enum { SSE_VMIX_EXPLICIT = 0, SSE_VMIX_IMPLICIT = 1 };
+/* Horizontal viscosity (Section 2 and its remark on hyperviscosity): DEL2 is
+ * nu_h lap u with nu_h in m^2/s; DEL4 is the scale-selective -nu_h lap(lap u)
+ * with nu_h in m^4/s that replaces it in global runs.  lap is the TRiSK
+ * vector Laplacian grad(div u) - k x grad(curl u); the inner Laplacian is
+ * zero on coast edges.  DEL4 adds three column passes per stage and
+ * workspace for four more 3D fields, and runs the direct edge pass only. */
+enum { SSE_HDIFF_DEL2 = 0, SSE_HDIFF_DEL4 = 1 };
 
 /*
  * Mesh description (host memory, caller numbering; copied by
@@ -102,13 +109,13 @@ typedef struct {
  *   n_layers L (1..128); scheme SSE_SCHEME_SSPRK2 | SSE_SCHEME_SSPRK3;
  *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 | SSE_MIXED;
  *   vcoord SSE_ZSTAR | SSE_ISOPYCNAL (Section 2, vertical coordinate);
- *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; dt > 0 (s); gravity g;
- *   rho0 (Boussinesq reference density); nu_h, nu_v (Laplacian horizontal
- *   and vertical viscosity, m^2/s); c_drag (bottom drag of Section 5,
- *   dimensionless).
+ *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; hdiff SSE_HDIFF_*; dt > 0
+ *   (s); gravity g; rho0 (Boussinesq reference density); nu_h (horizontal
+ *   viscosity, m^2/s for DEL2, m^4/s for DEL4); nu_v (vertical viscosity,
+ *   m^2/s); c_drag (bottom drag of Section 5, dimensionless).
  */
 typedef struct {
-    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile, vmix;
+    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile, vmix, hdiff;
     double dt, gravity, rho0, nu_h, nu_v, c_drag;
 } sse_params;
 

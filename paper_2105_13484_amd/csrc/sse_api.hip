@@ -41,6 +41,8 @@ struct Work {
         *Fh2, *Sh3, *Pp, *Ftot, *uA;         // [E]
     double *zeta_n, *z1, *z_half, *Kbot, *bt_zout;  // [C]
     int *flag;
+    void *D1, *L1, *D2, *Z2;                 // R, biharmonic runs only: div u [C][L], lap u [E][L],
+                                             // div(lap u) [C][L], curl(lap u) [V][L]
 };
 
 constexpr int kR3E = 3, kR3C = 2, kR3V = 1, kR2E = 4, kR2C = 4;  // arrays of type R
@@ -50,8 +52,10 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 size_t real_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : sizeof(double); }
 
-size_t workspace_bytes(int C, int E, int V, int L, size_t rs) {
+size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff) {
     size_t b = 0;
+    if (hdiff == SSE_HDIFF_DEL4)
+        b += align_up((size_t)E * L * rs) + 2 * align_up((size_t)C * L * rs) + align_up((size_t)V * L * rs);
     b += kR3E * align_up((size_t)E * L * rs);
     b += kR3C * align_up((size_t)C * L * rs);
     b += kR3V * align_up((size_t)V * L * rs);
@@ -64,7 +68,7 @@ size_t workspace_bytes(int C, int E, int V, int L, size_t rs) {
     return b;
 }
 
-Work carve(void *buf, int C, int E, int V, int L, size_t rs) {
+Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff) {
     char *p = static_cast<char *>(buf);
     auto take = [&](size_t n) {
         void *r = p;
@@ -89,6 +93,14 @@ Work carve(void *buf, int C, int E, int V, int L, size_t rs) {
     double **d2c[] = {&w.zeta_n, &w.z1, &w.z_half, &w.Kbot, &w.bt_zout};
     for (auto q : d2c) *q = static_cast<double *>(take((size_t)C * 8));
     w.flag = reinterpret_cast<int *>(p);
+    p += kAlign;
+    w.D1 = w.L1 = w.D2 = w.Z2 = nullptr;
+    if (hdiff == SSE_HDIFF_DEL4) {
+        w.D1 = take((size_t)C * L * rs);
+        w.L1 = take((size_t)E * L * rs);
+        w.D2 = take((size_t)C * L * rs);
+        w.Z2 = take((size_t)V * L * rs);
+    }
     return w;
 }
 
@@ -159,7 +171,7 @@ bool all_finite(const double *x, size_t n) {
 // key (seq = launch site in step order; j = substep evaluation inside a
 // barotropic loop), so that the same launch of every member can be merged
 // into one batched launch.
-enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, BT_TILE, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD };
+enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, BT_TILE, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD, LAP, DIV };
 
 struct RecEntry {
     Kind kind;
@@ -277,9 +289,11 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
     Work &w = s->w;
     const bool zstar = p.vcoord == SSE_ZSTAR;
     const int nk = nk_of(p.n_layers);
+    const bool del4 = p.hdiff == SSE_HDIFF_DEL4;
     {
         ProfScope ps(s, SSE_PROF_FE_CELL);
-        FECellArgs<R> a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, p.nu_h, rp<R>(w.B), rp<R>(w.Wt), w.Kbot};
+        FECellArgs<R> a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, del4 ? 0.0 : p.nu_h, rp<R>(w.B),
+                        del4 ? rp<R>(w.D1) : nullptr, rp<R>(w.Wt), w.Kbot};
         if (s->rec) record(s, Kind::FE_CELL, a, nk, add != nullptr, col_blocks(m.C, s->geom));
         else launch_fe_cell<R>(a, s->geom, s->stream);
     }
@@ -288,6 +302,23 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         FEVertexArgs<R> a{m, p.n_layers, X, add, rp<R>(w.Z)};
         if (s->rec) record(s, Kind::FE_VERTEX, a, nk, add != nullptr, col_blocks(m.V, s->geom));
         else launch_fe_vertex<R>(a, s->geom, s->stream);
+    }
+    if (!del4 && s->rec) {
+        // keep the launch sequence aligned with members that run the three
+        // biharmonic passes, so that batches merge the later phases
+        s->rec->seq += 3;
+    } else if (del4) {
+        // lap u at edges, then its divergence at cells and its curl at vertices
+        ProfScope ps(s, SSE_PROF_OTHER);
+        LapArgs<R> la{m, p.n_layers, rp<R>(w.D1), rp<R>(w.Z), rp<R>(w.L1)};
+        if (s->rec) record(s, Kind::LAP, la, nk, false, col_blocks(m.E, s->geom));
+        else launch_lap<R>(la, s->geom, s->stream);
+        DivArgs<R> da{m, p.n_layers, rp<R>(w.L1), rp<R>(w.D2)};
+        if (s->rec) record(s, Kind::DIV, da, nk, false, col_blocks(m.C, s->geom));
+        else launch_div<R>(da, s->geom, s->stream);
+        FEVertexArgs<R> va{m, p.n_layers, rp<R>(w.L1), nullptr, rp<R>(w.Z2)};
+        if (s->rec) record(s, Kind::FE_VERTEX, va, nk, false, col_blocks(m.V, s->geom));
+        else launch_fe_vertex<R>(va, s->geom, s->stream);
     }
     {
         ProfScope ps(s, SSE_PROF_FE_EDGE);
@@ -325,8 +356,14 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         a.nu_v = p.nu_v;
         a.c_drag = p.c_drag;
         a.vmix = p.vmix;
+        if (del4) {
+            a.nu_h = 0.0;
+            a.nu4 = p.nu_h;
+            a.D2 = rp<R>(w.D2);
+            a.Z2 = rp<R>(w.Z2);
+        }
         if (s->rec)
-            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, fe_edge_variant(m, p.vmix));
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, fe_edge_variant(m, p.vmix, del4));
         else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
@@ -585,6 +622,7 @@ int check_params(const sse_params *p) {
     if (p->vcoord != SSE_ZSTAR && p->vcoord != SSE_ISOPYCNAL) { set_error("vcoord must be ZSTAR or ISOPYCNAL"); return SSE_EINVAL; }
     if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
     if (p->vmix != SSE_VMIX_EXPLICIT && p->vmix != SSE_VMIX_IMPLICIT) { set_error("vmix must be SSE_VMIX_EXPLICIT or SSE_VMIX_IMPLICIT"); return SSE_EINVAL; }
+    if (p->hdiff != SSE_HDIFF_DEL2 && p->hdiff != SSE_HDIFF_DEL4) { set_error("hdiff must be SSE_HDIFF_DEL2 or SSE_HDIFF_DEL4"); return SSE_EINVAL; }
     const double v[] = {p->dt, p->gravity, p->rho0};
     for (double x : v)
         if (!(x > 0) || !std::isfinite(x)) { set_error("dt, gravity and rho0 must be positive"); return SSE_EINVAL; }
@@ -852,7 +890,7 @@ extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p,
     if (!m || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
     int rc = check_params(p);
     if (rc) return rc;
-    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision));
+    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision), p->hdiff);
     return SSE_OK;
 }
 
@@ -866,7 +904,7 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
     mb += bt_tiles_bytes(d);
-    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision));
+    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision), p->hdiff);
     return SSE_OK;
 }
 
@@ -877,7 +915,7 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     int rc = check_params(p);
     if (rc) return rc;
     const size_t rs = real_size(p->precision);
-    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs);
+    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs, p->hdiff);
     if (!dev_workspace || bytes < need) { set_error("state workspace too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) { set_error("state workspace must be 256-byte aligned"); return SSE_EINVAL; }
     sse_state *s = new sse_state();
@@ -885,7 +923,7 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->p = *p;
     s->stream = static_cast<hipStream_t>(stream);
     s->rs = rs;
-    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs);
+    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs, p->hdiff);
     s->bytes = bytes;
     int dev = 0, lds_max = 0;
     (void)hipGetDevice(&dev);
@@ -926,6 +964,10 @@ extern "C" int sse_state_set_edge_variant(sse_state *s, int variant) {
         return SSE_OK;
     }
     if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -1, 0, 1 or 2"); return SSE_EINVAL; }
+    if (s->p.hdiff == SSE_HDIFF_DEL4) {
+        set_error("edge variants 0, 1, 2 do not carry the biharmonic viscosity; use -1");
+        return SSE_EINVAL;
+    }
     const int rc = ensure_tiles(s->mesh, variant, s->stream);
     if (rc) return rc;
     const DevTiles &t = s->mesh->tiles[variant];
@@ -1282,13 +1324,14 @@ int batch_record(sse_batch *b) {
     if (b->members.empty()) { set_error("batch has no members"); return SSE_ESTATE; }
     const sse_state *s0 = b->members[0];
     struct Key {
-        int seq, j, kind, nk, var;
+        int seq, j, kind, nk, var, add;
         bool operator<(const Key &o) const {
             if (seq != o.seq) return seq < o.seq;
             if (j != o.j) return j < o.j;
             if (kind != o.kind) return kind < o.kind;
             if (nk != o.nk) return nk < o.nk;
-            return var < o.var;
+            if (var != o.var) return var < o.var;
+            return add < o.add;
         }
     };
     std::map<Key, std::vector<std::pair<int, RecEntry>>> groups;
@@ -1305,7 +1348,7 @@ int batch_record(sse_batch *b) {
         enqueue_step(s);
         s->rec = nullptr;
         s->geom = saved;
-        for (auto &e : r.entries) groups[Key{e.seq, e.j, (int)e.kind, e.nk, e.var}].emplace_back((int)mi, std::move(e));
+        for (auto &e : r.entries) groups[Key{e.seq, e.j, (int)e.kind, e.nk, e.var, e.add ? 1 : 0}].emplace_back((int)mi, std::move(e));
     }
     auto align = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     b->prog.clear();
@@ -1366,6 +1409,8 @@ void batch_enqueue(const sse_batch *b) {
             case Kind::ASSEMBLE: launch_assemble_batch<R>(bl<AssembleArgs<R>>(b, op), op.nk, g, st); break;
             case Kind::CONV_DF: launch_convert_batch<double, float>(bl<ConvArgs<double, float>>(b, op), g, st); break;
             case Kind::CONV_FD: launch_convert_batch<float, double>(bl<ConvArgs<float, double>>(b, op), g, st); break;
+            case Kind::LAP: launch_lap_batch<R>(bl<LapArgs<R>>(b, op), op.nk, g, st); break;
+            case Kind::DIV: launch_div_batch<R>(bl<DivArgs<R>>(b, op), op.nk, g, st); break;
         }
     }
 }

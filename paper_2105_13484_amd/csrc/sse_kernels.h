@@ -29,6 +29,7 @@ struct FECellArgs {
     const double *frac;      // h_ref / sum h_ref (z-star), null for isopycnal
     double nu_h;
     R *B;                    // [C][L]
+    R *D1;                   // [C][L] div u (biharmonic runs), nullable
     R *Wtop;                 // [C][L]
     double *Kbot;            // [C]
 };
@@ -71,7 +72,28 @@ struct FEEdgeArgs {
     const double *Ga, *Gb;
     int interp;               // 2: Ga/2 + G/2; 3: Ga/6 + Gb/6 + 2G/3
     int vmix;                 // 1: D^u by the implicit column solve (Algorithm 2)
+    const R *D2, *Z2;         // div and curl of lap u (biharmonic runs), nullable
+    double nu4;               // biharmonic coefficient (m^4/s); nu_h is 0 then
     double dt, g, rho0, nu_h, nu_v, c_drag;
+};
+
+// Vector Laplacian of u at edges from div u at cells and curl u at vertices:
+// out = (D_c2 - D_c1) / d_e - (Z_v2 - Z_v1) / l_e, zero on coast edges.
+template <typename R>
+struct LapArgs {
+    DevMesh m;
+    int L;
+    const R *D, *Z;
+    R *out;                   // [E][L]
+};
+
+// Divergence of an edge field at cells: out_i = sum_j (s l / A)_ij X_ej.
+template <typename R>
+struct DivArgs {
+    DevMesh m;
+    int L;
+    const R *X;
+    R *out;                   // [C][L]
 };
 
 // One forward-Euler evaluation of the barotropic system with frozen forcing,
@@ -188,6 +210,8 @@ int bt_blocks(int E, int C, const Geom &g);
 // form from whether ubar_add is non-null.
 template <typename R> void launch_fe_cell(const FECellArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s);
 // LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
 template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
@@ -220,9 +244,12 @@ struct BatchLaunch {
 };
 template <typename R> void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
+template <typename R> void launch_lap_batch(const BatchLaunch<LapArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
+template <typename R> void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 // Template variant of the edge pass: bit 0 canonical stencils with vertex
-// chains (mesh), bit 1 implicit vertical mixing (parameters).
-int fe_edge_variant(const DevMesh &m, int vmix);
+// chains (mesh), bit 1 implicit vertical mixing, bit 2 biharmonic viscosity
+// (parameters).
+int fe_edge_variant(const DevMesh &m, int vmix, bool del4);
 template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g, hipStream_t s);
 template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
 // table entries (member, patch); ks and lds: the largest over the members

@@ -271,7 +271,11 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
     if (!m.cmask[i]) {
 #pragma unroll
         for (int c = 0; c < NK; ++c)
-            if (ok[c]) { a.B[base + kk[c]] = R(0); a.Wtop[base + kk[c]] = R(0); }
+            if (ok[c]) {
+                a.B[base + kk[c]] = R(0);
+                a.Wtop[base + kk[c]] = R(0);
+                if (a.D1) a.D1[base + kk[c]] = R(0);
+            }
         if (lane_id() == 0) a.Kbot[i] = 0.0;
         return;
     }
@@ -322,6 +326,7 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
     for (int c = 0; c < NK; ++c) {
         if (ok[c]) {
             a.B[base + kk[c]] = K[c] - (R)a.nu_h * divu[c];
+            if (a.D1) a.D1[base + kk[c]] = divu[c];
             a.Wtop[base + kk[c]] = w[c];
             if (kk[c] == L - 1) a.Kbot[i] = (double)K[c];
         }
@@ -358,6 +363,56 @@ __device__ __forceinline__ void fe_vertex_body(const FEVertexArgs<R> &a, int col
 }
 
 // ---------------------------------------------------------------------------
+// Biharmonic viscosity: the vector Laplacian of u at edges, then the
+// divergence of that field at cells (its curl at vertices is the vertex pass
+// applied to it).
+// ---------------------------------------------------------------------------
+template <int NK, typename R>
+__device__ __forceinline__ void lap_body(const LapArgs<R> &a, int col) {
+    const DevMesh &m = a.m;
+    const int e = col;
+    if (e >= m.E) return;
+    const int L = a.L;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    const bool wet = m.emask[e] != 0;
+    const size_t b1 = (size_t)m.edge_cells[2 * e] * L, b2 = (size_t)m.edge_cells[2 * e + 1] * L;
+    const size_t w1 = (size_t)m.edge_verts[2 * e] * L, w2 = (size_t)m.edge_verts[2 * e + 1] * L;
+    const R idc = (R)m.inv_dc[e], idv = (R)m.inv_dv[e];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = kk[c];
+        const R d1 = a.D[b1 + k], d2 = a.D[b2 + k], z1 = a.Z[w1 + k], z2 = a.Z[w2 + k];
+        if (ok[c]) a.out[(size_t)e * L + k] = wet ? (d2 - d1) * idc - (z2 - z1) * idv : R(0);
+    }
+}
+
+template <int NK, typename R>
+__device__ __forceinline__ void div_body(const DivArgs<R> &a, int col) {
+    const DevMesh &m = a.m;
+    const int i = col;
+    if (i >= m.C) return;
+    const int L = a.L;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    R d[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) d[c] = R(0);
+#pragma unroll
+    for (int j = 0; j < kMaxEdges; ++j) {
+        const size_t eb = (size_t)m.cell_edges[i * kMaxEdges + j] * L;
+        const R cd = (R)m.cell_div[i * kMaxEdges + j];
+#pragma unroll
+        for (int c = 0; c < NK; ++c) d[c] += cd * a.X[eb + kk[c]];
+    }
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+        if (ok[c]) a.out[(size_t)i * L + kk[c]] = d[c];
+}
+
+// ---------------------------------------------------------------------------
 // Baroclinic forward Euler: edge pass (Algorithm 1 and the stage combination)
 //
 // The direct-gather and the LDS-staged kernels share everything after the
@@ -369,6 +424,7 @@ struct EdgeOperands {
     R u[NK], ut[NK], za[NK], zb[NK], B1[NK], B2[NK], W1[NK], W2[NK];
     double h1[NK], h2[NK], r1[NK], r2[NK];
     R cor[NK], vor[NK];
+    R lap2[NK];   // lap(lap u) (biharmonic runs; zero otherwise)
 };
 
 // kMix: D^u is left out of the tendency and applied by the implicit column
@@ -444,7 +500,7 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
             const R gradB = (o.B2[c] - o.B1[c]) * ridc;
             const R curlp = (o.zb[c] - o.za[c]) * ridv;
             const R vadv = R(0.5) * (at[c] + atn[c]);
-            const R tu = -gradB + o.vor[c] - vadv + (R)pgf[c] - nu_h * curlp;
+            const R tu = -gradB + o.vor[c] - vadv + (R)pgf[c] - nu_h * curlp - (R)a.nu4 * o.lap2[c];
             const R du = kMix ? R(0) : (tau[c] - taun[c]) * (R(1) / he[c]);
             ut1[c] = o.ut[c] + dt * (o.cor[c] + tu + du + gz);
         } else {
@@ -536,11 +592,14 @@ __device__ __forceinline__ void fe_edge_dry(const FEEdgeArgs<R> &a, int e) {
 // edge record holds the two cells' vertex chains, so the vorticity of the 10
 // distinct vertices is read once instead of at both ends of every stencil
 // edge; otherwise every stencil edge carries its own two vertices.
-// kVar bit 0: kChain; bit 1: kMix (see fe_edge_finish).
+// kVar bit 0: kChain; bit 1: kMix (see fe_edge_finish); bit 2: kDel4, the
+// biharmonic operand lap(lap u) is gathered (div and curl of lap u at the
+// edge's cells and vertices).
 template <int NK, typename R, bool kAdd, int kVar>
 __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     constexpr bool kChain = (kVar & 1) != 0;
     constexpr bool kMix = (kVar & 2) != 0;
+    constexpr bool kDel4 = (kVar & 4) != 0;
     const DevMesh &m = a.m;
     const int E = m.E;
     const int e = col;
@@ -618,6 +677,20 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
         o.W2[c] = ok[c] ? W2 : R(0);
         q[c] = R(0.5) * (o.za[c] + o.zb[c]);
         o.cor[c] = o.vor[c] = R(0);
+        o.lap2[c] = R(0);
+    }
+    if constexpr (kDel4) {
+        // lap(lap u) at the edge from div(lap u) at its cells and curl(lap u)
+        // at its vertices
+        const int v1 = kChain ? (a0_is_v1 ? rec[10] : rec[15]) : m.edge_verts[2 * e];
+        const int v2 = kChain ? (a0_is_v1 ? rec[15] : rec[10]) : m.edge_verts[2 * e + 1];
+        const size_t w1 = (size_t)v1 * L, w2 = (size_t)v2 * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k = kk[c];
+            const R d1 = a.D2[b1 + k], d2 = a.D2[b2 + k], z1 = a.Z2[w1 + k], z2 = a.Z2[w2 + k];
+            o.lap2[c] = ok[c] ? (d2 - d1) * (R)idc - (z2 - z1) * (R)idv : R(0);
+        }
     }
 
     // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
@@ -843,6 +916,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
             o.W2[c] = ok[c] ? W2 : R(0);
             q[c] = R(0.5) * (o.za[c] + o.zb[c]);
             o.cor[c] = o.vor[c] = R(0);
+            o.lap2[c] = R(0);  // the tiled variants run without the biharmonic term
         }
         const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
@@ -1384,6 +1458,21 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
 template <int NK, typename R>
 constexpr int edge_min_waves() { return NK != 1 ? 1 : (sizeof(R) == 8 ? 7 : 6); }
 
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) { lap_body<NK, R>(a, column_id(a.m.E)); }
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) lap_body<NK, R>(b.args[t.x], batch_column(t.y));
+}
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) { div_body<NK, R>(a, column_id(a.m.C)); }
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) div_body<NK, R>(b.args[t.x], batch_column(t.y));
+}
+
 template <int NK, typename R, bool kAdd, int kVar>
 __global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_kernel(FEEdgeArgs<R> a) {
     fe_edge_body<NK, R, kAdd, kVar>(a, column_id(a.m.E));
@@ -1513,8 +1602,8 @@ void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
 }
 // The edge pass has a fourth template parameter, the variant: bit 0 for
 // canonical stencils with vertex chains (the mesh's chain flag), bit 1 for
-// implicit vertical mixing (the state's vmix parameter).  Every member of a
-// batched launch shares it.
+// implicit vertical mixing (the state's vmix parameter), bit 2 for the
+// biharmonic viscosity (hdiff).  Every member of a batched launch shares it.
 #define SSE_NK_ADD_V(NK2, ADD, V, KERNEL, GRID, BLOCK, ARG)                             \
     do {                                                                               \
         if (!(NK2)) {                                                                  \
@@ -1531,15 +1620,44 @@ void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
             case 0: SSE_NK_ADD_V(NK2, ADD, 0, KERNEL, GRID, BLOCK, ARG); break;        \
             case 1: SSE_NK_ADD_V(NK2, ADD, 1, KERNEL, GRID, BLOCK, ARG); break;        \
             case 2: SSE_NK_ADD_V(NK2, ADD, 2, KERNEL, GRID, BLOCK, ARG); break;        \
-            default: SSE_NK_ADD_V(NK2, ADD, 3, KERNEL, GRID, BLOCK, ARG); break;       \
+            case 3: SSE_NK_ADD_V(NK2, ADD, 3, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 4: SSE_NK_ADD_V(NK2, ADD, 4, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 5: SSE_NK_ADD_V(NK2, ADD, 5, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 6: SSE_NK_ADD_V(NK2, ADD, 6, KERNEL, GRID, BLOCK, ARG); break;        \
+            default: SSE_NK_ADD_V(NK2, ADD, 7, KERNEL, GRID, BLOCK, ARG); break;       \
         }                                                                              \
     } while (0)
 
-int fe_edge_variant(const DevMesh &m, int vmix) { return (m.chain ? 1 : 0) | (vmix ? 2 : 0); }
+template <typename R>
+void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.E, g)), block = col_block(g);
+    if (a.L <= kWave) lap_kernel<1, R><<<grid, block, 0, s>>>(a);
+    else lap_kernel<2, R><<<grid, block, 0, s>>>(a);
+}
+template <typename R>
+void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.C, g)), block = col_block(g);
+    if (a.L <= kWave) div_kernel<1, R><<<grid, block, 0, s>>>(a);
+    else div_kernel<2, R><<<grid, block, 0, s>>>(a);
+}
+template <typename R>
+void launch_lap_batch(const BatchLaunch<LapArgs<R>> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) lap_batch<1, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else lap_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+}
+template <typename R>
+void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) div_batch<1, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else div_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+}
+
+int fe_edge_variant(const DevMesh &m, int vmix, bool del4) {
+    return (m.chain ? 1 : 0) | (vmix ? 2 : 0) | (del4 ? 4 : 0);
+}
 
 template <typename R>
 void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, fe_edge_variant(a.m, a.vmix), fe_edge_kernel,
+    SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, fe_edge_variant(a.m, a.vmix, a.D2 != nullptr), fe_edge_kernel,
                    xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
 }
 template <typename R>
@@ -1707,6 +1825,10 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
 #define SSE_INSTANTIATE(R)                                                                                   \
     template void launch_fe_cell<R>(const FECellArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_fe_vertex<R>(const FEVertexArgs<R> &, const Geom &, hipStream_t);                 \
+    template void launch_lap<R>(const LapArgs<R> &, const Geom &, hipStream_t);                           \
+    template void launch_div<R>(const DivArgs<R> &, const Geom &, hipStream_t);                           \
+    template void launch_lap_batch<R>(const BatchLaunch<LapArgs<R>> &, int, const Geom &, hipStream_t);  \
+    template void launch_div_batch<R>(const BatchLaunch<DivArgs<R>> &, int, const Geom &, hipStream_t);  \
     template void launch_fe_edge<R>(const FEEdgeArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_fe_cell_batch<R>(const BatchLaunch<FECellArgs<R>> &, int, bool, const Geom &,     \
                                           hipStream_t);                                                    \

@@ -21,6 +21,7 @@ SSE_FP64, SSE_MIXED = 0, 1
 SSE_ZSTAR, SSE_ISOPYCNAL = 0, 1
 SSE_RECONCILE_OFF, SSE_RECONCILE_EXACT, SSE_RECONCILE_LITERAL = 0, 1, 2
 SSE_VMIX_EXPLICIT, SSE_VMIX_IMPLICIT = 0, 1
+SSE_HDIFF_DEL2, SSE_HDIFF_DEL4 = 0, 1
 PROF_CLASSES = ("fe_edge", "fe_cell", "fe_vertex", "bt_eval", "thickness", "other")
 
 EXPORTED = (
@@ -62,7 +63,7 @@ class sse_mesh_desc(ctypes.Structure):
 class sse_params(ctypes.Structure):
     _fields_ = [
         ("n_layers", c_int32), ("scheme", c_int32), ("substeps", c_int32), ("precision", c_int32),
-        ("vcoord", c_int32), ("reconcile", c_int32), ("vmix", c_int32),
+        ("vcoord", c_int32), ("reconcile", c_int32), ("vmix", c_int32), ("hdiff", c_int32),
         ("dt", c_double), ("gravity", c_double), ("rho0", c_double), ("nu_h", c_double),
         ("nu_v", c_double), ("c_drag", c_double),
     ]

@@ -1,0 +1,132 @@
+"""GPU parity of the biharmonic horizontal viscosity against the oracle.
+
+The edge pass adds -nu_h lap(lap u), with lap u formed at edges by a column
+pass, its divergence and curl by the cell and vertex passes, and gathered by
+the edge pass at the edge's cells and vertices; the oracle applies its TRiSK
+Laplacian twice.  Bounds as in the other parity tests: relative L2 <= 1e-11
+per field in FP64 (self-drift allowance on long windows), the mixed bounds in
+mixed precision.  Coefficients are set near the scale-selective values of the
+paper's global run, scaled with the cell size (about d^3), and stable at the
+cases' time steps.
+"""
+import numpy as np
+import pytest
+
+from oracle import ssprk_se as S
+from oracle.layered import Setup
+from synthetic import cases
+from tests.helpers import rel_l2, smooth_case
+from tests.test_gpu_mixed import check_state
+from tests.test_gpu_parity import TOL, _assert_parity, _compare_state, _noisy_state, _report, _run_both
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_13484_amd import ssprkse
+    ssprkse.load()
+    return ssprkse
+
+
+def del4(case, nu):
+    return cases.with_params(case, hdiff=1, nu_h=nu)
+
+
+D4_CASES = {
+    "hex10x6_L4": lambda: del4(cases.with_params(smooth_case(n=10, L=4), scheme=3), 2e10),
+    "hex12_L60": lambda: del4(cases.c1(n=12, L=60, steps=1), 1e9),
+    "hex8_L100": lambda: del4(cases.c1(n=8, L=100, steps=1), 1e9),
+    "sphere3_land_L7": lambda: del4(cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0), 1e16),
+}
+
+
+@pytest.mark.parametrize("name", sorted(D4_CASES))
+def test_del4_feuler_parity(dev, name):
+    case = D4_CASES[name]()
+    st_o = Setup.from_case(case)
+    u, h = _noisy_state(case, steps=1)
+    ubar, _ = S.split(u, h, st_o)
+    zeta = S.ssh(h, st_o)
+    ut1, G = S.baroclinic_feuler(u, u - ubar[:, None], zeta, h, case.params.dt, st_o)
+    _, st = dev.state_from_case(case)
+    g_ut1, g_G = st.debug_baroclinic_feuler(u, ubar, zeta, h, case.params.dt)
+    errs = {"ut1": rel_l2(g_ut1, ut1), "G": rel_l2(g_G, G)}
+    _report(f"feuler del4 {name}", errs)
+    assert max(errs.values()) < TOL
+    # the biharmonic term is not negligible on these cases
+    del2 = cases.with_params(case, hdiff=0, nu_h=0.0)
+    ex, _ = S.baroclinic_feuler(u, u - ubar[:, None], zeta, h, case.params.dt, Setup.from_case(del2))
+    assert rel_l2(ex, ut1) > 1e3 * TOL
+
+
+@pytest.mark.parametrize("scheme,steps", [(2, 6), (3, 12)])
+def test_del4_steps(dev, scheme, steps):
+    case = del4(smooth_case(n=10, L=5, scheme=scheme, M=6, dt=180.0), 2e10)
+    rc, gpu, ref = _run_both(dev, case, steps)
+    assert rc == 0
+    _assert_parity(f"del4 scheme={scheme}", case, steps, _compare_state(gpu, *ref))
+
+
+def test_del4_c1_recipe_reduced(dev):
+    case = del4(cases.c1(n=32, L=60, steps=4), 1e9)
+    rc, gpu, ref = _run_both(dev, case, 4)
+    assert rc == 0
+    _assert_parity("del4 C1 recipe 32x32x60, 4 steps", case, 4, _compare_state(gpu, *ref))
+
+
+def test_del4_c2_recipe_reduced(dev):
+    case = del4(cases.sphere_case(3, 60, cases.SEED_BASE + 200, substeps=30, dt_btr=240.0), 1e16)
+    rc, gpu, ref = _run_both(dev, case, 3)
+    assert rc == 0
+    _assert_parity("del4 C2 recipe level 3 x 60, 3 steps", case, 3, _compare_state(gpu, *ref))
+
+
+def test_del4_with_vertical_mixing(dev):
+    case = cases.with_params(del4(cases.c1(n=16, L=20, steps=3), 1e9), vmix=1, nu_v=1e-2, c_drag=2e-3)
+    rc, gpu, ref = _run_both(dev, case, 3)
+    assert rc == 0
+    _assert_parity("del4 + vertical mixing 16x16x20, 3 steps", case, 3, _compare_state(gpu, *ref))
+
+
+@pytest.mark.parametrize("name", ["hex12_L60", "sphere3_land_L7"])
+def test_del4_mixed_precision(dev, name):
+    case = D4_CASES[name]()
+    dm, st = dev.state_from_case(cases.with_params(case, precision=1))
+    assert st.step(3) == 0, dev.last_error()
+    check_state(f"del4 {name}", case, st.read(), S.run(case, 3))
+
+
+def test_del4_rejects_tiled_edge_variants(dev):
+    _, st = dev.state_from_case(D4_CASES["hex12_L60"]())
+    assert not st.try_edge_variant(0)
+    assert "biharmonic" in dev.last_error()
+    assert st.try_edge_variant(-1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_del2_and_del4_members(dev, precision):
+    import torch
+    stream = torch.cuda.Stream()
+    cs = [cases.with_params(cases.c1(n=n, L=L, substeps=M, dt_btr=15.0, member=i, steps=3), precision=precision)
+          for i, (n, L, M) in enumerate([(12, 20, 6), (10, 70, 5), (8, 40, 4), (14, 9, 7)])]
+    cs = [del4(c, 1e9) if i % 2 == 0 else c for i, c in enumerate(cs)]
+    alone = []
+    for c in cs:
+        _, st = dev.state_from_case(c, stream=stream)
+        assert st.step(3) == 0
+        alone.append(st.read())
+    keep, b = [], dev.Batch(stream=stream)
+    for c in cs:
+        dm, st = dev.state_from_case(c, stream=stream)
+        keep.append(dm)
+        b.add(st)
+    b.compile()
+    assert b.step(3) == 0
+    for i, st in enumerate(b.members):
+        got = st.read()
+        for k in ("h", "u", "zeta", "ubar"):
+            assert np.array_equal(got[k], alone[i][k]), (i, k)
