@@ -24,6 +24,9 @@ Readings of what the paper leaves to MPAS (each stated where it is used):
   condition of Section 5), with |u|^2 = K_c1 + K_c2 of the bottom layer;
 * horizontal viscosity nu_h lap u, or the biharmonic -nu_h lap(lap u) with the
   inner Laplacian zeroed on coast edges;
+* tracers (temperature, when params.tracer is set): the content h T follows
+  the layered tracer equation with centred edge values and the thickness
+  stages' own fluxes and w; the density follows the linear EOS;
 * implicit vertical diffusion (Algorithm 2): the same operator with the drag
   speed |u| taken from the stage input and frozen, so that the solve is
   linear; the velocity multiplying c_drag |u| is the new one.
@@ -145,6 +148,46 @@ def T_h(h: np.ndarray, u: np.ndarray, st: Setup) -> np.ndarray:
         frac = safe_ratio(st.h_ref, colsum(st.h_ref)[:, None], st.cell_mask[:, None])
         th = -frac * colsum(div)[:, None]
     return np.where(st.cell_mask[:, None], th, 0.0)
+
+
+def eos(T: np.ndarray, st: Setup) -> np.ndarray:
+    """Linear equation of state (eqstate) with temperature only:
+    rho = rho0 (1 - alpha (T - T_ref))."""
+    p = st.params
+    return p.rho0 * (1.0 - p.eos_alpha * (T - p.eos_tref))
+
+
+def tracer_tendency(h: np.ndarray, T: np.ndarray, v: np.ndarray, st: Setup) -> np.ndarray:
+    """Tendency of the tracer content h_k T_k in the layered tracer equation
+    (tracer) of Section 2, for the layer thicknesses h and the velocity v that
+    transport the thickness in the same stage:
+
+        -div(h_e T_e v) - [Tbar^t w]_k + [Tbar^t w]_{k+1}
+        + div(h_e kappa_h grad T) + h_k D_{z^m}(kappa_v D_{z^t} T)_k
+
+    with T_e = (T_c1 + T_c2)/2 (centred), Tbar^t the mean of the two layers at
+    an interface, w the vertical velocity of the thickness equation for the
+    same h and v (z-star, zero for isopycnal), and no flux through the surface
+    and the bottom.  With T = 1 this is exactly the thickness tendency, so a
+    uniform tracer stays uniform.
+    """
+    m, p = st.mesh, st.params
+    C, L = h.shape
+    he = trisk.cell_to_edge(h, m)
+    Te = trisk.cell_to_edge(T, m)
+    adv = trisk.divergence(mask_edges(he * Te * v, st), m)
+    w = vertical_velocity(h, v, st)
+    Tt = np.zeros((C, L + 1))
+    Tt[:, 1:L] = 0.5 * (T[:, :-1] + T[:, 1:])
+    wT = Tt * w
+    vert = wT[:, :L] - wT[:, 1:]
+    tend = -adv - vert
+    if p.kappa_h:
+        tend = tend + trisk.divergence(mask_edges(he * p.kappa_h * trisk.gradient(T, m), st), m)
+    if p.kappa_v:
+        flux = p.kappa_v * D_zt(T, h)          # zero at the surface and the bottom
+        tend = tend + (flux[:, :-1] - flux[:, 1:])
+    return np.where(st.cell_mask[:, None], tend, 0.0)
 
 
 def pressure_gradient_force(h: np.ndarray, st: Setup) -> np.ndarray:

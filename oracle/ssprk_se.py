@@ -32,8 +32,10 @@ from __future__ import annotations
 import numpy as np
 
 from . import trisk
-from .layered import (Setup, T_h, T_u, D_u, bottom_speed, colsum, mask_edges, safe_ratio,
-                      vertical_diffusion_solve)
+from dataclasses import replace
+
+from .layered import (Setup, T_h, T_u, D_u, bottom_speed, colsum, eos, mask_edges, safe_ratio,
+                      tracer_tendency, vertical_diffusion_solve)
 
 
 def split(u: np.ndarray, h: np.ndarray, st: Setup):
@@ -147,6 +149,22 @@ def thickness_stage(h_in, u_stage, uA, dt, st: Setup):
     return h_in + dt * T_h(h_in, mask_edges(u_stage + uA[:, None], st), st)
 
 
+def tracer_stage(h_in, T_in, u_stage, uA, dt, st: Setup):
+    """(h T)_in + dt T^T(h_in, T_in, u_stage + u^A): the tracer content moved by
+    the same velocity and thickness fluxes as the matching thickness stage."""
+    return h_in * T_in + dt * tracer_tendency(h_in, T_in, mask_edges(u_stage + uA[:, None], st), st)
+
+
+def tracer_of(hT, h, st: Setup):
+    """T = (h T) / h on ocean cells."""
+    return safe_ratio(hT, h, st.cell_mask[:, None])
+
+
+def with_density(st: Setup, T):
+    """The setup with the density of temperature T (tracer runs); st itself otherwise."""
+    return st if T is None else replace(st, rho=eos(T, st))
+
+
 def ssh(h, st: Setup):
     """zeta = sum_k h_k - H (Section 2, definition of zeta)."""
     return np.where(st.cell_mask, colsum(h) - st.H, 0.0)
@@ -158,22 +176,25 @@ def _edge_sum(h, u, st: Setup):
     return mask_edges(colsum(he * u), st), mask_edges(colsum(he), st)
 
 
-def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None):
-    """One SSPRK2-SE step t_n -> t_{n+1} (Section 3.2 with Section 3.4)."""
+def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None, T=None):
+    """One SSPRK2-SE step t_n -> t_{n+1} (Section 3.2 with Section 3.4).  With a
+    temperature T (tracer runs) its content follows the thickness stages and
+    every baroclinic stage sees the density of its stage temperature."""
     p = st.params
     dt, M, rec = p.dt, p.substeps, p.reconcile
     zeta = ssh(h, st)
     ubar, ut = split(u, h, st)
     # Step 1, stage 1
-    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, st)
+    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, with_density(st, T))
     ub1, zb1, Fz1 = barotropic_ssprk2_substep(ubar, zeta, G0, dt, M, st)
     u1 = mask_edges(ub1[:, None] + ut1, st)
     Fh1, S1 = _edge_sum(h, u, st)
     uA1 = safe_ratio(Fz1 - Fh1, S1, st.edge_mask) if rec else np.zeros_like(ubar)
     h1 = thickness_stage(h, u, uA1, dt, st)
     z1 = ssh(h1, st)
+    T1 = None if T is None else tracer_of(tracer_stage(h, T, u, uA1, dt, st), h1, st)
     # Step 1, stage 2
-    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, st)
+    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, with_density(st, T1))
     ut_new = 0.5 * (ut + ut2)
     # Step 2
     ub_new, zb2, Fz2 = barotropic_ssprk2_substep(ubar, zeta, interp2(G0, G1), dt, M, st)
@@ -187,30 +208,36 @@ def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None):
         uA2 = safe_ratio(2.0 * (Fz2 - Fh2), S2, st.edge_mask)
     h2 = thickness_stage(h1, u_new, uA2, dt, st)
     h_new = 0.5 * (h + h2)
+    if T is not None:
+        T_new = tracer_of(0.5 * (h * T + tracer_stage(h1, T1, u_new, uA2, dt, st)), h_new, st)
     if diag is not None:
         diag.update(ubar=ubar, ut=ut, zeta=zeta, ut1=ut1, G0=G0, ub1=ub1, zeta_bt1=zb1, Fz1=Fz1,
                     Fh1=Fh1, uA1=uA1, h1=h1, zeta1=z1, ut2=ut2, G1=G1, ub_new=ub_new, zeta_bt2=zb2,
                     Fz2=Fz2, P=P, uA2=uA2, h2=h2, zeta_new=ssh(h_new, st))
+    if T is not None:
+        return u_new, h_new, T_new
     return u_new, h_new
 
 
-def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
-    """One SSPRK3-SE step t_n -> t_{n+1} (Section 3.3 with Section 3.4)."""
+def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None, T=None):
+    """One SSPRK3-SE step t_n -> t_{n+1} (Section 3.3 with Section 3.4); T as in
+    ssprk2_se_step."""
     p = st.params
     dt, M, rec = p.dt, p.substeps, p.reconcile
     zeta = ssh(h, st)
     ubar, ut = split(u, h, st)
     zero = np.zeros_like(ubar)
     # Step 1, stage 1
-    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, st)
+    ut1, G0 = bfe(u, ut, ubar, zeta, h, dt, with_density(st, T))
     ub1, zb1, Fz1 = barotropic_ssprk3_substep(ubar, zeta, G0, dt, M, st)
     u1 = mask_edges(ub1[:, None] + ut1, st)
     Fh1, S1 = _edge_sum(h, u, st)
     uA1 = safe_ratio(Fz1 - Fh1, S1, st.edge_mask) if rec else zero
     h1 = thickness_stage(h, u, uA1, dt, st)
     z1 = ssh(h1, st)
+    T1 = None if T is None else tracer_of(tracer_stage(h, T, u, uA1, dt, st), h1, st)
     # Step 1, stage 2
-    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, st)
+    ut2, G1 = bfe(u1, ut1, ub1, z1, h1, dt, with_density(st, T1))
     ut_half = 0.75 * ut + 0.25 * ut2
     ub2, zb2, Fz2 = barotropic_ssprk3_substep(ub1, z1, G1, dt, M, st)
     ub_half = 0.75 * ubar + 0.25 * ub2
@@ -220,8 +247,11 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
     h2 = thickness_stage(h1, u1, uA2, dt, st)
     h_half = 0.75 * h + 0.25 * h2
     z_half = ssh(h_half, st)
+    T_half = None
+    if T is not None:
+        T_half = tracer_of(0.75 * (h * T) + 0.25 * tracer_stage(h1, T1, u1, uA2, dt, st), h_half, st)
     # Step 1, stage 3
-    ut3, G_half = bfe(u_half, ut_half, ub_half, z_half, h_half, dt, st)
+    ut3, G_half = bfe(u_half, ut_half, ub_half, z_half, h_half, dt, with_density(st, T_half))
     ut_new = ut / 3.0 + 2.0 * ut3 / 3.0
     # Step 2
     ub_new, zb3, Fz3 = barotropic_ssprk3_substep(ubar, zeta, interp3(G0, G1, G_half), dt, M, st)
@@ -236,27 +266,42 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None):
         uA3 = safe_ratio(1.5 * (Fz3 - Fh3), S3, st.edge_mask)
     h3 = thickness_stage(h_half, 0.5 * (u + u_new), uA3, dt, st)
     h_new = h / 3.0 + 2.0 * h3 / 3.0
+    if T is not None:
+        hT3 = tracer_stage(h_half, T_half, 0.5 * (u + u_new), uA3, dt, st)
+        T_new = tracer_of((h * T) / 3.0 + 2.0 * hT3 / 3.0, h_new, st)
     if diag is not None:
         diag.update(ubar=ubar, ut=ut, zeta=zeta, ut1=ut1, G0=G0, ub1=ub1, zeta_bt1=zb1, Fz1=Fz1,
                     Fh1=Fh1, uA1=uA1, h1=h1, zeta1=z1, ut2=ut2, G1=G1, ub2=ub2, zeta_bt2=zb2,
                     Fz2=Fz2, Fh2=Fh2, uA2=uA2, h2=h2, h_half=h_half, zeta_half=z_half, ut3=ut3,
                     G_half=G_half, ub_new=ub_new, zeta_bt3=zb3, Fz3=Fz3, P=P, uA3=uA3, h3=h3,
                     zeta_new=ssh(h_new, st))
+    if T is not None:
+        return u_new, h_new, T_new
     return u_new, h_new
 
 
-def step(u, h, st: Setup, diag: dict | None = None):
+def step(u, h, st: Setup, diag: dict | None = None, T=None):
+    """One step; returns (u, h), or (u, h, T) when a temperature is carried."""
     if st.params.scheme == 2:
-        return ssprk2_se_step(u, h, st, diag)
-    return ssprk3_se_step(u, h, st, diag)
+        return ssprk2_se_step(u, h, st, diag, T)
+    return ssprk3_se_step(u, h, st, diag, T)
 
 
 def run(case, steps: int | None = None):
-    """Advance a synthetic case; returns (u, h, zeta, ubar) at the end."""
+    """Advance a synthetic case; returns (u, h, zeta, ubar) at the end, and the
+    temperature as a fifth value when the case carries a tracer."""
     st = Setup.from_case(case)
     u, h = case.u.astype(float).copy(), case.h.astype(float).copy()
     u = mask_edges(u, st)
+    T = None
+    if getattr(case.params, "tracer", 0):
+        T = np.where(st.cell_mask[:, None], case.temp.astype(float), 0.0)
     for _ in range(case.steps if steps is None else steps):
-        u, h = step(u, h, st)
+        if T is None:
+            u, h = step(u, h, st)
+        else:
+            u, h, T = step(u, h, st, T=T)
     ubar, _ = split(u, h, st)
+    if T is not None:
+        return u, h, ssh(h, st), ubar, T
     return u, h, ssh(h, st), ubar

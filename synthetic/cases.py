@@ -55,6 +55,11 @@ class Params:
     c_drag: float = 1.0e-3
     vmix: int = 0              # 1 = implicit vertical mixing (Algorithm 2)
     hdiff: int = 0             # 0 = nu_h lap u (m^2/s), 1 = -nu_h lap(lap u) (m^4/s)
+    tracer: int = 0            # 1 = temperature evolves and rho follows the linear EOS
+    kappa_h: float = 0.0       # tracer horizontal diffusivity (m^2/s)
+    kappa_v: float = 0.0       # tracer vertical diffusivity (m^2/s)
+    eos_alpha: float = 2.0e-4  # rho = rho0 (1 - eos_alpha (T - eos_tref))
+    eos_tref: float = 10.0
 
 
 @dataclass
@@ -71,6 +76,7 @@ class Case:
     steps: int = 1
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    temp: np.ndarray | None = None  # (C, L) temperature the density was derived from
 
     @property
     def edge_mask(self) -> np.ndarray:
@@ -137,7 +143,7 @@ def c1(n: int = 512, L: int = 60, member: int = 0, steps: int = 200, dc: float =
     rho = linear_eos(T)
     params = Params(n_layers=L, scheme=3, substeps=substeps, dt=substeps * dt_btr)
     return Case("c1", mesh, params, H, h_ref, rho, h_ref.copy(), np.zeros((E, L)),
-                np.ones(C, np.uint8), steps, seed, meta={"n": n})
+                np.ones(C, np.uint8), steps, seed, meta={"n": n}, temp=T)
 
 
 def _sphere_bumps(mesh: Mesh, rng, nb: int = 20) -> np.ndarray:
@@ -181,9 +187,10 @@ def sphere_case(level: int, L: int, seed: int, substeps: int, dt_btr: float,
     T = 25.0 - 23.0 * depth / 5000.0 + rng.normal(0.0, 0.5, size=(C, L))
     T = _smooth_cells(mesh, T, ocean, 2)
     rho = np.where(ocean[:, None], linear_eos(T), 0.0)
+    T = np.where(ocean[:, None], T, 0.0)
     params = Params(n_layers=L, scheme=3, substeps=substeps, dt=substeps * dt_btr)
     return Case(name, mesh, params, H, h_ref, rho, h_ref.copy(), np.zeros((E, L)),
-                ocean.astype(np.uint8), 1, seed, meta={"level": level})
+                ocean.astype(np.uint8), 1, seed, meta={"level": level}, temp=T)
 
 
 def c2(level: int = 7, L: int = 60, member: int = 0, mixed: bool = True) -> Case:
@@ -207,7 +214,7 @@ def c3_member(member: int) -> Case:
     T = _front_temperature(mesh.xCell[:, 0], _mid_depth(H, L), H, mesh.Lx / kfront, rng.uniform(0, 2 * np.pi))
     params = Params(n_layers=L, scheme=3, substeps=M, dt=30.0 * M, precision=1)
     return Case(f"c3[{member}]", mesh, params, H, h_ref, linear_eos(T), h_ref.copy(), np.zeros((E, L)),
-                np.ones(C, np.uint8), 100, seed, meta={"n": n, "kfront": kfront})
+                np.ones(C, np.uint8), 100, seed, meta={"n": n, "kfront": kfront}, temp=T)
 
 
 def served_dt_btr(level: int) -> float:
