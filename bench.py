@@ -10,7 +10,8 @@ timing starts.
 Prints ONE JSON line on stdout: cell-layer updates/s over the timed steps,
 the roofline of the dominant kernel class (algorithmic bytes / HIP-event time
 of that class in a second timed region), the same workload in mixed
-precision, with implicit vertical mixing and with biharmonic viscosity, the runtime to a fixed simulated time as the number of substeps
+precision, with implicit vertical mixing, with biharmonic viscosity and with an evolving
+temperature tracer, the runtime to a fixed simulated time as the number of substeps
 M varies (both schemes), the level-7 sphere (C2 recipe) in FP64 and mixed
 precision, a batched ensemble, a served request stream, and the FP64 CPU
 oracle timed on a bounded sample of the headline recipe.
@@ -279,6 +280,7 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the level-7 sphere timings")
     ap.add_argument("--no-vmix", action="store_true", help="skip the implicit-vertical-mixing timing")
     ap.add_argument("--no-del4", action="store_true", help="skip the biharmonic-viscosity timing")
+    ap.add_argument("--no-tracer", action="store_true", help="skip the evolving-tracer timing")
     ap.add_argument("--no-m-sweep", action="store_true", help="skip the runtime-vs-M sweep")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -370,6 +372,17 @@ def main():
         log(f"[bench] C1 with biharmonic viscosity: {ms_del4:.3f} ms/step")
         del st_d
 
+    # the same workload with the temperature evolving and the density following
+    # the linear EOS every stage (kappa_h = 10 m^2/s, kappa_v = 1e-5 m^2/s)
+    ms_tracer = None
+    if not args.no_tracer:
+        _, st_t = ssprkse.state_from_case(cases.with_params(case, tracer=1, kappa_h=10.0, kappa_v=1.0e-5),
+                                          device="cuda:0")
+        assert st_t.step(args.warmup) == 0
+        ms_tracer = timed_steps(torch, st_t, args.steps)
+        log(f"[bench] C1 with an evolving temperature tracer: {ms_tracer:.3f} ms/step")
+        del st_t
+
     # runtime vs the number of substeps at fixed T and dt_btr, both schemes
     m_sweep = None if args.no_m_sweep else m_sweep_leg(torch, ssprkse, dm, case)
     del dm
@@ -419,6 +432,7 @@ def main():
         "mixed_ms_per_step": ms_mixed,
         "vmix_ms_per_step": ms_vmix,
         "del4_ms_per_step": ms_del4,
+        "tracer_ms_per_step": ms_tracer,
         "per_class_ms_per_step": {k: v[1] / 3.0 for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -71,6 +71,17 @@ enum { SSE_VMIX_EXPLICIT = 0, SSE_VMIX_IMPLICIT = 1 };
  * zero on coast edges.  DEL4 adds three column passes per stage and
  * workspace for four more 3D fields, and runs the direct edge pass only. */
 enum { SSE_HDIFF_DEL2 = 0, SSE_HDIFF_DEL4 = 1 };
+/* Tracers (Section 2, equations tracer and eqstate): NONE keeps the density
+ * of sse_state_init frozen.  TEMPERATURE carries the layer temperature T: its
+ * content h T goes through every thickness stage of the scheme with the
+ * stage's own fluxes (centred edge values T_e = (T_c1 + T_c2)/2, the same
+ * velocity, u^A included, and the same z-star w as the thickness), with
+ * horizontal and vertical diffusion kappa_h, kappa_v, no flux through the
+ * surface, the bottom or coasts, and the same convex combinations, so a
+ * uniform T stays uniform; after every stage rho = rho0 (1 - eos_alpha
+ * (T - eos_tref)) feeds the next baroclinic stage.  T and rho are FP64 in
+ * both precisions. */
+enum { SSE_TRACER_NONE = 0, SSE_TRACER_TEMPERATURE = 1 };
 
 /*
  * Mesh description (host memory, caller numbering; copied by
@@ -109,14 +120,18 @@ typedef struct {
  *   n_layers L (1..128); scheme SSE_SCHEME_SSPRK2 | SSE_SCHEME_SSPRK3;
  *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 | SSE_MIXED;
  *   vcoord SSE_ZSTAR | SSE_ISOPYCNAL (Section 2, vertical coordinate);
- *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; hdiff SSE_HDIFF_*; dt > 0
- *   (s); gravity g; rho0 (Boussinesq reference density); nu_h (horizontal
- *   viscosity, m^2/s for DEL2, m^4/s for DEL4); nu_v (vertical viscosity,
- *   m^2/s); c_drag (bottom drag of Section 5, dimensionless).
+ *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; hdiff SSE_HDIFF_*; tracer
+ *   SSE_TRACER_*; dt > 0 (s); gravity g; rho0 (Boussinesq reference
+ *   density); nu_h (horizontal viscosity, m^2/s for DEL2, m^4/s for DEL4);
+ *   nu_v (vertical viscosity, m^2/s); c_drag (bottom drag of Section 5,
+ *   dimensionless); kappa_h, kappa_v (tracer diffusivities, m^2/s) and
+ *   eos_alpha (1/K), eos_tref (deg C) of the linear EOS, read in tracer runs
+ *   only.
  */
 typedef struct {
-    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile, vmix, hdiff;
+    int32_t n_layers, scheme, substeps, precision, vcoord, reconcile, vmix, hdiff, tracer;
     double dt, gravity, rho0, nu_h, nu_v, c_drag;
+    double kappa_h, kappa_v, eos_alpha, eos_tref;
 } sse_params;
 
 typedef struct sse_mesh sse_mesh;
@@ -169,6 +184,14 @@ int sse_state_destroy(sse_state *s);
  * land are forced to 0.  SSE_ENONFINITE if any input is NaN/Inf. */
 int sse_state_init(sse_state *s, const double *h, const double *u, const double *rho,
                    const double *h_ref);
+
+/* Tracer runs: the layer temperature T [C][L] (host, row-major, caller
+ * numbering; land cells are ignored), required once after sse_state_init and
+ * before the first step; it also sets rho from the EOS.  sse_read_tracer
+ * copies the state's temperature out.  SSE_EINVAL / SSE_ESTATE when the
+ * state carries no tracer; SSE_ENONFINITE for non-finite input. */
+int sse_state_set_tracer(sse_state *s, const double *T);
+int sse_read_tracer(const sse_state *s, double *T);
 
 /* Enqueue n steps t -> t + n dt on the state's stream, wait, and check the
  * state for NaN/Inf.  SSE_ENONFINITE after a blow-up (the state keeps the

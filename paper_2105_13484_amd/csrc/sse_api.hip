@@ -43,6 +43,8 @@ struct Work {
     int *flag;
     void *D1, *L1, *D2, *Z2;                 // R, biharmonic runs only: div u [C][L], lap u [E][L],
                                              // div(lap u) [C][L], curl(lap u) [V][L]
+    double *Tn, *T1s, *Th;                   // [C][L], tracer runs only: temperature of the state,
+                                             // of the first stage and of the n+1/2 stage
 };
 
 constexpr int kR3E = 3, kR3C = 2, kR3V = 1, kR2E = 4, kR2C = 4;  // arrays of type R
@@ -52,8 +54,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 size_t real_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : sizeof(double); }
 
-size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff) {
+size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff, int tracer) {
     size_t b = 0;
+    if (tracer) b += 3 * align_up((size_t)C * L * 8);
     if (hdiff == SSE_HDIFF_DEL4)
         b += align_up((size_t)E * L * rs) + 2 * align_up((size_t)C * L * rs) + align_up((size_t)V * L * rs);
     b += kR3E * align_up((size_t)E * L * rs);
@@ -68,7 +71,7 @@ size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff) {
     return b;
 }
 
-Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff) {
+Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff, int tracer) {
     char *p = static_cast<char *>(buf);
     auto take = [&](size_t n) {
         void *r = p;
@@ -100,6 +103,12 @@ Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff) {
         w.L1 = take((size_t)E * L * rs);
         w.D2 = take((size_t)C * L * rs);
         w.Z2 = take((size_t)V * L * rs);
+    }
+    w.Tn = w.T1s = w.Th = nullptr;
+    if (tracer) {
+        w.Tn = static_cast<double *>(take((size_t)C * L * 8));
+        w.T1s = static_cast<double *>(take((size_t)C * L * 8));
+        w.Th = static_cast<double *>(take((size_t)C * L * 8));
     }
     return w;
 }
@@ -171,7 +180,7 @@ bool all_finite(const double *x, size_t n) {
 // key (seq = launch site in step order; j = substep evaluation inside a
 // barotropic loop), so that the same launch of every member can be merged
 // into one batched launch.
-enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, BT_TILE, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD, LAP, DIV };
+enum class Kind : int { FE_CELL, FE_VERTEX, FE_EDGE, BT_EVAL, BT_TILE, THICK, THICK_ISO, RECON, ASSEMBLE, CONV_DF, CONV_FD, LAP, DIV, TRACER };
 
 struct RecEntry {
     Kind kind;
@@ -200,6 +209,7 @@ struct sse_state {
     size_t bytes = 0;
     size_t rs = 8;           // bytes of the real type R
     bool initialized = false;
+    bool tracer_set = false; // tracer runs: the temperature has been given
     Geom geom{};             // launch geometry (autotuner knob)
     int edge_variant = -1;   // -1: direct gathers; 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
     int bt_variant = 0;      // 0: one launch per barotropic evaluation; 1: one per substep (patches)
@@ -513,12 +523,49 @@ void recon(sse_state *s, int mode, const double *Fz, const double *Fh, const dou
 
 // Thickness stage.  z-star uses the 2D total flux w.Ftot; isopycnal rebuilds
 // the per-layer velocity c1 X1 + c2 X2 + ca1 a1 + u^A.
+// Thickness stage, fused with the temperature stage in tracer runs: T_in and
+// T_out are the stage's input and output temperature (base T^n when comb is
+// set); the density is updated in place.
 template <typename R>
 void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, double *h_out, double *zeta_out,
-               const R *X1, double c1, const R *X2, double c2, const double *a1, double ca1, double dt) {
+               const R *X1, double c1, const R *X2, double c2, const double *a1, double ca1, double dt,
+               const double *T_in = nullptr, double *T_out = nullptr) {
     ProfScope ps(s, SSE_PROF_THICKNESS);
     Work &w = s->w;
     const int nk = nk_of(s->p.n_layers), nb = col_blocks(s->mesh->d.C, s->geom);
+    if (s->p.tracer) {
+        const sse_params &p = s->p;
+        TracerArgs<R> a{};
+        a.m = s->mesh->d;
+        a.L = p.n_layers;
+        a.h_in = h_in;
+        a.h_n = h_n;
+        a.T_in = T_in;
+        a.T_n = w.Tn;
+        a.X1 = X1;
+        a.X2 = X2;
+        a.c1 = c1;
+        a.c2 = c2;
+        a.a1 = a1;
+        a.ca1 = ca1;
+        a.uA = w.uA;
+        a.frac = p.vcoord == SSE_ZSTAR ? w.frac : nullptr;
+        a.comb = comb;
+        a.dt = dt;
+        a.kappa_h = p.kappa_h;
+        a.kappa_v = p.kappa_v;
+        a.rho0 = p.rho0;
+        a.alpha = p.eos_alpha;
+        a.tref = p.eos_tref;
+        a.h_out = h_out;
+        a.zeta_out = zeta_out;
+        a.T_out = T_out;
+        a.rho_out = w.rho;
+        a.nonfinite = w.flag;
+        if (s->rec) record(s, Kind::TRACER, a, nk, false, nb);
+        else launch_tracer<R>(a, s->geom, s->stream);
+        return;
+    }
     if (s->p.vcoord == SSE_ZSTAR) {
         THArgs a{s->mesh->d, s->p.n_layers, h_in, h_n, w.frac, w.Ftot, comb, dt, h_out, zeta_out, w.flag};
         if (s->rec) record(s, Kind::THICK, a, nk, false, nb);
@@ -567,13 +614,13 @@ void step_ssprk3(sse_state *s) {
                nullptr, nullptr, nullptr, 0);
     bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
-    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt);
+    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt, w.Tn, w.T1s);
     // Stage 2: FE from (u-hat^{n+1}, ut-hat^{n+1}, zeta-hat^{n+1}, h-hat^{n+1}); second loop; thickness.
     fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_34, T2, w.G1, w.Sh2, w.Fh2, nullptr, 0, 0, nullptr,
                nullptr, nullptr, 0);
     bt_loop<R>(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
     recon(s, 0, w.Fz2, w.Fh2, w.Sh2, nullptr, nullptr, w.ub2, w.ub_half);
-    thickness<R>(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, T1, 1.0, none, 0.0, w.ub1, 1.0, dt);
+    thickness<R>(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, T1, 1.0, none, 0.0, w.ub1, 1.0, dt, w.T1s, w.Th);
     // Stage 3: FE from the n+1/2 stage -> ut^{n+1}; G interpolated by Interp_3.
     fe_pass<R>(s, T2, w.ub_half, nullptr, w.H2, w.z_half, COMB_THIRD, T1, w.Gh, w.Sh3, nullptr, w.Pp, 1.0, 1.0,
                w.Gi, w.G0, w.G1, 3);
@@ -581,7 +628,7 @@ void step_ssprk3(sse_state *s) {
     bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
     // Step 3: last thickness stage with u^A_3, then u^{n+1} and its split.
     recon(s, 1, w.Fz3, nullptr, w.Sh3, w.Pp, w.ubar_new, nullptr, nullptr);
-    thickness<R>(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, U, 0.5, T1, 0.5, w.ubar_new, 0.5, dt);
+    thickness<R>(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, U, 0.5, T1, 0.5, w.ubar_new, 0.5, dt, w.Th, w.Tn);
     assemble<R>(s, T1, w.ubar_new);
 }
 
@@ -596,12 +643,12 @@ void step_ssprk2(sse_state *s) {
                nullptr, nullptr, nullptr, 0);
     bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
-    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt);
+    thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt, w.Tn, w.T1s);
     fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_HALF, T2, w.G1, w.Sh2, nullptr, w.Pp, 0.0, 1.0, w.Gi,
                w.G0, nullptr, 2);
     bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
     recon(s, 2, w.Fz2, nullptr, w.Sh2, w.Pp, w.ubar_new, nullptr, nullptr);
-    thickness<R>(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, T2, 1.0, none, 0.0, w.ubar_new, 1.0, dt);
+    thickness<R>(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, T2, 1.0, none, 0.0, w.ubar_new, 1.0, dt, w.T1s, w.Tn);
     assemble<R>(s, T2, w.ubar_new);
 }
 
@@ -623,6 +670,14 @@ int check_params(const sse_params *p) {
     if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
     if (p->vmix != SSE_VMIX_EXPLICIT && p->vmix != SSE_VMIX_IMPLICIT) { set_error("vmix must be SSE_VMIX_EXPLICIT or SSE_VMIX_IMPLICIT"); return SSE_EINVAL; }
     if (p->hdiff != SSE_HDIFF_DEL2 && p->hdiff != SSE_HDIFF_DEL4) { set_error("hdiff must be SSE_HDIFF_DEL2 or SSE_HDIFF_DEL4"); return SSE_EINVAL; }
+    if (p->tracer != SSE_TRACER_NONE && p->tracer != SSE_TRACER_TEMPERATURE) { set_error("tracer must be SSE_TRACER_NONE or SSE_TRACER_TEMPERATURE"); return SSE_EINVAL; }
+    if (p->tracer) {
+        if (!(p->kappa_h >= 0) || !(p->kappa_v >= 0) || !std::isfinite(p->kappa_h) || !std::isfinite(p->kappa_v) ||
+            !std::isfinite(p->eos_alpha) || !std::isfinite(p->eos_tref)) {
+            set_error("kappa_h, kappa_v must be >= 0 and the EOS coefficients finite");
+            return SSE_EINVAL;
+        }
+    }
     const double v[] = {p->dt, p->gravity, p->rho0};
     for (double x : v)
         if (!(x > 0) || !std::isfinite(x)) { set_error("dt, gravity and rho0 must be positive"); return SSE_EINVAL; }
@@ -890,7 +945,7 @@ extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p,
     if (!m || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
     int rc = check_params(p);
     if (rc) return rc;
-    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision), p->hdiff);
+    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision), p->hdiff, p->tracer);
     return SSE_OK;
 }
 
@@ -904,7 +959,7 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
     mb += bt_tiles_bytes(d);
-    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision), p->hdiff);
+    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision), p->hdiff, p->tracer);
     return SSE_OK;
 }
 
@@ -915,7 +970,7 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     int rc = check_params(p);
     if (rc) return rc;
     const size_t rs = real_size(p->precision);
-    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs, p->hdiff);
+    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs, p->hdiff, p->tracer);
     if (!dev_workspace || bytes < need) { set_error("state workspace too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) { set_error("state workspace must be 256-byte aligned"); return SSE_EINVAL; }
     sse_state *s = new sse_state();
@@ -923,7 +978,7 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->p = *p;
     s->stream = static_cast<hipStream_t>(stream);
     s->rs = rs;
-    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs, p->hdiff);
+    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs, p->hdiff, p->tracer);
     s->bytes = bytes;
     int dev = 0, lds_max = 0;
     (void)hipGetDevice(&dev);
@@ -1082,9 +1137,48 @@ void batch_invalidate(sse_batch *b);
 
 }  // namespace
 
+extern "C" int sse_state_set_tracer(sse_state *s, const double *T) {
+    if (!s || !T) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (!s->p.tracer) { set_error("the state's parameters carry no tracer"); return SSE_EINVAL; }
+    if (!s->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
+    const sse_mesh *m = s->mesh;
+    const int L = s->p.n_layers;
+    const size_t CL = (size_t)m->C * L;
+    if (!all_finite(T, CL)) { set_error("non-finite temperature"); return SSE_ENONFINITE; }
+    std::vector<double> ti(CL), ri(CL);
+    rows_to_internal(T, ti.data(), m->cell_old, L);
+    std::vector<uint8_t> cmask(m->C);
+    SSE_HIP(hipMemcpy(cmask.data(), m->d.cmask, m->C, hipMemcpyDeviceToHost));
+    for (int i = 0; i < m->C; ++i)
+        for (int k = 0; k < L; ++k) {
+            double &t = ti[(size_t)i * L + k];
+            if (!cmask[i]) t = 0.0;
+            ri[(size_t)i * L + k] = s->p.rho0 * (1.0 - s->p.eos_alpha * (t - s->p.eos_tref));
+        }
+    SSE_HIP(hipMemcpyAsync(s->w.Tn, ti.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipMemcpyAsync(s->w.rho, ri.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
+    SSE_HIP(hipStreamSynchronize(s->stream));
+    s->tracer_set = true;
+    if (s->batch) batch_invalidate(s->batch);
+    return SSE_OK;
+}
+
+extern "C" int sse_read_tracer(const sse_state *s, double *T) {
+    if (!s || !T) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (!s->p.tracer || !s->tracer_set) { set_error("the state carries no temperature"); return SSE_ESTATE; }
+    const sse_mesh *m = s->mesh;
+    const size_t L = s->p.n_layers;
+    std::vector<double> ti((size_t)m->C * L);
+    SSE_HIP(hipMemcpyAsync(ti.data(), s->w.Tn, ti.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    SSE_HIP(hipStreamSynchronize(s->stream));
+    rows_to_user(ti.data(), T, m->cell_old, L);
+    return SSE_OK;
+}
+
 extern "C" int sse_step_async(sse_state *s, int32_t n) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
+    if (s->p.tracer && !s->tracer_set) { set_error("tracer runs need sse_state_set_tracer before stepping"); return SSE_ESTATE; }
     if (n < 0) { set_error("n must be >= 0"); return SSE_EINVAL; }
     if (s->use_graph) {
         if (!s->graph_exec) {
@@ -1245,6 +1339,10 @@ extern "C" int sse_debug_thickness_stage(sse_state *s, const double *h_in, const
                                          double dt, double *h_out, double *zeta_out) {
     if (!s || !h_in || !u || !uA || !h_out || !zeta_out) { set_error("NULL argument"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("state not initialised (h_ref is needed)"); return SSE_ESTATE; }
+    if (s->p.tracer) {
+        set_error("the thickness-stage debug entry needs a state without tracer (tracer stages update the density)");
+        return SSE_EINVAL;
+    }
     const sse_mesh *m = s->mesh;
     const size_t L = s->p.n_layers, C = m->C, E = m->E;
     Work &w = s->w;
@@ -1411,6 +1509,7 @@ void batch_enqueue(const sse_batch *b) {
             case Kind::CONV_FD: launch_convert_batch<float, double>(bl<ConvArgs<float, double>>(b, op), g, st); break;
             case Kind::LAP: launch_lap_batch<R>(bl<LapArgs<R>>(b, op), op.nk, g, st); break;
             case Kind::DIV: launch_div_batch<R>(bl<DivArgs<R>>(b, op), op.nk, g, st); break;
+            case Kind::TRACER: launch_tracer_batch<R>(bl<TracerArgs<R>>(b, op), op.nk, g, st); break;
         }
     }
 }
@@ -1443,6 +1542,7 @@ extern "C" int sse_batch_destroy(sse_batch *b) {
 extern "C" int sse_batch_add(sse_batch *b, sse_state *s) {
     if (!b || !s) { set_error("NULL argument"); return SSE_EINVAL; }
     if (!s->initialized) { set_error("batch members must be initialised"); return SSE_ESTATE; }
+    if (s->p.tracer && !s->tracer_set) { set_error("tracer members need their temperature first"); return SSE_ESTATE; }
     if (s->batch) { set_error("state already belongs to a batch"); return SSE_ESTATE; }
     if (s->stream != b->stream) { set_error("batch members must use the batch's stream"); return SSE_EINVAL; }
     if (!b->members.empty()) {

@@ -158,6 +158,29 @@ struct THIsoArgs {
     int *nonfinite;
 };
 
+// Thickness stage fused with the tracer (temperature) stage: the per-layer
+// fluxes h_e v and h_e T_e v of the stage velocity v = c1 X1 + c2 X2 + ca1 a1
+// + u^A give the new thickness (z-star: the distributed column total;
+// isopycnal: per layer), the stage's w, and the new tracer content; T = hT/h,
+// rho = rho0 (1 - alpha (T - T_ref)), zeta = sum h - H.
+template <typename R>
+struct TracerArgs {
+    DevMesh m;
+    int L;
+    const double *h_in, *h_n;      // stage input thickness, base of the combination
+    const double *T_in, *T_n;      // stage input temperature, base of the combination
+    const R *X1, *X2;
+    double c1, c2;
+    const double *a1;
+    double ca1;
+    const double *uA;
+    const double *frac;            // z-star fractions; null for isopycnal
+    int comb;
+    double dt, kappa_h, kappa_v, rho0, alpha, tref;
+    double *h_out, *zeta_out, *T_out, *rho_out;
+    int *nonfinite;
+};
+
 // Reconciliation deficits (Section 3.4) on edges.
 struct ReconArgs {
     DevMesh m;
@@ -211,6 +234,7 @@ int bt_blocks(int E, int C, const Geom &g);
 template <typename R> void launch_fe_cell(const FECellArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s);
+template <typename R> void launch_tracer(const TracerArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s);
 // LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
@@ -245,6 +269,7 @@ struct BatchLaunch {
 template <typename R> void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s);
 template <typename R> void launch_lap_batch(const BatchLaunch<LapArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
+template <typename R> void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 // Template variant of the edge pass: bit 0 canonical stencils with vertex
 // chains (mesh), bit 1 implicit vertical mixing, bit 2 biharmonic viscosity

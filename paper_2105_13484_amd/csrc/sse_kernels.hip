@@ -1236,6 +1236,112 @@ __device__ __forceinline__ void thickness_body(const THArgs &a, int col) {
     if (bad && a.nonfinite) *a.nonfinite = 1;
 }
 
+// Thickness stage fused with the temperature tracer stage (tracer runs).
+template <int NK, typename R>
+__device__ __forceinline__ void tracer_body(const TracerArgs<R> &a, int col) {
+    const int lane = lane_id();
+    const DevMesh &m = a.m;
+    const int i = col;
+    if (i >= m.C) return;
+    const int L = a.L;
+    const size_t base = (size_t)i * L;
+    const bool wet = m.cmask[i] != 0;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    double hi[NK], Ti[NK], dhv[NK], dhtv[NK], dif[NK];
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const double h = a.h_in[base + kk[c]], t = a.T_in[base + kk[c]];
+        hi[c] = ok[c] ? h : 0.0;
+        Ti[c] = ok[c] ? t : 0.0;
+        dhv[c] = dhtv[c] = dif[c] = 0.0;
+    }
+    if (wet) {
+        // padded slots carry zero coefficients
+#pragma unroll
+        for (int j = 0; j < kMaxEdges; ++j) {
+            const int e = m.cell_edges[i * kMaxEdges + j];
+            const int nb = m.cell_nbrs[i * kMaxEdges + j];
+            const double cd = m.cell_div[i * kMaxEdges + j];
+            const double ae = (a.a1 ? a.ca1 * a.a1[e] : 0.0) + (a.uA ? a.uA[e] : 0.0);
+            const double ew = m.emask[e] ? 1.0 : 0.0;
+            // (T_c2 - T_c1) / d_e seen from this cell
+            const double gs = (m.edge_cells[2 * e] == i ? 1.0 : -1.0) * m.inv_dc[e];
+            const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
+#pragma unroll
+            for (int c = 0; c < NK; ++c) {
+                const int k = kk[c];
+                const double x1 = (double)a.X1[eb + k], x2 = a.X2 ? (double)a.X2[eb + k] : 0.0;
+                const double hn = a.h_in[nbb + k], tn = a.T_in[nbb + k];
+                // lanes past the last layer loaded layer L - 1: they carry no flux
+                const double on = ok[c] ? ew : 0.0;
+                const double u = on * (a.c1 * x1 + a.c2 * x2 + ae);
+                const double he = 0.5 * (hi[c] + hn), te = 0.5 * (Ti[c] + tn);
+                dhv[c] += cd * (he * u);
+                dhtv[c] += cd * (he * te * u);
+                dif[c] += cd * (on * (he * a.kappa_h * ((tn - Ti[c]) * gs)));
+            }
+        }
+    }
+    // thickness tendency and w at the top of every layer
+    double th[NK], w[NK];
+    if (a.frac) {
+        const double tot = col_sum<NK>(dhv);
+        double src[NK];
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            th[c] = ok[c] ? -a.frac[base + kk[c]] * tot : 0.0;
+            src[c] = ok[c] ? (-dhv[c] - th[c]) : 0.0;
+        }
+        col_incl_suffix<NK>(src, w);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            th[c] = -dhv[c];
+            w[c] = 0.0;
+        }
+    }
+    // vertical fluxes at the interfaces: advective Tbar^t w and diffusive
+    // kappa_v (T_{k-1} - T_k) / hbar^t, zero at the surface and the bottom
+    double Tu[NK], hu[NK], fa[NK], fd[NK], fan[NK], fdn[NK];
+    col_up1<NK>(Ti, Tu);
+    col_up1<NK>(hi, hu);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        const bool inner = k >= 1 && k < L;
+        fa[c] = inner ? 0.5 * (Tu[c] + Ti[c]) * w[c] : 0.0;
+        fd[c] = inner ? a.kappa_v * ((Tu[c] - Ti[c]) / (0.5 * (hu[c] + hi[c]))) : 0.0;
+    }
+    col_down1<NK>(fa, fan);
+    col_down1<NK>(fd, fdn);
+    double hv[NK];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const int k = lane + c * kWave;
+        hv[c] = 0.0;
+        if (k < L) {
+            const double tend = wet ? (-dhtv[c] - (fa[c] - fan[c]) + dif[c] + (fd[c] - fdn[c])) : 0.0;
+            const double x = hi[c] + a.dt * (wet ? th[c] : 0.0);
+            const double xt = hi[c] * Ti[c] + a.dt * tend;
+            const double hb = a.comb != COMB_NONE ? a.h_n[base + k] : 0.0;
+            const double tb = a.comb != COMB_NONE ? a.h_n[base + k] * a.T_n[base + k] : 0.0;
+            hv[c] = combine<double>(a.comb, hb, x);
+            const double ht = combine<double>(a.comb, tb, xt);
+            const double T = wet ? ht / hv[c] : 0.0;
+            a.h_out[base + k] = hv[c];
+            a.T_out[base + k] = T;
+            a.rho_out[base + k] = a.rho0 * (1.0 - a.alpha * (T - a.tref));
+            bad |= !isfinite(hv[c]) || !isfinite(T);
+        }
+    }
+    const double s = col_sum<NK>(hv);
+    if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
+    if (bad && a.nonfinite) *a.nonfinite = 1;
+}
+
 // Thickness stage (isopycnal): per-layer flux divergence, w = 0.
 template <int NK, typename R>
 __device__ __forceinline__ void thickness_iso_body(const THIsoArgs<R> &a, int col) {
@@ -1459,6 +1565,14 @@ template <int NK, typename R>
 constexpr int edge_min_waves() { return NK != 1 ? 1 : (sizeof(R) == 8 ? 7 : 6); }
 
 template <int NK, typename R>
+__global__ void __launch_bounds__(1024) tracer_kernel(TracerArgs<R> a) { tracer_body<NK, R>(a, column_id(a.m.C)); }
+template <int NK, typename R>
+__global__ void __launch_bounds__(1024) tracer_batch(BatchLaunch<TracerArgs<R>> b) {
+    int2 t;
+    if (batch_entry(b.table, b.blocks, t)) tracer_body<NK, R>(b.args[t.x], batch_column(t.y));
+}
+
+template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) { lap_body<NK, R>(a, column_id(a.m.E)); }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
@@ -1627,6 +1741,18 @@ void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
             default: SSE_NK_ADD_V(NK2, ADD, 7, KERNEL, GRID, BLOCK, ARG); break;       \
         }                                                                              \
     } while (0)
+
+template <typename R>
+void launch_tracer(const TracerArgs<R> &a, const Geom &g, hipStream_t s) {
+    const dim3 grid = xcd_grid(col_blocks(a.m.C, g)), block = col_block(g);
+    if (a.L <= kWave) tracer_kernel<1, R><<<grid, block, 0, s>>>(a);
+    else tracer_kernel<2, R><<<grid, block, 0, s>>>(a);
+}
+template <typename R>
+void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> &b, int nk, const Geom &g, hipStream_t s) {
+    if (nk == 1) tracer_batch<1, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+    else tracer_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
+}
 
 template <typename R>
 void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s) {
@@ -1826,6 +1952,8 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template void launch_fe_cell<R>(const FECellArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_fe_vertex<R>(const FEVertexArgs<R> &, const Geom &, hipStream_t);                 \
     template void launch_lap<R>(const LapArgs<R> &, const Geom &, hipStream_t);                           \
+    template void launch_tracer<R>(const TracerArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_tracer_batch<R>(const BatchLaunch<TracerArgs<R>> &, int, const Geom &, hipStream_t); \
     template void launch_div<R>(const DivArgs<R> &, const Geom &, hipStream_t);                           \
     template void launch_lap_batch<R>(const BatchLaunch<LapArgs<R>> &, int, const Geom &, hipStream_t);  \
     template void launch_div_batch<R>(const BatchLaunch<DivArgs<R>> &, int, const Geom &, hipStream_t);  \

@@ -22,6 +22,7 @@ SSE_ZSTAR, SSE_ISOPYCNAL = 0, 1
 SSE_RECONCILE_OFF, SSE_RECONCILE_EXACT, SSE_RECONCILE_LITERAL = 0, 1, 2
 SSE_VMIX_EXPLICIT, SSE_VMIX_IMPLICIT = 0, 1
 SSE_HDIFF_DEL2, SSE_HDIFF_DEL4 = 0, 1
+SSE_TRACER_NONE, SSE_TRACER_TEMPERATURE = 0, 1
 PROF_CLASSES = ("fe_edge", "fe_cell", "fe_vertex", "bt_eval", "thickness", "other")
 
 EXPORTED = (
@@ -33,7 +34,7 @@ EXPORTED = (
     "sse_batch_create", "sse_batch_destroy", "sse_batch_add", "sse_batch_remove", "sse_batch_size",
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
     "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
-    "sse_state_set_bt_variant", "sse_state_get_bt_variant",
+    "sse_state_set_bt_variant", "sse_state_get_bt_variant", "sse_state_set_tracer", "sse_read_tracer",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -64,8 +65,10 @@ class sse_params(ctypes.Structure):
     _fields_ = [
         ("n_layers", c_int32), ("scheme", c_int32), ("substeps", c_int32), ("precision", c_int32),
         ("vcoord", c_int32), ("reconcile", c_int32), ("vmix", c_int32), ("hdiff", c_int32),
+        ("tracer", c_int32),
         ("dt", c_double), ("gravity", c_double), ("rho0", c_double), ("nu_h", c_double),
         ("nu_v", c_double), ("c_drag", c_double),
+        ("kappa_h", c_double), ("kappa_v", c_double), ("eos_alpha", c_double), ("eos_tref", c_double),
     ]
 
 
@@ -106,6 +109,8 @@ def load():
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_bt_variant": (c_int, [P, c_int]),
+        "sse_state_set_tracer": (c_int, [P, POINTER(c_double)]),
+        "sse_read_tracer": (c_int, [P, POINTER(c_double)]),
         "sse_state_get_bt_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_geometry": (c_int, [P, c_int, c_int]),
         "sse_state_use_graph": (c_int, [P, c_int]),
@@ -268,6 +273,16 @@ class DeviceState:
         _check(load().sse_state_init(self.handle, _dptr(h), _dptr(u), _dptr(rho),
                                      _dptr(hr) if hr is not None else None))
 
+    def set_tracer(self, T):
+        """Tracer runs: the layer temperature [C][L] (sets the density by the EOS)."""
+        T = _f64(T)
+        _check(load().sse_state_set_tracer(self.handle, _dptr(T)))
+
+    def read_tracer(self):
+        T = np.empty((self.mesh.C, self.L))
+        _check(load().sse_read_tracer(self.handle, _dptr(T)))
+        return T
+
     def step(self, n: int = 1) -> int:
         """Advance n steps; returns SSE_OK or SSE_ENONFINITE."""
         return _check(load().sse_step(self.handle, int(n)), allow=(SSE_ENONFINITE,))
@@ -378,6 +393,8 @@ def state_from_case(case, device="cuda", stream=None, params=None):
     dm = DeviceMesh(case.mesh, case.H, case.cell_mask, device=device, stream=stream)
     st = DeviceState(dm, params if params is not None else case.params, device=device, stream=stream)
     st.init(case.h, case.u, case.rho, case.h_ref)
+    if getattr(st.params, "tracer", 0):
+        st.set_tracer(case.temp)
     return dm, st
 
 
