@@ -16,10 +16,14 @@ Primitive Equations" (arXiv 2105.13484).
                    opening); this module states the standard TRiSK forms.
 * ``layered``   -- the layered equations of Section 2 (vertical operators,
                    hydrostatic pressure, z-star vertical velocity, the
-                   groupings T^u, D^u, T^h, the split BBspl).
-* ``ssprk_se``  -- Section 3: Algorithm 1 (Baroclinic_FEuler), Algorithms 3
-                   and 4 (barotropic SSPRK2/3 substepping), Interp_2 /
-                   Interp_3, the SSPRK2-SE and SSPRK3-SE steps and the
+                   groupings T^u, D^u, T^h, the split BBspl, the Laplacian or
+                   biharmonic horizontal viscosity, the tracer equation and
+                   the linear EOS) and the vertical diffusion solve of
+                   Algorithm 2.
+* ``ssprk_se``  -- Section 3: Algorithms 1 and 2 (Baroclinic_FEuler and its
+                   vertical-mixing form), Algorithms 3 and 4 (barotropic
+                   SSPRK2/3 substepping), Interp_2 / Interp_3, the SSPRK2-SE
+                   and SSPRK3-SE steps with the tracer stages, and the
                    flux-form SSH reconciliation of Section 3.4.
 
 Everything is FP64 NumPy with whole-array operations; column sums over the
@@ -28,7 +32,7 @@ layers use a fixed pairwise order (``layered.colsum``).
 Parity unpinned: the discrete forms of the nonlinear terms (pressure gradient
 in tilted layers, z-star vertical velocity, vertical boundary conditions,
 vorticity flux, barotropic (zeta + H) at edges) are fixed only by the readings
-listed in the repository's design notes, not by any number in the paper.
+stated in the docstrings of these modules, not by any number in the paper.
 They are pinned indirectly (conservation, lake at rest, closed forms on
 uniform flows, convergence order), not value by value.
 """
