@@ -290,7 +290,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the step would shard by horizontal domain decomposition with whole columns and halo exchanges).",
               file=sys.stderr)
         sys.exit(2)
