@@ -5,7 +5,8 @@
 // second register chunk).  Mesh indices are therefore wave-uniform (scalar
 // loads) and every neighbour access is one contiguous column read; vertical
 // sums and scans are cross-lane operations inside the wavefront.  Lanes past
-// the last layer carry zeros so that sums and scans need no masking.
+// the last layer load a copy of the last layer; what they hold is zeroed
+// before it reaches a sum or a scan over the layers.
 //
 // 2D kernels (barotropic loop, reconciliation): one thread per edge or cell,
 // reading slot-major neighbour tables.
@@ -46,106 +47,206 @@ __device__ __forceinline__ int column_id(int n) {
     return __builtin_amdgcn_readfirstlane(lb < 0 ? n : col);
 }
 
+// ---------------------------------------------------------------------------
+// Cross-lane operations of a column; every caller runs them with all 64
+// lanes active.  Two forms, chosen by the kernel (kDpp):
+//  * DPP: values move inside rows of 16 lanes, and by one lane across the
+//    wavefront, as DPP operands, with no LDS round trip and no wait.  An FP32
+//    step is one instruction (the move folds into the addition); an FP64
+//    step takes two moves besides the addition.
+//  * shuffles: lane permutes through the LDS crossbar, fewer VALU
+//    instructions for FP64 values.
+// The FP32 (mixed-precision) kernels use DPP for every value type; the FP64
+// kernels, with no VALU and register headroom, use shuffles.  The butterfly
+// steps that cross rows (i ^ 32, i ^ 16) are shuffles in both forms.
+// ---------------------------------------------------------------------------
+template <typename R>
+constexpr bool kDppFor = sizeof(R) == 4;
+
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppRowShl = 0x100;       // + n: lane j of a row reads lane j + n of the row
+constexpr int kDppRowShr = 0x110;       // + n: lane j of a row reads lane j - n of the row
+constexpr int kDppRowRor = 0x120;       // + n: rotation within a row
+constexpr int kDppWaveShl1 = 0x130;     // lane i reads lane i + 1
+constexpr int kDppWaveShr1 = 0x138;     // lane i reads lane i - 1
+constexpr int kDppRowBcast15 = 0x142;   // lane 15 of a row to the lanes of the next row
+constexpr int kDppRowBcast31 = 0x143;   // lane 31 to the lanes of rows 2 and 3
+
+// Lane i receives x from the lane the control names; lanes without a source
+// lane, and rows outside kRowMask, receive `old`.
+template <int kCtrl, int kRowMask = 0xF, typename T>
+__device__ __forceinline__ T dpp(T old, T x) {
+    return __builtin_amdgcn_update_dpp(old, x, kCtrl, kRowMask, 0xF, false);
+}
+
+// x of lane l, as a wave-uniform value
 template <typename T>
+__device__ __forceinline__ T lane_value(T x, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, l);
+        const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+    }
+}
+
+// Sum over the 64 lanes as a butterfly: every lane adds the value of lane
+// i ^ 32, then i ^ 16, i ^ 8, i ^ 4, i ^ 2, i ^ 1; the result is the pairwise
+// halving sum, the same bits in both forms.  (DPP: after the i ^ 8 step the
+// values repeat with period 8 inside a row, so the rotation by 4 hands every
+// lane the value of lane i ^ 4.)
+template <bool kDpp, typename T>
 __device__ __forceinline__ T wave_sum(T x) {
+    if constexpr (!kDpp) {
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return __shfl(x, 0, kWave);  // one value for the whole column
+        for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+        return __shfl(x, 0, kWave);  // one value for the whole column
+    } else {
+        x += __shfl_xor(x, 32, kWave);
+        x += __shfl_xor(x, 16, kWave);
+        x += dpp<kDppRowRor + 8>(T(0), x);
+        x += dpp<kDppRowRor + 4>(T(0), x);
+        x += dpp<kDppQuadXor2>(T(0), x);
+        x += dpp<kDppQuadXor1>(T(0), x);
+        return lane_value(x, 0);
+    }
 }
 
-template <typename T>
+// Inclusive scan over the lanes.  DPP: steps of 1, 2, 4, 8 inside each row,
+// then the row totals carried into the rows after them.
+template <bool kDpp, typename T>
 __device__ __forceinline__ T wave_incl_prefix(T x) {
-    const int l = lane_id();
+    if constexpr (!kDpp) {
+        const int l = lane_id();
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T y = __shfl_up(x, d, kWave);
-        if (l >= d) x += y;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const T y = __shfl_up(x, d, kWave);
+            if (l >= d) x += y;
+        }
+    } else {
+        x += dpp<kDppRowShr + 1>(T(0), x);
+        x += dpp<kDppRowShr + 2>(T(0), x);
+        x += dpp<kDppRowShr + 4>(T(0), x);
+        x += dpp<kDppRowShr + 8>(T(0), x);
+        x += dpp<kDppRowBcast15, 0xA>(T(0), x);
+        x += dpp<kDppRowBcast31, 0xC>(T(0), x);
     }
     return x;
 }
 
-template <typename T>
+// Inclusive suffix scan.  DPP: steps of 1, 2, 4, 8 inside each row, after
+// which lane 16 r holds the total t_r of row r; row 0 then adds
+// t1 + (t2 + t3), row 1 t2 + t3, row 2 t3.
+template <bool kDpp, typename T>
 __device__ __forceinline__ T wave_incl_suffix(T x) {
-    const int l = lane_id();
+    if constexpr (!kDpp) {
+        const int l = lane_id();
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T y = __shfl_down(x, d, kWave);
-        if (l + d < kWave) x += y;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const T y = __shfl_down(x, d, kWave);
+            if (l + d < kWave) x += y;
+        }
+        return x;
+    } else {
+        x += dpp<kDppRowShl + 1>(T(0), x);
+        x += dpp<kDppRowShl + 2>(T(0), x);
+        x += dpp<kDppRowShl + 4>(T(0), x);
+        x += dpp<kDppRowShl + 8>(T(0), x);
+        const T t3 = lane_value(x, 48);
+        const T t23 = lane_value(x, 32) + t3;
+        const T t123 = lane_value(x, 16) + t23;
+        const int row = lane_id() >> 4;
+        const T add = row == 0 ? t123 : row == 1 ? t23 : row == 2 ? t3 : T(0);
+        return x + add;
     }
-    return x;
 }
 
-// Sum over the layers: per-lane chunks first, then a butterfly whose result
+// v of lane i - 1 (lane 0: fill) and of lane i + 1 (lane 63: fill)
+template <bool kDpp, typename T>
+__device__ __forceinline__ T lane_prev(T fill, T v) {
+    if constexpr (!kDpp) {
+        const T y = __shfl_up(v, 1, kWave);
+        return lane_id() == 0 ? fill : y;
+    } else {
+        return dpp<kDppWaveShr1>(fill, v);
+    }
+}
+template <bool kDpp, typename T>
+__device__ __forceinline__ T lane_next(T fill, T v) {
+    if constexpr (!kDpp) {
+        const T y = __shfl_down(v, 1, kWave);
+        return lane_id() == kWave - 1 ? fill : y;
+    } else {
+        return dpp<kDppWaveShl1>(fill, v);
+    }
+}
+
+// Sum over the layers: per-lane chunks first, then the butterfly; the result
 // is the pairwise (halving) sum over the layers padded to 128.
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ T col_sum(const T (&v)[NK]) {
     T s = v[0];
 #pragma unroll
     for (int c = 1; c < NK; ++c) s += v[c];
-    return wave_sum(s);
+    return wave_sum<kDpp>(s);
 }
 
 // o_k = sum_{l<k} v_l
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ void col_excl_prefix(const T (&v)[NK], T (&o)[NK]) {
-    const int l = lane_id();
     T carry = T(0);
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        T inc = wave_incl_prefix(v[c]);
-        T exc = __shfl_up(inc, 1, kWave);
-        o[c] = (l == 0 ? T(0) : exc) + carry;
-        carry += __shfl(inc, kWave - 1, kWave);
+        const T inc = wave_incl_prefix<kDpp>(v[c]);
+        o[c] = lane_prev<kDpp>(T(0), inc) + carry;
+        if (c + 1 < NK) carry += __shfl(inc, kWave - 1, kWave);
     }
 }
 
 // o_k = sum_{l>k} v_l
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ void col_excl_suffix(const T (&v)[NK], T (&o)[NK]) {
-    const int l = lane_id();
     T carry = T(0);
 #pragma unroll
     for (int c = NK - 1; c >= 0; --c) {
-        T inc = wave_incl_suffix(v[c]);
-        T exc = __shfl_down(inc, 1, kWave);
-        o[c] = (l == kWave - 1 ? T(0) : exc) + carry;
-        carry += __shfl(inc, 0, kWave);
+        const T inc = wave_incl_suffix<kDpp>(v[c]);
+        o[c] = lane_next<kDpp>(T(0), inc) + carry;
+        if (c > 0) carry += __shfl(inc, 0, kWave);
     }
 }
 
 // o_k = sum_{l>=k} v_l
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ void col_incl_suffix(const T (&v)[NK], T (&o)[NK]) {
     T carry = T(0);
 #pragma unroll
     for (int c = NK - 1; c >= 0; --c) {
-        T inc = wave_incl_suffix(v[c]);
+        const T inc = wave_incl_suffix<kDpp>(v[c]);
         o[c] = inc + carry;
-        carry += __shfl(inc, 0, kWave);
+        if (c > 0) carry += __shfl(inc, 0, kWave);
     }
 }
 
 // o_k = v_{k-1}, o_0 = 0
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ void col_up1(const T (&v)[NK], T (&o)[NK]) {
-    const int l = lane_id();
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        T prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : T(0);
-        T y = __shfl_up(v[c], 1, kWave);
-        o[c] = (l == 0) ? prev_last : y;
+        const T prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : T(0);
+        o[c] = lane_prev<kDpp>(prev_last, v[c]);
     }
 }
 
 // o_k = v_{k+1}; zero past the last layer (lanes past L hold zeros)
-template <int NK, typename T>
+template <int NK, bool kDpp = false, typename T>
 __device__ __forceinline__ void col_down1(const T (&v)[NK], T (&o)[NK]) {
-    const int l = lane_id();
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        T next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : T(0);
-        T y = __shfl_down(v[c], 1, kWave);
-        o[c] = (l == kWave - 1) ? next_first : y;
+        const T next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : T(0);
+        o[c] = lane_next<kDpp>(next_first, v[c]);
     }
 }
 
@@ -240,9 +341,10 @@ __device__ __forceinline__ T combine(int mode, T b, T x) {
 }
 
 // Lane k holds layer k (chunk c: layer k + 64 c).  Lanes past the last layer
-// load layer L - 1 (always in bounds) and zero what they loaded, so loads are
-// never predicated: no branches split the load stream and all loads of a
-// stencil can be in flight together.
+// load layer L - 1 (always in bounds), so loads are never predicated: no
+// branches split the load stream and all loads of a stencil can be in flight
+// together.  What those lanes loaded is zeroed where it can reach a sum or a
+// scan over the layers; elsewhere it only feeds results that are not stored.
 template <int NK>
 __device__ __forceinline__ void lane_layers(int L, int (&kk)[NK], bool (&ok)[NK]) {
     const int lane = lane_id();
@@ -252,6 +354,33 @@ __device__ __forceinline__ void lane_layers(int L, int (&kk)[NK], bool (&ok)[NK]
         ok[c] = k < L;
         kk[c] = ok[c] ? k : L - 1;
     }
+}
+
+// Column access.  `col` is the first layer of a column and must be
+// wave-uniform; the lane reads or writes layer k.  The address is a scalar
+// base plus a 32-bit lane offset, a form the load and store instructions take
+// directly, so the columns of a stencil share one offset register and need no
+// 64-bit address arithmetic per lane (where scalar registers run short, the
+// compiler still forms some of the addresses in vector registers).  Measured
+// on the C1 edge pass: 6% faster than per-lane 64-bit addresses.
+typedef __attribute__((address_space(1))) char global_char;
+
+template <typename T>
+__device__ __forceinline__ global_char *uniform_global(const T *col) {
+    const unsigned long long p = reinterpret_cast<unsigned long long>(col);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)p);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(p >> 32));
+    return (global_char *)(((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T col_ld(const T *col, int k) {
+    return *(const __attribute__((address_space(1))) T *)(uniform_global(col) + (unsigned)k * (unsigned)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void col_st(T *col, int k, T v) {
+    *(__attribute__((address_space(1))) T *)(uniform_global(col) + (unsigned)k * (unsigned)sizeof(T)) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +412,7 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
     R divhu[NK], divu[NK], K[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        hi[c] = a.h[base + kk[c]];
+        hi[c] = col_ld(a.h + base, kk[c]);
         divhu[c] = divu[c] = K[c] = R(0);
     }
     // Padded slots hold a valid index with zero coefficients, so the stencil
@@ -298,8 +427,8 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
         const size_t eb = (size_t)e * L, nbb = (size_t)nb * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const R x = a.X[eb + kk[c]];
-            const double hn = a.h[nbb + kk[c]];
+            const R x = col_ld(a.X + eb, kk[c]);
+            const double hn = col_ld(a.h + nbb, kk[c]);
             const R u = ok[c] ? x + add : R(0);
             const R he = (R)(0.5 * (hi[c] + hn));
             divhu[c] += cd * (he * u);
@@ -310,14 +439,14 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
     R w[NK];
     if (a.frac) {
         // z-star: T^h_k = -frac_k sum_l div(h u)_l, and w_k - w_{k+1} = -div_k - T^h_k
-        const R tot = col_sum<NK>(divhu);
+        const R tot = col_sum<NK, kDppFor<R>>(divhu);
         R src[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const R th = -(R)a.frac[base + kk[c]] * tot;
+            const R th = -(R)col_ld(a.frac + base, kk[c]) * tot;
             src[c] = ok[c] ? (-divhu[c] - th) : R(0);
         }
-        col_incl_suffix<NK>(src, w);
+        col_incl_suffix<NK, kDppFor<R>>(src, w);
     } else {
 #pragma unroll
         for (int c = 0; c < NK; ++c) w[c] = R(0);
@@ -325,9 +454,9 @@ __device__ __forceinline__ void fe_cell_body(const FECellArgs<R> &a, int col) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         if (ok[c]) {
-            a.B[base + kk[c]] = K[c] - (R)a.nu_h * divu[c];
-            if (a.D1) a.D1[base + kk[c]] = divu[c];
-            a.Wtop[base + kk[c]] = w[c];
+            col_st(a.B + base, kk[c], K[c] - (R)a.nu_h * divu[c]);
+            if (a.D1) col_st(a.D1 + base, kk[c], divu[c]);
+            col_st(a.Wtop + base, kk[c], w[c]);
             if (kk[c] == L - 1) a.Kbot[i] = (double)K[c];
         }
     }
@@ -355,11 +484,11 @@ __device__ __forceinline__ void fe_vertex_body(const FEVertexArgs<R> &a, int col
         const R add = kAdd ? (R)a.ubar_add[e] : R(0);
         const size_t eb = (size_t)e * L;
 #pragma unroll
-        for (int c = 0; c < NK; ++c) z[c] += cr * (a.X[eb + kk[c]] + add);
+        for (int c = 0; c < NK; ++c) z[c] += cr * (col_ld(a.X + eb, kk[c]) + add);
     }
 #pragma unroll
     for (int c = 0; c < NK; ++c)
-        if (ok[c]) a.Z[(size_t)v * L + kk[c]] = z[c];
+        if (ok[c]) col_st(a.Z + (size_t)v * L, kk[c], z[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,11 +565,17 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
     const DevMesh &m = a.m;
     const int L = a.L;
     const size_t base = (size_t)e * L;
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
+    // Operands of lanes past the last layer are copies of layer L - 1; the
+    // edge thickness and the PGF differences, which reach the column sums and
+    // scans, are zeroed there.
     R he[NK];
     double hed[NK];
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        hed[c] = 0.5 * (o.h1[c] + o.h2[c]);
+        hed[c] = ok[c] ? 0.5 * (o.h1[c] + o.h2[c]) : 0.0;
         he[c] = (R)hed[c];
     }
     // Pressure gradient in z-star layers from the column differences, in FP64
@@ -450,11 +585,11 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
         double drh[NK], dh[NK], sp[NK], ss[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            drh[c] = o.r2[c] * o.h2[c] - o.r1[c] * o.h1[c];
-            dh[c] = o.h2[c] - o.h1[c];
+            drh[c] = ok[c] ? o.r2[c] * o.h2[c] - o.r1[c] * o.h1[c] : 0.0;
+            dh[c] = ok[c] ? o.h2[c] - o.h1[c] : 0.0;
         }
-        col_excl_prefix<NK>(drh, sp);
-        col_excl_suffix<NK>(dh, ss);
+        col_excl_prefix<NK, kDppFor<R>>(drh, sp);
+        col_excl_suffix<NK, kDppFor<R>>(dh, ss);
         const double dH = m.H[c2] - m.H[c1];
         const double pgf_scale = idc / a.rho0;
 #pragma unroll
@@ -467,8 +602,8 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
 
     // Vertical advection and vertical viscosity at interior interfaces.
     R uu[NK], hu[NK], at[NK], tau[NK], atn[NK], taun[NK];
-    col_up1<NK>(o.u, uu);
-    col_up1<NK>(he, hu);
+    col_up1<NK, kDppFor<R>>(o.u, uu);
+    col_up1<NK, kDppFor<R>>(he, hu);
     const R nu_v = (R)a.nu_v;
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
@@ -483,8 +618,8 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
             tau[c] = R(0);
         }
     }
-    col_down1<NK>(at, atn);
-    col_down1<NK>(tau, taun);
+    col_down1<NK, kDppFor<R>>(at, atn);
+    col_down1<NK, kDppFor<R>>(tau, taun);
     const R speed = (R)sqrt(a.Kbot[c1] + a.Kbot[c2]);
     const R gz = (R)(a.g * (a.zeta[c2] - a.zeta[c1]) * idc);
     const R dt = (R)a.dt, nu_h = (R)a.nu_h, c_drag = (R)a.c_drag;
@@ -511,8 +646,8 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
     }
     // Column sums that feed the barotropic forcing and the reconciliation are
     // formed in FP64 in both modes.
-    const double Sh = col_sum<NK>(hed);
-    const double G = col_sum<NK>(hut1) / Sh / a.dt;
+    const double Sh = col_sum<NK, kDppFor<R>>(hed);
+    const double G = col_sum<NK, kDppFor<R>>(hut1) / Sh / a.dt;
     const R dtG = (R)(a.dt * G);
     R x[NK];
 #pragma unroll
@@ -527,7 +662,7 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
             const int k = lane + c * kWave;
             Aup[c] = (k >= 1 && k < L) ? nu_v / (R(0.5) * (hu[c] + he[c])) : R(0);
         }
-        col_down1<NK>(Aup, Adn);
+        col_down1<NK, kDppFor<R>>(Aup, Adn);
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const int k = lane + c * kWave;
@@ -548,14 +683,18 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
-        const R utn = (a.Un && k < L) ? (R)((double)a.Un[base + k] - ubn) : R(0);
+        R utn = R(0);
+        if (a.Un) {
+            const double un = (double)col_ld(a.Un + base, kk[c]);
+            utn = k < L ? (R)(un - ubn) : R(0);
+        }
         outv[c] = (k < L) ? combine<R>(a.comb, utn, x[c]) : R(0);
-        if (k < L) a.out[base + k] = outv[c];
+        if (k < L) col_st(a.out + base, k, outv[c]);
         hp[c] = hed[c] * (a.psum_a * (double)utn + a.psum_b * (double)outv[c]);
     }
     double shu = 0.0, shp = 0.0;
-    if (a.sum_hu) shu = col_sum<NK>(hu_in);
-    if (a.sum_hp) shp = col_sum<NK>(hp);
+    if (a.sum_hu) shu = col_sum<NK, kDppFor<R>>(hu_in);
+    if (a.sum_hp) shp = col_sum<NK, kDppFor<R>>(hp);
     if (lane == 0) {
         a.G[e] = G;
         a.sum_h[e] = Sh;
@@ -629,21 +768,15 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     if constexpr (kChain) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            const size_t vb = (size_t)rec[10 + i] * L;
+            const R *zc = a.Z + (size_t)rec[10 + i] * L;
 #pragma unroll
-            for (int c = 0; c < NK; ++c) {
-                const R z = a.Z[vb + kk[c]];
-                zA[i][c] = ok[c] ? z : R(0);
-            }
+            for (int c = 0; c < NK; ++c) zA[i][c] = col_ld(zc, kk[c]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const size_t vb = (size_t)rec[16 + i] * L;
+            const R *zc = a.Z + (size_t)rec[16 + i] * L;
 #pragma unroll
-            for (int c = 0; c < NK; ++c) {
-                const R z = a.Z[vb + kk[c]];
-                zB[i][c] = ok[c] ? z : R(0);
-            }
+            for (int c = 0; c < NK; ++c) zB[i][c] = col_ld(zc, kk[c]);
         }
     }
     const bool a0_is_v1 = kChain ? rec[20] != 0 : false;
@@ -652,29 +785,27 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = kk[c];
-        const R x = a.X[base + k];
-        const double h1 = a.h[b1 + k], h2 = a.h[b2 + k], r1 = a.rho[b1 + k], r2 = a.rho[b2 + k];
-        const R B1 = a.B[b1 + k], B2 = a.B[b2 + k], W1 = a.Wtop[b1 + k], W2 = a.Wtop[b2 + k];
+        const R x = col_ld(a.X + base, k);
         R za, zb;
         if constexpr (kChain) {
             za = a0_is_v1 ? zA[0][c] : zA[5][c];
             zb = a0_is_v1 ? zA[5][c] : zA[0][c];
         } else {
-            za = a.Z[bv1 + k];
-            zb = a.Z[bv2 + k];
+            za = col_ld(a.Z + bv1, k);
+            zb = col_ld(a.Z + bv2, k);
         }
-        o.u[c] = ok[c] ? (kAdd ? x + ub_e : x) : R(0);
-        o.ut[c] = ok[c] ? (kAdd ? x : x - ub_e) : R(0);
-        o.h1[c] = ok[c] ? h1 : 0.0;
-        o.h2[c] = ok[c] ? h2 : 0.0;
-        o.r1[c] = ok[c] ? r1 : 0.0;
-        o.r2[c] = ok[c] ? r2 : 0.0;
-        o.za[c] = ok[c] ? za : R(0);
-        o.zb[c] = ok[c] ? zb : R(0);
-        o.B1[c] = ok[c] ? B1 : R(0);
-        o.B2[c] = ok[c] ? B2 : R(0);
-        o.W1[c] = ok[c] ? W1 : R(0);
-        o.W2[c] = ok[c] ? W2 : R(0);
+        o.u[c] = kAdd ? x + ub_e : x;
+        o.ut[c] = kAdd ? x : x - ub_e;
+        o.h1[c] = col_ld(a.h + b1, k);
+        o.h2[c] = col_ld(a.h + b2, k);
+        o.r1[c] = col_ld(a.rho + b1, k);
+        o.r2[c] = col_ld(a.rho + b2, k);
+        o.za[c] = za;
+        o.zb[c] = zb;
+        o.B1[c] = col_ld(a.B + b1, k);
+        o.B2[c] = col_ld(a.B + b2, k);
+        o.W1[c] = col_ld(a.Wtop + b1, k);
+        o.W2[c] = col_ld(a.Wtop + b2, k);
         q[c] = R(0.5) * (o.za[c] + o.zb[c]);
         o.cor[c] = o.vor[c] = R(0);
         o.lap2[c] = R(0);
@@ -688,8 +819,9 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const int k = kk[c];
-            const R d1 = a.D2[b1 + k], d2 = a.D2[b2 + k], z1 = a.Z2[w1 + k], z2 = a.Z2[w2 + k];
-            o.lap2[c] = ok[c] ? (d2 - d1) * (R)idc - (z2 - z1) * (R)idv : R(0);
+            const R d1 = col_ld(a.D2 + b1, k), d2 = col_ld(a.D2 + b2, k);
+            const R z1 = col_ld(a.Z2 + w1, k), z2 = col_ld(a.Z2 + w2, k);
+            o.lap2[c] = (d2 - d1) * (R)idc - (z2 - z1) * (R)idv;
         }
     }
 
@@ -708,7 +840,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
         const size_t pb2 = kChain ? 0 : (size_t)rec[11 + 2 * j] * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const R xp = a.X[pb + kk[c]];
+            const R xp = col_ld(a.X + pb, kk[c]);
             const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
             R qp;
             if constexpr (kChain) {
@@ -718,7 +850,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
                 const R zb_ = j < 5 ? zA[j < 5 ? j + 1 : 0][c] : (s == 4 ? zA[0][c] : zB[s < 4 && s >= 0 ? s : 0][c]);
                 qp = R(0.5) * (za_ + zb_);
             } else {
-                qp = R(0.5) * (a.Z[pb1 + kk[c]] + a.Z[pb2 + kk[c]]);
+                qp = R(0.5) * (col_ld(a.Z + pb1, kk[c]) + col_ld(a.Z + pb2, kk[c]));
             }
             o.cor[c] += wfj * utp;
             o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
@@ -1287,14 +1419,14 @@ __device__ __forceinline__ void tracer_body(const TracerArgs<R> &a, int col) {
     // thickness tendency and w at the top of every layer
     double th[NK], w[NK];
     if (a.frac) {
-        const double tot = col_sum<NK>(dhv);
+        const double tot = col_sum<NK, kDppFor<R>>(dhv);
         double src[NK];
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             th[c] = ok[c] ? -a.frac[base + kk[c]] * tot : 0.0;
             src[c] = ok[c] ? (-dhv[c] - th[c]) : 0.0;
         }
-        col_incl_suffix<NK>(src, w);
+        col_incl_suffix<NK, kDppFor<R>>(src, w);
     } else {
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
@@ -1305,8 +1437,8 @@ __device__ __forceinline__ void tracer_body(const TracerArgs<R> &a, int col) {
     // vertical fluxes at the interfaces: advective Tbar^t w and diffusive
     // kappa_v (T_{k-1} - T_k) / hbar^t, zero at the surface and the bottom
     double Tu[NK], hu[NK], fa[NK], fd[NK], fan[NK], fdn[NK];
-    col_up1<NK>(Ti, Tu);
-    col_up1<NK>(hi, hu);
+    col_up1<NK, kDppFor<R>>(Ti, Tu);
+    col_up1<NK, kDppFor<R>>(hi, hu);
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = lane + c * kWave;
@@ -1314,8 +1446,8 @@ __device__ __forceinline__ void tracer_body(const TracerArgs<R> &a, int col) {
         fa[c] = inner ? 0.5 * (Tu[c] + Ti[c]) * w[c] : 0.0;
         fd[c] = inner ? a.kappa_v * ((Tu[c] - Ti[c]) / (0.5 * (hu[c] + hi[c]))) : 0.0;
     }
-    col_down1<NK>(fa, fan);
-    col_down1<NK>(fd, fdn);
+    col_down1<NK, kDppFor<R>>(fa, fan);
+    col_down1<NK, kDppFor<R>>(fd, fdn);
     double hv[NK];
     bool bad = false;
 #pragma unroll
@@ -1337,7 +1469,7 @@ __device__ __forceinline__ void tracer_body(const TracerArgs<R> &a, int col) {
             bad |= !isfinite(hv[c]) || !isfinite(T);
         }
     }
-    const double s = col_sum<NK>(hv);
+    const double s = col_sum<NK, kDppFor<R>>(hv);
     if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
     if (bad && a.nonfinite) *a.nonfinite = 1;
 }
@@ -1393,7 +1525,7 @@ __device__ __forceinline__ void thickness_iso_body(const THIsoArgs<R> &a, int co
             bad |= !isfinite(hv[c]);
         }
     }
-    const double s = col_sum<NK>(hv);
+    const double s = col_sum<NK, kDppFor<R>>(hv);
     if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
     if (bad && a.nonfinite) *a.nonfinite = 1;
 }
