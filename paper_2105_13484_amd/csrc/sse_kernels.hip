@@ -1341,27 +1341,30 @@ __device__ __forceinline__ void thickness_body(const THArgs &a, int col) {
     if (i >= m.C) return;
     const int L = a.L;
     const size_t base = (size_t)i * L;
-    double divF = 0.0;
     const bool wet = m.cmask[i] != 0;
+    // Padded stencil slots hold a valid edge with a zero coefficient, so the
+    // sum runs its full width and all its loads are in flight together.
+    double divF = 0.0;
     if (wet) {
-        const int n = m.cell_nedges[i];
-        for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int j = 0; j < kMaxEdges; ++j)
             divF += m.cell_div[i * kMaxEdges + j] * a.Ftot[m.cell_edges[i * kMaxEdges + j]];
     }
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
     double hv[NK];
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        hv[c] = 0.0;
-        if (k < L) {
-            double th = wet ? -a.frac[base + k] * divF : 0.0;
-            double x = a.h_in[base + k] + a.dt * th;
-            double b = (a.comb != COMB_NONE) ? a.h_n[base + k] : 0.0;
-            hv[c] = combine<double>(a.comb, b, x);
-            a.h_out[base + k] = hv[c];
-            bad |= !isfinite(hv[c]);
-        }
+        const double fr = col_ld(a.frac + base, kk[c]);
+        const double hin = col_ld(a.h_in + base, kk[c]);
+        const double b = (a.comb != COMB_NONE) ? col_ld(a.h_n + base, kk[c]) : 0.0;
+        const double th = wet ? -fr * divF : 0.0;
+        const double x = hin + a.dt * th;
+        hv[c] = ok[c] ? combine<double>(a.comb, b, x) : 0.0;
+        if (ok[c]) col_st(a.h_out + base, kk[c], hv[c]);
+        bad |= ok[c] && !isfinite(hv[c]);
     }
     const double s = col_sum<NK>(hv);
     if (lane == 0) a.zeta_out[i] = wet ? s - m.H[i] : 0.0;
@@ -1585,19 +1588,20 @@ __device__ __forceinline__ void assemble_body(const AssembleArgs<R> &a, int col)
     const bool wet = m.emask[e] != 0;
     const int c1 = m.edge_cells[2 * e], c2 = m.edge_cells[2 * e + 1];
     const R ub = (a.ubar_bt && wet) ? (R)a.ubar_bt[e] : R(0);
+    int kk[NK];
+    bool ok[NK];
+    lane_layers<NK>(L, kk, ok);
     double he[NK], hu[NK];
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
-        int k = lane + c * kWave;
-        he[c] = hu[c] = 0.0;
-        if (k < L) {
-            const R u = wet ? (a.ubar_bt ? ub + a.X[base + k] : a.X[base + k]) : R(0);
-            a.U[base + k] = u;
-            he[c] = 0.5 * (a.h[(size_t)c1 * L + k] + a.h[(size_t)c2 * L + k]);
-            hu[c] = he[c] * (double)u;
-            bad |= !isfinite((double)u);
-        }
+        const R x = col_ld(a.X + base, kk[c]);
+        const double h1 = col_ld(a.h + (size_t)c1 * L, kk[c]), h2 = col_ld(a.h + (size_t)c2 * L, kk[c]);
+        const R u = wet ? (a.ubar_bt ? ub + x : x) : R(0);
+        if (ok[c]) col_st(a.U + base, kk[c], u);
+        he[c] = ok[c] ? 0.5 * (h1 + h2) : 0.0;
+        hu[c] = he[c] * (double)u;
+        bad |= ok[c] && !isfinite((double)u);
     }
     const double sh = col_sum<NK>(he);
     const double shu = col_sum<NK>(hu);
