@@ -851,9 +851,10 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
             pid.resize(d->n_cells);
             for (int i = 0; i < d->n_cells; ++i) pid[i] = pid0[ord.cell_old[i]];
             if (build_bt_tiles(d, pid, nP, &t, hb)) {
+                hipError_t put_err = hipSuccess;
                 auto put = [&](const void *src, size_t n) -> const void * {
                     char *dst = base + cursor;
-                    if (n) hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+                    if (n && put_err == hipSuccess) put_err = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
                     cursor += (n + kAlign - 1) / kAlign * kAlign;
                     return dst;
                 };
@@ -873,6 +874,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                 b.ccd = (const double *)put(hb.ccd.data(), hb.ccd.size() * 8);
                 b.ccd_f = (const float *)put(hb.ccd_f.data(), hb.ccd_f.size() * 4);
                 b.cwet = (const uint8_t *)put(hb.cwet.data(), hb.cwet.size());
+                SSE_HIP(put_err);
                 SSE_HIP(hipStreamSynchronize(s));
                 b.nP = hb.nP;
                 b.ks = hb.ks;
