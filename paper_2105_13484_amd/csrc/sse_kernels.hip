@@ -80,6 +80,14 @@ __device__ __forceinline__ T dpp(T old, T x) {
     return __builtin_amdgcn_update_dpp(old, x, kCtrl, kRowMask, 0xF, false);
 }
 
+// The same with zero for lanes without a source lane (bound control), every
+// row written: no register has to be cleared first, which matters for FP64
+// values, whose moves cannot fold into the addition that consumes them.
+template <int kCtrl, typename T>
+__device__ __forceinline__ T dpp_z(T x) {
+    return __builtin_amdgcn_update_dpp(T(0), x, kCtrl, 0xF, 0xF, true);
+}
+
 // x of lane l, as a wave-uniform value
 template <typename T>
 __device__ __forceinline__ T lane_value(T x, int l) {
@@ -107,10 +115,10 @@ __device__ __forceinline__ T wave_sum(T x) {
     } else {
         x += __shfl_xor(x, 32, kWave);
         x += __shfl_xor(x, 16, kWave);
-        x += dpp<kDppRowRor + 8>(T(0), x);
-        x += dpp<kDppRowRor + 4>(T(0), x);
-        x += dpp<kDppQuadXor2>(T(0), x);
-        x += dpp<kDppQuadXor1>(T(0), x);
+        x += dpp_z<kDppRowRor + 8>(x);
+        x += dpp_z<kDppRowRor + 4>(x);
+        x += dpp_z<kDppQuadXor2>(x);
+        x += dpp_z<kDppQuadXor1>(x);
         return lane_value(x, 0);
     }
 }
@@ -127,10 +135,10 @@ __device__ __forceinline__ T wave_incl_prefix(T x) {
             if (l >= d) x += y;
         }
     } else {
-        x += dpp<kDppRowShr + 1>(T(0), x);
-        x += dpp<kDppRowShr + 2>(T(0), x);
-        x += dpp<kDppRowShr + 4>(T(0), x);
-        x += dpp<kDppRowShr + 8>(T(0), x);
+        x += dpp_z<kDppRowShr + 1>(x);
+        x += dpp_z<kDppRowShr + 2>(x);
+        x += dpp_z<kDppRowShr + 4>(x);
+        x += dpp_z<kDppRowShr + 8>(x);
         x += dpp<kDppRowBcast15, 0xA>(T(0), x);
         x += dpp<kDppRowBcast31, 0xC>(T(0), x);
     }
@@ -151,10 +159,10 @@ __device__ __forceinline__ T wave_incl_suffix(T x) {
         }
         return x;
     } else {
-        x += dpp<kDppRowShl + 1>(T(0), x);
-        x += dpp<kDppRowShl + 2>(T(0), x);
-        x += dpp<kDppRowShl + 4>(T(0), x);
-        x += dpp<kDppRowShl + 8>(T(0), x);
+        x += dpp_z<kDppRowShl + 1>(x);
+        x += dpp_z<kDppRowShl + 2>(x);
+        x += dpp_z<kDppRowShl + 4>(x);
+        x += dpp_z<kDppRowShl + 8>(x);
         const T t3 = lane_value(x, 48);
         const T t23 = lane_value(x, 32) + t3;
         const T t123 = lane_value(x, 16) + t23;
@@ -201,7 +209,7 @@ __device__ __forceinline__ void col_excl_prefix(const T (&v)[NK], T (&o)[NK]) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const T inc = wave_incl_prefix<kDpp>(v[c]);
-        o[c] = lane_prev<kDpp>(T(0), inc) + carry;
+        o[c] = (kDpp ? dpp_z<kDppWaveShr1>(inc) : lane_prev<false>(T(0), inc)) + carry;
         if (c + 1 < NK) carry += __shfl(inc, kWave - 1, kWave);
     }
 }
@@ -213,7 +221,7 @@ __device__ __forceinline__ void col_excl_suffix(const T (&v)[NK], T (&o)[NK]) {
 #pragma unroll
     for (int c = NK - 1; c >= 0; --c) {
         const T inc = wave_incl_suffix<kDpp>(v[c]);
-        o[c] = lane_next<kDpp>(T(0), inc) + carry;
+        o[c] = (kDpp ? dpp_z<kDppWaveShl1>(inc) : lane_next<false>(T(0), inc)) + carry;
         if (c > 0) carry += __shfl(inc, 0, kWave);
     }
 }
@@ -236,7 +244,7 @@ __device__ __forceinline__ void col_up1(const T (&v)[NK], T (&o)[NK]) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const T prev_last = (c > 0) ? __shfl(v[c > 0 ? c - 1 : 0], kWave - 1, kWave) : T(0);
-        o[c] = lane_prev<kDpp>(prev_last, v[c]);
+        o[c] = (kDpp && c == 0) ? dpp_z<kDppWaveShr1>(v[c]) : lane_prev<kDpp>(prev_last, v[c]);
     }
 }
 
@@ -246,7 +254,7 @@ __device__ __forceinline__ void col_down1(const T (&v)[NK], T (&o)[NK]) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const T next_first = (c < NK - 1) ? __shfl(v[c < NK - 1 ? c + 1 : c], 0, kWave) : T(0);
-        o[c] = lane_next<kDpp>(next_first, v[c]);
+        o[c] = (kDpp && c == NK - 1) ? dpp_z<kDppWaveShl1>(v[c]) : lane_next<kDpp>(next_first, v[c]);
     }
 }
 
