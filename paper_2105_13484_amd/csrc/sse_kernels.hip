@@ -1703,10 +1703,12 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
 // Minimum waves per SIMD requested for the one-register-chunk edge pass.
 // Left alone the compiler settles at 79-81 VGPRs (5-6 waves); the
 // gather-bound pass runs faster with more loads in flight.  Measured on C1
-// (edge-pass time over 3 steps, FP64 / mixed): no request 12.1 / -, 5: 11.2,
-// 6: 11.6, 7: 10.8, 8: 11.4 ms in FP64; mixed steps are fastest at 5-6.
+// (edge-pass time over 3 steps): FP64 no request 12.1, 5: 11.2, 6: 11.6,
+// 7: 10.8, 8: 11.4 ms.  FP32 (with DPP lane moves): 6 leaves 106 scalar
+// registers and 7 resident waves, 8.86 ms; 7 fits 94 scalar registers and 8
+// resident waves, 8.40 ms; 8 spills to scratch.
 template <int NK, typename R>
-constexpr int edge_min_waves() { return NK != 1 ? 1 : (sizeof(R) == 8 ? 7 : 6); }
+constexpr int edge_min_waves() { return NK != 1 ? 1 : 7; }
 
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) tracer_kernel(TracerArgs<R> a) { tracer_body<NK, R>(a, column_id(a.m.C)); }
