@@ -235,7 +235,13 @@ def serve_leg(torch, ssprkse, cases, n_requests=24, load=0.8, full=False):
         return c, steps
 
     log(f"[bench] serving: building {n_requests} requests")
-    made = [make(i) for i in range(n_requests)]
+    made = []
+    for i in range(n_requests):
+        made.append(make(i))
+        if full:
+            c, s = made[-1]
+            log(f"[bench] serving: request {i}: {c.mesh.nCells} cells, {c.params.n_layers} layers, {s} steps, "
+                f"{'mixed' if c.params.precision else 'FP64'}")
 
     def requests(arrivals):
         return [Request(rid=i, case=c, steps=s, arrival=a) for i, ((c, s), a) in enumerate(zip(made, arrivals))]

@@ -115,7 +115,11 @@ namespace sse {
 // level by level, so a level-k set is a prefix of the region lists.  The
 // evaluation that produces level k reads level k + 1.
 constexpr int kBtThreads = 1024;   // threads per workgroup
-constexpr int kBtPatch = 384;      // target cells per patch
+// Target cells per patch.  One patch is one 1024-thread workgroup, and one
+// such workgroup fills a CU.  Measured (ms per 3 C1 steps of barotropic
+// substeps FP64 / mixed, C2 ms/step FP64 / mixed): 384: 9.20 / 6.94,
+// 5.93 / 4.76; 352: 9.20 / 6.78, 5.86 / 4.69; 320: 9.99 / 7.33, 6.37 / 5.02.
+constexpr int kBtPatch = 352;
 constexpr int kBtEdgeSlots = 2;    // edges of level 2 per thread (at most)
 constexpr int kBtRec = 12;         // ints per patch record
 struct DevBtTiles {
