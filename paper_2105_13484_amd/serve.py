@@ -12,7 +12,9 @@ and advances all of them together:
   one launch per step phase covers every member;
 * the batches advance in chunks of at most `chunk_steps` steps, never past
   the nearest completion, so that finished requests leave and waiting ones
-  join between chunks;
+  join between chunks; a request that arrives while a chunk runs is set up
+  (its mesh image built on the host and uploaded) during that chunk, and its
+  batch's program is rebuilt before the next;
 * a finished request's state is read back and its device memory released.
 
 A request's result does not depend on what else runs: a batch member
@@ -106,14 +108,18 @@ class Engine:
         t0 = clock()
         finished = []
         total = len(pending)
+
+        def admit():
+            # FIFO, no overtaking
+            while pending and pending[0].arrival <= clock() - t0 and \
+                    self.used_bytes + pending[0].footprint <= self.budget_bytes:
+                self._admit(pending.popleft(), clock() - t0)
+
         while len(finished) < total:
-            now = clock() - t0
-            # admission (FIFO, no overtaking)
-            while pending and pending[0].arrival <= now and self.used_bytes + pending[0].footprint <= self.budget_bytes:
-                self._admit(pending.popleft(), now)
             live = [p for p in self._active if self._active[p]]
             if not live:
-                if pending:
+                admit()
+                if not any(self._active[p] for p in self._active) and pending:
                     time.sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.01)))
                 continue
             # advance every non-empty batch by one chunk, the batches concurrently
@@ -122,11 +128,16 @@ class Engine:
                 k = min(self.chunk_steps, min(a.remaining for a in self._active[p]))
                 chunk[p] = k
                 self._batches[p].step_async(k)
+            # requests that have arrived are set up while the chunk runs; they
+            # join their batch with the next chunk
+            joined = {p: len(self._active[p]) for p in live}
+            admit()
             for p in live:
                 rc = self._batches[p].sync()
                 now = clock() - t0
                 still = []
-                for a in self._active[p]:
+                ran, newcomers = self._active[p][:joined[p]], self._active[p][joined[p]:]
+                for a in ran:
                     a.remaining -= chunk[p]
                     if rc != 0:
                         st_rc = a.state.sync()
@@ -139,7 +150,7 @@ class Engine:
                         finished.append(a.req)
                     else:
                         still.append(a)
-                self._active[p] = still
+                self._active[p] = still + newcomers   # admitted during the chunk, not stepped yet
             if on_progress:
                 on_progress(len(finished), total)
         wall = clock() - t0

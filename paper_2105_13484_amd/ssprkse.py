@@ -404,6 +404,10 @@ class Batch:
     Members must share precision, scheme and vertical coordinate and must have
     been created on the batch's stream.  ``compile()`` allocates the device
     buffer for the merged launch program (a torch tensor) and uploads it.
+
+    Members may be added while steps enqueued by ``step_async`` run: the
+    program those launches read stays allocated until the next ``sync`` (or
+    ``step``), and the new program is compiled at the next launch.
     """
 
     def __init__(self, stream=None):
@@ -412,28 +416,35 @@ class Batch:
         _check(load().sse_batch_create(_stream_ptr(stream), byref(self.handle)))
         self.members = []
         self.buf = None
+        self._retired = []     # programs that launches in flight may still read
+
+    def _retire(self):
+        if self.buf is not None:
+            self._retired.append(self.buf)
+        self.buf = None
 
     def add(self, state: "DeviceState"):
         _check(load().sse_batch_add(self.handle, state.handle))
         self.members.append(state)
-        self.buf = None
+        self._retire()
 
     def remove(self, state: "DeviceState"):
         _check(load().sse_batch_remove(self.handle, state.handle))
         self.members = [m for m in self.members if m is not state]
-        self.buf = None
+        self._retire()
 
     def __len__(self):
         return len(self.members)
 
     def set_geometry(self, cols_per_block: int = 4, block_2d: int = 256):
         _check(load().sse_batch_set_geometry(self.handle, int(cols_per_block), int(block_2d)))
-        self.buf = None
+        self._retire()
 
     def compile(self, device="cuda"):
         lib = load()
         nbytes = c_size_t()
         _check(lib.sse_batch_program_bytes(self.handle, byref(nbytes)))
+        self._retire()
         self.buf, ptr = _aligned_buffer(max(nbytes.value, 256), device)
         _check(lib.sse_batch_compile(self.handle, c_void_p(ptr), nbytes.value))
         return nbytes.value
@@ -449,7 +460,9 @@ class Batch:
     def step(self, n: int = 1) -> int:
         if self.buf is None:
             self.compile()
-        return _check(load().sse_batch_step(self.handle, int(n)), allow=(SSE_ENONFINITE,))
+        rc = _check(load().sse_batch_step(self.handle, int(n)), allow=(SSE_ENONFINITE,))
+        self._retired.clear()
+        return rc
 
     def step_async(self, n: int = 1):
         if self.buf is None:
@@ -457,7 +470,9 @@ class Batch:
         _check(load().sse_batch_step_async(self.handle, int(n)))
 
     def sync(self) -> int:
-        return _check(load().sse_batch_sync(self.handle), allow=(SSE_ENONFINITE,))
+        rc = _check(load().sse_batch_sync(self.handle), allow=(SSE_ENONFINITE,))
+        self._retired.clear()
+        return rc
 
     def close(self):
         if self.handle:
