@@ -283,9 +283,9 @@ int sse_state_use_graph(sse_state *s, int enable);
  * merged argument blocks and workgroup tables (256-byte aligned; the caller
  * owns it and keeps it alive while the batch steps).  Adding or removing a
  * member, or changing the geometry, invalidates the compiled program; these
- * calls touch host state only, so they may be made while launches enqueued
- * by sse_batch_step_async run, provided the buffer those launches read stays
- * allocated until sse_batch_sync returns.  A member must not be stepped on
+ * calls touch host state only, so without HIP graphs they may be made while
+ * launches enqueued by sse_batch_step_async run, provided the buffer those
+ * launches read stays allocated until sse_batch_sync returns.  A member must not be stepped on
  * its own while the batch runs.
  */
 typedef struct sse_batch sse_batch;
