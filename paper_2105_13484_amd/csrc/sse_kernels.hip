@@ -516,49 +516,79 @@ __device__ __forceinline__ void fe_vertex_body(const FEVertexArgs<R> &a, int fir
 // divergence of that field at cells (its curl at vertices is the vertex pass
 // applied to it).
 // ---------------------------------------------------------------------------
-template <int NK, typename R>
-__device__ __forceinline__ void lap_body(const LapArgs<R> &a, int col) {
+template <int NK, typename R, int Q>
+__device__ __forceinline__ void lap_body(const LapArgs<R> &a, int first) {
     const DevMesh &m = a.m;
-    const int e = col;
-    if (e >= m.E) return;
+    if (first >= m.E) return;
     const int L = a.L;
     int kk[NK];
     bool ok[NK];
     lane_layers<NK>(L, kk, ok);
-    const bool wet = m.emask[e] != 0;
-    const size_t b1 = (size_t)m.edge_cells[2 * e] * L, b2 = (size_t)m.edge_cells[2 * e + 1] * L;
-    const size_t w1 = (size_t)m.edge_verts[2 * e] * L, w2 = (size_t)m.edge_verts[2 * e + 1] * L;
-    const R idc = (R)m.inv_dc[e], idv = (R)m.inv_dv[e];
+    int ei[Q];
+    bool has[Q];
+    R d1[Q][NK], d2[Q][NK], z1[Q][NK], z2[Q][NK];
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        const int k = kk[c];
-        const R d1 = a.D[b1 + k], d2 = a.D[b2 + k], z1 = a.Z[w1 + k], z2 = a.Z[w2 + k];
-        if (ok[c]) a.out[(size_t)e * L + k] = wet ? (d2 - d1) * idc - (z2 - z1) * idv : R(0);
+    for (int q = 0; q < Q; ++q) {
+        has[q] = first + q < m.E;
+        const int e = ei[q] = has[q] ? first + q : first;
+        const size_t b1 = (size_t)m.edge_cells[2 * e] * L, b2 = (size_t)m.edge_cells[2 * e + 1] * L;
+        const size_t w1 = (size_t)m.edge_verts[2 * e] * L, w2 = (size_t)m.edge_verts[2 * e + 1] * L;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            d1[q][c] = col_ld(a.D + b1, kk[c]);
+            d2[q][c] = col_ld(a.D + b2, kk[c]);
+            z1[q][c] = col_ld(a.Z + w1, kk[c]);
+            z2[q][c] = col_ld(a.Z + w2, kk[c]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (!has[q]) continue;
+        const int e = ei[q];
+        const bool wet = m.emask[e] != 0;
+        const R idc = (R)m.inv_dc[e], idv = (R)m.inv_dv[e];
+#pragma unroll
+        for (int c = 0; c < NK; ++c)
+            if (ok[c])
+                col_st(a.out + (size_t)e * L, kk[c],
+                       wet ? (d2[q][c] - d1[q][c]) * idc - (z2[q][c] - z1[q][c]) * idv : R(0));
     }
 }
 
-template <int NK, typename R>
-__device__ __forceinline__ void div_body(const DivArgs<R> &a, int col) {
+template <int NK, typename R, int Q>
+__device__ __forceinline__ void div_body(const DivArgs<R> &a, int first) {
     const DevMesh &m = a.m;
-    const int i = col;
-    if (i >= m.C) return;
+    if (first >= m.C) return;
     const int L = a.L;
     int kk[NK];
     bool ok[NK];
     lane_layers<NK>(L, kk, ok);
-    R d[NK];
+    int ci[Q];
+    bool has[Q];
+    R x[Q][kMaxEdges][NK], cd[Q][kMaxEdges];
 #pragma unroll
-    for (int c = 0; c < NK; ++c) d[c] = R(0);
+    for (int q = 0; q < Q; ++q) {
+        has[q] = first + q < m.C;
+        const int i = ci[q] = has[q] ? first + q : first;
 #pragma unroll
-    for (int j = 0; j < kMaxEdges; ++j) {
-        const size_t eb = (size_t)m.cell_edges[i * kMaxEdges + j] * L;
-        const R cd = (R)m.cell_div[i * kMaxEdges + j];
+        for (int j = 0; j < kMaxEdges; ++j) {
+            const size_t eb = (size_t)m.cell_edges[i * kMaxEdges + j] * L;
+            cd[q][j] = (R)m.cell_div[i * kMaxEdges + j];
 #pragma unroll
-        for (int c = 0; c < NK; ++c) d[c] += cd * a.X[eb + kk[c]];
+            for (int c = 0; c < NK; ++c) x[q][j][c] = col_ld(a.X + eb, kk[c]);
+        }
     }
 #pragma unroll
-    for (int c = 0; c < NK; ++c)
-        if (ok[c]) a.out[(size_t)i * L + kk[c]] = d[c];
+    for (int q = 0; q < Q; ++q) {
+        if (!has[q]) continue;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            R d = R(0);
+#pragma unroll
+            for (int j = 0; j < kMaxEdges; ++j) d += cd[q][j] * x[q][j][c];
+            if (ok[c]) col_st(a.out + (size_t)ci[q] * L, kk[c], d);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1715,17 +1745,17 @@ __device__ __forceinline__ void convert_body(const ConvArgs<Tin, Tout> &a, int l
 // ---------------------------------------------------------------------------
 
 // The single-state launches of the light streaming column kernels (vertex,
-// thickness and assembly passes) give every wavefront kPairCols consecutive
-// columns and issue all their loads before any arithmetic: the wavefront
-// then has twice the loads in flight, which these kernels need to reach HBM
-// rates.  Measured per 3 C1 steps, FP64 / mixed: vertex pass 1.44 -> 1.19 /
-// 1.23 -> 0.89 ms, thickness 1.35 -> 1.14 ms, assembly and reconciliation
-// 1.06 -> 0.92 ms.  The cell pass, with 13 columns per cell, lost occupancy
-// with two cells (65 VGPRs, 106 scalar registers) and ran 5% slower, so it
-// keeps one.  (Processing the columns one after the other instead made
-// these kernels slower.)  Batched launches keep one column per wavefront, as
-// their workgroup tables count columns; the arithmetic per column is the
-// same in both forms.
+// thickness, assembly, Laplacian and divergence passes) give every wavefront
+// kPairCols consecutive columns and issue all their loads before any
+// arithmetic: the wavefront then has twice the loads in flight, which these
+// kernels need to reach HBM rates.  Measured per 3 C1 steps, FP64 / mixed:
+// vertex pass 1.44 -> 1.19 / 1.23 -> 0.89 ms, thickness 1.35 -> 1.14 ms,
+// assembly and reconciliation 1.06 -> 0.93 ms.  The cell pass, with 13
+// columns per cell, lost occupancy with two cells (65 VGPRs, 106 scalar
+// registers) and ran 5% slower, so it keeps one.  (Processing the columns
+// one after the other instead made these kernels slower.)  Batched launches
+// keep one column per wavefront, as their workgroup tables count columns;
+// the arithmetic per column is the same in both forms.
 constexpr int kPairCols = 2;
 __host__ __device__ constexpr int pair_cols(int n) { return (n + kPairCols - 1) / kPairCols; }
 
@@ -1783,18 +1813,22 @@ __global__ void __launch_bounds__(1024) tracer_batch(BatchLaunch<TracerArgs<R>> 
 }
 
 template <int NK, typename R>
-__global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) { lap_body<NK, R>(a, column_id(a.m.E)); }
+__global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) {
+    lap_body<NK, R, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.E)));
+}
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) lap_body<NK, R>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) lap_body<NK, R, 1>(b.args[t.x], batch_column(t.y));
 }
 template <int NK, typename R>
-__global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) { div_body<NK, R>(a, column_id(a.m.C)); }
+__global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) {
+    div_body<NK, R, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.C)));
+}
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) div_body<NK, R>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) div_body<NK, R, 1>(b.args[t.x], batch_column(t.y));
 }
 
 template <int NK, typename R, bool kAdd, int kVar>
@@ -1970,13 +2004,13 @@ void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> &b, int nk, const Geom
 
 template <typename R>
 void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(a.m.E, g)), block = col_block(g);
+    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.E), g)), block = col_block(g);
     if (a.L <= kWave) lap_kernel<1, R><<<grid, block, 0, s>>>(a);
     else lap_kernel<2, R><<<grid, block, 0, s>>>(a);
 }
 template <typename R>
 void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(a.m.C, g)), block = col_block(g);
+    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.C), g)), block = col_block(g);
     if (a.L <= kWave) div_kernel<1, R><<<grid, block, 0, s>>>(a);
     else div_kernel<2, R><<<grid, block, 0, s>>>(a);
 }
