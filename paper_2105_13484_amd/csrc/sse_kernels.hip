@@ -1746,18 +1746,21 @@ __device__ __forceinline__ void convert_body(const ConvArgs<Tin, Tout> &a, int l
 
 // The single-state launches of the light streaming column kernels (vertex,
 // thickness, assembly, Laplacian and divergence passes) give every wavefront
-// kPairCols consecutive columns and issue all their loads before any
-// arithmetic: the wavefront then has twice the loads in flight, which these
-// kernels need to reach HBM rates.  Measured per 3 C1 steps, FP64 / mixed:
-// vertex pass 1.44 -> 1.19 / 1.23 -> 0.89 ms, thickness 1.35 -> 1.14 ms,
-// assembly and reconciliation 1.06 -> 0.93 ms.  The cell pass, with 13
-// columns per cell, lost occupancy with two cells (65 VGPRs, 106 scalar
-// registers) and ran 5% slower, so it keeps one.  (Processing the columns
-// one after the other instead made these kernels slower.)  Batched launches
-// keep one column per wavefront, as their workgroup tables count columns;
-// the arithmetic per column is the same in both forms.
-constexpr int kPairCols = 2;
-__host__ __device__ constexpr int pair_cols(int n) { return (n + kPairCols - 1) / kPairCols; }
+// several consecutive columns and issue all their loads before any
+// arithmetic: the wavefront then has several times the loads in flight,
+// which these kernels need to reach HBM rates.  Measured per 3 C1 steps,
+// FP64 / mixed, one column against two: vertex pass 1.44 -> 1.19 / 1.23 ->
+// 0.89 ms, thickness 1.35 -> 1.14 ms, assembly and reconciliation 1.06 ->
+// 0.93 ms; two against four: vertex 1.19 / 1.13, assembly 0.92 / 0.81,
+// thickness 1.15 / 1.24.  The cell pass, with 13 columns per cell, lost
+// occupancy with two cells (65 VGPRs, 106 scalar registers) and ran 5%
+// slower, so it keeps one.  (Processing the columns one after the other
+// instead made these kernels slower.)  Batched launches keep one column per
+// wavefront, as their workgroup tables count columns; the arithmetic per
+// column is the same in every form.
+constexpr int kVertexCols = 4, kThickCols = 2, kAssembleCols = 4, kLapCols = 2, kDivCols = 2;
+template <int Q>
+__host__ __device__ constexpr int wave_groups(int n) { return (n + Q - 1) / Q; }
 
 // (member, member-local block) of this workgroup in a batched launch, with
 // the same XCD renumbering as the single-state launches.
@@ -1786,7 +1789,7 @@ __global__ void __launch_bounds__(1024) fe_cell_batch(BatchLaunch<FECellArgs<R>>
 
 template <int NK, typename R, bool kAdd>
 __global__ void __launch_bounds__(1024) fe_vertex_kernel(FEVertexArgs<R> a) {
-    fe_vertex_body<NK, R, kAdd, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.V)));
+    fe_vertex_body<NK, R, kAdd, kVertexCols>(a, kVertexCols * column_id(wave_groups<kVertexCols>(a.m.V)));
 }
 template <int NK, typename R, bool kAdd>
 __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs<R>> b) {
@@ -1814,7 +1817,7 @@ __global__ void __launch_bounds__(1024) tracer_batch(BatchLaunch<TracerArgs<R>> 
 
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) {
-    lap_body<NK, R, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.E)));
+    lap_body<NK, R, kLapCols>(a, kLapCols * column_id(wave_groups<kLapCols>(a.m.E)));
 }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
@@ -1823,7 +1826,7 @@ __global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
 }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) {
-    div_body<NK, R, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.C)));
+    div_body<NK, R, kDivCols>(a, kDivCols * column_id(wave_groups<kDivCols>(a.m.C)));
 }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
@@ -1843,7 +1846,7 @@ __global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_batch
 
 template <int NK>
 __global__ void __launch_bounds__(1024) thickness_kernel(THArgs a) {
-    thickness_body<NK, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.C)));
+    thickness_body<NK, kThickCols>(a, kThickCols * column_id(wave_groups<kThickCols>(a.m.C)));
 }
 template <int NK>
 __global__ void __launch_bounds__(1024) thickness_batch(BatchLaunch<THArgs> b) {
@@ -1861,7 +1864,7 @@ __global__ void __launch_bounds__(1024) thickness_iso_batch(BatchLaunch<THIsoArg
 
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) assemble_kernel(AssembleArgs<R> a) {
-    assemble_body<NK, R, kPairCols>(a, kPairCols * column_id(pair_cols(a.m.E)));
+    assemble_body<NK, R, kAssembleCols>(a, kAssembleCols * column_id(wave_groups<kAssembleCols>(a.m.E)));
 }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) assemble_batch(BatchLaunch<AssembleArgs<R>> b) {
@@ -1960,7 +1963,7 @@ void launch_fe_cell(const FECellArgs<R> &a, const Geom &g, hipStream_t s) {
 }
 template <typename R>
 void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_vertex_kernel, xcd_grid(col_blocks(pair_cols(a.m.V), g)), col_block(g), a);
+    SSE_NK_ADD(a.L > kWave, a.ubar_add != nullptr, fe_vertex_kernel, xcd_grid(col_blocks(wave_groups<kVertexCols>(a.m.V), g)), col_block(g), a);
 }
 // The edge pass has a fourth template parameter, the variant: bit 0 for
 // canonical stencils with vertex chains (the mesh's chain flag), bit 1 for
@@ -2004,13 +2007,13 @@ void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> &b, int nk, const Geom
 
 template <typename R>
 void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.E), g)), block = col_block(g);
+    const dim3 grid = xcd_grid(col_blocks(wave_groups<kLapCols>(a.m.E), g)), block = col_block(g);
     if (a.L <= kWave) lap_kernel<1, R><<<grid, block, 0, s>>>(a);
     else lap_kernel<2, R><<<grid, block, 0, s>>>(a);
 }
 template <typename R>
 void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.C), g)), block = col_block(g);
+    const dim3 grid = xcd_grid(col_blocks(wave_groups<kDivCols>(a.m.C), g)), block = col_block(g);
     if (a.L <= kWave) div_kernel<1, R><<<grid, block, 0, s>>>(a);
     else div_kernel<2, R><<<grid, block, 0, s>>>(a);
 }
@@ -2139,7 +2142,7 @@ void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, con
 }
 
 void launch_thickness(const THArgs &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.C), g));
+    const dim3 grid = xcd_grid(col_blocks(wave_groups<kThickCols>(a.m.C), g));
     if (a.L <= kWave) thickness_kernel<1><<<grid, col_block(g), 0, s>>>(a);
     else thickness_kernel<2><<<grid, col_block(g), 0, s>>>(a);
 }
@@ -2160,7 +2163,7 @@ void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, cons
 }
 template <typename R>
 void launch_assemble(const AssembleArgs<R> &a, const Geom &g, hipStream_t s) {
-    const dim3 grid = xcd_grid(col_blocks(pair_cols(a.m.E), g));
+    const dim3 grid = xcd_grid(col_blocks(wave_groups<kAssembleCols>(a.m.E), g));
     if (a.L <= kWave) assemble_kernel<1, R><<<grid, col_block(g), 0, s>>>(a);
     else assemble_kernel<2, R><<<grid, col_block(g), 0, s>>>(a);
 }
