@@ -310,7 +310,7 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
     {
         ProfScope ps(s, SSE_PROF_FE_VERTEX);
         FEVertexArgs<R> a{m, p.n_layers, X, add, rp<R>(w.Z)};
-        if (s->rec) record(s, Kind::FE_VERTEX, a, nk, add != nullptr, col_blocks(m.V, s->geom));
+        if (s->rec) record(s, Kind::FE_VERTEX, a, nk, add != nullptr, col_blocks(wave_groups<kVertexCols>(m.V), s->geom));
         else launch_fe_vertex<R>(a, s->geom, s->stream);
     }
     if (!del4 && s->rec) {
@@ -321,13 +321,13 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         // lap u at edges, then its divergence at cells and its curl at vertices
         ProfScope ps(s, SSE_PROF_OTHER);
         LapArgs<R> la{m, p.n_layers, rp<R>(w.D1), rp<R>(w.Z), rp<R>(w.L1)};
-        if (s->rec) record(s, Kind::LAP, la, nk, false, col_blocks(m.E, s->geom));
+        if (s->rec) record(s, Kind::LAP, la, nk, false, col_blocks(wave_groups<kLapCols>(m.E), s->geom));
         else launch_lap<R>(la, s->geom, s->stream);
         DivArgs<R> da{m, p.n_layers, rp<R>(w.L1), rp<R>(w.D2)};
-        if (s->rec) record(s, Kind::DIV, da, nk, false, col_blocks(m.C, s->geom));
+        if (s->rec) record(s, Kind::DIV, da, nk, false, col_blocks(wave_groups<kDivCols>(m.C), s->geom));
         else launch_div<R>(da, s->geom, s->stream);
         FEVertexArgs<R> va{m, p.n_layers, rp<R>(w.L1), nullptr, rp<R>(w.Z2)};
-        if (s->rec) record(s, Kind::FE_VERTEX, va, nk, false, col_blocks(m.V, s->geom));
+        if (s->rec) record(s, Kind::FE_VERTEX, va, nk, false, col_blocks(wave_groups<kVertexCols>(m.V), s->geom));
         else launch_fe_vertex<R>(va, s->geom, s->stream);
     }
     {
@@ -568,7 +568,7 @@ void thickness(sse_state *s, const double *h_in, const double *h_n, int comb, do
     }
     if (s->p.vcoord == SSE_ZSTAR) {
         THArgs a{s->mesh->d, s->p.n_layers, h_in, h_n, w.frac, w.Ftot, comb, dt, h_out, zeta_out, w.flag};
-        if (s->rec) record(s, Kind::THICK, a, nk, false, nb);
+        if (s->rec) record(s, Kind::THICK, a, nk, false, col_blocks(wave_groups<kThickCols>(s->mesh->d.C), s->geom));
         else launch_thickness(a, s->geom, s->stream);
     } else {
         THIsoArgs<R> a{};
@@ -598,7 +598,8 @@ void assemble(sse_state *s, const R *X, const double *ubar_bt) {
     ProfScope ps(s, SSE_PROF_OTHER);
     Work &w = s->w;
     AssembleArgs<R> a{s->mesh->d, s->p.n_layers, X, ubar_bt, w.Hs, rp<R>(w.U), w.ubar_n, w.flag};
-    if (s->rec) record(s, Kind::ASSEMBLE, a, nk_of(s->p.n_layers), false, col_blocks(a.m.E, s->geom));
+    if (s->rec)
+        record(s, Kind::ASSEMBLE, a, nk_of(s->p.n_layers), false, col_blocks(wave_groups<kAssembleCols>(a.m.E), s->geom));
     else launch_assemble<R>(a, s->geom, s->stream);
 }
 

@@ -226,6 +226,13 @@ bool geom_valid(const Geom &g);
 // Workgroups of a column kernel over n columns, and of a 2D kernel over n
 // entities (bt_eval: edge blocks, then cell blocks).
 int col_blocks(int n, const Geom &g);
+
+// Columns per wavefront of the light streaming column kernels (vertex,
+// thickness, assembly, Laplacian and divergence passes), in single-state and
+// batched launches alike; their grids count groups of that many columns.
+constexpr int kVertexCols = 4, kThickCols = 2, kAssembleCols = 4, kLapCols = 2, kDivCols = 2;
+template <int Q>
+__host__ __device__ constexpr int wave_groups(int n) { return (n + Q - 1) / Q; }
 int flat_blocks(size_t n, const Geom &g);
 int bt_blocks(int E, int C, const Geom &g);
 

@@ -1755,12 +1755,9 @@ __device__ __forceinline__ void convert_body(const ConvArgs<Tin, Tout> &a, int l
 // thickness 1.15 / 1.24.  The cell pass, with 13 columns per cell, lost
 // occupancy with two cells (65 VGPRs, 106 scalar registers) and ran 5%
 // slower, so it keeps one.  (Processing the columns one after the other
-// instead made these kernels slower.)  Batched launches keep one column per
-// wavefront, as their workgroup tables count columns; the arithmetic per
-// column is the same in every form.
-constexpr int kVertexCols = 4, kThickCols = 2, kAssembleCols = 4, kLapCols = 2, kDivCols = 2;
-template <int Q>
-__host__ __device__ constexpr int wave_groups(int n) { return (n + Q - 1) / Q; }
+// instead made these kernels slower.)  Batched launches take the same
+// groups (their workgroup tables count groups of columns); the arithmetic
+// per column is the same in every form.  The counts are in sse_kernels.h.
 
 // (member, member-local block) of this workgroup in a batched launch, with
 // the same XCD renumbering as the single-state launches.
@@ -1794,7 +1791,8 @@ __global__ void __launch_bounds__(1024) fe_vertex_kernel(FEVertexArgs<R> a) {
 template <int NK, typename R, bool kAdd>
 __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) fe_vertex_body<NK, R, kAdd, 1>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t))
+        fe_vertex_body<NK, R, kAdd, kVertexCols>(b.args[t.x], kVertexCols * batch_column(t.y));
 }
 
 // Minimum waves per SIMD requested for the one-register-chunk edge pass.
@@ -1822,7 +1820,7 @@ __global__ void __launch_bounds__(1024) lap_kernel(LapArgs<R> a) {
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) lap_batch(BatchLaunch<LapArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) lap_body<NK, R, 1>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) lap_body<NK, R, kLapCols>(b.args[t.x], kLapCols * batch_column(t.y));
 }
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) {
@@ -1831,7 +1829,7 @@ __global__ void __launch_bounds__(1024) div_kernel(DivArgs<R> a) {
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) div_body<NK, R, 1>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) div_body<NK, R, kDivCols>(b.args[t.x], kDivCols * batch_column(t.y));
 }
 
 template <int NK, typename R, bool kAdd, int kVar>
@@ -1851,7 +1849,7 @@ __global__ void __launch_bounds__(1024) thickness_kernel(THArgs a) {
 template <int NK>
 __global__ void __launch_bounds__(1024) thickness_batch(BatchLaunch<THArgs> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) thickness_body<NK, 1>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t)) thickness_body<NK, kThickCols>(b.args[t.x], kThickCols * batch_column(t.y));
 }
 
 template <int NK, typename R>
@@ -1869,7 +1867,8 @@ __global__ void __launch_bounds__(1024) assemble_kernel(AssembleArgs<R> a) {
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) assemble_batch(BatchLaunch<AssembleArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) assemble_body<NK, R, 1>(b.args[t.x], batch_column(t.y));
+    if (batch_entry(b.table, b.blocks, t))
+        assemble_body<NK, R, kAssembleCols>(b.args[t.x], kAssembleCols * batch_column(t.y));
 }
 
 // Barotropic evaluation: XCD x owns edge blocks [x pe, (x + 1) pe) and cell
