@@ -29,11 +29,13 @@ Primitive Equations" (arXiv 2105.13484).
 Everything is FP64 NumPy with whole-array operations; column sums over the
 layers use a fixed pairwise order (``layered.colsum``).
 
-Parity unpinned: the discrete forms of the nonlinear terms (pressure gradient
-in tilted layers, z-star vertical velocity, vertical boundary conditions,
-vorticity flux, barotropic (zeta + H) at edges) are fixed only by the readings
-stated in the docstrings of these modules, not by any number in the paper.
-They are pinned indirectly (conservation, lake at rest, closed forms on
-uniform flows, convergence order), not value by value.
+The discrete forms of the nonlinear terms (pressure gradient in tilted
+layers, z-star vertical velocity, vertical boundary conditions, vorticity
+flux, barotropic (zeta + H) at edges) are fixed by the readings stated in the
+docstrings of these modules, not by numbers in the paper.  They are pinned by
+exact properties the readings do not assume (closed forms of the pressure
+gradient, z-star proportional stretching, the column budget of the vertical
+fluxes, the layer-sum identity at edges) and, for the vorticity flux, by
+energy neutrality and second-order consistency with the continuous term.
 """
 from . import trisk, layered, ssprk_se  # noqa: F401
