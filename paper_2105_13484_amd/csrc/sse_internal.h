@@ -52,7 +52,7 @@ struct DevMesh {
     int chain = 0;                          // 1: stencils in canonical two-cell order (see sse_mesh.cpp)
     const double *w = nullptr;              // [10][E]  W_{e,j}
     const double *wf = nullptr;             // [10][E]  W_{e,j} (f_e + f_j) / 2
-    const double *wpair = nullptr;          // [E][10][2] (W_{e,j}, W_{e,j} (f_e + f_j) / 2), entity-major
+    const double *wpair = nullptr;          // [E][10][2] (W_{e,j} / 4, W_{e,j} (f_e + f_j) / 2), entity-major
     const double *dc = nullptr;             // [E]
     const double *dv = nullptr;             // [E]
     const double *inv_dc = nullptr;         // [E] 1 / d_e

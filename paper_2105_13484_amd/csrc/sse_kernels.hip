@@ -856,7 +856,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
         o.B2[c] = col_ld(a.B + b2, k);
         o.W1[c] = col_ld(a.Wtop + b1, k);
         o.W2[c] = col_ld(a.Wtop + b2, k);
-        q[c] = R(0.5) * (o.za[c] + o.zb[c]);
+        q[c] = o.za[c] + o.zb[c];  // twice the edge vorticity
         o.cor[c] = o.vor[c] = R(0);
         o.lap2[c] = R(0);
     }
@@ -876,7 +876,11 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     }
 
     // Coriolis on the baroclinic velocity (-f ut^perp) and the vorticity flux
-    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  Padded
+    // -(k.curl u) u^perp through the TRiSK tangential reconstruction.  The
+    // table holds W / 4 beside W (f_e + f_j) / 2, and the vertex sums are
+    // twice the edge vorticities, so W ((q_e + q_j) / 2) is (W / 4)(2 q_e +
+    // 2 q_j): the same bits with two multiplications fewer per stencil term
+    // (scaling by powers of two is exact).  Padded
     // stencil slots point at the edge itself with zero weights, so the loop
     // runs its full width; its column loads carry no branch between them.
     const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
@@ -898,12 +902,12 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
                 const int s = j - 5;
                 const R za_ = j < 5 ? zA[j < 5 ? j : 0][c] : (s == 0 ? zA[5][c] : zB[s > 0 ? s - 1 : 0][c]);
                 const R zb_ = j < 5 ? zA[j < 5 ? j + 1 : 0][c] : (s == 4 ? zA[0][c] : zB[s < 4 && s >= 0 ? s : 0][c]);
-                qp = R(0.5) * (za_ + zb_);
+                qp = za_ + zb_;
             } else {
-                qp = R(0.5) * (col_ld(a.Z + pb1, kk[c]) + col_ld(a.Z + pb2, kk[c]));
+                qp = col_ld(a.Z + pb1, kk[c]) + col_ld(a.Z + pb2, kk[c]);
             }
             o.cor[c] += wfj * utp;
-            o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
+            o.vor[c] += (wj * (q[c] + qp)) * up;
         }
     }
     fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idc, idv, o);
@@ -1096,7 +1100,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
             o.B2[c] = ok[c] ? B2 : R(0);
             o.W1[c] = ok[c] ? W1 : R(0);
             o.W2[c] = ok[c] ? W2 : R(0);
-            q[c] = R(0.5) * (o.za[c] + o.zb[c]);
+            q[c] = o.za[c] + o.zb[c];  // twice the edge vorticity
             o.cor[c] = o.vor[c] = R(0);
             o.lap2[c] = R(0);  // the tiled variants run without the biharmonic term
         }
@@ -1111,9 +1115,9 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
                 const int k = kk[c];
                 const R xp = sX[(size_t)sl * L + k];
                 const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
-                const R qp = R(0.5) * (sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k]);
+                const R qp = sZ[(size_t)sa * L + k] + sZ[(size_t)sb * L + k];
                 o.cor[c] += wfj * utp;
-                o.vor[c] += (wj * (R(0.5) * (q[c] + qp))) * up;
+                o.vor[c] += (wj * (q[c] + qp)) * up;
             }
         }
         fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idcv, idvv, o);

@@ -214,7 +214,7 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
     t.wpair.assign((size_t)E * 20, 0.0);
     for (int e = 0; e < E; ++e)
         for (int j = 0; j < 10; ++j) {
-            t.wpair[(size_t)e * 20 + 2 * j] = t.w[(size_t)j * E + e];
+            t.wpair[(size_t)e * 20 + 2 * j] = 0.25 * t.w[(size_t)j * E + e];
             t.wpair[(size_t)e * 20 + 2 * j + 1] = t.wf[(size_t)j * E + e];
         }
     t.erec.assign((size_t)E * kEdgeRec, 0);
