@@ -336,13 +336,29 @@ __device__ __forceinline__ void col_tridiag_solve(int L, T (&lo)[NK], T (&di)[NK
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Quotients by 3 and 6 in the bits of x / d but without the division
+// sequence (about ten instructions).  With r = RN(1/d), q = RN(x r) and the
+// residual x - q d (exact in one fused multiply-add), Markstein's theorem
+// makes RN(q + (x - q d) r) the correctly rounded quotient whenever q lies
+// within one ulp of x / d, which holds when |1 - d r| <= 2^-(p+1) for
+// precision p: 1 - 3 RN(1/3) is 2^-54 in FP64 and 2^-25 in FP32 (and RN(1/6)
+// is RN(1/3) / 2).  Valid while the quotient and the residual stay normal
+// (|x / d| above about 2^-960 in FP64, 2^-100 in FP32); x = -0 gives +0.
+// (Divisions by the run's dt and rho0 done this way, with host reciprocals,
+// made the edge pass slower, so those stay divisions.)
+template <typename T>
+__device__ __forceinline__ T div_by_near(T x, T d, T r) {
+    const T q = x * r;
+    return fmadd(fmadd(-q, d, x), r, q);
+}
+
 // The 3/4 combination is one fused multiply-add with an explicit operand
 // order (1/4 x is exact), so every kernel that forms it rounds alike.
 template <typename T>
 __device__ __forceinline__ T combine(int mode, T b, T x) {
     switch (mode) {
         case COMB_34: return fmadd(T(0.75), b, T(0.25) * x);
-        case COMB_THIRD: return b / T(3) + T(2) * x / T(3);
+        case COMB_THIRD: return div_by_near(b, T(3), T(1) / T(3)) + div_by_near(T(2) * x, T(3), T(1) / T(3));
         case COMB_HALF: return T(0.5) * (b + x);
         default: return x;
     }
@@ -752,7 +768,8 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
         if (a.sum_hp) a.sum_hp[e] = shp;
         if (a.Gi) {
             if (a.interp == 3)
-                a.Gi[e] = a.Ga[e] / 6.0 + a.Gb[e] / 6.0 + 2.0 * G / 3.0;
+                a.Gi[e] = div_by_near(a.Ga[e], 6.0, 1.0 / 6.0) + div_by_near(a.Gb[e], 6.0, 1.0 / 6.0) +
+                          div_by_near(2.0 * G, 3.0, 1.0 / 3.0);
             else
                 a.Gi[e] = 0.5 * a.Ga[e] + 0.5 * G;
         }
