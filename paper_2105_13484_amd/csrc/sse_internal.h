@@ -114,12 +114,17 @@ namespace sse {
 // first cell is in the patch; E_k = all edges of R_k for k >= 1), listed
 // level by level, so a level-k set is a prefix of the region lists.  The
 // evaluation that produces level k reads level k + 1.
-constexpr int kBtThreads = 1024;   // threads per workgroup
-// Target cells per patch.  One patch is one 1024-thread workgroup, and one
-// such workgroup fills a CU.  Measured (ms per 3 C1 steps of barotropic
-// substeps FP64 / mixed, C2 ms/step FP64 / mixed): 384: 9.20 / 6.94,
-// 5.93 / 4.76; 352: 9.20 / 6.78, 5.86 / 4.69; 320: 9.99 / 7.33, 6.37 / 5.02.
-constexpr int kBtPatch = 352;
+constexpr int kBtThreads = 512;    // threads per workgroup
+// Workgroups of a CU at once (4 waves per SIMD, 128 VGPRs): two, so one
+// workgroup's table loads overlap the other's evaluations.
+constexpr int kBtWavesPerSimd = 4;
+// Target cells per patch.  Measured, C1 FP64 / mixed ms/step and C2 FP64 /
+// mixed ms/step: 1024 threads and 352 cells (one workgroup per CU, no
+// overlap): 7.98 / 6.23, 5.69 / 4.46; 512 threads and 176 cells: 7.85 /
+// 6.08, 5.77 / 4.49; 160 cells: 7.87 / 6.12, 5.85 / 4.52.  From 192 cells
+// the level-2 edges of many patches exceed 2 x 512, and the split halves
+// cost more (8.45 ms C1).
+constexpr int kBtPatch = 176;
 constexpr int kBtEdgeSlots = 2;    // edges of level 2 per thread (at most)
 constexpr int kBtRec = 12;         // ints per patch record
 struct DevBtTiles {

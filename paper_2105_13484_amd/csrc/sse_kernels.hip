@@ -1919,14 +1919,14 @@ __global__ void __launch_bounds__(1024) bt_eval_batch(BatchLaunch<BTEvalArgs<R>>
 }
 
 template <typename R, int kScheme, int KS>
-__global__ void __launch_bounds__(kBtThreads) bt_substep_kernel(BTTileArgs<R> a) {
+__global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_substep_kernel(BTTileArgs<R> a) {
     const int p = xcd_block(a.t.nP);
     if (p >= 0) bt_substep_body<R, kScheme, KS>(a, p);
 }
 // Batched: one workgroup per (member, patch); the dynamic LDS is the
 // largest member's.
 template <typename R, int kScheme, int KS>
-__global__ void __launch_bounds__(kBtThreads) bt_substep_batch(BatchLaunch<BTTileArgs<R>> b) {
+__global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_substep_batch(BatchLaunch<BTTileArgs<R>> b) {
     int2 t;
     if (batch_entry(b.table, b.blocks, t)) bt_substep_body<R, kScheme, KS>(b.args[t.x], t.y);
 }
