@@ -222,7 +222,10 @@ int sse_profile_read(sse_state *s, int32_t *launches, double *milliseconds);
 /* Kernel variant of the baroclinic edge pass (results are identical up to
  * the order of FP64 rounding in no operation: every variant performs the same
  * arithmetic on the same operands).  variant -1: direct gathers from global
- * memory; 0, 1, 2: the operands of tiles of 8, 16 or 32 consecutive edges are
+ * memory, addressing each column by a 32-bit offset into its array while the
+ * largest per-layer array (entities x L x 8 bytes) stays below 4 GiB and by a
+ * 64-bit address otherwise; -2: direct gathers with 64-bit addresses always;
+ * 0, 1, 2: the operands of tiles of 8, 16 or 32 consecutive edges are
  * first staged in LDS.  SSE_EINVAL if the variant is unknown or does not fit
  * this mesh (a tile list longer than 255 columns) or the device's LDS for the
  * state's layer count and precision.  The default is -1.  The first

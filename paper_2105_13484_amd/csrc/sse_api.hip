@@ -211,7 +211,7 @@ struct sse_state {
     bool initialized = false;
     bool tracer_set = false; // tracer runs: the temperature has been given
     Geom geom{};             // launch geometry (autotuner knob)
-    int edge_variant = -1;   // -1: direct gathers; 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
+    int edge_variant = -1;   // -1: direct gathers (-2: with 64-bit column addresses); 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
     int bt_variant = 0;      // 0: one launch per barotropic evaluation; 1: one per substep (patches)
     size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
     Recorder *rec = nullptr; // non-null while a batch records this state's step
@@ -373,11 +373,12 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
             a.Z2 = rp<R>(w.Z2);
         }
         if (s->rec)
-            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1, fe_edge_variant(m, p.vmix, del4));
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1,
+                   fe_edge_variant(m, p.n_layers, p.vmix, del4) | (s->edge_variant == -2 ? 8 : 0));
         else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);
         else
-            launch_fe_edge<R>(a, s->geom, s->stream);
+            launch_fe_edge<R>(a, s->geom, s->stream, s->edge_variant == -2);
     }
 }
 
@@ -1015,13 +1016,13 @@ extern "C" int sse_state_get_bt_variant(const sse_state *s, int *variant) {
 
 extern "C" int sse_state_set_edge_variant(sse_state *s, int variant) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
-    if (variant == -1) {
-        s->edge_variant = -1;
+    if (variant == -1 || variant == -2) {
+        s->edge_variant = variant;
         if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
         s->graph_exec = nullptr;
         return SSE_OK;
     }
-    if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -1, 0, 1 or 2"); return SSE_EINVAL; }
+    if (variant < 0 || variant >= kTileVariants) { set_error("edge variant must be -2, -1, 0, 1 or 2"); return SSE_EINVAL; }
     if (s->p.hdiff == SSE_HDIFF_DEL4) {
         set_error("edge variants 0, 1, 2 do not carry the biharmonic viscosity; use -1");
         return SSE_EINVAL;

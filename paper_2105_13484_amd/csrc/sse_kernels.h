@@ -243,7 +243,8 @@ template <typename R> void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom
 template <typename R> void launch_lap(const LapArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_tracer(const TracerArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_div(const DivArgs<R> &a, const Geom &g, hipStream_t s);
-template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s);
+// wide: 64-bit column addressing whatever the array sizes (edge variant -2)
+template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s, bool wide = false);
 // LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
 template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
 template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
@@ -280,8 +281,9 @@ template <typename R> void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> 
 template <typename R> void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 // Template variant of the edge pass: bit 0 canonical stencils with vertex
 // chains (mesh), bit 1 implicit vertical mixing, bit 2 biharmonic viscosity
-// (parameters).
-int fe_edge_variant(const DevMesh &m, int vmix, bool del4);
+// (parameters), bit 3 64-bit column addressing (some array of L layers per
+// entity reaches 4 GiB).
+int fe_edge_variant(const DevMesh &m, int L, int vmix, bool del4);
 template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g, hipStream_t s);
 template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
 // table entries (member, patch); ks and lds: the largest over the members

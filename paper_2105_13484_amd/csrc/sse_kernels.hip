@@ -407,6 +407,27 @@ __device__ __forceinline__ void col_st(T *col, int k, T v) {
     *(__attribute__((address_space(1))) T *)(uniform_global(col) + (unsigned)k * (unsigned)sizeof(T)) = v;
 }
 
+// Layer k of the column that starts off elements into arr.  kWide: a 64-bit
+// scalar base per column (col_ld).  Otherwise (arrays below 4 GiB) through
+// one buffer descriptor of the whole array, with the column's byte offset in
+// a single 32-bit scalar register and the layer's in the lane's: half the
+// scalar registers per column and no 64-bit address arithmetic, which keeps
+// the edge pass, with its ~30 columns, from spilling scalar registers.
+template <bool kWide, typename T>
+__device__ __forceinline__ T col_ldv(const T *arr, size_t off, int k) {
+    if constexpr (kWide) {
+        return col_ld(arr + off, k);
+    } else {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void *)uniform_global(arr), (short)0, -1, 0x00020000);
+        const unsigned so = __builtin_amdgcn_readfirstlane((unsigned)(off * sizeof(T)));
+        if constexpr (sizeof(T) == 8)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)k * 8u, so, 0));
+        else
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)k * 4u, so, 0));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Baroclinic forward Euler (Algorithm 1): cell pass.
 // kAdd: the velocity is X + ubar_add (ubar_add non-null), else X itself.
@@ -624,7 +645,7 @@ struct EdgeOperands {
 
 // kMix: D^u is left out of the tendency and applied by the implicit column
 // solve of Algorithm 2 (the vertical-mixing form of the stage).
-template <int NK, typename R, bool kMix>
+template <int NK, typename R, bool kMix, bool kWide>
 __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, int c1, int c2, double idc, double idv,
                                                const EdgeOperands<NK, R> &o) {
     const int lane = lane_id();
@@ -751,7 +772,7 @@ __device__ __forceinline__ void fe_edge_finish(const FEEdgeArgs<R> &a, int e, in
         const int k = lane + c * kWave;
         R utn = R(0);
         if (a.Un) {
-            const double un = (double)col_ld(a.Un + base, kk[c]);
+            const double un = (double)col_ldv<kWide>(a.Un, base, kk[c]);
             utn = k < L ? (R)(un - ubn) : R(0);
         }
         outv[c] = (k < L) ? combine<R>(a.comb, utn, x[c]) : R(0);
@@ -806,6 +827,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     constexpr bool kChain = (kVar & 1) != 0;
     constexpr bool kMix = (kVar & 2) != 0;
     constexpr bool kDel4 = (kVar & 4) != 0;
+    constexpr bool kWide = (kVar & 8) != 0;
     const DevMesh &m = a.m;
     const int E = m.E;
     const int e = col;
@@ -835,15 +857,15 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     if constexpr (kChain) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            const R *zc = a.Z + (size_t)rec[10 + i] * L;
+            const size_t zo = (size_t)rec[10 + i] * L;
 #pragma unroll
-            for (int c = 0; c < NK; ++c) zA[i][c] = col_ld(zc, kk[c]);
+            for (int c = 0; c < NK; ++c) zA[i][c] = col_ldv<kWide>(a.Z, zo, kk[c]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const R *zc = a.Z + (size_t)rec[16 + i] * L;
+            const size_t zo = (size_t)rec[16 + i] * L;
 #pragma unroll
-            for (int c = 0; c < NK; ++c) zB[i][c] = col_ld(zc, kk[c]);
+            for (int c = 0; c < NK; ++c) zB[i][c] = col_ldv<kWide>(a.Z, zo, kk[c]);
         }
     }
     const bool a0_is_v1 = kChain ? rec[20] != 0 : false;
@@ -852,27 +874,27 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 #pragma unroll
     for (int c = 0; c < NK; ++c) {
         const int k = kk[c];
-        const R x = col_ld(a.X + base, k);
+        const R x = col_ldv<kWide>(a.X, base, k);
         R za, zb;
         if constexpr (kChain) {
             za = a0_is_v1 ? zA[0][c] : zA[5][c];
             zb = a0_is_v1 ? zA[5][c] : zA[0][c];
         } else {
-            za = col_ld(a.Z + bv1, k);
-            zb = col_ld(a.Z + bv2, k);
+            za = col_ldv<kWide>(a.Z, bv1, k);
+            zb = col_ldv<kWide>(a.Z, bv2, k);
         }
         o.u[c] = kAdd ? x + ub_e : x;
         o.ut[c] = kAdd ? x : x - ub_e;
-        o.h1[c] = col_ld(a.h + b1, k);
-        o.h2[c] = col_ld(a.h + b2, k);
-        o.r1[c] = col_ld(a.rho + b1, k);
-        o.r2[c] = col_ld(a.rho + b2, k);
+        o.h1[c] = col_ldv<kWide>(a.h, b1, k);
+        o.h2[c] = col_ldv<kWide>(a.h, b2, k);
+        o.r1[c] = col_ldv<kWide>(a.rho, b1, k);
+        o.r2[c] = col_ldv<kWide>(a.rho, b2, k);
         o.za[c] = za;
         o.zb[c] = zb;
-        o.B1[c] = col_ld(a.B + b1, k);
-        o.B2[c] = col_ld(a.B + b2, k);
-        o.W1[c] = col_ld(a.Wtop + b1, k);
-        o.W2[c] = col_ld(a.Wtop + b2, k);
+        o.B1[c] = col_ldv<kWide>(a.B, b1, k);
+        o.B2[c] = col_ldv<kWide>(a.B, b2, k);
+        o.W1[c] = col_ldv<kWide>(a.Wtop, b1, k);
+        o.W2[c] = col_ldv<kWide>(a.Wtop, b2, k);
         q[c] = o.za[c] + o.zb[c];  // twice the edge vorticity
         o.cor[c] = o.vor[c] = R(0);
         o.lap2[c] = R(0);
@@ -886,8 +908,8 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             const int k = kk[c];
-            const R d1 = col_ld(a.D2 + b1, k), d2 = col_ld(a.D2 + b2, k);
-            const R z1 = col_ld(a.Z2 + w1, k), z2 = col_ld(a.Z2 + w2, k);
+            const R d1 = col_ldv<kWide>(a.D2, b1, k), d2 = col_ldv<kWide>(a.D2, b2, k);
+            const R z1 = col_ldv<kWide>(a.Z2, w1, k), z2 = col_ldv<kWide>(a.Z2, w2, k);
             o.lap2[c] = (d2 - d1) * (R)idc - (z2 - z1) * (R)idv;
         }
     }
@@ -911,7 +933,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
         const size_t pb2 = kChain ? 0 : (size_t)rec[11 + 2 * j] * L;
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            const R xp = col_ld(a.X + pb, kk[c]);
+            const R xp = col_ldv<kWide>(a.X, pb, kk[c]);
             const R up = kAdd ? xp + ubp : xp, utp = kAdd ? xp : xp - ubp;
             R qp;
             if constexpr (kChain) {
@@ -921,13 +943,13 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
                 const R zb_ = j < 5 ? zA[j < 5 ? j + 1 : 0][c] : (s == 4 ? zA[0][c] : zB[s < 4 && s >= 0 ? s : 0][c]);
                 qp = za_ + zb_;
             } else {
-                qp = col_ld(a.Z + pb1, kk[c]) + col_ld(a.Z + pb2, kk[c]);
+                qp = col_ldv<kWide>(a.Z, pb1, kk[c]) + col_ldv<kWide>(a.Z, pb2, kk[c]);
             }
             o.cor[c] += wfj * utp;
             o.vor[c] += (wj * (q[c] + qp)) * up;
         }
     }
-    fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idc, idv, o);
+    fe_edge_finish<NK, R, kMix, kWide>(a, e, c1, c2, idc, idv, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -1137,7 +1159,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
                 o.vor[c] += (wj * (q[c] + qp)) * up;
             }
         }
-        fe_edge_finish<NK, R, kMix>(a, e, c1, c2, idcv, idvv, o);
+        fe_edge_finish<NK, R, kMix, true>(a, e, c1, c2, idcv, idvv, o);
     }
 }
 
@@ -2009,7 +2031,15 @@ void launch_fe_vertex(const FEVertexArgs<R> &a, const Geom &g, hipStream_t s) {
             case 4: SSE_NK_ADD_V(NK2, ADD, 4, KERNEL, GRID, BLOCK, ARG); break;        \
             case 5: SSE_NK_ADD_V(NK2, ADD, 5, KERNEL, GRID, BLOCK, ARG); break;        \
             case 6: SSE_NK_ADD_V(NK2, ADD, 6, KERNEL, GRID, BLOCK, ARG); break;        \
-            default: SSE_NK_ADD_V(NK2, ADD, 7, KERNEL, GRID, BLOCK, ARG); break;       \
+            case 7: SSE_NK_ADD_V(NK2, ADD, 7, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 8: SSE_NK_ADD_V(NK2, ADD, 8, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 9: SSE_NK_ADD_V(NK2, ADD, 9, KERNEL, GRID, BLOCK, ARG); break;        \
+            case 10: SSE_NK_ADD_V(NK2, ADD, 10, KERNEL, GRID, BLOCK, ARG); break;      \
+            case 11: SSE_NK_ADD_V(NK2, ADD, 11, KERNEL, GRID, BLOCK, ARG); break;      \
+            case 12: SSE_NK_ADD_V(NK2, ADD, 12, KERNEL, GRID, BLOCK, ARG); break;      \
+            case 13: SSE_NK_ADD_V(NK2, ADD, 13, KERNEL, GRID, BLOCK, ARG); break;      \
+            case 14: SSE_NK_ADD_V(NK2, ADD, 14, KERNEL, GRID, BLOCK, ARG); break;      \
+            default: SSE_NK_ADD_V(NK2, ADD, 15, KERNEL, GRID, BLOCK, ARG); break;      \
         }                                                                              \
     } while (0)
 
@@ -2048,14 +2078,19 @@ void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, h
     else div_batch<2, R><<<xcd_grid(b.blocks), col_block(g), 0, s>>>(b);
 }
 
-int fe_edge_variant(const DevMesh &m, int vmix, bool del4) {
-    return (m.chain ? 1 : 0) | (vmix ? 2 : 0) | (del4 ? 4 : 0);
+int fe_edge_variant(const DevMesh &m, int L, int vmix, bool del4) {
+    // 32-bit column offsets cover every array the pass reads while the
+    // largest (edges, vertices or cells) x L x 8 bytes stays below 4 GiB,
+    // with a margin for the layer offsets
+    const size_t n = (size_t)std::max(m.E, std::max(m.V, m.C));
+    const bool wide = n * (size_t)L * 8 + 4096 > ((size_t)1 << 32);
+    return (m.chain ? 1 : 0) | (vmix ? 2 : 0) | (del4 ? 4 : 0) | (wide ? 8 : 0);
 }
 
 template <typename R>
-void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s) {
-    SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, fe_edge_variant(a.m, a.vmix, a.D2 != nullptr), fe_edge_kernel,
-                   xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
+void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s, bool wide) {
+    const int var = fe_edge_variant(a.m, a.L, a.vmix, a.D2 != nullptr) | (wide ? 8 : 0);
+    SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, var, fe_edge_kernel, xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
 }
 template <typename R>
 void launch_fe_cell_batch(const BatchLaunch<FECellArgs<R>> &b, int nk, bool add, const Geom &g, hipStream_t s) {
@@ -2228,7 +2263,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template void launch_div<R>(const DivArgs<R> &, const Geom &, hipStream_t);                           \
     template void launch_lap_batch<R>(const BatchLaunch<LapArgs<R>> &, int, const Geom &, hipStream_t);  \
     template void launch_div_batch<R>(const BatchLaunch<DivArgs<R>> &, int, const Geom &, hipStream_t);  \
-    template void launch_fe_edge<R>(const FEEdgeArgs<R> &, const Geom &, hipStream_t);                     \
+    template void launch_fe_edge<R>(const FEEdgeArgs<R> &, const Geom &, hipStream_t, bool);               \
     template void launch_fe_cell_batch<R>(const BatchLaunch<FECellArgs<R>> &, int, bool, const Geom &,     \
                                           hipStream_t);                                                    \
     template void launch_fe_vertex_batch<R>(const BatchLaunch<FEVertexArgs<R>> &, int, bool, const Geom &, \

@@ -279,10 +279,12 @@ def test_nonfinite_input_rejected(dev):
 
 
 # ---------------------------------------------------------------------------
-# edge-pass variants (direct gathers, LDS tiles of 8 / 16 / 32 edges)
+# edge-pass variants (direct gathers with 32-bit column offsets or, -2, with
+# 64-bit column addresses as meshes with 4 GiB arrays take; LDS tiles of 8 /
+# 16 / 32 edges)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["hex12_L64", "hex8_L100", "sphere3_land_L7"])
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [-2, 0, 1, 2])
 def test_edge_variant_feuler_parity(dev, name, variant):
     case = KERNEL_CASES[name]()
     st_o = Setup.from_case(case)
@@ -299,7 +301,7 @@ def test_edge_variant_feuler_parity(dev, name, variant):
     assert max(errs.values()) < TOL
 
 
-@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
+@pytest.mark.parametrize("variant", [-2, 0, 1, 2])
 def test_edge_variants_bitwise_equal(dev, variant):
     """Every variant performs the same arithmetic on the same operands: whole
     steps agree bit for bit with the direct-gather kernel."""
@@ -312,6 +314,39 @@ def test_edge_variants_bitwise_equal(dev, variant):
         out[v] = st.read()
     for k in out[-1]:
         assert np.array_equal(out[-1][k], out[variant][k]), k
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_addressing_bitwise_equal(dev, precision):
+    """64-bit column addressing (the form meshes with arrays of 4 GiB or more
+    take) against 32-bit offsets, with every optional term on and two
+    register chunks, alone and in a batch."""
+    import torch
+    from tests.test_gpu_combined import all_terms
+    case = cases.with_params(all_terms(cases.c1(n=10, L=100, steps=2)), precision=precision)
+    out = {}
+    for v in (-1, -2):
+        _, st = dev.state_from_case(case)
+        assert st.try_edge_variant(v), dev.last_error()
+        assert st.step(2) == 0, dev.last_error()
+        out[v] = st.read()
+        out[v]["T"] = st.read_tracer()
+    for k in out[-1]:
+        assert np.array_equal(out[-1][k], out[-2][k]), k
+    stream = torch.cuda.Stream()
+    keep, b = [], dev.Batch(stream=stream)
+    for v in (-2, -1):
+        dm, st = dev.state_from_case(case, stream=stream)
+        assert st.try_edge_variant(v), dev.last_error()
+        keep.append(dm)
+        b.add(st)
+    b.compile()
+    assert b.step(2) == 0, dev.last_error()
+    for st in b.members:
+        got = st.read()
+        got["T"] = st.read_tracer()
+        for k in out[-1]:
+            assert np.array_equal(got[k], out[-1][k]), k
 
 
 # ---------------------------------------------------------------------------
