@@ -373,7 +373,7 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
             a.Z2 = rp<R>(w.Z2);
         }
         if (s->rec)
-            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, s->geom), -1,
+            record(s, Kind::FE_EDGE, a, nk, add != nullptr, col_blocks(m.E, edge_geom(s->geom, nk)), -1,
                    fe_edge_variant(m, p.n_layers, p.vmix, del4) | (s->edge_variant == -2 ? 8 : 0));
         else if (s->edge_variant >= 0)
             launch_fe_edge_tiled<R>(a, s->mesh->tiles[s->edge_variant], s->stream);

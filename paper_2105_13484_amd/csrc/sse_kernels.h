@@ -279,6 +279,12 @@ template <typename R> void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs
 template <typename R> void launch_lap_batch(const BatchLaunch<LapArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_tracer_batch(const BatchLaunch<TracerArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_div_batch(const BatchLaunch<DivArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
+// Geometry of the edge pass over nk register chunks: the two-chunk pass runs
+// workgroups of at most kEdge2MaxCols wavefronts (its launch bound); record
+// and launch both take their block counts and sizes from it.
+constexpr int kEdge2MaxCols = 4;
+constexpr int kEdge2Waves = 3;   // waves per SIMD requested for the two-chunk pass
+Geom edge_geom(const Geom &g, int nk);
 // Template variant of the edge pass: bit 0 canonical stencils with vertex
 // chains (mesh), bit 1 implicit vertical mixing, bit 2 biharmonic viscosity
 // (parameters), bit 3 64-bit column addressing (some array of L layers per

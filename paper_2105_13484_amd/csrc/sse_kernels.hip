@@ -1843,13 +1843,18 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
 
 // Minimum waves per SIMD requested for the one-register-chunk edge pass.
 // Left alone the compiler settles at 79-81 VGPRs (5-6 waves); the
-// gather-bound pass runs faster with more loads in flight.  Measured on C1
-// (edge-pass time over 3 steps): FP64 no request 12.1, 5: 11.2, 6: 11.6,
-// 7: 10.8, 8: 11.4 ms.  FP32 (with DPP lane moves): 6 leaves 106 scalar
-// registers and 7 resident waves, 8.86 ms; 7 fits 94 scalar registers and 8
-// resident waves, 8.40 ms; 8 spills to scratch.
+// gather-bound pass runs faster with more loads in flight.  With 64-bit
+// column bases the best request was 7 (C1 edge-pass time over 3 steps, FP64:
+// none 12.1, 5: 11.2, 6: 11.6, 7: 10.8, 8: 11.4 ms).  With 32-bit scalar
+// column offsets and DPP lane moves the pass fits 8 waves (57-63 VGPRs, 78
+// SGPRs, no scratch): FP64 9.78 -> 9.65 ms, C1 mixed 6.03 -> 5.94 ms/step.
 template <int NK, typename R>
-constexpr int edge_min_waves() { return NK != 1 ? 1 : 7; }
+constexpr int edge_min_waves() { return NK != 1 ? kEdge2Waves : 8; }
+// The two-chunk pass (L > 64) holds twice the operands per lane; with
+// workgroups of at most kEdge2MaxCols wavefronts its launch bound lets the
+// compiler keep them in registers instead of scratch.
+template <int NK>
+constexpr int edge_max_threads() { return NK == 1 ? 1024 : kEdge2MaxCols * kWave; }
 
 template <int NK, typename R>
 __global__ void __launch_bounds__(1024) tracer_kernel(TracerArgs<R> a) { tracer_body<NK, R>(a, column_id(a.m.C)); }
@@ -1879,11 +1884,11 @@ __global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
 }
 
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_kernel(FEEdgeArgs<R> a) {
+__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R>())) fe_edge_kernel(FEEdgeArgs<R> a) {
     fe_edge_body<NK, R, kAdd, kVar>(a, column_id(a.m.E));
 }
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(1024, (edge_min_waves<NK, R>())) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
+__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R>())) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
     int2 t;
     if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kVar>(b.args[t.x], batch_column(t.y));
 }
@@ -1979,6 +1984,11 @@ bool geom_valid(const Geom &g) {
            g.block_2d % 64 == 0;
 }
 int col_blocks(int n, const Geom &g) { return (n + g.cols_per_block - 1) / g.cols_per_block; }
+Geom edge_geom(const Geom &g, int nk) {
+    Geom e = g;
+    if (nk == 2 && e.cols_per_block > kEdge2MaxCols) e.cols_per_block = kEdge2MaxCols;
+    return e;
+}
 int flat_blocks(size_t n, const Geom &g) { return (int)((n + g.block_2d - 1) / g.block_2d); }
 int bt_blocks(int E, int C, const Geom &g) { return flat_blocks(E, g) + flat_blocks(C, g); }
 
@@ -2091,8 +2101,9 @@ int fe_edge_variant(const DevMesh &m, int L, int vmix, bool del4) {
 }
 
 template <typename R>
-void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s, bool wide) {
+void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g0, hipStream_t s, bool wide) {
     const int var = fe_edge_variant(a.m, a.L, a.vmix, a.D2 != nullptr) | (wide ? 8 : 0);
+    const Geom g = edge_geom(g0, a.L > kWave ? 2 : 1);
     SSE_NK_ADD_VAR(a.L > kWave, a.ubar_add != nullptr, var, fe_edge_kernel, xcd_grid(col_blocks(a.m.E, g)), col_block(g), a);
 }
 template <typename R>
@@ -2106,7 +2117,7 @@ void launch_fe_vertex_batch(const BatchLaunch<FEVertexArgs<R>> &b, int nk, bool 
 template <typename R>
 void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g,
                           hipStream_t s) {
-    SSE_NK_ADD_VAR(nk == 2, add, var, fe_edge_batch, xcd_grid(b.blocks), col_block(g), b);
+    SSE_NK_ADD_VAR(nk == 2, add, var, fe_edge_batch, xcd_grid(b.blocks), col_block(edge_geom(g, nk)), b);
 }
 
 template <typename R>
