@@ -100,14 +100,33 @@ def test_batch_rejects_mixed_schemes(dev, stream):
         b.add(s2)
 
 
+@pytest.mark.parametrize("L", [60, 100])
 @pytest.mark.parametrize("geom", [(1, 64), (2, 128), (8, 512), (16, 1024)])
-def test_geometry_does_not_change_results(dev, stream, geom):
-    case = cases.c1(n=12, L=60, steps=3)
+def test_geometry_does_not_change_results(dev, stream, geom, L):
+    # L = 100: the two-chunk edge pass caps its workgroups at 4 wavefronts,
+    # so geometries of 8 and 16 columns per block launch it with fewer
+    case = cases.c1(n=12, L=L, steps=3)
     ref = run_alone(dev, case, 3, stream)
     _, st = dev.state_from_case(case, stream=stream)
     st.set_geometry(*geom)
     assert st.step(3) == 0
     assert_same(st.read(), ref, f"geometry {geom}")
+
+
+@pytest.mark.parametrize("geom", [(8, 512), (16, 1024)])
+def test_batch_geometry_with_deep_members(dev, stream, geom):
+    cs = member_cases(0)
+    refs = [run_alone(dev, c, 3, stream) for c in cs]
+    keep, b = [], dev.Batch(stream=stream)
+    for c in cs:
+        dm, st = dev.state_from_case(c, stream=stream)
+        keep.append(dm)
+        b.add(st)
+    b.set_geometry(*geom)
+    b.compile()
+    assert b.step(3) == 0
+    for i, st in enumerate(b.members):
+        assert_same(st.read(), refs[i], f"batch geometry {geom}, member {i}")
 
 
 @pytest.mark.parametrize("precision", [0, 1])
