@@ -257,9 +257,11 @@ int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, size_t *byt
 
 /* Launch geometry of the state's kernels; results do not depend on it.
  * cols_per_block: wavefronts per workgroup of the column kernels (one
- * wavefront per vertical column), 1, 2, 4, 8 or 16; block_2d: threads per
- * workgroup of the 2D kernels (barotropic evaluations, reconciliation), a
- * multiple of 64 in [64, 1024].  Defaults 4 and 256.  SSE_EINVAL otherwise. */
+ * wavefront per vertical column), 1, 2, 4, 8 or 16 (the edge pass over more
+ * than 64 layers takes at most 4, to keep its operands in registers);
+ * block_2d: threads per workgroup of the 2D kernels (barotropic evaluations,
+ * reconciliation), a multiple of 64 in [64, 1024].  Defaults 4 and 256.
+ * SSE_EINVAL otherwise. */
 int sse_state_set_geometry(sse_state *s, int cols_per_block, int block_2d);
 
 /* enable != 0: the next sse_step / sse_step_async captures the launches of one
