@@ -58,10 +58,10 @@ __device__ __forceinline__ int column_id(int n) {
 //    instructions for FP64 values.
 // The kernels of both precisions use DPP for every value type (the FP64
 // edge pass, once its column loads took 32-bit scalar offsets, had the
-// registers for it and became 3.7% faster than with shuffles).  The
-// thickness and assembly passes, whose few column sums do not matter, keep
-// the default shuffle form.  The butterfly steps that cross rows (i ^ 32,
-// i ^ 16) are shuffles in both forms.
+// registers for it and became 3.7% faster than with shuffles; the assembly
+// pass, 11%).  The butterfly steps that cross rows (i ^ 32, i ^ 16) are
+// shuffles in both forms, and the butterfly keeps its pairwise order, so a
+// column sum has the same bits in both.
 // ---------------------------------------------------------------------------
 template <typename R>
 constexpr bool kDppFor = true;
@@ -1477,7 +1477,7 @@ __device__ __forceinline__ void thickness_body(const THArgs &a, int first) {
             if (ok[c]) col_st(a.h_out + base, kk[c], hv[c]);
             bad |= ok[c] && !isfinite(hv[c]);
         }
-        const double sum = col_sum<NK>(hv);
+        const double sum = col_sum<NK, true>(hv);
         if (lane == 0) a.zeta_out[i] = wet[q] ? sum - m.H[i] : 0.0;
     }
     if (bad && a.nonfinite) *a.nonfinite = 1;
@@ -1731,8 +1731,8 @@ __device__ __forceinline__ void assemble_body(const AssembleArgs<R> &a, int firs
             hu[c] = he[c] * (double)u;
             bad |= ok[c] && !isfinite((double)u);
         }
-        const double sh = col_sum<NK>(he);
-        const double shu = col_sum<NK>(hu);
+        const double sh = col_sum<NK, true>(he);
+        const double shu = col_sum<NK, true>(hu);
         if (lane == 0) a.ubar[e] = wet[q] ? shu / sh : 0.0;
     }
     if (bad && a.nonfinite) *a.nonfinite = 1;
@@ -1749,7 +1749,7 @@ __global__ void __launch_bounds__(1024) zeta_kernel(DevMesh m, int L, const doub
         int k = lane + c * kWave;
         hv[c] = (k < L) ? h[(size_t)i * L + k] : 0.0;
     }
-    const double s = col_sum<NK>(hv);
+    const double s = col_sum<NK, true>(hv);
     if (lane == 0) zeta[i] = m.cmask[i] ? s - m.H[i] : 0.0;
 }
 
@@ -1772,7 +1772,7 @@ __global__ void __launch_bounds__(1024) edge_flux_sum_kernel(DevMesh m, int L, c
             f[c] = he * ((double)X[(size_t)e * L + k] + ua);
         }
     }
-    const double s = col_sum<NK>(f);
+    const double s = col_sum<NK, true>(f);
     if (lane == 0) F[e] = m.emask[e] ? s : 0.0;
 }
 
