@@ -1848,8 +1848,11 @@ __global__ void __launch_bounds__(1024) fe_vertex_batch(BatchLaunch<FEVertexArgs
 // none 12.1, 5: 11.2, 6: 11.6, 7: 10.8, 8: 11.4 ms).  With 32-bit scalar
 // column offsets and DPP lane moves the pass fits 8 waves (57-63 VGPRs, 78
 // SGPRs, no scratch): FP64 9.78 -> 9.65 ms, C1 mixed 6.03 -> 5.94 ms/step.
-template <int NK, typename R>
-constexpr int edge_min_waves() { return NK != 1 ? kEdge2Waves : 8; }
+// The variants with the implicit vertical-mixing solve (kVar bit 1) hold
+// its tridiagonal operands as well and run better at 7 (C1 with mixing 8.68
+// -> 8.57 ms/step; the biharmonic variant gains nothing from 7).
+template <int NK, typename R, int kVar>
+constexpr int edge_min_waves() { return NK != 1 ? kEdge2Waves : (kVar & 2) ? 7 : 8; }
 // The two-chunk pass (L > 64) holds twice the operands per lane; with
 // workgroups of at most kEdge2MaxCols wavefronts its launch bound lets the
 // compiler keep them in registers instead of scratch.
@@ -1884,11 +1887,11 @@ __global__ void __launch_bounds__(1024) div_batch(BatchLaunch<DivArgs<R>> b) {
 }
 
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R>())) fe_edge_kernel(FEEdgeArgs<R> a) {
+__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R, kVar>())) fe_edge_kernel(FEEdgeArgs<R> a) {
     fe_edge_body<NK, R, kAdd, kVar>(a, column_id(a.m.E));
 }
 template <int NK, typename R, bool kAdd, int kVar>
-__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R>())) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
+__global__ void __launch_bounds__(edge_max_threads<NK>(), (edge_min_waves<NK, R, kVar>())) fe_edge_batch(BatchLaunch<FEEdgeArgs<R>> b) {
     int2 t;
     if (batch_entry(b.table, b.blocks, t)) fe_edge_body<NK, R, kAdd, kVar>(b.args[t.x], batch_column(t.y));
 }
