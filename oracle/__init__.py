@@ -27,7 +27,8 @@ Primitive Equations" (arXiv 2105.13484).
                    flux-form SSH reconciliation of Section 3.4.
 
 Everything is FP64 NumPy with whole-array operations; column sums over the
-layers use a fixed pairwise order (``layered.colsum``).
+layers are correctly rounded (``layered.colsum``), so no particular addition
+order is built in.
 
 The discrete forms of the nonlinear terms (pressure gradient in tilted
 layers, z-star vertical velocity, vertical boundary conditions, vorticity

@@ -33,6 +33,7 @@ Readings of what the paper leaves to MPAS (each stated where it is used):
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -63,27 +64,44 @@ class Setup:
         return self.h_ref.shape[1]
 
 
-COLSUM_WIDTH = 128
+SUM_ORDERS = ("exact", "top_down", "bottom_up")
+_sum_order = "exact"
+
+
+def set_sum_order(order: str) -> str:
+    """Selects how ``colsum`` adds the layers; returns the previous choice.
+
+    "exact" (the default, and the only one the parity tests compare against)
+    is the correctly rounded sum.  "top_down" and "bottom_up" add the layers
+    one after the other from the surface or from the bottom; they exist only
+    to measure how far the rounding of column sums alone moves a run, which is
+    what sets the parity bounds of long windows.
+    """
+    global _sum_order
+    if order not in SUM_ORDERS:
+        raise ValueError(f"unknown summation order {order!r}")
+    prev, _sum_order = _sum_order, order
+    return prev
 
 
 def colsum(x: np.ndarray) -> np.ndarray:
-    """sum_{k=1}^{L} x_k in a fixed pairwise order.
+    """sum_{k=1}^{L} x_k of every row, the sums over the layers of a column
+    (the split BBspl, G-bar of Algorithm 1, the fluxes F^h of Section 3.4,
+    zeta = sum h - H, the z-star column totals).
 
-    The layers are padded with zeros to 128 and added by repeated halving
-    (x_i + x_{i+64}, then + the partner 32 apart, ...).  The paper fixes no
-    summation order; a fixed pairwise one keeps the cancellation-prone column
-    diagnostics (zeta = sum h - H, the split, G-bar) reproducible.
+    The paper fixes no summation order.  The default is the correctly rounded
+    sum of the row (``math.fsum``, Shewchuk's exact partials), which no
+    addition order can improve on, so that the oracle carries no particular
+    association of its own.
     """
-    N, L = x.shape
-    if L > COLSUM_WIDTH:
-        raise ValueError("at most 128 layers")
-    a = np.zeros((N, COLSUM_WIDTH))
-    a[:, :L] = x
-    half = COLSUM_WIDTH // 2
-    while half >= 1:
-        a = a[:, :half] + a[:, half:2 * half]
-        half //= 2
-    return a[:, 0]
+    N = x.shape[0]
+    if _sum_order == "exact":
+        return np.fromiter(map(math.fsum, x), float, count=N)
+    cols = range(x.shape[1]) if _sum_order == "top_down" else range(x.shape[1] - 1, -1, -1)
+    acc = np.zeros(N)
+    for k in cols:
+        acc = acc + x[:, k]
+    return acc
 
 
 def safe_ratio(num: np.ndarray, den: np.ndarray, mask: np.ndarray) -> np.ndarray:
@@ -218,14 +236,22 @@ def pressure_gradient_force(h: np.ndarray, st: Setup) -> np.ndarray:
     return -(dp + p.gravity * rho_e * dz) / (p.rho0 * m.dcEdge[:, None])
 
 
-def T_u(u: np.ndarray, h: np.ndarray, st: Setup) -> np.ndarray:
-    """T^u_k(u) = -grad|u|^2/2 - (k.curl u) u^perp - \\bar(w D_{z^t} u)^m - grad p/rho0 + nu_h lap u."""
+def T_u(u: np.ndarray, h: np.ndarray, st: Setup, w: np.ndarray | None = None) -> np.ndarray:
+    """T^u_k(u) = -grad|u|^2/2 - (k.curl u) u^perp - \\bar(w D_{z^t} u)^m - grad p/rho0 + nu_h lap u.
+
+    w (cells, L + 1) is the interface vertical velocity; by default the one
+    the thickness equation gives for (h, u) (``vertical_velocity``).  At an
+    edge it is the mean of the two cells, and zero at the surface and the
+    bottom.
+    """
     m, p = st.mesh, st.params
     he = trisk.cell_to_edge(h, m)
     K = trisk.kinetic_energy(u, m)
     q = trisk.vorticity_on_edges(trisk.curl(u, m), m)
     vort = trisk.tangential_flux(q, u, m)
-    w_e = trisk.cell_to_edge(vertical_velocity(h, u, st), m)
+    if w is None:
+        w = vertical_velocity(h, u, st)
+    w_e = trisk.cell_to_edge(w, m)
     w_e[:, 0] = 0.0
     w_e[:, -1] = 0.0
     wdz = w_e * D_zt(u, he)
