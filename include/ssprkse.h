@@ -48,7 +48,15 @@ typedef enum {
 } sse_status;
 
 enum { SSE_SCHEME_SSPRK2 = 2, SSE_SCHEME_SSPRK3 = 3 };
-enum { SSE_FP64 = 0, SSE_MIXED = 1 };
+/* Precision (Section 3.4 keeps the conservation in the thickness and
+ * reconciliation updates): FP64 runs everything in double.  MIXED stores the
+ * velocity-like 3D fields and runs the tendency arithmetic and the barotropic
+ * substep state in float, keeping h, rho, zeta, the column sums that form
+ * G-bar and F^h, the accumulated transport F^zeta, u^A and D^e in double.
+ * MIXED_BT64 is MIXED with the barotropic substep loop (Algorithms 3 and 4)
+ * in double, so that zeta is not limited by float rounding inside the loop;
+ * its 3D part is MIXED's. */
+enum { SSE_FP64 = 0, SSE_MIXED = 1, SSE_MIXED_BT64 = 2 };
 enum { SSE_ZSTAR = 0, SSE_ISOPYCNAL = 1 };
 /* Reconciliation of Section 3.4: OFF sets u^A = 0; EXACT uses the fluxes the
  * thickness actually received in earlier stages (F^zeta_1, F^zeta_2) inside
@@ -118,7 +126,8 @@ typedef struct {
 /*
  * Run parameters.  Every physical constant is explicit:
  *   n_layers L (1..128); scheme SSE_SCHEME_SSPRK2 | SSE_SCHEME_SSPRK3;
- *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 | SSE_MIXED;
+ *   substeps M >= 1 (barotropic step dt / M); precision SSE_FP64 |
+ *   SSE_MIXED | SSE_MIXED_BT64;
  *   vcoord SSE_ZSTAR | SSE_ISOPYCNAL (Section 2, vertical coordinate);
  *   reconcile SSE_RECONCILE_*; vmix SSE_VMIX_*; hdiff SSE_HDIFF_*; tracer
  *   SSE_TRACER_*; dt > 0 (s); gravity g; rho0 (Boussinesq reference

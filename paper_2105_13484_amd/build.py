@@ -26,16 +26,34 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into ``libssprkse.so`` (always rebuilds)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    """Compile every source into ``libssprkse.so`` (always rebuilds).  The
+    sources compile in parallel to objects in a temporary folder, then link."""
+    import tempfile
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="ssprkse_build_") as tmpdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, src + ".o")
+            cmd = [cc, *[f for f in HIPCC_FLAGS if f != "-shared"], "-c", "-o", obj, os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+            objs.append(obj)
+        errors = []
+        for src, proc in procs:
+            out, err = proc.communicate()
+            if proc.returncode != 0:
+                errors.append(f"{src}: hipcc failed ({proc.returncode}):\n{out}\n{err}")
+        if errors:
+            raise RuntimeError("\n".join(errors))
+        tmp = LIB + ".tmp"
+        cmd = [cc, *HIPCC_FLAGS, "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc link failed ({res.returncode}):\n{res.stdout}\n{res.stderr}")
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -9,9 +9,10 @@
 // the reconciliation deficits.  Everything is enqueued on the state's stream.
 //
 // Precision: the orchestration is a template over the real type R of the
-// velocity-like 3D fields and the substep state (double for SSE_FP64, float
-// for SSE_MIXED); thickness, density, SSH and all 2D fields handed between
-// stages are double in both modes.
+// velocity-like 3D fields (double for SSE_FP64, float for SSE_MIXED and
+// SSE_MIXED_BT64); the barotropic substep state is R, except that
+// SSE_MIXED_BT64 keeps it double; thickness, density, SSH and all 2D fields
+// handed between stages are double in every mode.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,8 +35,8 @@ struct Work {
     void *U, *T1, *T2;                       // R [E][L]: u^n and two stage buffers
     void *B, *Wt;                            // R [C][L]: K - nu_h div u, w at layer tops
     void *Z;                                 // R [V][L]: relative vorticity
-    void *bt_u1, *bt_uh, *bt_ua, *bt_uo;     // R [E]: substep stages, loop input / output
-    void *bt_z1, *bt_zh, *bt_za, *bt_zo;     // R [C]
+    void *bt_u1, *bt_uh, *bt_ua, *bt_uo;     // [E] substep stages, loop input / output, in the loop's type
+    void *bt_z1, *bt_zh, *bt_za, *bt_zo;     // [C]
     double *Hs, *H1, *H2, *frac, *rho;       // [C][L]
     double *ubar_n, *ub1, *ub2, *ub_half, *ubar_new, *G0, *G1, *Gh, *Gi, *Fz1, *Fz2, *Fz3, *Sh1, *Fh1, *Sh2,
         *Fh2, *Sh3, *Pp, *Ftot, *uA;         // [E]
@@ -52,9 +53,12 @@ constexpr int kD3C = 5, kD2E = 20, kD2C = 5;                    // arrays of typ
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-size_t real_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : sizeof(double); }
+size_t real_size(int precision) { return precision == SSE_FP64 ? sizeof(double) : sizeof(float); }
 
-size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff, int tracer) {
+// Bytes of the barotropic loop's real type: FP32 only in SSE_MIXED.
+size_t bt_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : sizeof(double); }
+
+size_t workspace_bytes(int C, int E, int V, int L, size_t rs, size_t bs, int hdiff, int tracer) {
     size_t b = 0;
     if (tracer) b += 3 * align_up((size_t)C * L * 8);
     if (hdiff == SSE_HDIFF_DEL4)
@@ -62,8 +66,8 @@ size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff, int tra
     b += kR3E * align_up((size_t)E * L * rs);
     b += kR3C * align_up((size_t)C * L * rs);
     b += kR3V * align_up((size_t)V * L * rs);
-    b += kR2E * align_up((size_t)E * rs);
-    b += kR2C * align_up((size_t)C * rs);
+    b += kR2E * align_up((size_t)E * bs);
+    b += kR2C * align_up((size_t)C * bs);
     b += kD3C * align_up((size_t)C * L * 8);
     b += kD2E * align_up((size_t)E * 8);
     b += kD2C * align_up((size_t)C * 8);
@@ -71,7 +75,7 @@ size_t workspace_bytes(int C, int E, int V, int L, size_t rs, int hdiff, int tra
     return b;
 }
 
-Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff, int tracer) {
+Work carve(void *buf, int C, int E, int V, int L, size_t rs, size_t bs, int hdiff, int tracer) {
     char *p = static_cast<char *>(buf);
     auto take = [&](size_t n) {
         void *r = p;
@@ -85,9 +89,9 @@ Work carve(void *buf, int C, int E, int V, int L, size_t rs, int hdiff, int trac
     for (auto q : r3c) *q = take((size_t)C * L * rs);
     w.Z = take((size_t)V * L * rs);
     void **r2e[] = {&w.bt_u1, &w.bt_uh, &w.bt_ua, &w.bt_uo};
-    for (auto q : r2e) *q = take((size_t)E * rs);
+    for (auto q : r2e) *q = take((size_t)E * bs);
     void **r2c[] = {&w.bt_z1, &w.bt_zh, &w.bt_za, &w.bt_zo};
-    for (auto q : r2c) *q = take((size_t)C * rs);
+    for (auto q : r2c) *q = take((size_t)C * bs);
     double **d3c[] = {&w.Hs, &w.H1, &w.H2, &w.frac, &w.rho};
     for (auto q : d3c) *q = static_cast<double *>(take((size_t)C * L * 8));
     double **d2e[] = {&w.ubar_n, &w.ub1, &w.ub2, &w.ub_half, &w.ubar_new, &w.G0, &w.G1, &w.Gh, &w.Gi, &w.Fz1,
@@ -208,6 +212,7 @@ struct sse_state {
     Work w{};
     size_t bytes = 0;
     size_t rs = 8;           // bytes of the real type R
+    bool bt64 = true;        // the barotropic loop runs in FP64 (SSE_FP64, SSE_MIXED_BT64)
     bool initialized = false;
     bool tracer_set = false; // tracer runs: the temperature has been given
     Geom geom{};             // launch geometry (autotuner knob)
@@ -286,7 +291,7 @@ int nk_of(int L) { return L <= kWave ? 1 : 2; }
 // the largest patch's LDS fits the device.
 bool bt_tiles_fit(const sse_state *s) {
     const DevBtTiles &t = s->mesh->bt;
-    return t.nP > 0 && (s->rs == 8 ? t.lds_d : t.lds_f) <= s->lds_max;
+    return t.nP > 0 && (s->bt64 ? t.lds_d : t.lds_f) <= s->lds_max;
 }
 
 // ---- building blocks -------------------------------------------------------
@@ -443,7 +448,7 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
             a.zeroF = sub == 0;
             if (s->rec) {
                 record(s, Kind::BT_TILE, a, 1, false, a.t.nP, sub, a.t.ks);
-                s->rec->entries.back().lds = s->rs == 8 ? a.t.lds_d : a.t.lds_f;
+                s->rec->entries.back().lds = std::is_same<R, double>::value ? a.t.lds_d : a.t.lds_f;
             } else {
                 ProfScope ps(s, SSE_PROF_BT_EVAL);
                 launch_bt_substep<R>(a, scheme, s->stream);
@@ -604,6 +609,16 @@ void assemble(sse_state *s, const R *X, const double *ubar_bt) {
     else launch_assemble<R>(a, s->geom, s->stream);
 }
 
+// The step's barotropic loop: FP32 state in SSE_MIXED, FP64 otherwise.
+template <typename R>
+void bt_loop_of(sse_state *s, int scheme, int M, double dt, const double *in_u, const double *in_z,
+                const double *G, double *out_u, double *out_z, double *F) {
+    if (s->bt64)
+        bt_loop<double>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F);
+    else
+        bt_loop<float>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F);
+}
+
 template <typename R>
 void step_ssprk3(sse_state *s) {
     Work &w = s->w;
@@ -614,20 +629,20 @@ void step_ssprk3(sse_state *s) {
     // Stage 1: baroclinic FE from (u^n, ut^n, zeta^n, h^n); predictor loop; thickness.
     fe_pass<R>(s, U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
                nullptr, nullptr, nullptr, 0);
-    bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    bt_loop_of<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
     thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt, w.Tn, w.T1s);
     // Stage 2: FE from (u-hat^{n+1}, ut-hat^{n+1}, zeta-hat^{n+1}, h-hat^{n+1}); second loop; thickness.
     fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_34, T2, w.G1, w.Sh2, w.Fh2, nullptr, 0, 0, nullptr,
                nullptr, nullptr, 0);
-    bt_loop<R>(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
+    bt_loop_of<R>(s, 3, M, dt, w.ub1, w.z1, w.G1, w.ub2, w.bt_zout, w.Fz2);
     recon(s, 0, w.Fz2, w.Fh2, w.Sh2, nullptr, nullptr, w.ub2, w.ub_half);
     thickness<R>(s, w.H1, w.Hs, COMB_34, w.H2, w.z_half, T1, 1.0, none, 0.0, w.ub1, 1.0, dt, w.T1s, w.Th);
     // Stage 3: FE from the n+1/2 stage -> ut^{n+1}; G interpolated by Interp_3.
     fe_pass<R>(s, T2, w.ub_half, nullptr, w.H2, w.z_half, COMB_THIRD, T1, w.Gh, w.Sh3, nullptr, w.Pp, 1.0, 1.0,
                w.Gi, w.G0, w.G1, 3);
     // Step 2: corrector loop from (ubar^n, zeta^n).
-    bt_loop<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
+    bt_loop_of<R>(s, 3, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz3);
     // Step 3: last thickness stage with u^A_3, then u^{n+1} and its split.
     recon(s, 1, w.Fz3, nullptr, w.Sh3, w.Pp, w.ubar_new, nullptr, nullptr);
     thickness<R>(s, w.H2, w.Hs, COMB_THIRD, w.Hs, w.zeta_n, U, 0.5, T1, 0.5, w.ubar_new, 0.5, dt, w.Th, w.Tn);
@@ -643,12 +658,12 @@ void step_ssprk2(sse_state *s) {
     const R *none = nullptr;
     fe_pass<R>(s, U, nullptr, w.ubar_n, w.Hs, w.zeta_n, COMB_NONE, T1, w.G0, w.Sh1, w.Fh1, nullptr, 0, 0,
                nullptr, nullptr, nullptr, 0);
-    bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
+    bt_loop_of<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.G0, w.ub1, w.bt_zout, w.Fz1);
     recon(s, 0, w.Fz1, w.Fh1, w.Sh1, nullptr, nullptr, nullptr, nullptr);
     thickness<R>(s, w.Hs, nullptr, COMB_NONE, w.H1, w.z1, U, 1.0, none, 0.0, nullptr, 0.0, dt, w.Tn, w.T1s);
     fe_pass<R>(s, T1, w.ub1, nullptr, w.H1, w.z1, COMB_HALF, T2, w.G1, w.Sh2, nullptr, w.Pp, 0.0, 1.0, w.Gi,
                w.G0, nullptr, 2);
-    bt_loop<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
+    bt_loop_of<R>(s, 2, M, dt, w.ubar_n, w.zeta_n, w.Gi, w.ubar_new, w.bt_zout, w.Fz2);
     recon(s, 2, w.Fz2, nullptr, w.Sh2, w.Pp, w.ubar_new, nullptr, nullptr);
     thickness<R>(s, w.H1, w.Hs, COMB_HALF, w.Hs, w.zeta_n, T2, 1.0, none, 0.0, w.ubar_new, 1.0, dt, w.T1s, w.Tn);
     assemble<R>(s, T2, w.ubar_new);
@@ -667,7 +682,10 @@ int check_params(const sse_params *p) {
     if (p->n_layers < 1 || p->n_layers > 2 * kWave) { set_error("n_layers must be in [1, 128]"); return SSE_EINVAL; }
     if (p->scheme != SSE_SCHEME_SSPRK2 && p->scheme != SSE_SCHEME_SSPRK3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
     if (p->substeps < 1) { set_error("substeps must be >= 1"); return SSE_EINVAL; }
-    if (p->precision != SSE_FP64 && p->precision != SSE_MIXED) { set_error("precision must be SSE_FP64 or SSE_MIXED"); return SSE_EINVAL; }
+    if (p->precision != SSE_FP64 && p->precision != SSE_MIXED && p->precision != SSE_MIXED_BT64) {
+        set_error("precision must be SSE_FP64, SSE_MIXED or SSE_MIXED_BT64");
+        return SSE_EINVAL;
+    }
     if (p->vcoord != SSE_ZSTAR && p->vcoord != SSE_ISOPYCNAL) { set_error("vcoord must be ZSTAR or ISOPYCNAL"); return SSE_EINVAL; }
     if (p->reconcile < SSE_RECONCILE_OFF || p->reconcile > SSE_RECONCILE_LITERAL) { set_error("invalid reconcile mode"); return SSE_EINVAL; }
     if (p->vmix != SSE_VMIX_EXPLICIT && p->vmix != SSE_VMIX_IMPLICIT) { set_error("vmix must be SSE_VMIX_EXPLICIT or SSE_VMIX_IMPLICIT"); return SSE_EINVAL; }
@@ -949,7 +967,8 @@ extern "C" int sse_state_workspace_bytes(const sse_mesh *m, const sse_params *p,
     if (!m || !bytes) { set_error("NULL argument"); return SSE_EINVAL; }
     int rc = check_params(p);
     if (rc) return rc;
-    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision), p->hdiff, p->tracer);
+    *bytes = workspace_bytes(m->C, m->E, m->V, p->n_layers, real_size(p->precision), bt_size(p->precision), p->hdiff,
+                             p->tracer);
     return SSE_OK;
 }
 
@@ -963,7 +982,8 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
     mb += bt_tiles_bytes(d);
-    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision), p->hdiff, p->tracer);
+    *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision),
+                                  bt_size(p->precision), p->hdiff, p->tracer);
     return SSE_OK;
 }
 
@@ -973,8 +993,8 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     *out = nullptr;
     int rc = check_params(p);
     if (rc) return rc;
-    const size_t rs = real_size(p->precision);
-    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs, p->hdiff, p->tracer);
+    const size_t rs = real_size(p->precision), bs = bt_size(p->precision);
+    size_t need = workspace_bytes(m->C, m->E, m->V, p->n_layers, rs, bs, p->hdiff, p->tracer);
     if (!dev_workspace || bytes < need) { set_error("state workspace too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) { set_error("state workspace must be 256-byte aligned"); return SSE_EINVAL; }
     sse_state *s = new sse_state();
@@ -982,7 +1002,8 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->p = *p;
     s->stream = static_cast<hipStream_t>(stream);
     s->rs = rs;
-    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs, p->hdiff, p->tracer);
+    s->bt64 = bs == sizeof(double);
+    s->w = carve(dev_workspace, m->C, m->E, m->V, p->n_layers, rs, bs, p->hdiff, p->tracer);
     s->bytes = bytes;
     int dev = 0, lds_max = 0;
     (void)hipGetDevice(&dev);
@@ -1324,10 +1345,10 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
     SSE_HIP(hipMemcpyAsync(w.ub1, bi.data(), E * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.z1, zi.data(), C * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.G0, gi.data(), E * 8, hipMemcpyHostToDevice, st));
-    if (s->rs == 4)
-        bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
-    else
+    if (s->bt64)
         bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+    else
+        bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipMemcpyAsync(bo.data(), w.ub2, E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(zo.data(), w.bt_zout, C * 8, hipMemcpyDeviceToHost, st));
@@ -1439,7 +1460,7 @@ int batch_record(sse_batch *b) {
     std::map<Key, std::vector<std::pair<int, RecEntry>>> groups;
     for (size_t mi = 0; mi < b->members.size(); ++mi) {
         sse_state *s = b->members[mi];
-        if (s->rs != s0->rs || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
+        if (s->p.precision != s0->p.precision || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
             set_error("batch members must share precision, scheme and vertical coordinate");
             return SSE_EINVAL;
         }
@@ -1496,14 +1517,23 @@ template <typename R>
 void batch_enqueue(const sse_batch *b) {
     const Geom &g = b->geom;
     hipStream_t st = b->stream;
+    const bool bt64 = b->members[0]->bt64;  // members share their precision mode
     for (const BatchOp &op : b->prog) {
         switch (op.kind) {
             case Kind::FE_CELL: launch_fe_cell_batch<R>(bl<FECellArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_VERTEX: launch_fe_vertex_batch<R>(bl<FEVertexArgs<R>>(b, op), op.nk, op.add, g, st); break;
             case Kind::FE_EDGE: launch_fe_edge_batch<R>(bl<FEEdgeArgs<R>>(b, op), op.nk, op.add, op.var, g, st); break;
-            case Kind::BT_EVAL: launch_bt_eval_batch<R>(bl<BTEvalArgs<R>>(b, op), op.var != 0, g, st); break;
+            case Kind::BT_EVAL:
+                if (bt64) launch_bt_eval_batch<double>(bl<BTEvalArgs<double>>(b, op), op.var != 0, g, st);
+                else launch_bt_eval_batch<float>(bl<BTEvalArgs<float>>(b, op), op.var != 0, g, st);
+                break;
             case Kind::BT_TILE:
-                launch_bt_substep_batch<R>(bl<BTTileArgs<R>>(b, op), b->members[0]->p.scheme, op.var, op.lds, st);
+                if (bt64)
+                    launch_bt_substep_batch<double>(bl<BTTileArgs<double>>(b, op), b->members[0]->p.scheme, op.var,
+                                                    op.lds, st);
+                else
+                    launch_bt_substep_batch<float>(bl<BTTileArgs<float>>(b, op), b->members[0]->p.scheme, op.var,
+                                                   op.lds, st);
                 break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;
@@ -1551,7 +1581,7 @@ extern "C" int sse_batch_add(sse_batch *b, sse_state *s) {
     if (s->stream != b->stream) { set_error("batch members must use the batch's stream"); return SSE_EINVAL; }
     if (!b->members.empty()) {
         const sse_state *s0 = b->members[0];
-        if (s->rs != s0->rs || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
+        if (s->p.precision != s0->p.precision || s->p.scheme != s0->p.scheme || s->p.vcoord != s0->p.vcoord) {
             set_error("batch members must share precision, scheme and vertical coordinate");
             return SSE_EINVAL;
         }

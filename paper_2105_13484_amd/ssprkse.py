@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SSE_LIB_PATH") or os.path.join(_HERE, "libssprkse.so")
 
 SSE_OK, SSE_EINVAL, SSE_ENOMEM, SSE_EDEVICE, SSE_ENONFINITE, SSE_ESTATE = range(6)
-SSE_FP64, SSE_MIXED = 0, 1
+SSE_FP64, SSE_MIXED, SSE_MIXED_BT64 = 0, 1, 2
 SSE_ZSTAR, SSE_ISOPYCNAL = 0, 1
 SSE_RECONCILE_OFF, SSE_RECONCILE_EXACT, SSE_RECONCILE_LITERAL = 0, 1, 2
 SSE_VMIX_EXPLICIT, SSE_VMIX_IMPLICIT = 0, 1

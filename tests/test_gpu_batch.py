@@ -48,7 +48,7 @@ def run_alone(dev, case, steps, stream):
     return st.read()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_equals_alone(dev, stream, precision, graph):
     cs = member_cases(precision)

@@ -17,7 +17,8 @@ from oracle.layered import Setup
 from synthetic import cases
 from tests.helpers import rel_l2, smooth_case
 from tests.test_gpu_mixed import check_state
-from tests.test_gpu_parity import TOL, _assert_parity, _compare_state, _noisy_state, _report, _run_both
+from tests.parity_cases import del4
+from tests.test_gpu_parity import TOL, _check_kernel, _noisy_state, check_case
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +31,6 @@ def dev():
     from paper_2105_13484_amd import ssprkse
     ssprkse.load()
     return ssprkse
-
-
-def del4(case, nu):
-    return cases.with_params(case, hdiff=1, nu_h=nu)
 
 
 D4_CASES = {
@@ -54,42 +51,19 @@ def test_del4_feuler_parity(dev, name):
     ut1, G = S.baroclinic_feuler(u, u - ubar[:, None], zeta, h, case.params.dt, st_o)
     _, st = dev.state_from_case(case)
     g_ut1, g_G = st.debug_baroclinic_feuler(u, ubar, zeta, h, case.params.dt)
-    errs = {"ut1": rel_l2(g_ut1, ut1), "G": rel_l2(g_G, G)}
-    _report(f"feuler del4 {name}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"feuler del4 {name}", {"ut1": (g_ut1, ut1), "G": (g_G, G)})
     # the biharmonic term is not negligible on these cases
     del2 = cases.with_params(case, hdiff=0, nu_h=0.0)
     ex, _ = S.baroclinic_feuler(u, u - ubar[:, None], zeta, h, case.params.dt, Setup.from_case(del2))
     assert rel_l2(ex, ut1) > 1e3 * TOL
 
 
-@pytest.mark.parametrize("scheme,steps", [(2, 6), (3, 12)])
-def test_del4_steps(dev, scheme, steps):
-    case = del4(smooth_case(n=10, L=5, scheme=scheme, M=6, dt=180.0), 2e10)
-    rc, gpu, ref = _run_both(dev, case, steps)
-    assert rc == 0
-    _assert_parity(f"del4 scheme={scheme}", case, steps, _compare_state(gpu, *ref))
-
-
-def test_del4_c1_recipe_reduced(dev):
-    case = del4(cases.c1(n=32, L=60, steps=4), 1e9)
-    rc, gpu, ref = _run_both(dev, case, 4)
-    assert rc == 0
-    _assert_parity("del4 C1 recipe 32x32x60, 4 steps", case, 4, _compare_state(gpu, *ref))
-
-
-def test_del4_c2_recipe_reduced(dev):
-    case = del4(cases.sphere_case(3, 60, cases.SEED_BASE + 200, substeps=30, dt_btr=240.0), 1e16)
-    rc, gpu, ref = _run_both(dev, case, 3)
-    assert rc == 0
-    _assert_parity("del4 C2 recipe level 3 x 60, 3 steps", case, 3, _compare_state(gpu, *ref))
-
-
-def test_del4_with_vertical_mixing(dev):
-    case = cases.with_params(del4(cases.c1(n=16, L=20, steps=3), 1e9), vmix=1, nu_v=1e-2, c_drag=2e-3)
-    rc, gpu, ref = _run_both(dev, case, 3)
-    assert rc == 0
-    _assert_parity("del4 + vertical mixing 16x16x20, 3 steps", case, 3, _compare_state(gpu, *ref))
+@pytest.mark.parametrize("name", ["del4_ssprk2", "del4_ssprk3", "del4_c1_recipe_32x32x60",
+                                  "del4_c2_recipe_level3x60", "del4_vmix_16x16x20"])
+def test_del4_steps(dev, name):
+    """Smooth stratified hex with both schemes; the C1 recipe on a 32x32 hex; the
+    C2 recipe at level 3; together with implicit vertical mixing."""
+    check_case(dev, name)
 
 
 @pytest.mark.parametrize("name", ["hex12_L60", "sphere3_land_L7"])

@@ -9,19 +9,19 @@
 * a batch whose members span these extremes gives each member its solo bits;
 * sse_step(0) is a no-op.
 
-Bounds as in the other parity files: FP64 relative L2 <= 1e-11 per field
-(4x the oracle's own drift where that is larger); mixed precision 1e-5 on
-velocities and 1e-9 on h and on SSH relative to zeta + H.
+FP64 cases and bounds come from ``tests/parity_cases.py`` (relative L2 1e-11 and
+largest element error 1e-10 per field, or four times the oracle's own measured
+rounding spread where that is larger); mixed precision as in the mixed-precision
+parity file.
 """
 import numpy as np
 import pytest
 
+from oracle import ssprk_se as S
 from synthetic import cases
 from tests.helpers import rel_l2
-from tests.test_gpu_combined import all_terms
 from tests.test_gpu_mixed import check_state
-from tests.test_gpu_parity import _assert_parity, _compare_state, _run_both
-from tests.test_gpu_tracer import _check_fp64, _run
+from tests.test_gpu_parity import check_case, run_case
 
 pytestmark = pytest.mark.gpu
 
@@ -36,26 +36,17 @@ def dev():
     return ssprkse
 
 
-FP64_CASES = {
-    "hex8_L128": (lambda: cases.c1(n=8, L=128, steps=2), 2),
-    "hex10_L65": (lambda: cases.c1(n=10, L=65, steps=2), 2),
-    "hex12_L1_ssprk3": (lambda: cases.c1(n=12, L=1, steps=6), 6),
-    "hex12_L1_ssprk2": (lambda: cases.with_params(cases.c1(n=12, L=1, steps=4), scheme=2), 4),
-    "sphere3_land_L1": (lambda: cases.sphere_case(3, 1, 91, substeps=5, dt_btr=200.0), 4),
-    "hex10_L20_M1_ssprk3": (lambda: cases.c1(n=10, L=20, substeps=1, dt_btr=15.0, steps=6), 6),
-    "hex10_L20_M1_ssprk2": (lambda: cases.with_params(cases.c1(n=10, L=20, substeps=1, dt_btr=15.0, steps=4),
-                                                      scheme=2), 4),
-}
+FP64_CASES = ["hex8_L128", "hex10_L65", "hex12_L1_ssprk3", "hex12_L1_ssprk2", "sphere3_land_L1",
+              "hex10_L20_M1_ssprk3", "hex10_L20_M1_ssprk2"]
 
 
-@pytest.mark.parametrize("name", sorted(FP64_CASES))
+@pytest.mark.parametrize("name", FP64_CASES)
 def test_extreme_shapes_fp64(dev, name):
-    make, steps = FP64_CASES[name]
-    case = make()
-    rc, gpu, ref = _run_both(dev, case, steps)
+    rc, gpu, ref = run_case(dev, name)
     assert rc == 0, dev.last_error()
-    _assert_parity(f"extreme {name}, {steps} steps", case, steps, _compare_state(gpu, *ref))
-    if case.params.n_layers == 1:
+    from tests import parity_cases as P
+    P.check(name, gpu, ref)
+    if gpu["u"].shape[1] == 1:
         # one layer: the velocity is its own barotropic part (to roundoff: the
         # forcing subtraction u - dt ((h u / h) / dt) need not cancel exactly)
         assert np.abs(gpu["u"][:, 0] - gpu["ubar"]).max() <= 1e-13 * np.abs(gpu["ubar"]).max()
@@ -63,15 +54,14 @@ def test_extreme_shapes_fp64(dev, name):
 
 def test_max_layers_mixed(dev):
     case = cases.with_params(cases.c1(n=8, L=128, steps=3), precision=1)
-    rc, gpu, ref = _run_both(dev, case, 3)
+    dm, st = dev.state_from_case(case)
+    rc, gpu, ref = st.step(3), st.read(), S.run(case, 3)
     assert rc == 0, dev.last_error()
     check_state("hex8_L128, 3 steps", case, gpu, ref)
 
 
 def test_max_layers_all_terms(dev):
-    case = all_terms(cases.c1(n=8, L=128, steps=2))
-    g, r = _run(dev, case, 2)
-    _check_fp64("all terms hex8_L128, 2 steps", case, 2, g, r)
+    check_case(dev, "all_terms_hex8_L128")
 
 
 @pytest.mark.parametrize("precision", [0, 1])

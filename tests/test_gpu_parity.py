@@ -1,12 +1,15 @@
 """GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
 
-Tolerance: relative L2 <= 1e-11 per field in FP64 (u, h, zeta, ubar).  Long
-runs amplify rounding: when the oracle itself, restarted from inputs perturbed
-by one unit in the last place, drifts further than that, the bound for a field
-becomes 4x that self-drift (measured in the test) -- the GPU then agrees with
-the oracle as well as the oracle agrees with itself.  Sizes are small enough
-for the oracle to finish in seconds, chosen with ragged tails (entity counts
-that are not multiples of the 4-column blocks or the 256-thread 2D blocks).
+Every comparison reports two measures per field: the relative L2 error and the
+largest element error relative to the field's largest magnitude.  Kernel-level
+comparisons (the debug entry points) must meet 1e-11 and 1e-10.  Whole steps
+take their case and their bounds from ``tests/parity_cases.py``: 1e-11 / 1e-10,
+or, where the oracle itself moves further under a different rounding of its
+column sums or a one-ulp change of its inputs (measured on the CPU and recorded
+in ``tests/golden/parity_bounds.json``), four times that measured spread.
+Sizes are small enough for the oracle to finish in seconds, chosen with ragged
+tails (entity counts that are not multiples of the 4-column blocks or the
+256-thread 2D blocks).
 """
 import os
 
@@ -16,11 +19,13 @@ import pytest
 from oracle import ssprk_se as S
 from oracle.layered import Setup
 from synthetic import cases
-from tests.helpers import rel_l2, smooth_case
+from tests import parity_cases as P
+from tests.helpers import smooth_case
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-11
+TOL = P.TOL_L2
+TOL_MAX = P.TOL_MAX
 
 
 @pytest.fixture(scope="module")
@@ -33,8 +38,8 @@ def dev():
     return ssprkse
 
 
-def _report(name, errs):
-    line = f"[parity] {name}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items())
+def _report(name, errs=None):
+    line = name if errs is None else f"[parity] {name}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items())
     print(line, flush=True)
     path = os.environ.get("SSE_PARITY_LOG")
     if path:
@@ -42,43 +47,30 @@ def _report(name, errs):
             f.write(line + "\n")
 
 
-def _self_drift(case, steps, seed=1):
-    """Oracle vs oracle started from inputs perturbed by ~1 ulp (relative 1e-16)."""
-    st = Setup.from_case(case)
-    rng = np.random.default_rng(seed)
-    u1, h1 = case.u.copy(), case.h.copy()
-    u2 = np.where(st.edge_mask[:, None], case.u * (1 + 1e-16 * rng.standard_normal(case.u.shape)), 0.0)
-    h2 = case.h * (1 + 1e-16 * rng.standard_normal(case.h.shape))
-    for _ in range(steps):
-        u1, h1 = S.step(u1, h1, st)
-        u2, h2 = S.step(u2, h2, st)
-    b1, _ = S.split(u1, h1, st)
-    b2, _ = S.split(u2, h2, st)
-    return {"u": rel_l2(u2, u1), "h": rel_l2(h2, h1), "zeta": rel_l2(S.ssh(h2, st), S.ssh(h1, st)),
-            "ubar": rel_l2(b2, b1)}
+def _check_kernel(name, errs):
+    """errs: {field: (gpu, oracle)}; both measures against 1e-11 / 1e-10."""
+    e = {k: P.field_errors(g, r) for k, (g, r) in errs.items()}
+    _report(name + ": " + P.format_errors(e))
+    for k, v in e.items():
+        assert v["l2"] <= TOL and v["max"] <= TOL_MAX, (name, k, v)
+    return e
 
 
-def _assert_parity(name, case, steps, errs):
-    _report(name, errs)
-    if max(errs.values()) < TOL:
-        return
-    drift = _self_drift(case, steps)
-    _report(name + " (oracle self-drift)", drift)
-    for k, v in errs.items():
-        assert v < max(TOL, 4.0 * drift[k]), (k, v, drift[k])
-
-
-def _compare_state(gpu, u, h, zeta, ubar):
-    return {"u": rel_l2(gpu["u"], u), "h": rel_l2(gpu["h"], h),
-            "zeta": rel_l2(gpu["zeta"], zeta), "ubar": rel_l2(gpu["ubar"], ubar)}
-
-
-def _run_both(dev, case, steps):
-    dm, st = dev.state_from_case(case)
+def run_case(dev, name, **state_kw):
+    """Runs a case of ``tests/parity_cases.py`` on the GPU and in the oracle."""
+    case, steps = P.build(name)
+    dm, st = dev.state_from_case(case, **state_kw)
     rc = st.step(steps)
     gpu = st.read()
-    u, h, zeta, ubar = S.run(case, steps)
-    return rc, gpu, (u, h, zeta, ubar)
+    if getattr(case.params, "tracer", 0):
+        gpu["T"] = st.read_tracer()
+    return rc, gpu, P.oracle_fields(case, steps)
+
+
+def check_case(dev, name):
+    rc, gpu, ref = run_case(dev, name)
+    assert rc == 0, dev.last_error()
+    return P.check(name, gpu, ref, report=_report)
 
 
 def _noisy_state(case, steps=3, seed=0):
@@ -114,9 +106,7 @@ def test_baroclinic_feuler_parity(dev, name):
     ut1, G = S.baroclinic_feuler(u, ut, zeta, h, case.params.dt, st_o)
     _, st = dev.state_from_case(case)
     g_ut1, g_G = st.debug_baroclinic_feuler(u, ubar, zeta, h, case.params.dt)
-    errs = {"ut1": rel_l2(g_ut1, ut1), "G": rel_l2(g_G, G)}
-    _report(f"feuler {name}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"feuler {name}", {"ut1": (g_ut1, ut1), "G": (g_G, G)})
 
 
 @pytest.mark.parametrize("name", sorted(KERNEL_CASES))
@@ -133,9 +123,7 @@ def test_barotropic_substep_parity(dev, name, scheme):
     u1, z1, F = sub(ubar, zeta, G, dt, M, st_o)
     _, st = dev.state_from_case(case)
     g_u1, g_z1, g_F = st.debug_barotropic_substep(scheme, M, dt, ubar, zeta, G)
-    errs = {"ubar": rel_l2(g_u1, u1), "zeta": rel_l2(g_z1, z1), "Fzeta": rel_l2(g_F, F)}
-    _report(f"bt{scheme} {name}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"bt{scheme} {name}", {"ubar": (g_u1, u1), "zeta": (g_z1, z1), "Fzeta": (g_F, F)})
 
 
 @pytest.mark.parametrize("name", sorted(KERNEL_CASES))
@@ -151,36 +139,25 @@ def test_thickness_stage_parity(dev, name, vcoord):
     z_out = S.ssh(h_out, st_o)
     _, st = dev.state_from_case(case)
     g_h, g_z = st.debug_thickness_stage(h, u, uA, dt)
-    errs = {"h": rel_l2(g_h, h_out), "zeta": rel_l2(g_z, z_out)}
-    _report(f"thickness vcoord={vcoord} {name}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"thickness vcoord={vcoord} {name}", {"h": (g_h, h_out), "zeta": (g_z, z_out)})
 
 
 # ---------------------------------------------------------------------------
 # whole steps
 # ---------------------------------------------------------------------------
-def test_c0_ssprk3_100_steps(dev):
-    case = cases.with_params(cases.c0(), scheme=3)
-    rc, gpu, ref = _run_both(dev, case, 100)
-    assert rc == 0
-    _assert_parity("C0 geometry, SSPRK3-SE, 100 steps", case, 100, _compare_state(gpu, *ref))
-
-
-def test_c0_ssprk3_20_steps_strict(dev):
-    case = cases.with_params(cases.c0(), scheme=3)
-    rc, gpu, ref = _run_both(dev, case, 20)
-    assert rc == 0
-    errs = _compare_state(gpu, *ref)
-    _report("C0 geometry, SSPRK3-SE, 20 steps (strict)", errs)
-    assert max(errs.values()) < TOL
+@pytest.mark.parametrize("name", ["c0_ssprk3_100", "c0_ssprk3_20", "c1_recipe_32x32x60",
+                                  "c2_recipe_level3x60", "hex8_L100"])
+def test_whole_steps(dev, name):
+    """C0 geometry with SSPRK3-SE over 20 and 100 steps; the C1 recipe (bathymetry,
+    density front, 60 layers, M = 20) on a 32x32 hex; the C2 recipe (sphere,
+    30 % land, variable f, 60 layers, M = 30) at level 3; L = 100 > 64 layers
+    (two register chunks per lane)."""
+    check_case(dev, name)
 
 
 def test_c0_ssprk2_stable_window(dev):
     """C0 as specified (SSPRK2-SE, dt = 300 s, M = 10): parity over the first 30 steps."""
-    case = cases.c0()
-    rc, gpu, ref = _run_both(dev, case, 30)
-    assert rc == 0
-    _assert_parity("C0 SSPRK2-SE, 30 steps", case, 30, _compare_state(gpu, *ref))
+    check_case(dev, "c0_ssprk2_30")
 
 
 def test_c0_ssprk2_blowup_is_reported(dev):
@@ -189,7 +166,8 @@ def test_c0_ssprk2_blowup_is_reported(dev):
     case = cases.c0()
     dm, st = dev.state_from_case(case)
     rc = st.step(100)
-    u, h, zeta, ubar = S.run(case, 100)
+    with np.errstate(all="ignore"):
+        u, h, zeta, ubar = S.run(case, 100)
     assert not np.isfinite(u).all()
     assert rc == dev.SSE_ENONFINITE
 
@@ -197,46 +175,12 @@ def test_c0_ssprk2_blowup_is_reported(dev):
 @pytest.mark.parametrize("scheme", [2, 3])
 @pytest.mark.parametrize("reconcile", [0, 1, 2])
 def test_reconcile_modes(dev, scheme, reconcile):
-    # Without the exact reconciliation the split system amplifies roundoff in
-    # h by orders of magnitude per step (test_reconciliation_conditioning), so
-    # those modes are compared over a short window.
-    steps = 12 if reconcile == 1 else 3
-    case = smooth_case(n=10, L=5, scheme=scheme, reconcile=reconcile, M=6, dt=180.0)
-    rc, gpu, ref = _run_both(dev, case, steps)
-    assert rc == 0
-    _assert_parity(f"reconcile={reconcile} scheme={scheme}", case, steps, _compare_state(gpu, *ref))
+    check_case(dev, f"reconcile{reconcile}_ssprk{scheme}")
 
 
 @pytest.mark.parametrize("scheme", [2, 3])
 def test_isopycnal_steps(dev, scheme):
-    case = cases.with_params(smooth_case(n=10, L=5, scheme=scheme, M=6, dt=180.0), vcoord=1)
-    rc, gpu, ref = _run_both(dev, case, 12)
-    assert rc == 0
-    _assert_parity(f"isopycnal scheme={scheme}", case, 12, _compare_state(gpu, *ref))
-
-
-def test_c1_recipe_reduced(dev):
-    """C1 recipe (bathymetry, density front, 60 layers, M = 20) on a 32x32 hex."""
-    case = cases.c1(n=32, L=60, steps=4)
-    rc, gpu, ref = _run_both(dev, case, 4)
-    assert rc == 0
-    _assert_parity("C1 recipe 32x32x60, 4 steps", case, 4, _compare_state(gpu, *ref))
-
-
-def test_c2_recipe_reduced_fp64(dev):
-    """C2 recipe (sphere, 30% land, variable f, 60 layers, M = 30) at level 3, FP64."""
-    case = cases.sphere_case(3, 60, cases.SEED_BASE + 200, substeps=30, dt_btr=240.0)
-    rc, gpu, ref = _run_both(dev, case, 3)
-    assert rc == 0
-    _assert_parity("C2 recipe level 3 x 60, 3 steps", case, 3, _compare_state(gpu, *ref))
-
-
-def test_deep_columns_two_chunks(dev):
-    """L = 100 > 64 layers: two register chunks per lane."""
-    case = cases.c1(n=8, L=100, steps=2)
-    rc, gpu, ref = _run_both(dev, case, 2)
-    assert rc == 0
-    _assert_parity("hex 8x8x100, 2 steps", case, 2, _compare_state(gpu, *ref))
+    check_case(dev, f"isopycnal_ssprk{scheme}")
 
 
 def test_determinism_bitwise(dev):
@@ -296,9 +240,7 @@ def test_edge_variant_feuler_parity(dev, name, variant):
     if not st.try_edge_variant(variant):
         pytest.skip(f"variant {variant} does not fit: {dev.last_error()}")
     g_ut1, g_G = st.debug_baroclinic_feuler(u, ubar, zeta, h, case.params.dt)
-    errs = {"ut1": rel_l2(g_ut1, ut1), "G": rel_l2(g_G, G)}
-    _report(f"feuler variant={variant} {name}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"feuler variant={variant} {name}", {"ut1": (g_ut1, ut1), "G": (g_G, G)})
 
 
 @pytest.mark.parametrize("variant", [-2, 0, 1, 2])
@@ -322,7 +264,7 @@ def test_wide_addressing_bitwise_equal(dev, precision):
     take) against 32-bit offsets, with every optional term on and two
     register chunks, alone and in a batch."""
     import torch
-    from tests.test_gpu_combined import all_terms
+    from tests.parity_cases import all_terms
     case = cases.with_params(all_terms(cases.c1(n=10, L=100, steps=2)), precision=precision)
     out = {}
     for v in (-1, -2):
@@ -362,7 +304,7 @@ BT_CASES = {
 
 @pytest.mark.parametrize("name", sorted(BT_CASES))
 @pytest.mark.parametrize("scheme", [2, 3])
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_bt_variants_bitwise_equal(dev, name, scheme, precision):
     """The per-substep (patch) kernel performs the per-evaluation kernel's
     arithmetic on the same operands: whole steps agree bit for bit."""
@@ -393,6 +335,4 @@ def test_barotropic_substep_variants_parity(dev, scheme, variant):
     _, st = dev.state_from_case(case)
     assert st.try_bt_variant(variant), dev.last_error()
     g_u1, g_z1, g_F = st.debug_barotropic_substep(scheme, M, dt, ubar, zeta, G)
-    errs = {"ubar": rel_l2(g_u1, u1), "zeta": rel_l2(g_z1, z1), "Fzeta": rel_l2(g_F, F)}
-    _report(f"bt{scheme} variant={variant}", errs)
-    assert max(errs.values()) < TOL
+    _check_kernel(f"bt{scheme} variant={variant}", {"ubar": (g_u1, u1), "zeta": (g_z1, z1), "Fzeta": (g_F, F)})
