@@ -349,6 +349,33 @@ int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double
 int sse_debug_thickness_stage(sse_state *s, const double *h_in, const double *u, const double *uA,
                               double dt, double *h_out, double *zeta_out);
 
+/*
+ * Allocation-free barotropic loop, for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same operation as
+ * sse_debug_barotropic_substep (Algorithm 3 for scheme 2, Algorithm 4 for
+ * scheme 3: M substeps over dt with G frozen, accumulating F^zeta of Section
+ * 3.4), in the state's barotropic precision (FP32 for SSE_MIXED, else FP64),
+ * but on DEVICE arrays in the caller's numbering: inputs ubar [E], zeta [C],
+ * G [E]; outputs ubar1 [E], zeta1 [C], Fzeta [E] (outputs may alias inputs:
+ * every input is read before any output is written).  The state supplies the
+ * mesh, gravity, the barotropic kernel variant and the stream; its own
+ * fields and workspace are not touched.  The loop's stages live in a static
+ * device array of 64 MiB per device, reserved when the library's code is
+ * loaded on that device and held until the process ends; its address is
+ * resolved by sse_state_create.  The call allocates nothing, enqueues its
+ * kernels on the state's stream and returns without waiting.  All calls on
+ * one device share that array, which keeps the last call's contents: calls
+ * that overlap in time on one device race.  SSE_ENOMEM if the mesh needs more
+ * than the array ((6 E + 4 C) x 8 bytes plus alignment); SSE_EINVAL for NULL
+ * arguments, scheme not 2 or 3, M < 1, dt <= 0, or a current device other
+ * than the state's; SSE_EDEVICE if a launch fails or the array's address is
+ * unavailable.
+ */
+int sse_barotropic_substep_noalloc(sse_state *s, int32_t scheme, int32_t M, double dt,
+                                   const double *ubar, const double *zeta, const double *G,
+                                   double *ubar1, double *zeta1, double *Fzeta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <cmath>
 #include <cstdlib>
@@ -28,7 +29,34 @@
 
 using namespace sse;
 
+// Scratch of the allocation-free barotropic entry point
+// (sse_barotropic_substep_noalloc): one array per device, held until the
+// process ends and shared by every call on that device.  Host code never
+// passes the symbol itself: its device address comes from
+// hipGetSymbolAddress once per device (scratch_address) and only that
+// address reaches kernels.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch[kMaxDevices];
+
+// Resolves (once per device, with that device current) the address of this
+// device's scratch array; nullptr if the runtime cannot give it.
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    void *p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_scratch[dev].store(q, std::memory_order_release);
+    return q;
+}
 
 // Device workspace of one state.  Arrays marked R hold the mode's real type.
 struct Work {
@@ -211,6 +239,7 @@ struct sse_state {
     hipStream_t stream = nullptr;
     Work w{};
     size_t bytes = 0;
+    int device = 0;          // the device current at creation
     size_t rs = 8;           // bytes of the real type R
     bool bt64 = true;        // the barotropic loop runs in FP64 (SSE_FP64, SSE_MIXED_BT64)
     bool initialized = false;
@@ -397,15 +426,23 @@ void convert(sse_state *s, const Tin *src, Tout *dst, size_t n) {
         launch_convert<Tin, Tout>(a, s->geom, s->stream);
 }
 
+// Stage buffers of one barotropic loop, in the loop's real type: the stages
+// (u1, uh, z1, zh) and, for the FP32 loop, its rounded input and its output
+// before widening (ua, za, uo, zo).
+struct BtBufs {
+    void *u1, *uh, *z1, *zh, *ua, *za, *uo, *zo;
+};
+
+BtBufs bt_bufs(const Work &w) { return {w.bt_u1, w.bt_uh, w.bt_z1, w.bt_zh, w.bt_ua, w.bt_za, w.bt_uo, w.bt_zo}; }
+
 // Algorithm 3 (scheme 2) / Algorithm 4 (scheme 3): M substeps of dt / M with
 // G frozen, accumulating F^zeta in FP64.  The inputs are not modified.  In
 // mixed precision the loop state is FP32: the FP64 inputs are rounded once on
 // entry and the result widened once on exit.
 template <typename R>
 void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, const double *in_z, const double *G,
-             double *out_u, double *out_z, double *F) {
+             double *out_u, double *out_z, double *F, const BtBufs &w) {
     const DevMesh &m = s->mesh->d;
-    Work &w = s->w;
     const R *iu;
     const R *iz;
     R *ou;
@@ -416,14 +453,14 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         ou = out_u;
         oz = out_z;
     } else {
-        convert<double, R>(s, in_u, rp<R>(w.bt_ua), m.E);
-        convert<double, R>(s, in_z, rp<R>(w.bt_za), m.C);
-        iu = rp<R>(w.bt_ua);
-        iz = rp<R>(w.bt_za);
-        ou = rp<R>(w.bt_uo);
-        oz = rp<R>(w.bt_zo);
+        convert<double, R>(s, in_u, rp<R>(w.ua), m.E);
+        convert<double, R>(s, in_z, rp<R>(w.za), m.C);
+        iu = rp<R>(w.ua);
+        iz = rp<R>(w.za);
+        ou = rp<R>(w.uo);
+        oz = rp<R>(w.zo);
     }
-    R *u1 = rp<R>(w.bt_u1), *uh = rp<R>(w.bt_uh), *z1 = rp<R>(w.bt_z1), *zh = rp<R>(w.bt_zh);
+    R *u1 = rp<R>(w.u1), *uh = rp<R>(w.uh), *z1 = rp<R>(w.z1), *zh = rp<R>(w.zh);
     if (s->bt_variant == 1) {
         // one launch per substep; outputs alternate between the loop's
         // output and a scratch pair so that no launch reads what another
@@ -614,9 +651,9 @@ template <typename R>
 void bt_loop_of(sse_state *s, int scheme, int M, double dt, const double *in_u, const double *in_z,
                 const double *G, double *out_u, double *out_z, double *F) {
     if (s->bt64)
-        bt_loop<double>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F);
+        bt_loop<double>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F, bt_bufs(s->w));
     else
-        bt_loop<float>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F);
+        bt_loop<float>(s, scheme, M, dt, in_u, in_z, G, out_u, out_z, F, bt_bufs(s->w));
 }
 
 template <typename R>
@@ -792,7 +829,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.vert_edges.data(), t.vert_curl.data(), t.erec.data(), t.inv_dc.data(),
                          t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
                          t.cell_div_t_f.data(), t.H_f.data(), t.eoe16.data(), t.ecells16.data(),
-                         t.cedges16.data(), t.cnbrs16.data()};
+                         t.cedges16.data(), t.cnbrs16.data(), ord.cell_old.data(), ord.edge_old.data()};
     static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
     size_t nb[kMeshTables];
     mesh_table_sizes(d->n_cells, d->n_edges, d->n_vertices, nb);
@@ -845,6 +882,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.ecells16 = (const int32_t *)P(30);
     dm.cedges16 = (const int16_t *)P(31);
     dm.cnbrs16 = (const int16_t *)P(32);
+    dm.cell_old = (const int32_t *)P(33);
+    dm.edge_old = (const int32_t *)P(34);
     dm.delta16 = t.delta16;
     dm.ratio_ce = t.ratio_ce;
     dm.ratio_ec = t.ratio_ec;
@@ -1007,6 +1046,8 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->bytes = bytes;
     int dev = 0, lds_max = 0;
     (void)hipGetDevice(&dev);
+    s->device = dev;
+    (void)scratch_address(dev);  // set-up of the allocation-free entry point on this device
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds_max = 65536;
     set_tiled_lds_limit((size_t)lds_max);
     s->lds_max = (size_t)lds_max;
@@ -1346,9 +1387,9 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
     SSE_HIP(hipMemcpyAsync(w.z1, zi.data(), C * 8, hipMemcpyHostToDevice, st));
     SSE_HIP(hipMemcpyAsync(w.G0, gi.data(), E * 8, hipMemcpyHostToDevice, st));
     if (s->bt64)
-        bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+        bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1, bt_bufs(w));
     else
-        bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1);
+        bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1, bt_bufs(w));
     SSE_HIP(hipGetLastError());
     SSE_HIP(hipMemcpyAsync(bo.data(), w.ub2, E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(zo.data(), w.bt_zout, C * 8, hipMemcpyDeviceToHost, st));
@@ -1357,6 +1398,70 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
     rows_to_user(bo.data(), ubar1, m->edge_old, 1);
     rows_to_user(zo.data(), zeta1, m->cell_old, 1);
     rows_to_user(fo.data(), Fzeta, m->edge_old, 1);
+    return SSE_OK;
+}
+
+extern "C" int sse_barotropic_substep_noalloc(sse_state *s, int32_t scheme, int32_t M, double dt, const double *ubar,
+                                              const double *zeta, const double *G, double *ubar1, double *zeta1,
+                                              double *Fzeta) {
+    if (!s || !ubar || !zeta || !G || !ubar1 || !zeta1 || !Fzeta) { set_error("NULL argument"); return SSE_EINVAL; }
+    if (scheme != 2 && scheme != 3) { set_error("scheme must be 2 or 3"); return SSE_EINVAL; }
+    if (M < 1 || !(dt > 0) || !std::isfinite(dt)) { set_error("M must be >= 1 and dt > 0"); return SSE_EINVAL; }
+    if (s->rec) { set_error("state is being recorded into a batch"); return SSE_ESTATE; }
+    const DevMesh &dm = s->mesh->d;
+    const size_t E = dm.E, C = dm.C;
+    // 6 edge and 4 cell arrays of doubles (input, forcing, output and flux
+    // permuted to the internal numbering, and the stages), each 256-byte aligned
+    const size_t need = (6 * E + 4 * C) * sizeof(double) + 16 * kAlign;
+    if (need > kStaticScratchBytes) {
+        set_error("mesh too large for the allocation-free barotropic entry point (needs (6 E + 4 C) x 8 bytes of "
+                  "its 64 MiB scratch)");
+        return SSE_ENOMEM;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != s->device) {
+        set_error("the state's device must be current");
+        return SSE_EINVAL;
+    }
+    void *base = scratch_address(dev);
+    if (!base) { set_error("no device address for the static scratch array"); return SSE_EDEVICE; }
+    char *p = static_cast<char *>(base);
+    auto take = [&](size_t n) {
+        void *r = p;
+        p += align_up(n);
+        return r;
+    };
+    const size_t bs = s->bt64 ? sizeof(double) : sizeof(float);
+    double *iu = static_cast<double *>(take(E * 8)), *iz = static_cast<double *>(take(C * 8));
+    double *iG = static_cast<double *>(take(E * 8)), *ou = static_cast<double *>(take(E * 8));
+    double *oz = static_cast<double *>(take(C * 8)), *oF = static_cast<double *>(take(E * 8));
+    BtBufs b{};
+    b.u1 = take(E * bs);
+    b.uh = take(E * bs);
+    b.z1 = take(C * bs);
+    b.zh = take(C * bs);
+    if (!s->bt64) {
+        b.ua = take(E * bs);
+        b.za = take(C * bs);
+        b.uo = take(E * bs);
+        b.zo = take(C * bs);
+    }
+    hipStream_t st = s->stream;
+    // caller numbering -> internal; every input is read before any output is written
+    launch_permute(ubar, dm.edge_old, iu, (int)E, false, s->geom, st);
+    launch_permute(zeta, dm.cell_old, iz, (int)C, false, s->geom, st);
+    launch_permute(G, dm.edge_old, iG, (int)E, false, s->geom, st);
+    const bool prof = s->prof;
+    s->prof = false;  // no per-class events: their bookkeeping would grow host vectors
+    if (s->bt64)
+        bt_loop<double>(s, scheme, M, dt, iu, iz, iG, ou, oz, oF, b);
+    else
+        bt_loop<float>(s, scheme, M, dt, iu, iz, iG, ou, oz, oF, b);
+    s->prof = prof;
+    launch_permute(ou, dm.edge_old, ubar1, (int)E, true, s->geom, st);
+    launch_permute(oz, dm.cell_old, zeta1, (int)C, true, s->geom, st);
+    launch_permute(oF, dm.edge_old, Fzeta, (int)E, true, s->geom, st);
+    SSE_HIP(hipGetLastError());
     return SSE_OK;
 }
 

@@ -77,6 +77,10 @@ struct DevMesh {
     const int32_t *ecells16 = nullptr;      // [E]
     const int16_t *cedges16 = nullptr;      // [6][C]
     const int16_t *cnbrs16 = nullptr;       // [6][C]
+    // the caller's numbering: internal cell i / edge e is caller cell
+    // cell_old[i] / edge edge_old[e]
+    const int32_t *cell_old = nullptr;      // [C]
+    const int32_t *edge_old = nullptr;      // [E]
 };
 
 // Fixed-point base of the 16-bit offsets (see DevMesh).
@@ -183,7 +187,7 @@ namespace sse {
 
 // Sizes of the device mesh image (bytes) and the offsets of its tables, in
 // the order in which mesh_create uploads them.
-constexpr int kMeshTables = 33;
+constexpr int kMeshTables = 35;
 void mesh_table_sizes(int C, int E, int V, size_t (&sizes)[kMeshTables]);
 struct MeshLayout {
     size_t off[kMeshTables] = {};

@@ -262,6 +262,10 @@ void launch_convert(const ConvArgs<Tin, Tout> &a, const Geom &g, hipStream_t s);
 void launch_thickness(const THArgs &a, const Geom &g, hipStream_t s);
 void launch_recon(const ReconArgs &a, const Geom &g, hipStream_t s);
 void launch_zeta_from_h(const DevMesh &m, int L, const double *h, double *zeta, hipStream_t s);
+// dst[i] = src[idx[i]] (scatter false) or dst[idx[i]] = src[i] (scatter true), i < n;
+// idx is a permutation of 0 .. n-1 and dst does not alias src.
+void launch_permute(const double *src, const int32_t *idx, double *dst, int n, bool scatter, const Geom &g,
+                    hipStream_t s);
 
 // Batched launches: one kernel launch over the blocks of several states.
 // table[b] = (member index into args, that member's block index) for the

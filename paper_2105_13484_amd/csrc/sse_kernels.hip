@@ -2256,6 +2256,18 @@ void launch_edge_flux_sum(const DevMesh &m, int L, const double *h, const R *X, 
     if (L <= kWave) edge_flux_sum_kernel<1, R><<<grid, 256, 0, s>>>(m, L, h, X, uA, F);
     else edge_flux_sum_kernel<2, R><<<grid, 256, 0, s>>>(m, L, h, X, uA, F);
 }
+__global__ void permute_kernel(const double *__restrict__ src, const int32_t *__restrict__ idx,
+                               double *__restrict__ dst, int n, int scatter) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = idx[i];
+    if (scatter) dst[j] = src[i];
+    else dst[i] = src[j];
+}
+void launch_permute(const double *src, const int32_t *idx, double *dst, int n, bool scatter, const Geom &g,
+                    hipStream_t s) {
+    if (n > 0) permute_kernel<<<flat_blocks((size_t)n, g), g.block_2d, 0, s>>>(src, idx, dst, n, scatter ? 1 : 0);
+}
 void launch_recon(const ReconArgs &a, const Geom &g, hipStream_t s) {
     recon_kernel<<<flat_blocks(a.m.E, g), g.block_2d, 0, s>>>(a);
 }

@@ -127,7 +127,8 @@ void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
         V * 3 * 4, V * 3 * 8,                                   // vert_edges, vert_curl
         E * 32 * 4, E * 8, E * 8, E * 20 * 8,                   // erec, inv_dc, inv_dv, wpair
         E * 10 * 4, E * 4, C * 6 * 4, C * 4,                    // wf_f, inv_dc_f, cell_div_t_f, H_f
-        E * 10 * 2, E * 4, C * 6 * 2, C * 6 * 2};               // eoe16, ecells16, cedges16, cnbrs16
+        E * 10 * 2, E * 4, C * 6 * 2, C * 6 * 2,                // eoe16, ecells16, cedges16, cnbrs16
+        C * 4, E * 4};                                          // cell_old, edge_old
     for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
 }
 

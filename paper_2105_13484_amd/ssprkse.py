@@ -35,6 +35,7 @@ EXPORTED = (
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
     "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
     "sse_state_set_bt_variant", "sse_state_get_bt_variant", "sse_state_set_tracer", "sse_read_tracer",
+    "sse_barotropic_substep_noalloc",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -106,6 +107,7 @@ def load():
         "sse_debug_baroclinic_feuler": (c_int, [P, dp, dp, dp, dp, c_double, dp, dp]),
         "sse_debug_barotropic_substep": (c_int, [P, c_int32, c_int32, c_double, dp, dp, dp, dp, dp, dp]),
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
+        "sse_barotropic_substep_noalloc": (c_int, [P, c_int32, c_int32, c_double, P, P, P, P, P, P]),
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_bt_variant": (c_int, [P, c_int]),
@@ -367,6 +369,19 @@ class DeviceState:
         _check(load().sse_debug_barotropic_substep(self.handle, int(scheme), int(M), float(dt), _dptr(ubar),
                                                    _dptr(zeta), _dptr(G), _dptr(u1), _dptr(z1), _dptr(F)))
         return u1, z1, F
+
+    def barotropic_substep_noalloc(self, scheme, M, dt, ubar, zeta, G, ubar1, zeta1, Fzeta):
+        """The allocation-free barotropic loop on device tensors (float64,
+        contiguous, on the state's device; caller numbering).  Enqueued on the
+        state's stream; returns without waiting."""
+        import torch
+        C, E = self.mesh.C, self.mesh.E
+        for t, n in ((ubar, E), (zeta, C), (G, E), (ubar1, E), (zeta1, C), (Fzeta, E)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+                raise ValueError("expected contiguous float64 device tensors of the mesh's sizes")
+        _check(load().sse_barotropic_substep_noalloc(self.handle, int(scheme), int(M), float(dt), ubar.data_ptr(),
+                                                     zeta.data_ptr(), G.data_ptr(), ubar1.data_ptr(),
+                                                     zeta1.data_ptr(), Fzeta.data_ptr()))
 
     def debug_thickness_stage(self, h_in, u, uA, dt):
         C, L = self.mesh.C, self.L

@@ -1,0 +1,106 @@
+"""The allocation-free barotropic loop (sse_barotropic_substep_noalloc)
+against the workspace-based entry point it is a variant of
+(sse_debug_barotropic_substep): the same kernels on the same operands, so
+the results must agree bit for bit.  Two calls in a row share the static
+scratch array; the second runs on a smaller mesh, and the first call's
+outputs must not change.  A mesh too large for the array is rejected
+before anything is launched.
+"""
+import numpy as np
+import pytest
+
+from synthetic import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_13484_amd import ssprkse
+    ssprkse.load()
+    return ssprkse
+
+
+def _inputs(case, seed):
+    rng = np.random.default_rng(seed)
+    c = case.mesh.cellsOnEdge
+    cm = case.cell_mask.astype(bool)
+    em = cm[c[:, 0]] & cm[c[:, 1]]
+    ubar = np.where(em, rng.normal(0, 0.05, case.mesh.nEdges), 0.0)
+    zeta = np.where(cm, rng.normal(0, 0.05, case.mesh.nCells), 0.0)
+    G = np.where(em, rng.normal(0, 1e-5, case.mesh.nEdges), 0.0)
+    return ubar, zeta, G
+
+
+def _noalloc(st, scheme, M, dt, ubar, zeta, G):
+    import torch
+    d = torch.device("cuda")
+    t_in = [torch.from_numpy(np.ascontiguousarray(a)).to(d) for a in (ubar, zeta, G)]
+    outs = [torch.full((n,), np.nan, dtype=torch.float64, device=d) for n in (ubar.size, zeta.size, ubar.size)]
+    st.barotropic_substep_noalloc(scheme, M, dt, *t_in, *outs)
+    torch.cuda.current_stream().synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+CALLS = [
+    # (case, scheme, M, precision); the second call's mesh is the smaller one
+    (lambda: cases.c1(n=32, L=4, steps=1), 3, 7, 0),
+    (lambda: cases.sphere_case(3, 3, 77, substeps=5, dt_btr=200.0), 2, 5, 0),
+]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_noalloc_equals_workspace_entry_two_calls(dev, variant, precision):
+    kept = []
+    for k, (make, scheme, M, _) in enumerate(CALLS):
+        case = cases.with_params(make(), precision=precision)
+        dm, st = dev.state_from_case(case)
+        if not st.try_bt_variant(variant):
+            pytest.skip(f"barotropic variant {variant} does not fit: {dev.last_error()}")
+        ubar, zeta, G = _inputs(case, 11 + k)
+        dt = case.params.dt
+        ref = st.debug_barotropic_substep(scheme, M, dt, ubar, zeta, G)
+        got = _noalloc(st, scheme, M, dt, ubar, zeta, G)
+        for name, a, b in zip(("ubar1", "zeta1", "Fzeta"), got, ref):
+            assert np.array_equal(a, b), (k, name, float(np.nanmax(np.abs(a - b))))
+        kept.append((got, ref, dm, st))
+    # the first call's results are unaffected by the second call's use of the scratch
+    for got, ref, _, _ in kept:
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+
+
+def test_noalloc_outputs_may_alias_inputs(dev):
+    import torch
+    case = cases.c1(n=16, L=3, steps=1)
+    dm, st = dev.state_from_case(case)
+    ubar, zeta, G = _inputs(case, 5)
+    ref = st.debug_barotropic_substep(3, 4, case.params.dt, ubar, zeta, G)
+    d = torch.device("cuda")
+    tu, tz, tG = (torch.from_numpy(a.copy()).to(d) for a in (ubar, zeta, G))
+    st.barotropic_substep_noalloc(3, 4, case.params.dt, tu, tz, tG, tu, tz, tG)
+    torch.cuda.current_stream().synchronize()
+    for a, b in zip((tu, tz, tG), ref):
+        assert np.array_equal(a.cpu().numpy(), b)
+
+
+def test_noalloc_rejects_a_mesh_beyond_its_scratch(dev):
+    """(6 E + 4 C) x 8 bytes above 64 MiB: SSE_ENOMEM, nothing written."""
+    import torch
+    case = cases.c1(n=700, L=1, steps=1)
+    assert (6 * case.mesh.nEdges + 4 * case.mesh.nCells) * 8 > 64 << 20
+    dm, st = dev.state_from_case(case)
+    d = torch.device("cuda")
+    E, C = case.mesh.nEdges, case.mesh.nCells
+    ins = [torch.zeros(n, dtype=torch.float64, device=d) for n in (E, C, E)]
+    outs = [torch.full((n,), 7.0, dtype=torch.float64, device=d) for n in (E, C, E)]
+    with pytest.raises(dev.SSEError) as ei:
+        st.barotropic_substep_noalloc(3, 2, case.params.dt, *ins, *outs)
+    assert ei.value.code == dev.SSE_ENOMEM
+    torch.cuda.synchronize()
+    for o in outs:
+        assert bool(torch.all(o == 7.0))
