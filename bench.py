@@ -21,6 +21,7 @@ Progress goes to stderr.
 FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 run) and exits.
 """
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -50,8 +51,11 @@ def kernel_bytes(cls, C, E, V, L, b=8.0, bt_tiled=True):
     class launches once per substep (bt_tiled, the default) or once per
     evaluation."""
     if cls == "fe_edge":
-        # X, h, rho, B, w, Z read; out written; u^n read by 2 of the 3 stages
-        return b * L * (2 * E + 4 * C + V + (2.0 / 3.0) * E)
+        # the forward-Euler passes at ideal fusion, averaged over the three
+        # stages of SSPRK3-SE: FE1 reads u^n, h, rho and writes the stage
+        # (2 edge and 2 cell touches); FE2 and FE3 also read u^n for the stage
+        # combination (3 edge, 2 cell touches)
+        return b * L * ((8.0 / 3.0) * E + 2 * C)
     if cls == "fe_cell":
         return b * L * (E + 4 * C)          # X, h, frac read; B, w written
     if cls == "fe_vertex":
@@ -69,6 +73,34 @@ def kernel_bytes(cls, C, E, V, L, b=8.0, bt_tiled=True):
     if cls == "other":
         return b * L * (2 * E + C)          # assembly: X read, u written, h read
     raise KeyError(cls)
+
+
+def intermediate_bytes(cls, C, E, V, L, b=8.0):
+    """Bytes a launch moves beyond the ideal-fusion count: for the edge pass
+    the intermediates that the cell and vertex passes write for it (K - nu
+    div u and w at cells, the relative vorticity at vertices), read back."""
+    if cls == "fe_edge":
+        return b * L * (2 * C + V)
+    return 0.0
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device copy (bytes read + written
+    per second), HIP events around `reps` copies of `nbytes`."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    bb = torch.empty_like(a)
+    bb.copy_(a)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        bb.copy_(a)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    s = ev0.elapsed_time(ev1) * 1e-3 / reps
+    del a, bb
+    return 2.0 * nbytes / s / 1e9
 
 
 def source_sha256(path):
@@ -91,7 +123,7 @@ def measured_traffic(dom):
     return float(c["fetch_bytes_per_launch"]) + float(c["write_bytes_per_launch"])
 
 
-def cpu_baseline(n=128, steps=6):
+def cpu_baseline(n=128, steps=2):
     """The FP64 oracle on the same recipe at n x n cells (same L, M, dt)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import ssprk_se
@@ -107,7 +139,8 @@ def cpu_baseline(n=128, steps=6):
     cl = case.active_cell_layers
     return {"value": cl * steps / dt, "unit": "cell-layer updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} SSPRK3-SE steps of the same recipe on a {n}x{n} hex (C={case.mesh.nCells}, "
-                      f"L=60, M=20), NumPy FP64, one thread; {dt:.1f} s",
+                      f"L=60, M=20), NumPy FP64, one thread; {dt:.1f} s (the 512x512 mesh takes minutes "
+                      f"per oracle step, too long for this run)",
             "cores_available": len(os.sched_getaffinity(0))}
 
 
@@ -213,20 +246,24 @@ def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
     return out
 
 
-def serve_leg(torch, ssprkse, cases, n_requests=24, load=0.8, full=False):
+def serve_leg(torch, ssprkse, cases, n_requests=64, load=0.8, n_capacity=12, reduced=False):
     """C4: Poisson arrivals of sphere requests, continuous batching under an HBM
-    budget.  Capacity is measured first with every request queued at t = 0;
-    arrivals then come at `load` x that capacity.  The default mix is the
-    served recipe at reduced size (levels 4-6, 10-40 steps); full=True uses
-    levels 5-8 and 50-500 steps."""
+    budget.  The served recipe: icosahedral levels 5-8, 16-100 layers,
+    50-500 steps, FP64 or mixed at random.  The service rate is measured
+    first by serving the first `n_capacity` requests with all of them queued
+    at t = 0 (cell-layer updates per second); the `n_requests` requests then
+    arrive as a Poisson process at `load` times that rate divided by their
+    mean work.  reduced=True serves a smaller mix (levels 4-6, 10-40 steps)."""
     import numpy as np
     from paper_2105_13484_amd.serve import Engine, Request, poisson_arrivals
 
+    meshes = {}
+
     def make(i):
-        rng = np.random.default_rng(cases.SEED_BASE + 400 + i)
-        if full:
-            c = cases.c4_request(i)
+        if not reduced:
+            c = cases.c4_request(i, meshes=meshes)
             return c, int(c.steps)
+        rng = np.random.default_rng(cases.SEED_BASE + 400 + i)
         level = int(rng.integers(4, 7))
         L = int(rng.integers(16, 101))
         steps = int(rng.integers(10, 41))
@@ -235,33 +272,40 @@ def serve_leg(torch, ssprkse, cases, n_requests=24, load=0.8, full=False):
         return c, steps
 
     log(f"[bench] serving: building {n_requests} requests")
-    made = []
-    for i in range(n_requests):
-        made.append(make(i))
-        if full:
-            c, s = made[-1]
-            log(f"[bench] serving: request {i}: {c.mesh.nCells} cells, {c.params.n_layers} layers, {s} steps, "
-                f"{'mixed' if c.params.precision else 'FP64'}")
+    made = [make(i) for i in range(n_requests)]
+    levels = collections.Counter(int(round(np.log((c.mesh.nCells - 2) / 10) / np.log(4))) for c, _ in made)
+    work = [c.active_cell_layers * s for c, s in made]
+    log(f"[bench] serving: levels {dict(sorted(levels.items()))}, {sum(work):.3g} cell-layer updates in all")
 
-    def requests(arrivals):
-        return [Request(rid=i, case=c, steps=s, arrival=a) for i, ((c, s), a) in enumerate(zip(made, arrivals))]
+    def requests(sel, arrivals):
+        return [Request(rid=i, case=made[i][0], steps=made[i][1], arrival=a) for i, a in zip(sel, arrivals)]
 
     eng = Engine(budget_bytes=200 << 30, chunk_steps=10, keep_results=False)
-    closed = eng.run(requests([0.0] * n_requests))
-    cap = n_requests / closed["wall_s"]
-    log(f"[bench] serving capacity (all queued at t=0): {cap:.2f} requests/s, "
-        f"{closed['cell_layer_updates_per_s']:.3g} cell-layer updates/s")
+    closed = eng.run(requests(range(n_capacity), [0.0] * n_capacity))
+    rate = closed["cell_layer_updates_per_s"]
+    cap = rate / (sum(work) / n_requests)
+    log(f"[bench] serving capacity ({n_capacity} requests queued at t=0): {rate:.3g} cell-layer updates/s, "
+        f"{cap:.3f} requests/s of the mix")
     arr = poisson_arrivals(n_requests, load * cap, cases.SEED_BASE + 499)
-    opened = eng.run(requests(arr))
+    shown = set()
+
+    def progress(k, n):
+        if k % 8 == 0 and k not in shown:
+            shown.add(k)
+            log(f"[bench] serving: {k}/{n} done")
+
+    opened = eng.run(requests(range(n_requests), arr), on_progress=progress)
     eng.close()
     log(f"[bench] serving at {load:.1f}x capacity: p50 {opened['p50_s']:.3f} s, p99 {opened['p99_s']:.3f} s")
-    return {"workload": ("C4 served recipe: icosahedral levels 5-8, L 16-100, 50-500 steps" if full else
-                         "C4 served recipe at reduced size: icosahedral levels 4-6, L 16-100, 10-40 steps") +
+    return {"workload": ("C4 served recipe at reduced size: icosahedral levels 4-6, L 16-100, 10-40 steps" if reduced else
+                         "C4 served recipe: icosahedral levels 5-8, L 16-100, 50-500 steps") +
                         ", FP64 or mixed at random, M = 30, HBM budget 200 GB",
-            "requests": n_requests, "capacity_requests_per_s": cap,
-            "closed_loop_cell_layer_updates_per_s": closed["cell_layer_updates_per_s"],
-            "load": load, "p50_s": opened["p50_s"], "p99_s": opened["p99_s"],
-            "cell_layer_updates_per_s": opened["cell_layer_updates_per_s"], "failed": opened["failed"]}
+            "requests": n_requests, "levels": dict(sorted(levels.items())),
+            "capacity_cell_layer_updates_per_s": rate, "capacity_requests_per_s": cap,
+            "capacity_sample_requests": n_capacity,
+            "load": load, "p50_s": opened["p50_s"], "p99_s": opened["p99_s"], "max_s": opened["max_s"],
+            "cell_layer_updates_per_s": opened["cell_layer_updates_per_s"], "wall_s": opened["wall_s"],
+            "failed": opened["failed"]}
 
 
 def copy_probe():
@@ -290,7 +334,8 @@ def main():
     ap.add_argument("--no-m-sweep", action="store_true", help="skip the runtime-vs-M sweep")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-full", action="store_true", help="serving leg with the full request recipe")
+    ap.add_argument("--serve-reduced", action="store_true", help="serving leg with a smaller request mix")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg")
     ap.add_argument("--copy-probe", action="store_true", help="run only a plain device copy and exit")
     args = ap.parse_args()
 
@@ -328,6 +373,9 @@ def main():
     dom = max(prof, key=lambda k: prof[k][1])
     log("[bench] per-class ms over 3 steps: " + ", ".join(f"{k}={v[1]:.3f}({v[0]})" for k, v in prof.items()))
 
+    copy_gbs = copy_bandwidth(torch)
+    log(f"[bench] plain 1 GiB device copy: {copy_gbs:.0f} GB/s (bytes read + written)")
+
     # timed region 1: clean
     t0 = time.perf_counter()
     ms_step = timed_steps(torch, st, args.steps)
@@ -342,6 +390,7 @@ def main():
     st.profile(())
     avg_ms = ms_dom / max(n_dom, 1)
     kb = kernel_bytes(dom, C, E, V, L, bt_tiled=st.bt_variant == 1)
+    ib = intermediate_bytes(dom, C, E, V, L)
     achieved = kb / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom)
     log(f"[bench] dominant class {dom}: {n_dom} launches, {avg_ms * 1e3:.1f} us avg, "
@@ -350,13 +399,20 @@ def main():
     assert np.isfinite(final["u"]).all() and np.isfinite(final["h"]).all()
     del st
 
-    # the same workload in mixed precision (FP32 tendencies and substeps)
-    ms_mixed = None
+    # the same workload in mixed precision: FP32 tendencies and substeps
+    # (SSE_MIXED), and FP32 tendencies with the barotropic loop in FP64
+    # (SSE_MIXED_BT64)
+    ms_mixed = ms_bt64 = None
     if not args.no_mixed:
         _, st_m = ssprkse.state_from_case(cases.with_params(case, precision=1), device="cuda:0")
         assert st_m.step(args.warmup) == 0
         ms_mixed = timed_steps(torch, st_m, args.steps)
         log(f"[bench] C1 mixed precision: {ms_mixed:.3f} ms/step")
+        del st_m
+        _, st_m = ssprkse.state_from_case(cases.with_params(case, precision=2), device="cuda:0")
+        assert st_m.step(args.warmup) == 0
+        ms_bt64 = timed_steps(torch, st_m, args.steps)
+        log(f"[bench] C1 mixed precision with the barotropic loop in FP64: {ms_bt64:.3f} ms/step")
         del st_m
 
     # the same workload with implicit vertical mixing (Algorithm 2 in every stage)
@@ -412,7 +468,8 @@ def main():
         c2["mixed_vs_fp64_speedup"] = c2["fp64_ms_per_step"] / c2["mixed_ms_per_step"]
 
     ensemble = None if args.no_ensemble else ensemble_leg(torch, ssprkse, cases)
-    serving = None if args.no_serve else serve_leg(torch, ssprkse, cases, full=args.serve_full)
+    serving = None if args.no_serve else serve_leg(torch, ssprkse, cases, n_requests=args.serve_requests,
+                                                    reduced=args.serve_reduced)
 
     value = cell_layers / (ms_step * 1e-3)
     step_gbs = STEP_BYTES_PER_CELL_LAYER * cell_layers / (ms_step * 1e-3) / 1e9
@@ -434,15 +491,19 @@ def main():
                                f"bathymetry + density front, FP64",
                    "cells": C, "edges": E, "layers": L, "substeps": 20, "scheme": "SSPRK3-SE"},
         "hbm_frac_step": step_gbs / HBM_PEAK_GBS,
+        "hbm_frac_step_target": 0.60,
         "mixed_vs_fp64_speedup": (ms_step / ms_mixed) if ms_mixed else None,
         "mixed_ms_per_step": ms_mixed,
+        "mixed_bt64_vs_fp64_speedup": (ms_step / ms_bt64) if ms_bt64 else None,
+        "mixed_bt64_ms_per_step": ms_bt64,
         "vmix_ms_per_step": ms_vmix,
         "del4_ms_per_step": ms_del4,
         "tracer_ms_per_step": ms_tracer,
         "per_class_ms_per_step": {k: v[1] / 3.0 for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": kb, "launch_ms": avg_ms},
+                     "bytes_per_launch": kb, "intermediate_bytes_per_launch": ib, "launch_ms": avg_ms,
+                     "achievable_copy_gbs": copy_gbs},
         "c2": c2,
         "m_sweep": m_sweep,
         "ensemble": ensemble,

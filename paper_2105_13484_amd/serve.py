@@ -157,10 +157,14 @@ class Engine:
         lat = sorted(r.done - r.arrival for r in finished)
 
         def pct(q):
-            return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+            # linear interpolation between the two nearest order statistics
+            x = q * (len(lat) - 1)
+            i = min(int(x), len(lat) - 1)
+            j = min(i + 1, len(lat) - 1)
+            return lat[i] + (x - i) * (lat[j] - lat[i])
 
         work = sum(r.work for r in finished)
-        return {"requests": total, "wall_s": wall, "p50_s": pct(0.50), "p99_s": pct(0.99),
+        return {"requests": total, "wall_s": wall, "p50_s": pct(0.50), "p99_s": pct(0.99), "max_s": lat[-1],
                 "mean_s": sum(lat) / len(lat), "cell_layer_updates_per_s": work / wall,
                 "failed": sum(1 for r in finished if r.status != 0)}
 

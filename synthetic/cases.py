@@ -225,14 +225,21 @@ def served_dt_btr(level: int) -> float:
     return 60.0 * 2.0 ** min(0, 7 - level)
 
 
-def c4_request(i: int, max_level: int = 8) -> Case:
+def c4_request(i: int, max_level: int = 8, meshes: dict | None = None) -> Case:
+    """Served request i.  ``meshes`` (level -> Mesh) lets many requests share
+    one icosahedral mesh per level instead of generating it again."""
     seed = SEED_BASE + 400 + i
     rng = np.random.default_rng(seed)
     level = int(rng.integers(5, max_level + 1))
     L = int(rng.integers(16, 101))
     steps = int(rng.integers(50, 501))
     mixed = bool(rng.integers(0, 2))
-    case = sphere_case(level, L, seed, substeps=30, dt_btr=served_dt_btr(level), name=f"c4[{i}]")
+    mesh = None
+    if meshes is not None:
+        if level not in meshes:
+            meshes[level] = icosahedral(level)
+        mesh = meshes[level]
+    case = sphere_case(level, L, seed, substeps=30, dt_btr=served_dt_btr(level), name=f"c4[{i}]", mesh=mesh)
     case.params.precision = 1 if mixed else 0
     case.steps = steps
     return case

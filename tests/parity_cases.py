@@ -72,6 +72,44 @@ def _smooth_tracer(scheme):
     return with_temp(tracer(base, kappa_h=20.0, kappa_v=1e-3), T0)
 
 
+def drop_stencil_pairs(case, n_pairs=24, seed=5):
+    """The case on a copy of its mesh where n_pairs symmetric pairs of
+    reconstruction-stencil entries (e' in the stencil of e and e in that of e')
+    are removed, weights included.  The weights stay antisymmetric, so the
+    Coriolis and vorticity terms stay energy neutral, but those stencils are no
+    longer "all other edges of the two cells": the library cannot put them in
+    its canonical two-cell order and its edge pass takes the generic tables
+    (every stencil edge with its own two vertices)."""
+    from dataclasses import replace
+    m = case.mesh
+    rng = np.random.default_rng(seed)
+    eoe, neoe, w = m.edgesOnEdge.copy(), m.nEdgesOnEdge.copy(), m.weightsOnEdge.copy()
+
+    def remove(e, ep):
+        n = int(neoe[e])
+        j = int(np.nonzero(eoe[e, :n] == ep)[0][0])
+        eoe[e, j:n - 1], w[e, j:n - 1] = eoe[e, j + 1:n].copy(), w[e, j + 1:n].copy()
+        eoe[e, n - 1], w[e, n - 1] = -1, 0.0
+        neoe[e] = n - 1
+
+    done, touched = 0, set()
+    for e in rng.permutation(m.nEdges):
+        if done == n_pairs:
+            break
+        if e in touched:
+            continue
+        cand = [int(x) for x in eoe[e, :neoe[e]] if int(x) not in touched and int(x) != e]
+        if not cand:
+            continue
+        ep = cand[0]
+        remove(e, ep)
+        remove(ep, e)
+        touched.update((int(e), ep))
+        done += 1
+    mesh = replace(m, edgesOnEdge=eoe, nEdgesOnEdge=neoe, weightsOnEdge=w)
+    return replace(case, mesh=mesh)
+
+
 def _c2_small(**kw):
     return cases.sphere_case(3, 60, cases.SEED_BASE + 200, substeps=30, dt_btr=240.0, **kw)
 
@@ -113,6 +151,10 @@ CASES = {
     "all_terms_sphere3_land_L7": (lambda: all_terms(cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0),
                                                     nu4=1e13), 3),
     "all_terms_hex8_L128": (lambda: all_terms(cases.c1(n=8, L=128, steps=2)), 2),
+    # reconstruction stencils the library cannot put in canonical two-cell order
+    "generic_stencils_hex12_L20": (lambda: drop_stencil_pairs(cases.c1(n=12, L=20, steps=3)), 3),
+    "generic_stencils_sphere3_land_L7": (lambda: drop_stencil_pairs(
+        cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0)), 3),
     # ends of the accepted ranges (test_gpu_extremes)
     "hex8_L128": (lambda: cases.c1(n=8, L=128, steps=2), 2),
     "hex10_L65": (lambda: cases.c1(n=10, L=65, steps=2), 2),

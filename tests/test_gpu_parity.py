@@ -89,6 +89,7 @@ def _noisy_state(case, steps=3, seed=0):
 # ---------------------------------------------------------------------------
 KERNEL_CASES = {
     "hex10x6_L4": lambda: cases.with_params(smooth_case(n=10, L=4), scheme=3),
+    "hex12_L20_generic_stencils": lambda: P.build("generic_stencils_hex12_L20")[0],
     "sphere3_land_L7": lambda: cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0),
     "hex8_L100": lambda: cases.c1(n=8, L=100, steps=1),
     "hex12_L64": lambda: cases.c1(n=12, L=64, steps=1),
@@ -146,12 +147,15 @@ def test_thickness_stage_parity(dev, name, vcoord):
 # whole steps
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["c0_ssprk3_100", "c0_ssprk3_20", "c1_recipe_32x32x60",
-                                  "c2_recipe_level3x60", "hex8_L100"])
+                                  "c2_recipe_level3x60", "hex8_L100", "generic_stencils_hex12_L20",
+                                  "generic_stencils_sphere3_land_L7"])
 def test_whole_steps(dev, name):
     """C0 geometry with SSPRK3-SE over 20 and 100 steps; the C1 recipe (bathymetry,
     density front, 60 layers, M = 20) on a 32x32 hex; the C2 recipe (sphere,
     30 % land, variable f, 60 layers, M = 30) at level 3; L = 100 > 64 layers
-    (two register chunks per lane)."""
+    (two register chunks per lane); meshes whose reconstruction stencils are
+    not all other edges of the two cells, so that the edge pass runs on its
+    generic tables."""
     check_case(dev, name)
 
 
