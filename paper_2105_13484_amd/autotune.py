@@ -8,11 +8,14 @@ The knobs change how the work is laid out on the GPU, never the arithmetic
 * 2D-kernel workgroup size (barotropic evaluations, reconciliation):
   64 .. 1024 threads;
 * for single states, the edge-pass variant: direct gathers, or LDS tiles of
-  8, 16 or 32 edges.
+  8, 16 or 32 edges;
+* the barotropic-loop kernel (single states and every member of a batch):
+  one launch per substep over cell patches with their halo rings, or one
+  launch per forward-Euler evaluation.
 
 The tuner times whole steps with HIP events on the state's (batch's) stream
 and keeps the fastest setting.  It searches one knob at a time (coordinate
-descent from the defaults), which needs 5 + 5 (+ 4) trials instead of the
+descent from the defaults), which needs 5 + 5 + 1 (+ 4) trials instead of the
 full product.  Trial steps advance the state: tune a copy, or count them.
 """
 from __future__ import annotations
@@ -21,6 +24,7 @@ import time
 
 COLS_PER_BLOCK = (1, 2, 4, 8, 16)
 BLOCK_2D = (64, 128, 256, 512, 1024)
+BT_VARIANTS = (1, 0)
 
 
 def _time_steps(torch, stream, run, steps: int) -> float:
@@ -63,30 +67,41 @@ def tune_state(state, steps: int = 2, variants=None) -> dict:
         state.set_geometry(cfg["cols_per_block"], cfg["block_2d"])
         if not state.try_edge_variant(cfg["edge_variant"]):
             return None
+        if not state.try_bt_variant(cfg["bt_variant"]):
+            return None
         state.step(1)  # first launch of a new configuration
         return _time_steps(torch, state.stream, lambda n: state.step_async(n), steps)
 
     t0 = time.perf_counter()
-    best, log = _descend(trial, {"cols_per_block": 4, "block_2d": 256, "edge_variant": -1},
-                         {"edge_variant": variants, "cols_per_block": COLS_PER_BLOCK, "block_2d": BLOCK_2D})
+    start = {"cols_per_block": 4, "block_2d": 256, "edge_variant": -1, "bt_variant": state.bt_variant}
+    best, log = _descend(trial, start, {"edge_variant": variants, "bt_variant": BT_VARIANTS,
+                                        "cols_per_block": COLS_PER_BLOCK, "block_2d": BLOCK_2D})
     state.set_geometry(best["cols_per_block"], best["block_2d"])
     state.try_edge_variant(best["edge_variant"])
-    return {"best": best, "trials": log, "seconds": time.perf_counter() - t0}
+    state.try_bt_variant(best["bt_variant"])
+    return {"best": best, "trials": log, "default_ms": log[0][1], "seconds": time.perf_counter() - t0}
 
 
 def tune_batch(batch, steps: int = 2) -> dict:
-    """Tune a Batch in place (recompiles its program per geometry)."""
+    """Tune a Batch in place (recompiles its program per setting)."""
     import torch
 
+    def set_bt(variant):
+        return all(m.try_bt_variant(variant) for m in batch.members)
+
     def trial(cfg):
+        if not set_bt(cfg["bt_variant"]):
+            return None
         batch.set_geometry(cfg["cols_per_block"], cfg["block_2d"])
         batch.compile()
         batch.step(1)
         return _time_steps(torch, batch.stream, lambda n: batch.step_async(n), steps)
 
     t0 = time.perf_counter()
-    best, log = _descend(trial, {"cols_per_block": 4, "block_2d": 256},
-                         {"block_2d": BLOCK_2D, "cols_per_block": COLS_PER_BLOCK})
+    first = batch.members[0].bt_variant if batch.members else 1
+    best, log = _descend(trial, {"cols_per_block": 4, "block_2d": 256, "bt_variant": first},
+                         {"bt_variant": BT_VARIANTS, "block_2d": BLOCK_2D, "cols_per_block": COLS_PER_BLOCK})
+    set_bt(best["bt_variant"])
     batch.set_geometry(best["cols_per_block"], best["block_2d"])
     batch.compile()
-    return {"best": best, "trials": log, "seconds": time.perf_counter() - t0}
+    return {"best": best, "trials": log, "default_ms": log[0][1], "seconds": time.perf_counter() - t0}

@@ -93,6 +93,7 @@ KERNEL_CASES = {
     "sphere3_land_L7": lambda: cases.sphere_case(3, 7, 77, substeps=5, dt_btr=200.0),
     "hex8_L100": lambda: cases.c1(n=8, L=100, steps=1),
     "hex12_L64": lambda: cases.c1(n=12, L=64, steps=1),
+    "sphere3_land_L8": lambda: cases.sphere_case(3, 8, 78, substeps=5, dt_btr=200.0),
 }
 
 
@@ -231,7 +232,7 @@ def test_nonfinite_input_rejected(dev):
 # 64-bit column addresses as meshes with 4 GiB arrays take; LDS tiles of 8 /
 # 16 / 32 edges)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["hex12_L64", "hex8_L100", "sphere3_land_L7"])
+@pytest.mark.parametrize("name", ["hex12_L64", "hex8_L100", "sphere3_land_L7", "sphere3_land_L8"])
 @pytest.mark.parametrize("variant", [-2, 0, 1, 2])
 def test_edge_variant_feuler_parity(dev, name, variant):
     case = KERNEL_CASES[name]()
