@@ -4,14 +4,15 @@ benchmark times.
 At 512 x 512 cells x 60 layers (and on the level-7 sphere) the FP64 oracle
 takes minutes per step, so whole steps are compared with oracle values stored
 by ``tests/golden/make_fullsize.py`` (which calls the oracle only): three
-SSPRK3-SE steps of the C1 recipe in FP64 and of the C2 recipe, compared on a
+SSPRK3-SE steps of the C1 recipe in FP64 and of the C2 recipe in FP64 and
+both mixed modes, compared on a
 seeded sample of every field (65,536 velocities, 32,768 values of h, zeta and
 ubar).  The measures are the relative L2 over the sample and the largest
 sampled element error relative to the field's largest magnitude.  Bounds:
 
-  * C1, FP64: 1e-11 / 1e-10, or four times the spread that the oracle itself
-    shows at full size between correctly rounded, top-down and bottom-up
-    column sums (recorded beside the samples);
+  * C1 and C2, FP64: 1e-11 / 1e-10, or four times the spread that the oracle
+    itself shows at full size between correctly rounded, top-down and
+    bottom-up column sums (recorded beside the samples);
   * C2 in both mixed modes: velocity 1e-5, h 1e-9, SSH 1e-9 relative to
     zeta + H, SSH relative to zeta alone reported (and held to 1e-5).
 
@@ -77,6 +78,23 @@ def test_c1_full_three_steps_against_the_oracle(dev, c1_full):
     assert st.step(steps) == 0, dev.last_error()
     errs = _sampled_errors(st.read(), ref)
     _report("full C1 512x512x60, 3 steps vs stored oracle samples: " + P.format_errors(errs))
+    for f, e in errs.items():
+        b2 = max(P.TOL_L2, P.AMPLIFICATION * float(ref[f"spread_l2_{f}"]))
+        bm = max(P.TOL_MAX, P.AMPLIFICATION * float(ref[f"spread_inf_{f}"]))
+        assert e["l2"] <= b2 and e["max"] <= bm, (f, e, b2, bm)
+
+
+def test_c2_full_three_steps_fp64_against_the_oracle(dev):
+    """Three SSPRK3-SE steps of the C2 recipe (level-7 sphere, 60 layers, 30 %
+    land, M = 30) in FP64 against the same stored oracle samples, at the FP64
+    bounds."""
+    ref = _stored("c2")
+    steps = int(ref["steps"])
+    case = cases.c2()
+    dm, st = dev.state_from_case(cases.with_params(case, precision=0))
+    assert st.step(steps) == 0, dev.last_error()
+    errs = _sampled_errors(st.read(), ref)
+    _report("full C2 level 7 x 60, 3 steps, FP64 vs stored oracle samples: " + P.format_errors(errs))
     for f, e in errs.items():
         b2 = max(P.TOL_L2, P.AMPLIFICATION * float(ref[f"spread_l2_{f}"]))
         bm = max(P.TOL_MAX, P.AMPLIFICATION * float(ref[f"spread_inf_{f}"]))
