@@ -250,11 +250,19 @@ int sse_state_get_edge_variant(const sse_state *s, int *variant);
  * (3M per SSPRK3 loop, 2M per SSPRK2 loop).  1: one launch per substep: the
  * mesh is cut into patches of a few hundred cells, and one workgroup carries
  * its patch, extended by the halo rings the substep's evaluations read,
- * through all evaluations of the substep in LDS.  The default is 1 when the
- * mesh has such patches (sse_mesh_create builds them when every patch's halo
- * region fits a workgroup and every reconstruction stencil stays within the
- * two cells of its edge) and they fit the device's LDS, else 0.  SSE_EINVAL
- * for 1 otherwise.  Each member of a batch uses its own variant. */
+ * through all evaluations of the substep in LDS.  2: one cooperative launch
+ * per loop (persistent): every patch has its own workgroup for all M
+ * substeps, keeps its stencil tables, frozen forcing and F^zeta sums in
+ * registers, and waits at a grid barrier between substeps; available when
+ * the device holds a workgroup for every patch at once (small meshes: a few
+ * hundred patches).  A barrier wait is bounded: if one runs out, the step
+ * call reports SSE_EDEVICE and the state is not valid.  Steps captured in a
+ * HIP graph, and batch members, run variant 1 in place of 2.  The default is
+ * 1 when the mesh has such patches (sse_mesh_create builds them when every
+ * patch's halo region fits a workgroup and every reconstruction stencil stays
+ * within the two cells of its edge) and they fit the device's LDS, else 0.
+ * SSE_EINVAL for 1 or 2 where they do not apply.  Each member of a batch uses
+ * its own variant. */
 int sse_state_set_bt_variant(sse_state *s, int variant);
 int sse_state_get_bt_variant(const sse_state *s, int *variant);
 

@@ -9,9 +9,10 @@ The knobs change how the work is laid out on the GPU, never the arithmetic
   64 .. 1024 threads;
 * for single states, the edge-pass variant: direct gathers, or LDS tiles of
   8, 16 or 32 edges;
-* the barotropic-loop kernel (single states and every member of a batch):
-  one launch per substep over cell patches with their halo rings, or one
-  launch per forward-Euler evaluation.
+* the barotropic-loop kernel: one launch per substep over cell patches with
+  their halo rings, one launch per forward-Euler evaluation, or (single
+  states whose patches all fit the device at once) one cooperative launch for
+  the whole loop; batch members choose between the first two.
 
 The tuner times whole steps with HIP events on the state's (batch's) stream
 and keeps the fastest setting.  It searches one knob at a time (coordinate
@@ -24,7 +25,8 @@ import time
 
 COLS_PER_BLOCK = (1, 2, 4, 8, 16)
 BLOCK_2D = (64, 128, 256, 512, 1024)
-BT_VARIANTS = (1, 0)
+BT_VARIANTS = (1, 0, 2)
+BATCH_BT_VARIANTS = (1, 0)
 
 
 def _time_steps(torch, stream, run, steps: int) -> float:
@@ -100,7 +102,7 @@ def tune_batch(batch, steps: int = 2) -> dict:
     t0 = time.perf_counter()
     first = batch.members[0].bt_variant if batch.members else 1
     best, log = _descend(trial, {"cols_per_block": 4, "block_2d": 256, "bt_variant": first},
-                         {"bt_variant": BT_VARIANTS, "block_2d": BLOCK_2D, "cols_per_block": COLS_PER_BLOCK})
+                         {"bt_variant": BATCH_BT_VARIANTS, "block_2d": BLOCK_2D, "cols_per_block": COLS_PER_BLOCK})
     set_bt(best["bt_variant"])
     batch.set_geometry(best["cols_per_block"], best["block_2d"])
     batch.compile()

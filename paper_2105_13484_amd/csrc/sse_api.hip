@@ -69,7 +69,9 @@ struct Work {
     double *ubar_n, *ub1, *ub2, *ub_half, *ubar_new, *G0, *G1, *Gh, *Gi, *Fz1, *Fz2, *Fz3, *Sh1, *Fh1, *Sh2,
         *Fh2, *Sh3, *Pp, *Ftot, *uA;         // [E]
     double *zeta_n, *z1, *z_half, *Kbot, *bt_zout;  // [C]
-    int *flag;
+    int *flag;                               // [0]: non-finite flag; [16], [48]: barrier counter and
+                                             // generation, [32]: barrier error of the persistent
+                                             // barotropic loop
     void *D1, *L1, *D2, *Z2;                 // R, biharmonic runs only: div u [C][L], lap u [E][L],
                                              // div(lap u) [C][L], curl(lap u) [V][L]
     double *Tn, *T1s, *Th;                   // [C][L], tracer runs only: temperature of the state,
@@ -246,7 +248,12 @@ struct sse_state {
     bool tracer_set = false; // tracer runs: the temperature has been given
     Geom geom{};             // launch geometry (autotuner knob)
     int edge_variant = -1;   // -1: direct gathers (-2: with 64-bit column addresses); 0 / 1 / 2: LDS tiles of 8 / 16 / 32 edges
-    int bt_variant = 0;      // 0: one launch per barotropic evaluation; 1: one per substep (patches)
+    int bt_variant = 0;      // 0: one launch per barotropic evaluation; 1: one per substep (patches);
+                             // 2: one cooperative launch per loop, one workgroup per patch
+    int bt_capacity[2] = {0, 0};  // workgroups of the persistent loop kernel the device holds at once
+                                  // (SSPRK2, SSPRK3 forms)
+    bool capturing = false;  // a HIP graph capture of the step is in progress
+    hipError_t launch_error = hipSuccess;  // the last failed cooperative launch, reported by the step call
     size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
     Recorder *rec = nullptr; // non-null while a batch records this state's step
     sse_batch *batch = nullptr;
@@ -321,6 +328,13 @@ int nk_of(int L) { return L <= kWave ? 1 : 2; }
 bool bt_tiles_fit(const sse_state *s) {
     const DevBtTiles &t = s->mesh->bt;
     return t.nP > 0 && (s->bt64 ? t.lds_d : t.lds_f) <= s->lds_max;
+}
+
+// The persistent loop kernel can give every patch its own workgroup at once
+// (a cooperative launch of the XCD-padded patch count) for this scheme.
+bool bt_loop_fits(const sse_state *s, int scheme) {
+    const int nP = s->mesh->bt.nP;
+    return bt_tiles_fit(s) && kXcd * ((nP + kXcd - 1) / kXcd) <= s->bt_capacity[scheme == SSE_SCHEME_SSPRK3 ? 1 : 0];
 }
 
 // ---- building blocks -------------------------------------------------------
@@ -461,7 +475,43 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         oz = rp<R>(w.zo);
     }
     R *u1 = rp<R>(w.u1), *uh = rp<R>(w.uh), *z1 = rp<R>(w.z1), *zh = rp<R>(w.zh);
-    if (s->bt_variant == 1) {
+    if (s->bt_variant == 2 && !s->rec && !s->capturing && bt_loop_fits(s, scheme)) {
+        // one cooperative launch: every patch in its own workgroup for all M
+        // substeps, grid barriers between them
+        BTTileArgs<R> a{};
+        a.t = s->mesh->bt;
+        a.G = G;
+        a.F = F;
+        a.zeroF = 1;
+        a.tau = dt / M;
+        a.g = s->p.gravity;
+        a.w1 = scheme == SSE_SCHEME_SSPRK3 ? 1.0 / (6.0 * M) : 1.0 / (2.0 * M);
+        a.w3 = scheme == SSE_SCHEME_SSPRK3 ? 2.0 / (3.0 * M) : 0.0;
+        BtLoop<R> l{};
+        l.M = M;
+        l.u_in = iu;
+        l.z_in = iz;
+        l.bu0 = u1;
+        l.bu1 = uh;
+        l.bz0 = z1;
+        l.bz1 = zh;
+        l.u_out = ou;
+        l.z_out = oz;
+        l.bar = reinterpret_cast<unsigned *>(s->w.flag + 16);
+        l.gen = reinterpret_cast<unsigned *>(s->w.flag + 48);
+        l.err = s->w.flag + 32;
+        {
+            ProfScope ps(s, SSE_PROF_BT_EVAL);
+            const hipError_t e = launch_bt_loop<R>(a, l, scheme, s->stream);
+            if (e != hipSuccess) s->launch_error = e;
+        }
+        if constexpr (!std::is_same<R, double>::value) {
+            convert<R, double>(s, ou, out_u, m.E);
+            convert<R, double>(s, oz, out_z, m.C);
+        }
+        return;
+    }
+    if (s->bt_variant >= 1) {
         // one launch per substep; outputs alternate between the loop's
         // output and a scratch pair so that no launch reads what another
         // workgroup of the same launch writes, ending in the output
@@ -745,12 +795,23 @@ int check_params(const sse_params *p) {
 }
 
 int read_flag(sse_state *s) {
-    int flag = 0;
-    SSE_HIP(hipMemcpyAsync(&flag, s->w.flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    int flag[33] = {};
+    SSE_HIP(hipMemcpyAsync(flag, s->w.flag, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
     SSE_HIP(hipStreamSynchronize(s->stream));
     if (s->prof) prof_flush(s);
-    if (flag) { set_error("non-finite value in the state (the step blew up)"); return SSE_ENONFINITE; }
+    if (flag[32]) {
+        set_error("a grid barrier of the persistent barotropic loop timed out; the state is not valid");
+        return SSE_EDEVICE;
+    }
+    if (flag[0]) { set_error("non-finite value in the state (the step blew up)"); return SSE_ENONFINITE; }
     return SSE_OK;
+}
+
+// A cooperative launch that failed while steps were enqueued.
+int take_launch_error(sse_state *s) {
+    const hipError_t e = s->launch_error;
+    s->launch_error = hipSuccess;
+    return e == hipSuccess ? SSE_OK : hip_fail(e, "hipLaunchCooperativeKernel");
 }
 
 // Host <-> device copies of an array of the state's real type from / to FP64
@@ -1053,15 +1114,23 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
     s->lds_max = (size_t)lds_max;
     s->edge_variant = -1;
     s->bt_variant = bt_tiles_fit(s) ? 1 : 0;
+    for (int q = 0; q < 2; ++q)
+        s->bt_capacity[q] = !bt_tiles_fit(s) ? 0
+                            : s->bt64 ? bt_loop_capacity<double>(s->mesh->bt, 2 + q)
+                                      : bt_loop_capacity<float>(s->mesh->bt, 2 + q);
     *out = s;
     return SSE_OK;
 }
 
 extern "C" int sse_state_set_bt_variant(sse_state *s, int variant) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
-    if (variant != 0 && variant != 1) { set_error("barotropic variant must be 0 or 1"); return SSE_EINVAL; }
-    if (variant == 1 && !bt_tiles_fit(s)) {
-        set_error("barotropic variant 1: the mesh has no patches that fit a workgroup");
+    if (variant < 0 || variant > 2) { set_error("barotropic variant must be 0, 1 or 2"); return SSE_EINVAL; }
+    if (variant >= 1 && !bt_tiles_fit(s)) {
+        set_error("barotropic variants 1 and 2: the mesh has no patches that fit a workgroup");
+        return SSE_EINVAL;
+    }
+    if (variant == 2 && !bt_loop_fits(s, s->p.scheme)) {
+        set_error("barotropic variant 2: the device cannot hold a workgroup for every patch at once");
         return SSE_EINVAL;
     }
     s->bt_variant = variant;
@@ -1155,7 +1224,7 @@ extern "C" int sse_state_init(sse_state *s, const double *h, const double *u, co
     SSE_TRY(upload_real(s, w.U, um.data(), EL));
     SSE_HIP(hipMemcpyAsync(w.rho, ri.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
     SSE_HIP(hipMemcpyAsync(w.frac, frac.data(), CL * 8, hipMemcpyHostToDevice, s->stream));
-    SSE_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), s->stream));
+    SSE_HIP(hipMemsetAsync(w.flag, 0, kAlign, s->stream));
     launch_zeta_from_h(m->d, L, w.Hs, w.zeta_n, s->stream);
     if (s->rs == 4) {
         AssembleArgs<float> a{m->d, L, rp<float>(w.U), nullptr, w.Hs, rp<float>(w.U), w.ubar_n, w.flag};
@@ -1248,7 +1317,11 @@ extern "C" int sse_step_async(sse_state *s, int32_t n) {
     if (n < 0) { set_error("n must be >= 0"); return SSE_EINVAL; }
     if (s->use_graph) {
         if (!s->graph_exec) {
+            // the captured step uses the per-substep barotropic kernel: the
+            // persistent one is a cooperative launch
+            s->capturing = true;
             int rc = capture(s->stream, [&] { enqueue_step(s); }, &s->graph_exec);
+            s->capturing = false;
             if (rc) return rc;
         }
         for (int i = 0; i < n; ++i) SSE_HIP(hipGraphLaunch(s->graph_exec, s->stream));
@@ -1259,6 +1332,7 @@ extern "C" int sse_step_async(sse_state *s, int32_t n) {
         for (auto &e : s->events) SSE_HIP(hipEventCreate(&e));
     }
     for (int i = 0; i < n; ++i) enqueue_step(s);
+    if (int rc = take_launch_error(s)) return rc;
     SSE_HIP(hipGetLastError());
     return SSE_OK;
 }
@@ -1390,11 +1464,18 @@ extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_
         bt_loop<double>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1, bt_bufs(w));
     else
         bt_loop<float>(s, scheme, M, dt, w.ub1, w.z1, w.G0, w.ub2, w.bt_zout, w.Fz1, bt_bufs(w));
+    if (int rc = take_launch_error(s)) return rc;
     SSE_HIP(hipGetLastError());
+    int barrier_err = 0;
     SSE_HIP(hipMemcpyAsync(bo.data(), w.ub2, E * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(zo.data(), w.bt_zout, C * 8, hipMemcpyDeviceToHost, st));
     SSE_HIP(hipMemcpyAsync(fo.data(), w.Fz1, E * 8, hipMemcpyDeviceToHost, st));
+    SSE_HIP(hipMemcpyAsync(&barrier_err, w.flag + 32, sizeof(int), hipMemcpyDeviceToHost, st));
     SSE_HIP(hipStreamSynchronize(st));
+    if (barrier_err) {
+        set_error("a grid barrier of the persistent barotropic loop timed out");
+        return SSE_EDEVICE;
+    }
     rows_to_user(bo.data(), ubar1, m->edge_old, 1);
     rows_to_user(zo.data(), zeta1, m->cell_old, 1);
     rows_to_user(fo.data(), Fzeta, m->edge_old, 1);
@@ -1458,6 +1539,7 @@ extern "C" int sse_barotropic_substep_noalloc(sse_state *s, int32_t scheme, int3
     else
         bt_loop<float>(s, scheme, M, dt, iu, iz, iG, ou, oz, oF, b);
     s->prof = prof;
+    if (int rc = take_launch_error(s)) return rc;
     launch_permute(ou, dm.edge_old, ubar1, (int)E, true, s->geom, st);
     launch_permute(oz, dm.cell_old, zeta1, (int)C, true, s->geom, st);
     launch_permute(oF, dm.edge_old, Fzeta, (int)E, true, s->geom, st);

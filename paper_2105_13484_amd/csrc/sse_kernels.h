@@ -126,6 +126,18 @@ struct BTTileArgs {
     double w1, w3;            // flux weights: SSPRK3 w1, w1, w3; SSPRK2 w1, w1
 };
 
+// Buffers and barrier of the persistent barotropic loop: all M substeps in
+// one cooperative launch, one workgroup per patch.
+template <typename R>
+struct BtLoop {
+    int M;
+    const R *u_in, *z_in;     // loop input (not modified)
+    R *bu0, *bu1, *bz0, *bz1; // outputs of the substeps before the last, alternating
+    R *u_out, *z_out;         // the last substep's output
+    unsigned *bar, *gen;      // arrival counter and generation of the grid barriers (reset by the launch)
+    int *err;                 // set when a barrier wait runs out
+};
+
 // Thickness stage with the z-star distribution of a 2D total flux.
 struct THArgs {
     DevMesh m;
@@ -252,6 +264,12 @@ void set_tiled_lds_limit(size_t bytes);
 template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
 // scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit).
 template <typename R> void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s);
+// Workgroups of the persistent loop kernel the device holds at once for this
+// tile set, precision and scheme (0 if it cannot launch cooperatively).
+template <typename R> int bt_loop_capacity(const DevBtTiles &t, int scheme);
+// The whole loop (a: tables, G, F, tau, g and flux weights; the per-substep
+// pointers of a are unused); returns the launch's HIP error.
+template <typename R> hipError_t launch_bt_loop(const BTTileArgs<R> &a, const BtLoop<R> &l, int scheme, hipStream_t s);
 template <typename R> void launch_thickness_iso(const THIsoArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble(const AssembleArgs<R> &a, const Geom &g, hipStream_t s);
 template <typename R>

@@ -1281,6 +1281,228 @@ struct BtTab<float> {
     __device__ static const float *cd(const DevBtTiles &t) { return t.ccd_f; }
 };
 
+// Grid-wide barrier of a cooperative launch: the writes of every workgroup
+// before it are visible to every workgroup after it.  One thread per
+// workgroup arrives on a counter (after the workgroup barrier and a
+// device-scope release, which writes back its XCD's L2); the last of the
+// k-th round (the counter reaching k * gridDim.x) publishes generation k, for
+// which the others poll; a device-scope acquire then drops stale cache lines.
+// The wait is bounded: if it runs out (or another workgroup's did), the
+// workgroup sets *err and stops waiting, so every wavefront of the launch
+// still finishes; the host reports the error and the results are not used.
+constexpr unsigned kBarrierSpins = 1u << 22;  // about 0.3 s of sleeps
+
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned *gen, int *err, unsigned round) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned target = round * gridDim.x;
+        const unsigned old = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == target) {
+            __hip_atomic_store(gen, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                if (++spins > kBarrierSpins) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// The persistent form of the tiled substep (bt_substep_body below): all l.M
+// substeps of the loop for patch p in one workgroup of a cooperative launch
+// in which every patch has its own workgroup (p < 0: a padding workgroup that
+// only takes part in the barriers).  The stencil tables, the frozen forcing
+// and the F^zeta sums stay in registers for the whole loop; substep s reads
+// the previous substep's output (the loop input for s = 0) and writes one of
+// two stage buffers (the loop output for the last), with a grid barrier
+// between substeps.  Every evaluation performs exactly the arithmetic of the
+// one-evaluation kernel, so all forms give the same bits.
+template <typename R, int kScheme, int KS>
+__device__ __forceinline__ void bt_loop_body(const BTTileArgs<R> &a, const BtLoop<R> &l, int p) {
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) double lds_d[];
+    const DevBtTiles &T = a.t;
+    const int tid = threadIdx.x;
+    const bool on_patch = p >= 0;
+    const int pp = on_patch ? p : 0;
+    const int32_t *rec = T.patch + (size_t)pp * kBtRec;
+    const int e0 = rec[0], es0 = rec[1], c0 = rec[2], cs0 = rec[3];
+    int ne[4], nc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ne[k] = on_patch ? rec[4 + k] : 0;
+        nc[k] = on_patch ? rec[8 + k] : 0;
+    }
+    constexpr int kIn = kScheme == 3 ? 3 : 2;  // level of the substep input
+    const int nEin = ne[kIn], nCin = nc[kIn];
+    const int nE1 = ne[kIn - 1], nC1 = nc[kIn - 1];  // level of the first evaluation
+    const int se = ne[2], sc = nc[2];                // strides of the stencil tables
+
+    // LDS: H (double) | U0 U1 U2 | Z0 Z1 Z2 | H in R (FP32 state only)
+    double *H64b = lds_d;
+    R *U0b = reinterpret_cast<R *>(H64b + nc[3]);
+    R *U1b = U0b + ne[3];
+    R *U2b = U1b + ne[2];
+    R *Z0b = U2b + ne[1];
+    R *Z1b = Z0b + nc[3];
+    R *Z2b = Z1b + nc[2];
+    const R *Hrb;
+    if constexpr (sizeof(R) == 8) {
+        Hrb = reinterpret_cast<const R *>(H64b);
+    } else {
+        R *h = Z2b + nc[1];
+        for (int lc = tid; lc < nCin; lc += kBtThreads) h[lc] = T.cH_f[c0 + lc];
+        Hrb = h;
+    }
+    for (int lc = tid; lc < nCin; lc += kBtThreads) H64b[lc] = T.cH[c0 + lc];
+
+    // this thread's edges (le = s kBtThreads + tid) and cell (lc = tid)
+    const R *__restrict__ wt = BtTab<R>::w(T);
+    R w[KS][kMaxEdges2], idc[KS], Gv[KS];
+    uint32_t nbw[KS][kMaxEdges2 / 2], ecw[KS];
+    double Fa[KS];
+    int ge[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int le = s * kBtThreads + tid;
+        const bool on = le < nE1;
+        const int q = on ? le : 0;
+        ecw[s] = on ? T.ec[es0 + q] : 0u;
+        ge[s] = T.eid[e0 + q];
+        idc[s] = BtTab<R>::idc(T)[es0 + q];
+        Gv[s] = (R)a.G[ge[s]];
+#pragma unroll
+        for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = wt[(size_t)kMaxEdges2 * es0 + (size_t)j * se + q];
+#pragma unroll
+        for (int i = 0; i < kMaxEdges2 / 2; ++i) nbw[s][i] = T.enb[(size_t)(kMaxEdges2 / 2) * es0 + (size_t)i * se + q];
+        Fa[s] = (a.F && le < ne[0]) ? (a.zeroF ? 0.0 : a.F[ge[s]]) : 0.0;
+    }
+    const bool con = tid < nC1;
+    const int qc = con ? tid : 0;
+    const bool cwet = con && T.cwet[cs0 + qc] != 0;
+    const int gc = T.cid[c0 + qc];
+    R cd[kMaxEdges];
+    uint32_t cen[kMaxEdges];
+#pragma unroll
+    for (int j = 0; j < kMaxEdges; ++j) {
+        cd[j] = BtTab<R>::cd(T)[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
+        cen[j] = T.cen[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
+    }
+
+    const R tau = (R)a.tau, g = (R)a.g;
+    const int nsub = l.M;
+#pragma unroll 1
+    for (int sub = 0; sub < nsub; ++sub) {
+        // LDS bases offset by an opaque zero, so that the compiler recomputes
+        // the stage addresses in every substep instead of hoisting all of them
+        // out of the loop (which needs more registers than the tables)
+        int zoff = 0;
+        {
+            asm volatile("" : "+s"(zoff));
+            // the packed index words likewise: decoded once per substep, not
+            // kept decoded across the loop
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) {
+                asm volatile("" : "+v"(ecw[s2]));
+#pragma unroll
+                for (int i = 0; i < kMaxEdges2 / 2; ++i) asm volatile("" : "+v"(nbw[s2][i]));
+            }
+#pragma unroll
+            for (int j = 0; j < kMaxEdges; ++j) asm volatile("" : "+v"(cen[j]));
+        }
+        R *const U0 = U0b + zoff, *const U1 = U1b + zoff, *const U2 = U2b + zoff;
+        R *const Z0 = Z0b + zoff, *const Z1 = Z1b + zoff, *const Z2 = Z2b + zoff;
+        const double *const H64 = H64b + zoff;
+        const R *const Hr = Hrb + zoff;
+        const bool odd = (sub & 1) != 0;
+        const R *ua = sub == 0 ? l.u_in : (odd ? l.bu0 : l.bu1);
+        const R *za = sub == 0 ? l.z_in : (odd ? l.bz0 : l.bz1);
+        R *uo = sub == nsub - 1 ? l.u_out : (odd ? l.bu1 : l.bu0);
+        R *zo = sub == nsub - 1 ? l.z_out : (odd ? l.bz1 : l.bz0);
+#pragma unroll 1
+        for (int le = tid; le < nEin; le += kBtThreads) U0[le] = ua[T.eid[e0 + le]];
+#pragma unroll 1
+        for (int lc = tid; lc < nCin; lc += kBtThreads) Z0[lc] = za[T.cid[c0 + lc]];
+        __syncthreads();
+
+        // One evaluation producing level lvl from (Ui, Zi); the last one writes
+        // the substep output to global memory.
+        auto evaluate = [&](const R *Ui, const R *Zi, int lvl, int comb, double wF, R *Uo, R *Zo, bool last) {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int le = s * kBtThreads + tid;
+                if (le < ne[lvl]) {
+                    const uint32_t c = ecw[s];
+                    R out = R(0);
+                    if ((c >> 30) & 1u) {
+                        const int l1 = (int)(c & 0x7fffu), l2 = (int)((c >> 15) & 0x7fffu);
+                        const R u = Ui[le];
+                        const R z1 = Zi[l1], z2 = Zi[l2];
+                        R cor = R(0);
+#pragma unroll
+                        for (int j = 0; j < kMaxEdges2; ++j) {
+                            const int lj = (int)((nbw[s][j >> 1] >> (16 * (j & 1))) & 0xffffu);
+                            cor = fmadd(w[s][j], Ui[lj], cor);
+                        }
+                        const R ru = fmadd(-(g * (z2 - z1)), idc[s], cor) + Gv[s];
+                        const R base = comb != COMB_NONE ? U0[le] : R(0);
+                        out = combine<R>(comb, base, fmadd(tau, ru, u));
+                        if (a.F && le < ne[0]) {
+                            const double flux = (double)u * (0.5 * (((double)z1 + H64[l1]) + ((double)z2 + H64[l2])));
+                            Fa[s] = fmadd(wF, flux, Fa[s]);
+                        }
+                    }
+                    if (last) uo[ge[s]] = out;
+                    else Uo[le] = out;
+                }
+            }
+            if (tid < nc[lvl]) {
+                R out = R(0);
+                if (cwet) {
+                    const R zi = Zi[tid] + Hr[tid];
+                    R div = R(0);
+#pragma unroll
+                    for (int j = 0; j < kMaxEdges; ++j) {
+                        const int le = (int)(cen[j] & 0xffffu), ln = (int)(cen[j] >> 16);
+                        const R zn = Zi[ln] + Hr[ln];
+                        div = fmadd(cd[j], Ui[le] * (R(0.5) * (zi + zn)), div);
+                    }
+                    const R base = comb != COMB_NONE ? Z0[tid] : R(0);
+                    out = combine<R>(comb, base, fmadd(tau, -div, Zi[tid]));
+                }
+                if (last) zo[gc] = out;
+                else Zo[tid] = out;
+            }
+        };
+        if constexpr (kScheme == 3) {
+            evaluate(U0, Z0, 2, COMB_NONE, a.w1, U1, Z1, false);
+            __syncthreads();
+            evaluate(U1, Z1, 1, COMB_34, a.w1, U2, Z2, false);
+            __syncthreads();
+            evaluate(U2, Z2, 0, COMB_THIRD, a.w3, nullptr, nullptr, true);
+        } else {
+            evaluate(U0, Z0, 1, COMB_NONE, a.w1, U1, Z1, false);
+            __syncthreads();
+            evaluate(U1, Z1, 0, COMB_HALF, a.w1, nullptr, nullptr, true);
+        }
+        if (sub + 1 < nsub) grid_barrier(l.bar, l.gen, l.err, (unsigned)(sub + 1));
+    }
+    if (a.F) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (s * kBtThreads + tid < ne[0]) a.F[ge[s]] = Fa[s];
+    }
+}
+
 template <typename R, int kScheme, int KS>
 __device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
 #pragma clang fp contract(off)
@@ -1964,6 +2186,20 @@ __global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_substep_batch(
     if (batch_entry(b.table, b.blocks, t)) bt_substep_body<R, kScheme, KS>(b.args[t.x], t.y);
 }
 
+// The whole barotropic loop in one cooperative launch, one workgroup per
+// patch (workgroups past the last patch only take part in the barriers).
+template <typename R, int kScheme, int KS>
+__global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_loop_kernel(BTTileArgs<R> a, BtLoop<R> l) {
+    bt_loop_body<R, kScheme, KS>(a, l, xcd_block(a.t.nP));
+}
+
+__global__ void __launch_bounds__(64) bt_loop_reset_kernel(unsigned *bar, unsigned *gen) {
+    if (threadIdx.x == 0) {
+        *bar = 0u;
+        *gen = 0u;
+    }
+}
+
 __global__ void __launch_bounds__(1024) recon_kernel(ReconArgs a) { recon_body(a, blockIdx.x); }
 __global__ void __launch_bounds__(1024) recon_batch(BatchLaunch<ReconArgs> b) {
     int2 t;
@@ -2140,6 +2376,17 @@ void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t
 #undef SSE_TILED
 }
 
+template <typename R, int kScheme, int KS>
+static const void *bt_loop_fn() {
+    return reinterpret_cast<const void *>(bt_loop_kernel<R, kScheme, KS>);
+}
+
+template <typename R>
+static const void *bt_loop_select(int scheme, int ks) {
+    if (scheme == 3) return ks == 1 ? bt_loop_fn<R, 3, 1>() : bt_loop_fn<R, 3, 2>();
+    return ks == 1 ? bt_loop_fn<R, 2, 1>() : bt_loop_fn<R, 2, 2>();
+}
+
 // Allow the tiled kernels the device's full LDS per workgroup.
 void set_tiled_lds_limit(size_t bytes) {
 #define SSE_TILED_FN(NK_, R_, ADD_, MIX_) reinterpret_cast<const void *>(fe_edge_tiled_kernel<NK_, R_, ADD_, MIX_>)
@@ -2168,6 +2415,10 @@ void set_tiled_lds_limit(size_t bytes) {
                          reinterpret_cast<const void *>(bt_substep_batch<float, 2, 1>),
                          reinterpret_cast<const void *>(bt_substep_batch<float, 2, 2>)};
     for (const void *f : btb) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *btl[] = {bt_loop_fn<double, 3, 1>(), bt_loop_fn<double, 3, 2>(), bt_loop_fn<double, 2, 1>(),
+                         bt_loop_fn<double, 2, 2>(), bt_loop_fn<float, 3, 1>(),  bt_loop_fn<float, 3, 2>(),
+                         bt_loop_fn<float, 2, 1>(),  bt_loop_fn<float, 2, 2>()};
+    for (const void *f : btl) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -2182,6 +2433,31 @@ void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s) {
         if (a.t.ks == 1) bt_substep_kernel<R, 2, 1><<<grid, block, lds, s>>>(a);
         else bt_substep_kernel<R, 2, 2><<<grid, block, lds, s>>>(a);
     }
+}
+
+template <typename R>
+int bt_loop_capacity(const DevBtTiles &t, int scheme) {
+    if (t.nP <= 0) return 0;
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const size_t lds = sizeof(R) == 8 ? t.lds_d : t.lds_f;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bt_loop_select<R>(scheme, t.ks), kBtThreads, lds) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+template <typename R>
+hipError_t launch_bt_loop(const BTTileArgs<R> &a, const BtLoop<R> &l, int scheme, hipStream_t s) {
+    bt_loop_reset_kernel<<<1, 64, 0, s>>>(l.bar, l.gen);
+    const size_t lds = sizeof(R) == 8 ? a.t.lds_d : a.t.lds_f;
+    BTTileArgs<R> aa = a;
+    BtLoop<R> ll = l;
+    void *args[] = {&aa, &ll};
+    return hipLaunchCooperativeKernel(bt_loop_select<R>(scheme, a.t.ks), xcd_grid(a.t.nP), dim3(kBtThreads), args,
+                                      (unsigned)lds, s);
 }
 
 template <typename R>
@@ -2303,6 +2579,8 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_bt_substep<R>(const BTTileArgs<R> &, int, hipStream_t);                           \
+    template int bt_loop_capacity<R>(const DevBtTiles &, int);                                             \
+    template hipError_t launch_bt_loop<R>(const BTTileArgs<R> &, const BtLoop<R> &, int, hipStream_t);       \
     template void launch_bt_substep_batch<R>(const BatchLaunch<BTTileArgs<R>> &, int, int, size_t, hipStream_t); \
     template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, bool, const Geom &, hipStream_t); \
     template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \

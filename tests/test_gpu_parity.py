@@ -297,7 +297,7 @@ def test_wide_addressing_bitwise_equal(dev, precision):
 
 
 # ---------------------------------------------------------------------------
-# barotropic loop variants (one launch per evaluation, one per substep)
+# barotropic loop variants (one launch per evaluation, one per substep, one per loop)
 # ---------------------------------------------------------------------------
 BT_CASES = {
     "c0_one_patch": lambda: cases.c0(),
@@ -311,22 +311,44 @@ BT_CASES = {
 @pytest.mark.parametrize("scheme", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_bt_variants_bitwise_equal(dev, name, scheme, precision):
-    """The per-substep (patch) kernel performs the per-evaluation kernel's
+    """The per-substep (patch) kernel and the persistent loop kernel (all
+    substeps in one cooperative launch) perform the per-evaluation kernel's
     arithmetic on the same operands: whole steps agree bit for bit."""
     case = cases.with_params(BT_CASES[name](), scheme=scheme, precision=precision)
     out = {}
-    for v in (0, 1):
+    for v in (0, 1, 2):
         _, st = dev.state_from_case(case)
-        assert st.try_bt_variant(v), dev.last_error()
+        assert st.try_bt_variant(v), (v, dev.last_error())
         assert st.bt_variant == v
         assert st.step(2) == 0
         out[v] = st.read()
-    for k in out[0]:
-        assert np.array_equal(out[0][k], out[1][k]), k
+    for v in (1, 2):
+        for k in out[0]:
+            assert np.array_equal(out[0][k], out[v][k]), (v, k)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_loop_in_graph_and_eager_alike(dev, precision):
+    """A step captured as a HIP graph runs the per-substep kernel in place of
+    the persistent loop (a cooperative launch); replays and eager steps agree
+    bit for bit."""
+    import torch
+    case = cases.with_params(BT_CASES["sphere4_land_L9"](), precision=precision)
+    stream = torch.cuda.Stream()
+    _, eager = dev.state_from_case(case, stream=stream)
+    _, g = dev.state_from_case(case, stream=stream)
+    assert eager.try_bt_variant(2) and g.try_bt_variant(2), dev.last_error()
+    g.use_graph(True)
+    for k in range(3):
+        assert eager.step(1) == 0
+        assert g.step(1) == 0
+        a, b = eager.read(), g.read()
+        for f in a:
+            assert np.array_equal(a[f], b[f]), (k, f)
 
 
 @pytest.mark.parametrize("scheme", [2, 3])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_barotropic_substep_variants_parity(dev, scheme, variant):
     case = KERNEL_CASES["sphere3_land_L7"]()
     st_o = Setup.from_case(case)
