@@ -52,7 +52,7 @@ CALLS = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_noalloc_equals_workspace_entry_two_calls(dev, variant, precision):
     kept = []
