@@ -351,6 +351,15 @@ int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double
                                  const double *ubar, const double *zeta, const double *G,
                                  double *ubar1, double *zeta1, double *Fzeta);
 
+/* Polls a grid barrier of the persistent barotropic loop (variant 2) makes
+ * before it gives up, reports the timeout and lets every workgroup finish;
+ * 0 restores the default (about 0.3 s of waiting).  For tests of that error
+ * path: with 1, the first workgroup to reach a barrier finds it closed and
+ * gives up at once (whenever the launch has more than one workgroup), the
+ * step call returns SSE_EDEVICE and the state must be initialised again.
+ * SSE_EINVAL for a NULL state. */
+int sse_debug_set_barrier_spins(sse_state *s, uint32_t spins);
+
 /* One thickness stage h_out = h_in + dt T^h(h_in, u + uA) (Section 3.4 revised
  * thickness updates) with the state's vertical coordinate: inputs h_in [C][L],
  * u [E][L], uA [E]; outputs h_out [C][L] and zeta_out [C] = sum h_out - H. */

@@ -254,6 +254,7 @@ struct sse_state {
                                   // (SSPRK2, SSPRK3 forms)
     bool capturing = false;  // a HIP graph capture of the step is in progress
     hipError_t launch_error = hipSuccess;  // the last failed cooperative launch, reported by the step call
+    unsigned barrier_spins = kBarrierSpins;  // polls before a barrier of the persistent loop gives up
     size_t lds_max = 0;      // LDS bytes per workgroup on the state's device
     Recorder *rec = nullptr; // non-null while a batch records this state's step
     sse_batch *batch = nullptr;
@@ -500,6 +501,7 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         l.bar = reinterpret_cast<unsigned *>(s->w.flag + 16);
         l.gen = reinterpret_cast<unsigned *>(s->w.flag + 48);
         l.err = s->w.flag + 32;
+        l.spins = s->barrier_spins;
         {
             ProfScope ps(s, SSE_PROF_BT_EVAL);
             const hipError_t e = launch_bt_loop<R>(a, l, scheme, s->stream);
@@ -1136,6 +1138,12 @@ extern "C" int sse_state_set_bt_variant(sse_state *s, int variant) {
     s->bt_variant = variant;
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     s->graph_exec = nullptr;
+    return SSE_OK;
+}
+
+extern "C" int sse_debug_set_barrier_spins(sse_state *s, uint32_t spins) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    s->barrier_spins = spins ? spins - 1 : kBarrierSpins;  // the kernel gives up once it has slept this often
     return SSE_OK;
 }
 

@@ -136,6 +136,7 @@ struct BtLoop {
     R *u_out, *z_out;         // the last substep's output
     unsigned *bar, *gen;      // arrival counter and generation of the grid barriers (reset by the launch)
     int *err;                 // set when a barrier wait runs out
+    unsigned spins;           // polls before a barrier wait runs out
 };
 
 // Thickness stage with the z-star distribution of a 2D total flux.
@@ -264,6 +265,8 @@ void set_tiled_lds_limit(size_t bytes);
 template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
 // scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit).
 template <typename R> void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s);
+// Polls before a grid barrier of the persistent loop gives up (about 0.3 s).
+constexpr unsigned kBarrierSpins = 1u << 22;
 // Workgroups of the persistent loop kernel the device holds at once for this
 // tile set, precision and scheme (0 if it cannot launch cooperatively).
 template <typename R> int bt_loop_capacity(const DevBtTiles &t, int scheme);

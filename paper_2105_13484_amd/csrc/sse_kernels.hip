@@ -1290,9 +1290,8 @@ struct BtTab<float> {
 // The wait is bounded: if it runs out (or another workgroup's did), the
 // workgroup sets *err and stops waiting, so every wavefront of the launch
 // still finishes; the host reports the error and the results are not used.
-constexpr unsigned kBarrierSpins = 1u << 22;  // about 0.3 s of sleeps
-
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned *gen, int *err, unsigned round) {
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned *gen, int *err, unsigned round,
+                                             unsigned max_spins) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1304,7 +1303,7 @@ __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned *gen, int *
             unsigned spins = 0;
             while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
                 if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                if (++spins > kBarrierSpins) {
+                if (++spins > max_spins) {
                     __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
@@ -1494,7 +1493,7 @@ __device__ __forceinline__ void bt_loop_body(const BTTileArgs<R> &a, const BtLoo
             __syncthreads();
             evaluate(U1, Z1, 0, COMB_HALF, a.w1, nullptr, nullptr, true);
         }
-        if (sub + 1 < nsub) grid_barrier(l.bar, l.gen, l.err, (unsigned)(sub + 1));
+        if (sub + 1 < nsub) grid_barrier(l.bar, l.gen, l.err, (unsigned)(sub + 1), l.spins);
     }
     if (a.F) {
 #pragma unroll

@@ -35,7 +35,7 @@ EXPORTED = (
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
     "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
     "sse_state_set_bt_variant", "sse_state_get_bt_variant", "sse_state_set_tracer", "sse_read_tracer",
-    "sse_barotropic_substep_noalloc",
+    "sse_barotropic_substep_noalloc", "sse_debug_set_barrier_spins",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -108,6 +108,7 @@ def load():
         "sse_debug_barotropic_substep": (c_int, [P, c_int32, c_int32, c_double, dp, dp, dp, dp, dp, dp]),
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
         "sse_barotropic_substep_noalloc": (c_int, [P, c_int32, c_int32, c_double, P, P, P, P, P, P]),
+        "sse_debug_set_barrier_spins": (c_int, [P, ctypes.c_uint32]),
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_bt_variant": (c_int, [P, c_int]),
@@ -337,6 +338,10 @@ class DeviceState:
     @bt_variant.setter
     def bt_variant(self, variant: int):
         _check(load().sse_state_set_bt_variant(self.handle, int(variant)))
+
+    def set_barrier_spins(self, spins: int = 0):
+        """Polls before a grid barrier of the persistent barotropic loop gives up (0: default)."""
+        _check(load().sse_debug_set_barrier_spins(self.handle, int(spins)))
 
     def try_bt_variant(self, variant: int) -> bool:
         """Select a barotropic loop variant; False (and no change) if unavailable."""

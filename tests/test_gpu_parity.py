@@ -347,6 +347,28 @@ def test_persistent_loop_in_graph_and_eager_alike(dev, precision):
             assert np.array_equal(a[f], b[f]), (k, f)
 
 
+def test_persistent_loop_barrier_timeout_is_reported(dev):
+    """A grid barrier that gives up (forced from the host with a one-poll limit)
+    lets every workgroup finish; the step reports SSE_EDEVICE, and after
+    initialising again the state steps and matches the per-substep kernel."""
+    case = BT_CASES["sphere4_land_L9"]()
+    _, ref = dev.state_from_case(case)
+    assert ref.step(2) == 0
+    want = ref.read()
+    _, st = dev.state_from_case(case)
+    assert st.try_bt_variant(2), dev.last_error()
+    st.set_barrier_spins(1)
+    with pytest.raises(dev.SSEError) as info:
+        st.step(1)
+    assert "barrier" in str(info.value)
+    st.set_barrier_spins(0)
+    st.init(case.h, case.u, case.rho, case.h_ref)
+    assert st.step(2) == 0
+    got = st.read()
+    for k in want:
+        assert np.array_equal(want[k], got[k]), k
+
+
 @pytest.mark.parametrize("scheme", [2, 3])
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_barotropic_substep_variants_parity(dev, scheme, variant):
