@@ -376,8 +376,9 @@ int sse_debug_thickness_stage(sse_state *s, const double *h_in, const double *u,
  * but on DEVICE arrays in the caller's numbering: inputs ubar [E], zeta [C],
  * G [E]; outputs ubar1 [E], zeta1 [C], Fzeta [E] (outputs may alias inputs:
  * every input is read before any output is written).  The state supplies the
- * mesh, gravity, the barotropic kernel variant and the stream; its own
- * fields and workspace are not touched.  The loop's stages live in a static
+ * mesh, gravity, the barotropic kernel variant (variant 2, the persistent
+ * loop kernel, runs as variant 1 here) and the stream; its own fields and
+ * workspace are not touched.  The loop's stages live in a static
  * device array of 64 MiB per device, reserved when the library's code is
  * loaded on that device and held until the process ends; its address is
  * resolved by sse_state_create.  The call allocates nothing, enqueues its

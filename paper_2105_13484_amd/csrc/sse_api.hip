@@ -1540,13 +1540,18 @@ extern "C" int sse_barotropic_substep_noalloc(sse_state *s, int32_t scheme, int3
     launch_permute(ubar, dm.edge_old, iu, (int)E, false, s->geom, st);
     launch_permute(zeta, dm.cell_old, iz, (int)C, false, s->geom, st);
     launch_permute(G, dm.edge_old, iG, (int)E, false, s->geom, st);
-    const bool prof = s->prof;
+    const bool prof = s->prof, capturing = s->capturing;
     s->prof = false;  // no per-class events: their bookkeeping would grow host vectors
+    // callers may capture this call in a graph, and it must leave the state's
+    // workspace alone: never the persistent (cooperative) loop kernel, whose
+    // barrier words live in the workspace
+    s->capturing = true;
     if (s->bt64)
         bt_loop<double>(s, scheme, M, dt, iu, iz, iG, ou, oz, oF, b);
     else
         bt_loop<float>(s, scheme, M, dt, iu, iz, iG, ou, oz, oF, b);
     s->prof = prof;
+    s->capturing = capturing;
     if (int rc = take_launch_error(s)) return rc;
     launch_permute(ou, dm.edge_old, ubar1, (int)E, true, s->geom, st);
     launch_permute(oz, dm.cell_old, zeta1, (int)C, true, s->geom, st);

@@ -4,7 +4,10 @@ against the workspace-based entry point it is a variant of
 the results must agree bit for bit.  Two calls in a row share the static
 scratch array; the second runs on a smaller mesh, and the first call's
 outputs must not change.  A mesh too large for the array is rejected
-before anything is launched.
+before anything is launched.  A state set to the persistent loop kernel
+(barotropic variant 2) runs the per-substep kernel in the allocation-free
+entry point, while the workspace entry runs the persistent one: that case
+also compares the two kernels.
 """
 import numpy as np
 import pytest
