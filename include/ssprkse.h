@@ -121,15 +121,6 @@ typedef struct {
     const double *bottom_depth;       /* [C] H (total column height at rest)  */
     const double *area_triangle;      /* [V]                                  */
     const uint8_t *cell_mask;         /* [C] 1 = ocean, 0 = land              */
-    /* Optional (may be NULL): kite areas of the cells, [C][max_edges], entry
-     * (i, m) the part of cell i nearest to the vertex between its edge slots
-     * m and m+1 (Thuburn et al. 2009).  Where W follows from them by the
-     * TRiSK rule  W[e][e'] = s(i,e) s(i,e') (1/2 - sum of R(i,v) over the
-     * vertices v of i from e to e') l_e' / d_e,  R = kite area / cell area,
-     * each sum taken in counter-clockwise order from e, barotropic variant 3
-     * rebuilds the stencil weights on chip instead of reading them (see
-     * sse_state_set_bt_variant); results do not depend on this table. */
-    const double *kite_areas_on_cell;
 } sse_mesh_desc;
 
 /*
@@ -270,18 +261,8 @@ int sse_state_get_edge_variant(const sse_state *s, int *variant);
  * 1 when the mesh has such patches (sse_mesh_create builds them when every
  * patch's halo region fits a workgroup and every reconstruction stencil stays
  * within the two cells of its edge) and they fit the device's LDS, else 0.
- * 3: variant 1 with its tables made smaller: the stencil weights
- * W (f_e + f_e') / 2, the stencil edge lists, 1 / d_e and the divergence
- * coefficients s l_e / A are rebuilt in each launch, on chip, from per-cell
- * kite fractions, edge lists and orientation bits and per-edge lengths and
- * Coriolis parameters, with the same floating-point operations that form
- * them on the host, so the tables and the results are bitwise those of
- * variants 0-2.  Available when the mesh description carries kite areas and
- * sse_mesh_create found every stored weight, reciprocal and coefficient
- * reproduced bit for bit by that rebuild (TRiSK weights formed in the order
- * of the kite_areas_on_cell comment), and the larger LDS layout fits.
- * SSE_EINVAL for 1, 2 or 3 where they do not apply.  Each member of a batch
- * uses its own variant. */
+ * SSE_EINVAL for 1 or 2 where they do not apply.  Each member of a batch uses
+ * its own variant. */
 int sse_state_set_bt_variant(sse_state *s, int variant);
 int sse_state_get_bt_variant(const sse_state *s, int *variant);
 

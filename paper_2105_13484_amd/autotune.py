@@ -25,8 +25,8 @@ import time
 
 COLS_PER_BLOCK = (1, 2, 4, 8, 16)
 BLOCK_2D = (64, 128, 256, 512, 1024)
-BT_VARIANTS = (1, 3, 0, 2)
-BATCH_BT_VARIANTS = (1, 3, 0)
+BT_VARIANTS = (1, 0, 2)
+BATCH_BT_VARIANTS = (1, 0)
 
 
 def _time_steps(torch, stream, run, steps: int) -> float:

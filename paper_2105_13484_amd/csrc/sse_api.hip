@@ -330,11 +330,6 @@ bool bt_tiles_fit(const sse_state *s) {
     const DevBtTiles &t = s->mesh->bt;
     return t.nP > 0 && (s->bt64 ? t.lds_d : t.lds_f) <= s->lds_max;
 }
-// ... and its rebuilding form (variant 3) is usable too.
-bool bt_rebuild_fits(const sse_state *s) {
-    const DevBtTiles &t = s->mesh->bt;
-    return bt_tiles_fit(s) && t.rb && (s->bt64 ? t.lds_rd : t.lds_rf) <= s->lds_max;
-}
 
 // The persistent loop kernel can give every patch its own workgroup at once
 // (a cooperative launch of the XCD-padded patch count) for this scheme.
@@ -531,7 +526,6 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
         a.w1 = scheme == SSE_SCHEME_SSPRK3 ? 1.0 / (6.0 * M) : 1.0 / (2.0 * M);
         a.w3 = scheme == SSE_SCHEME_SSPRK3 ? 2.0 / (3.0 * M) : 0.0;
         const R *pu = iu, *pz = iz;
-        const bool rebuild = s->bt_variant == 3;
         if (s->rec) s->rec->loop_seq = s->rec->seq++;
         for (int sub = 0; sub < M; ++sub) {
             const bool to_out = (M - 1 - sub) % 2 == 0;
@@ -542,11 +536,11 @@ void bt_loop(sse_state *s, int scheme, int M, double dt, const double *in_u, con
             a.zo = tz;
             a.zeroF = sub == 0;
             if (s->rec) {
-                record(s, Kind::BT_TILE, a, 1, false, a.t.nP, sub, a.t.ks | (rebuild ? kBtRebuildVar : 0));
-                s->rec->entries.back().lds = bt_substep_lds<R>(a.t, rebuild);
+                record(s, Kind::BT_TILE, a, 1, false, a.t.nP, sub, a.t.ks);
+                s->rec->entries.back().lds = std::is_same<R, double>::value ? a.t.lds_d : a.t.lds_f;
             } else {
                 ProfScope ps(s, SSE_PROF_BT_EVAL);
-                launch_bt_substep<R>(a, scheme, rebuild, s->stream);
+                launch_bt_substep<R>(a, scheme, s->stream);
             }
             pu = tu;
             pz = tz;
@@ -1002,18 +996,6 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                 b.ccd = (const double *)put(hb.ccd.data(), hb.ccd.size() * 8);
                 b.ccd_f = (const float *)put(hb.ccd_f.data(), hb.ccd_f.size() * 4);
                 b.cwet = (const uint8_t *)put(hb.cwet.data(), hb.cwet.size());
-                if (hb.rb) {
-                    b.rlf = (const double *)put(hb.rlf.data(), hb.rlf.size() * 8);
-                    b.rR = (const double *)put(hb.rR.data(), hb.rR.size() * 8);
-                    b.rel = (const uint32_t *)put(hb.rel.data(), hb.rel.size() * 4);
-                    b.rcm = (const uint32_t *)put(hb.rcm.data(), hb.rcm.size() * 4);
-                    b.epos = (const uint8_t *)put(hb.epos.data(), hb.epos.size());
-                    b.edc = (const double *)put(hb.edc.data(), hb.edc.size() * 8);
-                    b.carea = (const double *)put(hb.carea.data(), hb.carea.size() * 8);
-                    b.rb = 1;
-                    b.lds_rd = hb.lds_rd;
-                    b.lds_rf = hb.lds_rf;
-                }
                 SSE_HIP(put_err);
                 SSE_HIP(hipStreamSynchronize(s));
                 b.nP = hb.nP;
@@ -1144,15 +1126,9 @@ extern "C" int sse_state_create(const sse_mesh *m, const sse_params *p, void *de
 
 extern "C" int sse_state_set_bt_variant(sse_state *s, int variant) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
-    if (variant < 0 || variant > 3) { set_error("barotropic variant must be 0, 1, 2 or 3"); return SSE_EINVAL; }
+    if (variant < 0 || variant > 2) { set_error("barotropic variant must be 0, 1 or 2"); return SSE_EINVAL; }
     if (variant >= 1 && !bt_tiles_fit(s)) {
-        set_error("barotropic variants 1 to 3: the mesh has no patches that fit a workgroup");
-        return SSE_EINVAL;
-    }
-    if (variant == 3 && !bt_rebuild_fits(s)) {
-        set_error(s->mesh->bt.rb ? "barotropic variant 3: its LDS layout does not fit the device"
-                                 : "barotropic variant 3: the mesh description has no kite areas that reproduce its "
-                                   "weights bit for bit");
+        set_error("barotropic variants 1 and 2: the mesh has no patches that fit a workgroup");
         return SSE_EINVAL;
     }
     if (variant == 2 && !bt_loop_fits(s, s->p.scheme)) {
@@ -1753,13 +1729,11 @@ void batch_enqueue(const sse_batch *b) {
                 break;
             case Kind::BT_TILE:
                 if (bt64)
-                    launch_bt_substep_batch<double>(bl<BTTileArgs<double>>(b, op), b->members[0]->p.scheme,
-                                                    op.var & ~kBtRebuildVar, (op.var & kBtRebuildVar) != 0, op.lds,
-                                                    st);
+                    launch_bt_substep_batch<double>(bl<BTTileArgs<double>>(b, op), b->members[0]->p.scheme, op.var,
+                                                    op.lds, st);
                 else
-                    launch_bt_substep_batch<float>(bl<BTTileArgs<float>>(b, op), b->members[0]->p.scheme,
-                                                   op.var & ~kBtRebuildVar, (op.var & kBtRebuildVar) != 0, op.lds,
-                                                   st);
+                    launch_bt_substep_batch<float>(bl<BTTileArgs<float>>(b, op), b->members[0]->p.scheme, op.var,
+                                                   op.lds, st);
                 break;
             case Kind::THICK: launch_thickness_batch(bl<THArgs>(b, op), op.nk, g, st); break;
             case Kind::THICK_ISO: launch_thickness_iso_batch<R>(bl<THIsoArgs<R>>(b, op), op.nk, g, st); break;

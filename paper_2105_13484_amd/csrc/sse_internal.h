@@ -130,79 +130,6 @@ constexpr int kBtWavesPerSimd = 4;
 // cost more (8.45 ms C1).
 constexpr int kBtPatch = 176;
 constexpr int kBtEdgeSlots = 2;    // edges of level 2 per thread (at most)
-
-// Rebuild of the tiled barotropic tables (variant 3) from the region arrays
-// of one patch: lf[2 le], lf[2 le + 1] = l_e, f_e of region edge le;
-// R[6 lc + v] = kite fraction A_kite / A of vertex slot v of region cell lc
-// (the vertex between edge slots v and v + 1); el[6 lc + m] = the region edge
-// of edge slot m; cm[lc] = n | (1 << (3 + m)) for every slot m whose edge
-// normal points out of the cell.  The TRiSK weights (Thuburn et al. 2009)
-// W = s(c,e) s(c,e') (1/2 - sum R) l_e' / d_e, summed counter-clockwise from
-// e, scaled by (f_e + f_e') / 2 for the Coriolis term; the divergence
-// coefficients s l_e / A.  The host runs these same functions to check them
-// against the stored tables bit for bit before the kernel may use them, so
-// both take the same operations in the same order.
-//
-// Quotient x / d (d > 0) from the correctly rounded reciprocal r = 1 / d:
-// the product x r is within an ulp of x / d, and one correction with the
-// exact remainder fma(-q, d, x) rounds it correctly (Markstein's theorem for
-// round to nearest); the host check confirms it for every entry of the mesh.
-// The correction of a zero quotient is +0, so the sign is taken from x r,
-// which has the quotient's sign (-0 / d = -0, a zero TRiSK weight).
-__host__ __device__ __forceinline__ double bt_rb_quot(double x, double d, double r) {
-    const double q = x * r;
-    return __builtin_copysign(__builtin_fma(__builtin_fma(-q, d, x), r, q), q);
-}
-// a or -a (an exact sign flip)
-__host__ __device__ __forceinline__ double bt_rb_neg_if(double a, bool neg) {
-    uint64_t b;
-    __builtin_memcpy(&b, &a, sizeof b);
-    b ^= (uint64_t)neg << 63;
-    __builtin_memcpy(&a, &b, sizeof a);
-    return a;
-}
-// One side of edge le's stencil: its cell c (region index), the slot m of e
-// in c, first = c is the cell the normal of e points away from, rd = 1 / d_e;
-// w[k], lj[k] for the cell's stencil slots k = 0..4 (unused slots: weight 0,
-// edge le).
-__host__ __device__ __forceinline__ void bt_rb_side(const double *lf, const double *R, const uint16_t *el,
-                                                     const uint32_t *cm, int c, int m, bool first, double fe,
-                                                     double dce, double rd, int le, double *w, int *lj) {
-#pragma clang fp contract(off)
-    const uint32_t cw = cm[c];
-    const int n = (int)(cw & 7u);
-    const double *Rc = R + 6 * c;
-    const uint16_t *elc = el + 6 * c;
-    double cum = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        // Computed for every k without branches and kept for k < n - 1.  With
-        // m < n <= 6 both slots stay inside the cell's row of 6, and where the
-        // host accepted the mesh (every cell with 5 or 6 edges) the entry of a
-        // pentagon's fifth slot is edge le itself.
-        int v = m + k;
-        if (v >= n) v -= n;
-        cum = cum + Rc[v];
-        const int t = v + 1 < n ? v + 1 : v + 1 - n;
-        const int ej = elc[t];
-        // s(c,e) s(c,e') = -1 when exactly one of the two normals points out of c
-        const bool neg = first != (((cw >> (3 + t)) & 1u) != 0);
-        const double x = bt_rb_neg_if(0.5 - cum, neg) * lf[2 * ej];
-        const double wk = bt_rb_quot(x, dce, rd) * (0.5 * (fe + lf[2 * ej + 1]));
-        const bool used = k < n - 1;
-        w[k] = used ? wk : 0.0;
-        lj[k] = used ? ej : le;
-    }
-}
-// Divergence coefficient of edge slot j of a cell (cw = its cm word, le the
-// region edge of the slot, area the cell's area, ra = 1 / area); 0 for
-// padding slots.
-__host__ __device__ __forceinline__ double bt_rb_div(const double *lf, uint32_t cw, int j, int le, double area,
-                                                    double ra) {
-#pragma clang fp contract(off)
-    if (j >= (int)(cw & 7u)) return 0.0;
-    return bt_rb_quot(bt_rb_neg_if(lf[2 * le], ((cw >> (3 + j)) & 1u) == 0), area, ra);
-}
 constexpr int kBtRec = 12;         // ints per patch record
 struct DevBtTiles {
     int nP = 0;                    // patches (0: tiling not available)
@@ -228,17 +155,6 @@ struct DevBtTiles {
     const double *ccd = nullptr;      // [6][..] s l / A
     const float *ccd_f = nullptr;
     const uint8_t *cwet = nullptr;    // [..]
-    // Rebuild inputs (barotropic variant 3; rb = 1 when the host found them
-    // to reproduce ew, ew_f, enb, eidc, eidc_f, ccd and ccd_f bit for bit).
-    int rb = 0;
-    size_t lds_rd = 0, lds_rf = 0;    // dynamic LDS bytes of the rebuilding kernel
-    const double *rlf = nullptr;      // [sum ne3][2] l_e, f_e of the region edges
-    const double *rR = nullptr;       // [sum nc3][6] kite fraction of each vertex slot
-    const uint32_t *rel = nullptr;    // [sum nc3][3] local edges of the edge slots, two 16-bit per word
-    const uint32_t *rcm = nullptr;    // [sum nc3] n | out-pointing-normal bit of slot m << (3 + m)
-    const uint8_t *epos = nullptr;    // [sum ne2] slot of e in c1 | slot in c2 << 3
-    const double *edc = nullptr;      // [sum ne2] d_e
-    const double *carea = nullptr;    // [sum nc2] A of the cells of levels 0..2
 };
 }  // namespace sse
 
@@ -325,7 +241,7 @@ void locality_order(const sse_mesh_desc *d, int patch, MeshOrder &o);
 struct PermutedDesc {
     sse_mesh_desc d{};
     std::vector<int32_t> coe, eoc, neoc, voe, eov, eoe, neoe;
-    std::vector<double> w, dc, dv, f, area, H, tri, kite;
+    std::vector<double> w, dc, dv, f, area, H, tri;
     std::vector<uint8_t> mask;
 };
 void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p);
@@ -352,12 +268,6 @@ struct HostBtTiles {
     std::vector<float> cH_f, ew_f, eidc_f, ccd_f;
     std::vector<uint32_t> ec, enb, cen;
     std::vector<uint8_t> cwet;
-    // rebuild inputs (filled when the description has kite areas)
-    bool rb = false;
-    size_t lds_rd = 0, lds_rf = 0;
-    std::vector<double> rlf, rR, edc, carea;
-    std::vector<uint32_t> rel, rcm;
-    std::vector<uint8_t> epos;
 };
 // Region lists and tables of the partition pid (numbering of d, the same
 // numbering as the tables t).  With t == nullptr only the sizes are filled

@@ -263,18 +263,8 @@ template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
 template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
 void set_tiled_lds_limit(size_t bytes);
 template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
-// scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit);
-// rebuild (variant 3): the stencil tables rebuilt on chip, requires a.t.rb.
-template <typename R> void launch_bt_substep(const BTTileArgs<R> &a, int scheme, bool rebuild, hipStream_t s);
-// Dynamic LDS bytes of the substep kernel for tile set t.
-template <typename R>
-inline size_t bt_substep_lds(const DevBtTiles &t, bool rebuild) {
-    if (rebuild) return sizeof(R) == 8 ? t.lds_rd : t.lds_rf;
-    return sizeof(R) == 8 ? t.lds_d : t.lds_f;
-}
-// Flag of the rebuilding substep kernel in the variant word of a batched
-// launch (beside the edge slots per thread, 1 or 2).
-constexpr int kBtRebuildVar = 4;
+// scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit).
+template <typename R> void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s);
 // Polls before a grid barrier of the persistent loop gives up (about 0.3 s).
 constexpr unsigned kBarrierSpins = 1u << 22;
 // Workgroups of the persistent loop kernel the device holds at once for this
@@ -327,11 +317,9 @@ Geom edge_geom(const Geom &g, int nk);
 int fe_edge_variant(const DevMesh &m, int L, int vmix, bool del4);
 template <typename R> void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add, int var, const Geom &g, hipStream_t s);
 template <typename R> void launch_bt_eval_batch(const BatchLaunch<BTEvalArgs<R>> &b, bool delta16, const Geom &g, hipStream_t s);
-// table entries (member, patch); the members share ks and rebuild; lds: the
-// largest over the members
+// table entries (member, patch); ks and lds: the largest over the members
 template <typename R>
-void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, bool rebuild, size_t lds,
-                             hipStream_t s);
+void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, size_t lds, hipStream_t s);
 template <typename R> void launch_thickness_iso_batch(const BatchLaunch<THIsoArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename R> void launch_assemble_batch(const BatchLaunch<AssembleArgs<R>> &b, int nk, const Geom &g, hipStream_t s);
 template <typename Tin, typename Tout>

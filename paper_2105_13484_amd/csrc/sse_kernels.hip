@@ -1502,12 +1502,7 @@ __device__ __forceinline__ void bt_loop_body(const BTTileArgs<R> &a, const BtLoo
     }
 }
 
-// kRb (variant 3): the stencil weights and edges, 1 / d_e and the
-// divergence coefficients are rebuilt from the patch's rebuild inputs (staged
-// in LDS beside the substep input) by the functions the host checked them
-// with, instead of being read from the stored tables: the same values, read
-// from fewer bytes.
-template <typename R, int kScheme, int KS, bool kRb>
+template <typename R, int kScheme, int KS>
 __device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
 #pragma clang fp contract(off)
     extern __shared__ __align__(16) double lds_d[];
@@ -1526,67 +1521,34 @@ __device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
     const int nE1 = ne[kIn - 1], nC1 = nc[kIn - 1];  // level of the first evaluation
     const int se = ne[2], sc = nc[2];                // strides of the stencil tables
 
-    // LDS: H (double) | U0 U1 U2 | Z0 Z1 Z2 | H in R (FP32 state only).
-    // Rebuilding form: H | U0 | Z0 | H in R, then from a 16-byte boundary
-    // U1 U2 Z1 Z2 over the rebuild inputs (l, f of the region edges; kite
-    // fractions, edge slots and slot words of the region cells), which are
-    // dead before the first evaluation writes U1.
+    // LDS: H (double) | U0 U1 U2 | Z0 Z1 Z2 | H in R (FP32 state only)
     double *H64 = lds_d;
-    R *U0, *U1, *U2, *Z0, *Z1, *Z2, *Hw = nullptr;
-    double *SLF = nullptr, *SR = nullptr;
-    uint32_t *SEL = nullptr, *SCM = nullptr;
-    if constexpr (!kRb) {
-        U0 = reinterpret_cast<R *>(H64 + nc[3]);
-        U1 = U0 + ne[3];
-        U2 = U1 + ne[2];
-        Z0 = U2 + ne[1];
-        Z1 = Z0 + nc[3];
-        Z2 = Z1 + nc[2];
-        if constexpr (sizeof(R) != 8) Hw = Z2 + nc[1];
-    } else {
-        U0 = reinterpret_cast<R *>(H64 + nc[3]);
-        Z0 = U0 + ne[3];
-        size_t head = 8 * (size_t)nc[3] + sizeof(R) * ((size_t)ne[3] + nc[3]);
-        if constexpr (sizeof(R) != 8) {
-            Hw = Z0 + nc[3];
-            head += sizeof(R) * (size_t)nc[3];
-        }
-        head = (head + 15) / 16 * 16;
-        char *x = reinterpret_cast<char *>(lds_d) + head;
-        U1 = reinterpret_cast<R *>(x);
-        U2 = U1 + ne[2];
-        Z1 = U2 + ne[1];
-        Z2 = Z1 + nc[2];
-        SLF = reinterpret_cast<double *>(x);
-        SR = SLF + 2 * ne[3];
-        SEL = reinterpret_cast<uint32_t *>(SR + 6 * nc[3]);
-        SCM = SEL + 3 * nc[3];
-    }
+    R *U0 = reinterpret_cast<R *>(H64 + nc[3]);
+    R *U1 = U0 + ne[3];
+    R *U2 = U1 + ne[2];
+    R *Z0 = U2 + ne[1];
+    R *Z1 = Z0 + nc[3];
+    R *Z2 = Z1 + nc[2];
     const R *Hr;
     if constexpr (sizeof(R) == 8) {
         Hr = reinterpret_cast<const R *>(H64);
     } else {
-        for (int lc = tid; lc < nCin; lc += kBtThreads) Hw[lc] = T.cH_f[c0 + lc];
-        Hr = Hw;
+        R *h = Z2 + nc[1];
+        for (int lc = tid; lc < nCin; lc += kBtThreads) h[lc] = T.cH_f[c0 + lc];
+        Hr = h;
     }
     for (int le = tid; le < nEin; le += kBtThreads) U0[le] = a.ua[T.eid[e0 + le]];
     for (int lc = tid; lc < nCin; lc += kBtThreads) {
         Z0[lc] = a.za[T.cid[c0 + lc]];
         H64[lc] = T.cH[c0 + lc];
     }
-    if constexpr (kRb) {
-        const double2 *lf = reinterpret_cast<const double2 *>(T.rlf) + e0;
-        for (int le = tid; le < nEin; le += kBtThreads) reinterpret_cast<double2 *>(SLF)[le] = lf[le];
-        for (int i = tid; i < 6 * nCin; i += kBtThreads) SR[i] = T.rR[6 * (size_t)c0 + i];
-        for (int i = tid; i < 3 * nCin; i += kBtThreads) SEL[i] = T.rel[3 * (size_t)c0 + i];
-        for (int i = tid; i < nCin; i += kBtThreads) SCM[i] = T.rcm[c0 + i];
-    }
 
     // this thread's edges (le = s kBtThreads + tid) and cell (lc = tid)
+    const R *__restrict__ wt = BtTab<R>::w(T);
     R w[KS][kMaxEdges2], idc[KS], Gv[KS];
     uint32_t nbw[KS][kMaxEdges2 / 2], ecw[KS];
-    double Fa[KS], dce[KS];
-    int ge[KS], pos[KS];
+    double Fa[KS];
+    int ge[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
         const int le = s * kBtThreads + tid;
@@ -1594,19 +1556,12 @@ __device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
         const int q = on ? le : 0;
         ecw[s] = on ? T.ec[es0 + q] : 0u;
         ge[s] = T.eid[e0 + q];
+        idc[s] = BtTab<R>::idc(T)[es0 + q];
         Gv[s] = (R)a.G[ge[s]];
-        if constexpr (!kRb) {
-            const R *__restrict__ wt = BtTab<R>::w(T);
-            idc[s] = BtTab<R>::idc(T)[es0 + q];
 #pragma unroll
-            for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = wt[(size_t)kMaxEdges2 * es0 + (size_t)j * se + q];
+        for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = wt[(size_t)kMaxEdges2 * es0 + (size_t)j * se + q];
 #pragma unroll
-            for (int i = 0; i < kMaxEdges2 / 2; ++i)
-                nbw[s][i] = T.enb[(size_t)(kMaxEdges2 / 2) * es0 + (size_t)i * se + q];
-        } else {
-            dce[s] = T.edc[es0 + q];
-            pos[s] = T.epos[es0 + q];
-        }
+        for (int i = 0; i < kMaxEdges2 / 2; ++i) nbw[s][i] = T.enb[(size_t)(kMaxEdges2 / 2) * es0 + (size_t)i * se + q];
         Fa[s] = (a.F && le < ne[0]) ? (a.zeroF ? 0.0 : a.F[ge[s]]) : 0.0;
     }
     const bool con = tid < nC1;
@@ -1617,50 +1572,10 @@ __device__ __forceinline__ void bt_substep_body(const BTTileArgs<R> &a, int p) {
     uint32_t cen[kMaxEdges];
 #pragma unroll
     for (int j = 0; j < kMaxEdges; ++j) {
-        if constexpr (!kRb) cd[j] = BtTab<R>::cd(T)[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
+        cd[j] = BtTab<R>::cd(T)[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
         cen[j] = T.cen[(size_t)kMaxEdges * cs0 + (size_t)j * sc + qc];
     }
-    double carea = 0.0;
-    if constexpr (kRb) carea = T.carea[cs0 + qc];
     __syncthreads();
-    if constexpr (kRb) {
-        // the tables of this thread's edges and cell from the staged inputs
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int le = s * kBtThreads + tid;
-            if (le < nE1) {
-                const uint32_t c = ecw[s];
-                double wd[kMaxEdges2];
-                int lj[kMaxEdges2];
-                const double fe = SLF[2 * le + 1], rd = 1.0 / dce[s];
-                const uint16_t *el = reinterpret_cast<const uint16_t *>(SEL);
-                bt_rb_side(SLF, SR, el, SCM, (int)(c & 0x7fffu), pos[s] & 7, true, fe, dce[s], rd, le, wd, lj);
-                bt_rb_side(SLF, SR, el, SCM, (int)((c >> 15) & 0x7fffu), (pos[s] >> 3) & 7, false, fe, dce[s], rd,
-                           le, wd + 5, lj + 5);
-#pragma unroll
-                for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = (R)wd[j];
-#pragma unroll
-                for (int i = 0; i < kMaxEdges2 / 2; ++i) nbw[s][i] = (uint32_t)lj[2 * i] | ((uint32_t)lj[2 * i + 1] << 16);
-                idc[s] = (R)rd;
-            } else {
-#pragma unroll
-                for (int j = 0; j < kMaxEdges2; ++j) w[s][j] = R(0);
-#pragma unroll
-                for (int i = 0; i < kMaxEdges2 / 2; ++i) nbw[s][i] = 0u;
-                idc[s] = R(0);
-            }
-        }
-        if (con) {
-            const uint32_t cw = SCM[tid];
-            const double ra = 1.0 / carea;
-#pragma unroll
-            for (int j = 0; j < kMaxEdges; ++j) cd[j] = (R)bt_rb_div(SLF, cw, j, (int)(cen[j] & 0xffffu), carea, ra);
-        } else {
-#pragma unroll
-            for (int j = 0; j < kMaxEdges; ++j) cd[j] = R(0);
-        }
-        __syncthreads();
-    }
 
     const R tau = (R)a.tau, g = (R)a.g;
     // One evaluation producing level lvl from (Ui, Zi); the last one writes the
@@ -2257,17 +2172,17 @@ __global__ void __launch_bounds__(1024) bt_eval_batch(BatchLaunch<BTEvalArgs<R>>
         bt_eval_body<R, kD16>(a, false, t.y - nEB);
 }
 
-template <typename R, int kScheme, int KS, bool kRb>
+template <typename R, int kScheme, int KS>
 __global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_substep_kernel(BTTileArgs<R> a) {
     const int p = xcd_block(a.t.nP);
-    if (p >= 0) bt_substep_body<R, kScheme, KS, kRb>(a, p);
+    if (p >= 0) bt_substep_body<R, kScheme, KS>(a, p);
 }
 // Batched: one workgroup per (member, patch); the dynamic LDS is the
 // largest member's.
-template <typename R, int kScheme, int KS, bool kRb>
+template <typename R, int kScheme, int KS>
 __global__ void __launch_bounds__(kBtThreads, kBtWavesPerSimd) bt_substep_batch(BatchLaunch<BTTileArgs<R>> b) {
     int2 t;
-    if (batch_entry(b.table, b.blocks, t)) bt_substep_body<R, kScheme, KS, kRb>(b.args[t.x], t.y);
+    if (batch_entry(b.table, b.blocks, t)) bt_substep_body<R, kScheme, KS>(b.args[t.x], t.y);
 }
 
 // The whole barotropic loop in one cooperative launch, one workgroup per
@@ -2481,15 +2396,24 @@ void set_tiled_lds_limit(size_t bytes) {
                          SSE_TILED_FNS(float, true)};
 #undef SSE_TILED_FNS
 #undef SSE_TILED_FN
-#define SSE_BT_FNS(K_, RB_)                                                                                    \
-    reinterpret_cast<const void *>(K_<double, 3, 1, RB_>), reinterpret_cast<const void *>(K_<double, 3, 2, RB_>), \
-        reinterpret_cast<const void *>(K_<double, 2, 1, RB_>), reinterpret_cast<const void *>(K_<double, 2, 2, RB_>), \
-        reinterpret_cast<const void *>(K_<float, 3, 1, RB_>), reinterpret_cast<const void *>(K_<float, 3, 2, RB_>),   \
-        reinterpret_cast<const void *>(K_<float, 2, 1, RB_>), reinterpret_cast<const void *>(K_<float, 2, 2, RB_>)
-    const void *bt[] = {SSE_BT_FNS(bt_substep_kernel, false), SSE_BT_FNS(bt_substep_kernel, true),
-                        SSE_BT_FNS(bt_substep_batch, false), SSE_BT_FNS(bt_substep_batch, true)};
-#undef SSE_BT_FNS
+    const void *bt[] = {reinterpret_cast<const void *>(bt_substep_kernel<double, 3, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 3, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 2, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<double, 2, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 3, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 3, 2>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 1>),
+                        reinterpret_cast<const void *>(bt_substep_kernel<float, 2, 2>)};
     for (const void *f : bt) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *btb[] = {reinterpret_cast<const void *>(bt_substep_batch<double, 3, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 3, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 2, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<double, 2, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 3, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 3, 2>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 2, 1>),
+                         reinterpret_cast<const void *>(bt_substep_batch<float, 2, 2>)};
+    for (const void *f : btb) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     const void *btl[] = {bt_loop_fn<double, 3, 1>(), bt_loop_fn<double, 3, 2>(), bt_loop_fn<double, 2, 1>(),
                          bt_loop_fn<double, 2, 2>(), bt_loop_fn<float, 3, 1>(),  bt_loop_fn<float, 3, 2>(),
                          bt_loop_fn<float, 2, 1>(),  bt_loop_fn<float, 2, 2>()};
@@ -2497,22 +2421,17 @@ void set_tiled_lds_limit(size_t bytes) {
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename R, bool kRb>
-static void launch_bt_substep_rb(const BTTileArgs<R> &a, int scheme, hipStream_t s) {
-    const dim3 grid = xcd_grid(a.t.nP), block(kBtThreads);
-    const size_t lds = bt_substep_lds<R>(a.t, kRb);
-    if (scheme == 3) {
-        if (a.t.ks == 1) bt_substep_kernel<R, 3, 1, kRb><<<grid, block, lds, s>>>(a);
-        else bt_substep_kernel<R, 3, 2, kRb><<<grid, block, lds, s>>>(a);
-    } else {
-        if (a.t.ks == 1) bt_substep_kernel<R, 2, 1, kRb><<<grid, block, lds, s>>>(a);
-        else bt_substep_kernel<R, 2, 2, kRb><<<grid, block, lds, s>>>(a);
-    }
-}
 template <typename R>
-void launch_bt_substep(const BTTileArgs<R> &a, int scheme, bool rebuild, hipStream_t s) {
-    if (rebuild) launch_bt_substep_rb<R, true>(a, scheme, s);
-    else launch_bt_substep_rb<R, false>(a, scheme, s);
+void launch_bt_substep(const BTTileArgs<R> &a, int scheme, hipStream_t s) {
+    const dim3 grid = xcd_grid(a.t.nP), block(kBtThreads);
+    const size_t lds = sizeof(R) == 8 ? a.t.lds_d : a.t.lds_f;
+    if (scheme == 3) {
+        if (a.t.ks == 1) bt_substep_kernel<R, 3, 1><<<grid, block, lds, s>>>(a);
+        else bt_substep_kernel<R, 3, 2><<<grid, block, lds, s>>>(a);
+    } else {
+        if (a.t.ks == 1) bt_substep_kernel<R, 2, 1><<<grid, block, lds, s>>>(a);
+        else bt_substep_kernel<R, 2, 2><<<grid, block, lds, s>>>(a);
+    }
 }
 
 template <typename R>
@@ -2540,23 +2459,16 @@ hipError_t launch_bt_loop(const BTTileArgs<R> &a, const BtLoop<R> &l, int scheme
                                       (unsigned)lds, s);
 }
 
-template <typename R, bool kRb>
-static void launch_bt_substep_batch_rb(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, size_t lds,
-                                       hipStream_t s) {
+template <typename R>
+void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, size_t lds, hipStream_t s) {
     const dim3 grid = xcd_grid(b.blocks), block(kBtThreads);
     if (scheme == 3) {
-        if (ks == 1) bt_substep_batch<R, 3, 1, kRb><<<grid, block, lds, s>>>(b);
-        else bt_substep_batch<R, 3, 2, kRb><<<grid, block, lds, s>>>(b);
+        if (ks == 1) bt_substep_batch<R, 3, 1><<<grid, block, lds, s>>>(b);
+        else bt_substep_batch<R, 3, 2><<<grid, block, lds, s>>>(b);
     } else {
-        if (ks == 1) bt_substep_batch<R, 2, 1, kRb><<<grid, block, lds, s>>>(b);
-        else bt_substep_batch<R, 2, 2, kRb><<<grid, block, lds, s>>>(b);
+        if (ks == 1) bt_substep_batch<R, 2, 1><<<grid, block, lds, s>>>(b);
+        else bt_substep_batch<R, 2, 2><<<grid, block, lds, s>>>(b);
     }
-}
-template <typename R>
-void launch_bt_substep_batch(const BatchLaunch<BTTileArgs<R>> &b, int scheme, int ks, bool rebuild, size_t lds,
-                             hipStream_t s) {
-    if (rebuild) launch_bt_substep_batch_rb<R, true>(b, scheme, ks, lds, s);
-    else launch_bt_substep_batch_rb<R, false>(b, scheme, ks, lds, s);
 }
 
 template <typename R>
@@ -2665,11 +2577,10 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
-    template void launch_bt_substep<R>(const BTTileArgs<R> &, int, bool, hipStream_t);                     \
+    template void launch_bt_substep<R>(const BTTileArgs<R> &, int, hipStream_t);                           \
     template int bt_loop_capacity<R>(const DevBtTiles &, int);                                             \
     template hipError_t launch_bt_loop<R>(const BTTileArgs<R> &, const BtLoop<R> &, int, hipStream_t);       \
-    template void launch_bt_substep_batch<R>(const BatchLaunch<BTTileArgs<R>> &, int, int, bool, size_t,        \
-                                             hipStream_t);                                                      \
+    template void launch_bt_substep_batch<R>(const BatchLaunch<BTTileArgs<R>> &, int, int, size_t, hipStream_t); \
     template void launch_bt_eval_batch<R>(const BatchLaunch<BTEvalArgs<R>> &, bool, const Geom &, hipStream_t); \
     template void launch_thickness_iso<R>(const THIsoArgs<R> &, const Geom &, hipStream_t);                \
     template void launch_thickness_iso_batch<R>(const BatchLaunch<THIsoArgs<R>> &, int, const Geom &,      \

@@ -77,11 +77,6 @@ int validate_desc(const sse_mesh_desc *d, std::string &err) {
         if (!(d->area_cell[i] > 0) || !std::isfinite(d->area_cell[i])) { err = fmt("area_cell[%ld] not positive", i); return SSE_EINVAL; }
         if (!(d->bottom_depth[i] >= 0) || !std::isfinite(d->bottom_depth[i])) { err = fmt("bottom_depth[%ld] invalid", i); return SSE_EINVAL; }
         if (d->cell_mask[i] && !(d->bottom_depth[i] > 0)) { err = fmt("ocean cell %ld has zero depth", i); return SSE_EINVAL; }
-        if (d->kite_areas_on_cell)
-            for (int j = 0; j < n; ++j) {
-                const double k = d->kite_areas_on_cell[i * me + j];
-                if (!(k >= 0) || !std::isfinite(k)) { err = fmt("kite_areas_on_cell[%ld][%ld] invalid", i, j); return SSE_EINVAL; }
-            }
         for (int j = 0; j < n; ++j) {
             long e = d->edges_on_cell[i * me + j];
             if (e < 0 || e >= E) { err = fmt("edges_on_cell[%ld][%ld] out of range", i, j); return SSE_EINVAL; }
@@ -472,12 +467,9 @@ void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p) {
     p.area.resize(C);
     p.H.resize(C);
     p.mask.resize(C);
-    p.kite.resize(d->kite_areas_on_cell ? (size_t)C * me : 0);
     for (int i = 0; i < C; ++i) {
         const int c = o.cell_old[i];
         for (int j = 0; j < me; ++j) p.eoc[(size_t)i * me + j] = map(o.edge_new, d->edges_on_cell[(size_t)c * me + j]);
-        if (d->kite_areas_on_cell)
-            for (int j = 0; j < me; ++j) p.kite[(size_t)i * me + j] = d->kite_areas_on_cell[(size_t)c * me + j];
         p.neoc[i] = d->n_edges_on_cell[c];
         p.area[i] = d->area_cell[c];
         p.H[i] = d->bottom_depth[c];
@@ -506,7 +498,6 @@ void permute_desc(const sse_mesh_desc *d, const MeshOrder &o, PermutedDesc &p) {
     p.d.bottom_depth = p.H.data();
     p.d.area_triangle = p.tri.data();
     p.d.cell_mask = p.mask.data();
-    p.d.kite_areas_on_cell = d->kite_areas_on_cell ? p.kite.data() : nullptr;
 }
 
 
@@ -692,64 +683,7 @@ size_t bt_lds_bytes(const int (&ne)[4], const int (&nc)[4]) {
     return b;
 }
 
-// The rebuilding form (variant 3): H, U0, Z0 (and H in R), then, from a
-// 16-byte boundary, the later stages U1 U2 Z1 Z2 over the rebuild inputs
-// (l and f of the region edges; kite fractions, edge slots and the slot word
-// of the region cells), which are dead before the first evaluation.
-template <typename R>
-size_t bt_lds_bytes_rb(const int (&ne)[4], const int (&nc)[4]) {
-    size_t head = 8 * (size_t)nc[3] + sizeof(R) * ((size_t)ne[3] + nc[3]);
-    if (sizeof(R) != 8) head += sizeof(R) * (size_t)nc[3];
-    head = (head + 15) / 16 * 16;
-    const size_t stages = sizeof(R) * ((size_t)ne[2] + ne[1] + nc[2] + nc[1]);
-    const size_t inputs = 16 * (size_t)ne[3] + (48 + 12 + 4) * (size_t)nc[3];
-    return head + std::max(stages, inputs);
-}
-
 constexpr size_t kBtLdsMax = 160 * 1024;
-
-// Rebuilds the stencil tables of one patch from its rebuild inputs with the
-// kernel's own functions and compares them with the stored tables bit for
-// bit; also checks that every index the rebuild produces stays within the
-// levels the substep of either scheme stages.
-bool check_rebuild(const HostBtTiles &bt, size_t b, size_t cb, size_t lb, size_t cb3, const int (&ne)[4],
-                   const int (&nc)[4]) {
-    const double *lf = bt.rlf.data() + 2 * lb, *R = bt.rR.data() + 6 * cb3;
-    // the slot words hold two 16-bit edges each, the even slot in the low half
-    const uint16_t *el = reinterpret_cast<const uint16_t *>(bt.rel.data() + 3 * cb3);
-    const uint32_t *cm = bt.rcm.data() + cb3;
-    const int ne2 = ne[2], nc2 = nc[2];
-    auto same = [](double x, double y) { return std::memcmp(&x, &y, sizeof(double)) == 0; };
-    for (int le = 0; le < ne2; ++le) {
-        // level-1 edges are also the first level of SSPRK2 substeps, which stage levels up to 2
-        const int lim_e = le < ne[1] ? ne[2] : ne[3], lim_c = le < ne[1] ? nc[2] : nc[3];
-        const uint32_t ec = bt.ec[b + le];
-        const int c1 = (int)(ec & 0x7fffu), c2 = (int)((ec >> 15) & 0x7fffu);
-        if (c1 >= lim_c || c2 >= lim_c) return false;
-        const int pos = bt.epos[b + le];
-        const double dce = bt.edc[b + le], rd = 1.0 / dce;
-        double w[10];
-        int lj[10];
-        bt_rb_side(lf, R, el, cm, c1, pos & 7, true, lf[2 * le + 1], dce, rd, le, w, lj);
-        bt_rb_side(lf, R, el, cm, c2, (pos >> 3) & 7, false, lf[2 * le + 1], dce, rd, le, w + 5, lj + 5);
-        for (int j = 0; j < 10; ++j) {
-            if (lj[j] < 0 || lj[j] >= lim_e) return false;
-            if (!same(w[j], bt.ew[10 * b + (size_t)j * ne2 + le])) return false;
-            const uint32_t word = bt.enb[5 * b + (size_t)(j >> 1) * ne2 + le];
-            if ((int)((word >> (16 * (j & 1))) & 0xffffu) != lj[j]) return false;
-        }
-        if (!same(rd, bt.eidc[b + le])) return false;
-    }
-    for (int lc = 0; lc < nc2; ++lc) {
-        const double area = bt.carea[cb + lc], ra = 1.0 / area;
-        for (int j = 0; j < 6; ++j) {
-            const int le = (int)(bt.cen[6 * cb + (size_t)j * nc2 + lc] & 0xffffu);
-            if (le >= ne[2]) return false;
-            if (!same(bt_rb_div(lf, cm[lc], j, le, area, ra), bt.ccd[6 * cb + (size_t)j * nc2 + lc])) return false;
-        }
-    }
-    return true;
-}
 
 }  // namespace
 
@@ -822,8 +756,6 @@ bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int
     bt.nP = nP;
     bt.patch.assign((size_t)nP * kBtRec, 0);
     int e0 = 0, es0 = 0, c0 = 0, cs0 = 0, max_ne2 = 0;
-    const int me = d->max_edges;
-    bool rb_ok = t != nullptr && d->kite_areas_on_cell != nullptr;
     for (int p = 0; p < nP; ++p) {
         rb.build(own[p], pid, p);
         if (!rb.fits()) return false;
@@ -833,8 +765,6 @@ bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int
         max_ne2 = std::max(max_ne2, rb.ne[2]);
         bt.lds_d = std::max(bt.lds_d, bt_lds_bytes<double>(rb.ne, rb.nc));
         bt.lds_f = std::max(bt.lds_f, bt_lds_bytes<float>(rb.ne, rb.nc));
-        bt.lds_rd = std::max(bt.lds_rd, bt_lds_bytes_rb<double>(rb.ne, rb.nc));
-        bt.lds_rf = std::max(bt.lds_rf, bt_lds_bytes_rb<float>(rb.ne, rb.nc));
         if (t) {
             const int ne2 = rb.ne[2], nc2 = rb.nc[2];
             bt.eid.insert(bt.eid.end(), rb.edges.begin(), rb.edges.end());
@@ -883,44 +813,6 @@ bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int
                     bt.ccd_f[6 * cb + (size_t)j * nc2 + lc] = t->cell_div_t_f[(size_t)j * C + i];
                 }
             }
-            if (rb_ok) {
-                // rebuild inputs of the region, then the check against the tables above
-                const int ne3 = rb.ne[3], nc3 = rb.nc[3];
-                const size_t lb = bt.rlf.size() / 2, cb3 = bt.rcm.size();
-                for (int le = 0; le < ne3; ++le) {
-                    const int e = rb.edges[le];
-                    bt.rlf.push_back(d->dv_edge[e]);
-                    bt.rlf.push_back(d->f_edge[e]);
-                }
-                for (int lc = 0; lc < nc3; ++lc) {
-                    const int c = rb.cells[lc], n = d->n_edges_on_cell[c];
-                    uint32_t cm = (uint32_t)n, words[3] = {0u, 0u, 0u};
-                    for (int m = 0; m < 6; ++m) {
-                        bt.rR.push_back(m < n ? d->kite_areas_on_cell[(size_t)c * me + m] / d->area_cell[c] : 0.0);
-                        if (m >= n) continue;
-                        const int e = d->edges_on_cell[(size_t)c * me + m];
-                        if (!in_e(e)) { rb_ok = false; continue; }
-                        words[m >> 1] |= (uint32_t)rb.eloc[e] << (16 * (m & 1));
-                        if (d->cells_on_edge[2 * (size_t)e] == c) cm |= 1u << (3 + m);
-                    }
-                    bt.rel.insert(bt.rel.end(), words, words + 3);
-                    bt.rcm.push_back(cm);
-                }
-                for (int le = 0; le < ne2; ++le) {
-                    const int e = rb.edges[le];
-                    int pos[2] = {-1, -1};
-                    for (int k = 0; k < 2; ++k) {
-                        const int c = d->cells_on_edge[2 * (size_t)e + k];
-                        for (int m = 0; m < d->n_edges_on_cell[c]; ++m)
-                            if (d->edges_on_cell[(size_t)c * me + m] == e) pos[k] = m;
-                    }
-                    if (pos[0] < 0 || pos[1] < 0) rb_ok = false;
-                    bt.epos.push_back((uint8_t)(std::max(pos[0], 0) | (std::max(pos[1], 0) << 3)));
-                    bt.edc.push_back(d->dc_edge[e]);
-                }
-                for (int lc = 0; lc < nc2; ++lc) bt.carea.push_back(d->area_cell[rb.cells[lc]]);
-                if (rb_ok) rb_ok = check_rebuild(bt, b, cb, lb, cb3, rb.ne, rb.nc);
-            }
         }
         e0 += rb.ne[3];
         es0 += rb.ne[2];
@@ -928,11 +820,6 @@ bool build_bt_tiles(const sse_mesh_desc *d, const std::vector<int32_t> &pid, int
         cs0 += rb.nc[2];
     }
     bt.ks = (max_ne2 + kBtThreads - 1) / kBtThreads;
-    bt.rb = rb_ok;
-    if (!rb_ok) {
-        bt.rlf.clear(); bt.rR.clear(); bt.edc.clear(); bt.carea.clear();
-        bt.rel.clear(); bt.rcm.clear(); bt.epos.clear();
-    }
     if (!t) {
         // sizes only
         bt.eid.resize(e0);
@@ -968,22 +855,18 @@ struct PartitionEntry {
     bool ok;
     int nP;
     std::vector<int32_t> pid;
-    size_t bytes, bytes_rb;  // without / with the rebuild inputs
+    size_t bytes;
 };
 std::mutex g_part_mu;
 std::deque<PartitionEntry> g_part_cache;  // most recent first
 constexpr size_t kPartCache = 8;
 
-// Device bytes of the tables of a partition (sizes as build_bt_tiles fills
-// them), with or without the rebuild inputs, in the order of the upload.
-size_t bt_bytes_of(const HostBtTiles &bt, bool with_rb) {
+size_t bt_bytes_of(const HostBtTiles &bt) {
     auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
     const size_t TE = bt.eid.size(), TC = bt.cid.size(), SE = bt.ec.size(), SC = bt.cwet.size();
-    size_t n = al(bt.patch.size() * 4) + al(TE * 4) + al(TC * 4) + al(TC * 8) + al(TC * 4) + al(SE * 4) +
-               al(SE * 5 * 4) + al(SE * 10 * 8) + al(SE * 10 * 4) + al(SE * 8) + al(SE * 4) + al(SC * 6 * 4) +
-               al(SC * 6 * 8) + al(SC * 6 * 4) + al(SC);
-    if (with_rb) n += al(TE * 16) + al(TC * 48) + al(TC * 12) + al(TC * 4) + al(SE) + al(SE * 8) + al(SC * 8);
-    return n;
+    return al(bt.patch.size() * 4) + al(TE * 4) + al(TC * 4) + al(TC * 8) + al(TC * 4) + al(SE * 4) +
+           al(SE * 5 * 4) + al(SE * 10 * 8) + al(SE * 10 * 4) + al(SE * 8) + al(SE * 4) + al(SC * 6 * 4) +
+           al(SC * 6 * 8) + al(SC * 6 * 4) + al(SC);
 }
 
 // Partition of d with its table bytes (0 if d cannot be tiled), cached.
@@ -999,13 +882,12 @@ PartitionEntry cached_partition(const sse_mesh_desc *d) {
                 return e;
             }
     }
-    PartitionEntry e{key, false, 0, {}, 0, 0};
+    PartitionEntry e{key, false, 0, {}, 0};
     if (bt_partition(d, e.pid, e.nP)) {
         HostBtTiles bt;
         if (build_bt_tiles(d, e.pid, e.nP, nullptr, bt)) {
             e.ok = true;
-            e.bytes = bt_bytes_of(bt, false);
-            e.bytes_rb = bt_bytes_of(bt, true);
+            e.bytes = bt_bytes_of(bt);
         }
     }
     std::lock_guard<std::mutex> g(g_part_mu);
@@ -1016,10 +898,7 @@ PartitionEntry cached_partition(const sse_mesh_desc *d) {
 
 }  // namespace
 
-size_t bt_tiles_bytes(const sse_mesh_desc *d) {
-    const PartitionEntry e = cached_partition(d);
-    return d->kite_areas_on_cell ? e.bytes_rb : e.bytes;
-}
+size_t bt_tiles_bytes(const sse_mesh_desc *d) { return cached_partition(d).bytes; }
 
 bool bt_cached_partition(const sse_mesh_desc *d, std::vector<int32_t> &pid, int &nP) {
     PartitionEntry e = cached_partition(d);

@@ -59,7 +59,6 @@ class sse_mesh_desc(ctypes.Structure):
         ("dc_edge", POINTER(c_double)), ("dv_edge", POINTER(c_double)), ("f_edge", POINTER(c_double)),
         ("area_cell", POINTER(c_double)), ("bottom_depth", POINTER(c_double)),
         ("area_triangle", POINTER(c_double)), ("cell_mask", POINTER(c_uint8)),
-        ("kite_areas_on_cell", POINTER(c_double)),
     ]
 
 
@@ -177,9 +176,6 @@ def mesh_desc(mesh, bottom_depth, cell_mask):
         "f": _f64(mesh.fEdge), "ac": _f64(mesh.areaCell), "H": _f64(bottom_depth),
         "at": _f64(mesh.areaTriangle), "mask": np.ascontiguousarray(cell_mask, np.uint8),
     }
-    kite = getattr(mesh, "kiteAreasOnCell", None)
-    if kite is not None:
-        keep["kite"] = _f64(np.asarray(kite)[:, :keep["eoc"].shape[1]])
     d = sse_mesh_desc()
     d.n_cells, d.n_edges, d.n_vertices = mesh.nCells, mesh.nEdges, mesh.nVertices
     d.max_edges, d.max_edges2 = keep["eoc"].shape[1], keep["eoe"].shape[1]
@@ -189,8 +185,6 @@ def mesh_desc(mesh, bottom_depth, cell_mask):
     d.weights_on_edge, d.dc_edge, d.dv_edge, d.f_edge = _dptr(keep["w"]), _dptr(keep["dc"]), _dptr(keep["dv"]), _dptr(keep["f"])
     d.area_cell, d.bottom_depth, d.area_triangle = _dptr(keep["ac"]), _dptr(keep["H"]), _dptr(keep["at"])
     d.cell_mask = keep["mask"].ctypes.data_as(POINTER(c_uint8))
-    if "kite" in keep:
-        d.kite_areas_on_cell = _dptr(keep["kite"])
     return d, keep
 
 
@@ -336,8 +330,7 @@ class DeviceState:
 
     @property
     def bt_variant(self) -> int:
-        """Barotropic loop kernels: 0 one launch per evaluation, 1 one per substep, 2 one
-        persistent launch per loop, 3 one per substep with the stencil tables rebuilt on chip."""
+        """Barotropic loop kernels: 0 one launch per evaluation, 1 one per substep."""
         v = c_int(0)
         _check(load().sse_state_get_bt_variant(self.handle, ctypes.byref(v)))
         return int(v.value)

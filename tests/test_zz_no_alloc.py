@@ -55,7 +55,7 @@ CALLS = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_noalloc_equals_workspace_entry_two_calls(dev, variant, precision):
     kept = []
