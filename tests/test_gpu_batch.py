@@ -165,3 +165,60 @@ def test_batch_members_with_either_barotropic_variant(dev, stream, precision):
     assert b.step(3) == 0
     for i, st in enumerate(b.members):
         assert_same(st.read(), alone[i], f"member {i}")
+
+
+def _random_members(seed):
+    """Five members that share the scheme, the precision mode and the vertical
+    coordinate (what a batch requires) and differ at random in everything
+    else: planar hexes and land-masked spheres, layer counts on both sides of
+    64, M, reconciliation, vertical mixing, biharmonic viscosity, tracer."""
+    rng = np.random.default_rng(seed)
+    shared = dict(scheme=int(rng.choice([2, 3])), precision=int(rng.choice([0, 1, 2])),
+                  vcoord=int(rng.choice([0, 1])))
+    out = []
+    for i in range(5):
+        L = int(rng.choice([2, 7, 31, 64, 65, 100]))
+        if rng.random() < 0.3:
+            base = cases.sphere_case(2, L, 900 + 10 * seed + i, substeps=5, dt_btr=200.0)
+            nu4 = 1e13
+        else:
+            base = cases.c1(n=int(rng.choice([6, 8, 10])), L=L, member=i, steps=2)
+            nu4 = 1e9
+        M = int(rng.choice([1, 3, 7]))
+        kw = dict(shared, substeps=M, dt=base.params.dt / base.params.substeps * M,
+                  reconcile=int(rng.choice([0, 1, 2])))
+        if rng.random() < 0.4:
+            kw.update(vmix=1, nu_v=1e-3, c_drag=2e-3)
+        if rng.random() < 0.4:
+            kw.update(hdiff=1, nu_h=nu4)
+        if rng.random() < 0.4:
+            kw.update(tracer=1, kappa_h=20.0, kappa_v=1e-4)
+        out.append(cases.with_params(base, **kw))
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_random_batches_equal_alone(dev, stream, seed):
+    """Batches of members with randomly differing options: every member,
+    tracer included, computes in the batch exactly what it computes alone."""
+    cs = _random_members(seed)
+    alone = []
+    for c in cs:
+        _, st = dev.state_from_case(c, stream=stream)
+        assert st.step(2) == 0, dev.last_error()
+        r = st.read()
+        if c.params.tracer:
+            r["T"] = st.read_tracer()
+        alone.append(r)
+    keep, b = [], dev.Batch(stream=stream)
+    for c in cs:
+        dm, st = dev.state_from_case(c, stream=stream)
+        keep.append((dm, st))
+        b.add(st)
+    assert b.step(2) == 0, dev.last_error()
+    for i, (c, (_, st)) in enumerate(zip(cs, keep)):
+        got = st.read()
+        assert_same(got, alone[i], f"seed {seed} member {i}")
+        if c.params.tracer:
+            assert np.array_equal(st.read_tracer(), alone[i]["T"]), (seed, i)
+    b.close()
