@@ -213,7 +213,7 @@ def ssprk2_se_step(u, h, st: Setup, diag: dict | None = None, T=None):
     if diag is not None:
         diag.update(ubar=ubar, ut=ut, zeta=zeta, ut1=ut1, G0=G0, ub1=ub1, zeta_bt1=zb1, Fz1=Fz1,
                     Fh1=Fh1, uA1=uA1, h1=h1, zeta1=z1, ut2=ut2, G1=G1, ub_new=ub_new, zeta_bt2=zb2,
-                    Fz2=Fz2, P=P, uA2=uA2, h2=h2, zeta_new=ssh(h_new, st))
+                    Fz2=Fz2, P=P, uA2=uA2, h2=h2, zeta_new=ssh(h_new, st), T1=T1)
     if T is not None:
         return u_new, h_new, T_new
     return u_new, h_new
@@ -274,7 +274,7 @@ def ssprk3_se_step(u, h, st: Setup, diag: dict | None = None, T=None):
                     Fh1=Fh1, uA1=uA1, h1=h1, zeta1=z1, ut2=ut2, G1=G1, ub2=ub2, zeta_bt2=zb2,
                     Fz2=Fz2, Fh2=Fh2, uA2=uA2, h2=h2, h_half=h_half, zeta_half=z_half, ut3=ut3,
                     G_half=G_half, ub_new=ub_new, zeta_bt3=zb3, Fz3=Fz3, P=P, uA3=uA3, h3=h3,
-                    zeta_new=ssh(h_new, st))
+                    zeta_new=ssh(h_new, st), T1=T1, T_half=T_half)
     if T is not None:
         return u_new, h_new, T_new
     return u_new, h_new

@@ -51,3 +51,25 @@ def test_substep_is_shu_osher(scheme, kind):
     np.testing.assert_allclose(z1, zf, rtol=0, atol=1e-13 * np.abs(zeta).max())
     a = case.mesh.areaCell
     assert abs((a * z1).sum() - (a * zeta).sum()) < 1e-13 * (a * np.abs(zeta)).sum()
+
+
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_no_flow_through_coasts(scheme):
+    """Land edges carry no barotropic velocity and land cells no SSH at any
+    substep: a state with SSH and flow right up to the coast, and a forcing
+    there, leaves ubar and F^zeta exactly zero on every edge that touches land
+    and zeta zero on land, while the wet part moves."""
+    from oracle.layered import Setup
+    case = cases.sphere_case(3, 4, 61, substeps=6, dt_btr=200.0)
+    st = Setup.from_case(case)
+    assert (~st.edge_mask.astype(bool)).sum() > 0
+    rng = np.random.default_rng(9)
+    wet_e, wet_c = st.edge_mask.astype(bool), st.cell_mask.astype(bool)
+    ubar = np.where(wet_e, rng.normal(0, 0.1, case.mesh.nEdges), 0.0)
+    zeta = np.where(wet_c, rng.normal(0, 0.3, case.mesh.nCells), 0.0)
+    G = np.where(wet_e, rng.normal(0, 1e-5, case.mesh.nEdges), 0.0)
+    sub = S.barotropic_ssprk2_substep if scheme == 2 else S.barotropic_ssprk3_substep
+    u1, z1, F = sub(ubar, zeta, G, case.params.dt, 6, st)
+    assert np.all(u1[~wet_e] == 0.0) and np.all(F[~wet_e] == 0.0)
+    assert np.all(z1[~wet_c] == 0.0)
+    assert np.abs(u1[wet_e] - ubar[wet_e]).max() > 0

@@ -6,7 +6,8 @@ Each is checked against something the readings do not assume:
 * pressure gradient: exactly -g (rho / rho0) grad zeta for a uniform density
   over bathymetry (the hydrostatic pressure plus the layer-midpoint height is
   g rho zeta in every layer); exactly the hydrostatic integral of a linear
-  horizontal density gradient for flat layers;
+  horizontal density gradient for flat layers, and over a sloping bottom,
+  where the density at the edge (the mean of the two cells) enters;
 * z-star: every layer's thickness tendency is the same fraction of its
   reference thickness, the column tendencies add up to minus the column flux
   divergence, and w vanishes at the bottom and, to roundoff, at the surface;
@@ -82,6 +83,38 @@ def test_pgf_of_a_horizontal_density_gradient_in_flat_layers():
     assert np.abs(pgf[ok] - ref[ok]).max() <= 1e-10 * np.abs(ref[ok]).max()
 
 
+def test_pgf_of_density_gradients_over_a_sloping_bottom():
+    """Layers of uniform thickness over a linear bottom slope, each with its own
+    linear horizontal density gradient: the layer mid-depths all follow the
+    bottom, z_k = -H + sum_{l>k} h_l + h_k / 2, and the hydrostatic pressure at
+    them is p_k = g (sum_{l<k} rho_l h_l + rho_k h_k / 2), so the force is
+    -(g / rho0) [sum_{l<k} h_l drho_l/dn + h_k/2 drho_k/dn - rho_k dH/dn] with
+    rho_k taken at the edge.  For linear fields the centred differences are
+    exact and rho at the edge is the mean of the two cells, so this holds to
+    roundoff at every edge that does not wrap around the periodic domain."""
+    hk = np.array([40.0, 70.0, 120.0, 200.0])
+    case = uniform_case(L=4, h_layers=hk, n=8)
+    m = case.mesh
+    a = np.array([[2e-6, -1e-6], [1e-6, 3e-6], [-2e-6, 1e-6], [4e-6, 2e-6]])   # d rho_k / d(x, y)
+    slope = np.array([1.5e-3, -0.8e-3])                                          # dH / d(x, y)
+    case.rho[:] = case.params.rho0 + m.xCell[:, :2] @ a.T
+    case.H[:] = hk.sum() + 60.0 + m.xCell[:, :2] @ slope
+    st = Setup.from_case(case)
+    pgf = pressure_gradient_force(case.h, st)
+    an = m.normalEdge[:, :2] @ a.T                      # d rho_k / dn at every edge
+    Hn = m.normalEdge[:, :2] @ slope                    # dH / dn
+    c1, c2 = m.cellsOnEdge[:, 0], m.cellsOnEdge[:, 1]
+    xe = 0.5 * (m.xCell[c1, :2] + m.xCell[c2, :2])      # edge midpoints (interior edges)
+    rho_e = case.params.rho0 + xe @ a.T
+    g, rho0 = case.params.gravity, case.params.rho0
+    ref = np.zeros_like(pgf)
+    for k in range(4):
+        ref[:, k] = -(g / rho0) * ((an[:, :k] * hk[:k]).sum(1) + an[:, k] * 0.5 * hk[k] - rho_e[:, k] * Hn)
+    ok = _interior_edges(m)
+    assert ok.sum() > m.nEdges // 2
+    assert np.abs(pgf[ok] - ref[ok]).max() <= 1e-10 * np.abs(ref[ok]).max()
+
+
 def test_zstar_layers_stretch_in_proportion():
     case = cases.sphere_case(3, 7, 4451, substeps=4, dt_btr=200.0)
     st, h, u = _perturbed(case, 12)
@@ -95,6 +128,10 @@ def test_zstar_layers_stretch_in_proportion():
     w = vertical_velocity(h, u, st)
     assert np.all(w[:, -1] == 0.0)                       # no flux through the bottom
     assert np.all(np.abs(w[wet, 0]) <= 1e-12 * col)      # none through the surface, to roundoff
+    # and w is the one the layer thickness equation dh_k/dt = -div_k - (w_k - w_{k+1})
+    # gives for this T^h: the momentum and tracer equations move with the same w
+    dw = w[:, :-1] - w[:, 1:]
+    assert np.abs(dw[wet] + div[wet] + th[wet]).max() <= 1e-12 * col.max()
 
 
 def test_vertical_boundary_fluxes_close_the_column_budget():

@@ -15,12 +15,16 @@
   div(h kappa grad T) = h kappa lambda T with the closed-form eigenvalue of the
   hexagonal Laplacian, so every step multiplies T by the SSPRK stability
   polynomial R_p(kappa lambda dt).
+* Vertical advection with centred interface values: for a temperature linear
+  in the layer index, the tendency differs from T times the thickness tendency
+  by exactly (b / 2)(w_k + w_{k+1}).
+* Each baroclinic stage takes its density from that stage's temperature.
 """
 import numpy as np
 import pytest
 
 from oracle import ssprk_se as S
-from oracle.layered import Setup, eos
+from oracle.layered import Setup, T_h, eos, tracer_tendency, vertical_velocity
 from synthetic import cases
 from tests.helpers import smooth_case, uniform_case
 
@@ -163,3 +167,46 @@ def test_advection_of_a_plane_wave_by_uniform_flow(scheme):
     expect = 10.0 + np.real(R ** 3 * np.exp(1j * phase))[:, None]
     assert np.abs(u - case.u).max() <= 1e-13
     assert np.abs(T - expect).max() <= 1e-11 * 10.0
+
+
+def test_vertical_advection_of_a_linear_profile():
+    """z-star, a divergent flow (so w is not zero), and a temperature that is
+    horizontally uniform in each layer and linear in the layer index,
+    T_k = a + b k: the horizontal flux of layer k carries exactly T_k times the
+    thickness flux, and the centred interface values (T_k + T_{k+1}) / 2 leave
+    tendency(h T)_k - T_k T^h_k = (b / 2)(w_k + w_{k+1}), w at the interfaces
+    of layer k (zero through the surface and the bottom)."""
+    case = _tracer(cases.sphere_case(3, 7, 41, substeps=4, dt_btr=200.0), kappa_h=0.0, kappa_v=0.0)
+    st = Setup.from_case(case)
+    rng = np.random.default_rng(3)
+    C, L = case.h.shape
+    h = case.h * (1.0 + 0.1 * rng.uniform(-1.0, 1.0, case.h.shape))
+    v = np.where(st.edge_mask[:, None], rng.normal(0.0, 0.2, case.u.shape), 0.0)
+    a, b = 11.0, -0.75
+    T = np.tile(a + b * np.arange(L, dtype=float), (C, 1))
+    tend = tracer_tendency(h, T, v, st)
+    w = vertical_velocity(h, v, st)
+    expect = T * T_h(h, v, st) + 0.5 * b * (w[:, :-1] + w[:, 1:])
+    wet = st.cell_mask.astype(bool)
+    scale = np.abs(tend[wet]).max()
+    assert np.abs(w[wet]).max() > 0
+    assert np.abs(tend[wet] - expect[wet]).max() <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_later_stages_see_the_density_of_their_own_temperature(scheme):
+    """Every baroclinic stage takes its density from the temperature of that
+    stage (the stage's thickness and tracer content), not from the step's
+    initial temperature: the second stage's G-bar equals Algorithm 1 run on
+    the stage-1 state with rho = eos(T of stage 1)."""
+    case = _tracer(cases.c1(n=8, L=6, steps=1), scheme=scheme, kappa_h=20.0, kappa_v=1e-4, eos_alpha=2e-3)
+    st = Setup.from_case(case)
+    d = {}
+    S.step(case.u.copy(), case.h.copy(), st, diag=d, T=case.temp.copy())
+    T1 = d["T1"]
+    assert np.abs(T1 - case.temp).max() > 1e-6            # the temperature moved in stage 1
+    st1 = Setup.from_case(case)
+    st1.rho = eos(T1, st)
+    u1 = S.mask_edges(d["ub1"][:, None] + d["ut1"], st)
+    _, G1 = S.baroclinic_feuler(u1, d["ut1"], d["zeta1"], d["h1"], case.params.dt, st1)
+    assert np.array_equal(G1, d["G1"])
