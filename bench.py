@@ -258,14 +258,16 @@ def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
     return out
 
 
-def serve_leg(torch, ssprkse, cases, n_requests=64, load=0.8, n_capacity=12, reduced=False):
+def serve_leg(torch, ssprkse, cases, n_requests=64, loads=(0.8,), n_capacity=12, reduced=False):
     """C4: Poisson arrivals of sphere requests, continuous batching under an HBM
     budget.  The served recipe: icosahedral levels 5-8, 16-100 layers,
     50-500 steps, FP64 or mixed at random.  The service rate is measured
     first by serving the first `n_capacity` requests with all of them queued
     at t = 0 (cell-layer updates per second); the `n_requests` requests then
     arrive as a Poisson process at `load` times that rate divided by their
-    mean work.  reduced=True serves a smaller mix (levels 4-6, 10-40 steps)."""
+    mean work, once for every load in `loads` (the first one fills the
+    top-level fields of the result, all of them `by_load`).  reduced=True
+    serves a smaller mix (levels 4-6, 10-40 steps)."""
     import numpy as np
     from paper_2105_13484_amd.serve import Engine, Request, poisson_arrivals
 
@@ -298,26 +300,32 @@ def serve_leg(torch, ssprkse, cases, n_requests=64, load=0.8, n_capacity=12, red
     cap = rate / (sum(work) / n_requests)
     log(f"[bench] serving capacity ({n_capacity} requests queued at t=0): {rate:.3g} cell-layer updates/s, "
         f"{cap:.3f} requests/s of the mix")
-    arr = poisson_arrivals(n_requests, load * cap, cases.SEED_BASE + 499)
-    shown = set()
+    by_load = []
+    for load in loads:
+        arr = poisson_arrivals(n_requests, load * cap, cases.SEED_BASE + 499)
+        shown = set()
 
-    def progress(k, n):
-        if k % 8 == 0 and k not in shown:
-            shown.add(k)
-            log(f"[bench] serving: {k}/{n} done")
+        def progress(k, n):
+            if k % 8 == 0 and k not in shown:
+                shown.add(k)
+                log(f"[bench] serving at {load:.1f}x: {k}/{n} done")
 
-    opened = eng.run(requests(range(n_requests), arr), on_progress=progress)
+        opened = eng.run(requests(range(n_requests), arr), on_progress=progress)
+        log(f"[bench] serving at {load:.1f}x capacity: p50 {opened['p50_s']:.3f} s, p99 {opened['p99_s']:.3f} s")
+        by_load.append({"load": load, "p50_s": opened["p50_s"], "p99_s": opened["p99_s"], "max_s": opened["max_s"],
+                        "cell_layer_updates_per_s": opened["cell_layer_updates_per_s"], "wall_s": opened["wall_s"],
+                        "failed": opened["failed"]})
     eng.close()
-    log(f"[bench] serving at {load:.1f}x capacity: p50 {opened['p50_s']:.3f} s, p99 {opened['p99_s']:.3f} s")
-    return {"workload": ("C4 served recipe at reduced size: icosahedral levels 4-6, L 16-100, 10-40 steps" if reduced else
-                         "C4 served recipe: icosahedral levels 5-8, L 16-100, 50-500 steps") +
-                        ", FP64 or mixed at random, M = 30, HBM budget 200 GB",
-            "requests": n_requests, "levels": dict(sorted(levels.items())),
-            "capacity_cell_layer_updates_per_s": rate, "capacity_requests_per_s": cap,
-            "capacity_sample_requests": n_capacity,
-            "load": load, "p50_s": opened["p50_s"], "p99_s": opened["p99_s"], "max_s": opened["max_s"],
-            "cell_layer_updates_per_s": opened["cell_layer_updates_per_s"], "wall_s": opened["wall_s"],
-            "failed": opened["failed"]}
+    out = {"workload": ("C4 served recipe at reduced size: icosahedral levels 4-6, L 16-100, 10-40 steps" if reduced else
+                        "C4 served recipe: icosahedral levels 5-8, L 16-100, 50-500 steps") +
+                       ", FP64 or mixed at random, M = 30, HBM budget 200 GB",
+           "requests": n_requests, "levels": dict(sorted(levels.items())),
+           "capacity_cell_layer_updates_per_s": rate, "capacity_requests_per_s": cap,
+           "capacity_sample_requests": n_capacity}
+    out.update(by_load[0])
+    if len(by_load) > 1:
+        out["by_load"] = by_load
+    return out
 
 
 def copy_probe():
@@ -348,6 +356,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-reduced", action="store_true", help="serving leg with a smaller request mix")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests in the serving leg")
+    ap.add_argument("--serve-loads", default="0.8",
+                    help="comma-separated arrival rates of the serving leg, as fractions of its measured capacity")
     ap.add_argument("--copy-probe", action="store_true", help="run only a plain device copy and exit")
     args = ap.parse_args()
 
@@ -481,6 +491,7 @@ def main():
 
     ensemble = None if args.no_ensemble else ensemble_leg(torch, ssprkse, cases)
     serving = None if args.no_serve else serve_leg(torch, ssprkse, cases, n_requests=args.serve_requests,
+                                                    loads=tuple(float(x) for x in args.serve_loads.split(",")),
                                                     reduced=args.serve_reduced)
 
     value = cell_layers / (ms_step * 1e-3)
