@@ -145,6 +145,28 @@ def cpu_baseline(n=128, steps=4):
             "cores_available": len(os.sched_getaffinity(0))}
 
 
+def gather_only(torch, st, E, L, reps=10):
+    """The direct edge pass's 30 column gathers per edge without its
+    arithmetic (sse_debug_edge_gathers), timed with HIP events on the state's
+    stream: the time its memory accesses alone take at its access pattern."""
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.debug_edge_gathers()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        st.debug_edge_gathers()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    rs = 8 if int(st.params.precision) == 0 else 4
+    # u, u^n, K - nu div u, w, the 10 stencil edges and 10 vertices in the
+    # state's real type; h and rho at both cells in FP64
+    nbytes = float(E) * L * (26 * rs + 4 * 8)
+    return {"gather_only_launch_ms": ms, "columns_gathered_per_edge": 30,
+            "gathered_bytes_per_launch": nbytes, "gathered_gbs": nbytes / (ms * 1e-3) / 1e9}
+
+
 def timed_steps(torch, st, steps):
     """ms per step of `steps` steps, HIP events on the state's stream."""
     stream = torch.cuda.current_stream()
@@ -230,6 +252,24 @@ def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
     ms_loop = autotune._time_steps(torch, stream, loop, steps)
     reinit()
     log(f"[bench] ensemble per-member loop: {ms_loop:.2f} ms/step")
+
+    # the plain method: the same members in FP64, one after the other
+    keep64 = [ssprkse.state_from_case(cases.with_params(c, precision=0), device="cuda:0", stream=stream) for c in cs]
+    sts64 = [st for _, st in keep64]
+
+    def loop64(n):
+        for _ in range(n):
+            for st in sts64:
+                st.step_async(1)
+
+    for st in sts64:
+        assert st.step(1) == 0
+    ms_loop64 = autotune._time_steps(torch, stream, loop64, steps)
+    for dm, st in keep64:
+        st.close()
+        dm.close()
+    del keep64, sts64
+    log(f"[bench] ensemble per-member loop in FP64: {ms_loop64:.2f} ms/step")
     b = ssprkse.Batch(stream=stream)
     for st in sts:
         b.add(st)
@@ -251,8 +291,10 @@ def ensemble_leg(torch, ssprkse, cases, members=64, steps=10):
            "batch_default_geometry_ms_per_step": ms_plain, "batch_best_trial_ms_per_step": ms_tuned,
            "batch_tuned_graph_ms_per_step": ms_batch,
            "per_member_loop_cell_layer_updates_per_s": cl / (ms_loop * 1e-3),
+           "per_member_loop_fp64_ms_per_step": ms_loop64,
            "batch_cell_layer_updates_per_s": cl / (ms_batch * 1e-3),
-           "speedup_vs_per_member_loop": ms_loop / ms_batch, "tuned": tuned["best"],
+           "speedup_vs_per_member_loop": ms_loop / ms_batch,
+           "speedup_vs_fp64_per_member_loop": ms_loop64 / ms_batch, "tuned": tuned["best"],
            "tuning_trials": len(tuned["trials"]), "launches_per_step": b.launches_per_step()}
     b.close()
     return out
@@ -300,6 +342,26 @@ def serve_leg(torch, ssprkse, cases, n_requests=64, loads=(0.8,), n_capacity=12,
     cap = rate / (sum(work) / n_requests)
     log(f"[bench] serving capacity ({n_capacity} requests queued at t=0): {rate:.3g} cell-layer updates/s, "
         f"{cap:.3f} requests/s of the mix")
+    # the plain method on the same requests: one at a time in arrival order,
+    # each alone on the device (upload, its steps, result to the host), in the
+    # precision it asks for, and once more with every request in FP64
+    plain = {}
+    for tag, prec in (("as_requested", None), ("fp64", 0)):
+        t0 = time.perf_counter()
+        done = 0
+        for i in range(n_capacity):
+            c, steps = made[i]
+            if prec is not None:
+                c = cases.with_params(c, precision=prec)
+            dm, st = ssprkse.state_from_case(c, device="cuda:0")
+            assert st.step(steps) == 0, f"request {i} failed alone"
+            st.read()
+            st.close()
+            dm.close()
+            done += work[i]
+        plain[tag] = done / (time.perf_counter() - t0)
+    log(f"[bench] serving the same {n_capacity} requests one at a time: {plain['as_requested']:.3g} cell-layer "
+        f"updates/s as requested, {plain['fp64']:.3g} all in FP64")
     by_load = []
     for load in loads:
         arr = poisson_arrivals(n_requests, load * cap, cases.SEED_BASE + 499)
@@ -321,7 +383,11 @@ def serve_leg(torch, ssprkse, cases, n_requests=64, loads=(0.8,), n_capacity=12,
                        ", FP64 or mixed at random, M = 30, HBM budget 200 GB",
            "requests": n_requests, "levels": dict(sorted(levels.items())),
            "capacity_cell_layer_updates_per_s": rate, "capacity_requests_per_s": cap,
-           "capacity_sample_requests": n_capacity}
+           "capacity_sample_requests": n_capacity,
+           "one_at_a_time_cell_layer_updates_per_s": plain["as_requested"],
+           "one_at_a_time_fp64_cell_layer_updates_per_s": plain["fp64"],
+           "capacity_speedup_vs_one_at_a_time": rate / plain["as_requested"],
+           "capacity_speedup_vs_one_at_a_time_fp64": rate / plain["fp64"]}
     out.update(by_load[0])
     if len(by_load) > 1:
         out["by_load"] = by_load
@@ -417,6 +483,13 @@ def main():
     traffic = measured_traffic(dom)
     log(f"[bench] dominant class {dom}: {n_dom} launches, {avg_ms * 1e3:.1f} us avg, "
         f"{achieved:.0f} GB/s algorithmic, measured traffic per launch {traffic}")
+    gather = {}
+    if dom == "fe_edge":
+        gather = gather_only(torch, st, E, L)
+        gather["launch_over_gather_only"] = avg_ms / gather["gather_only_launch_ms"]
+        log(f"[bench] the edge pass's column gathers alone: {gather['gather_only_launch_ms'] * 1e3:.1f} us per "
+            f"launch ({gather['gathered_gbs']:.0f} GB/s into registers); the pass takes "
+            f"{gather['launch_over_gather_only']:.2f}x that")
     final = st.read()
     assert np.isfinite(final["u"]).all() and np.isfinite(final["h"]).all()
     del st
@@ -526,7 +599,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kb, "intermediate_bytes_per_launch": ib, "launch_ms": avg_ms,
-                     "achievable_copy_gbs": copy_gbs},
+                     "achievable_copy_gbs": copy_gbs, **gather},
         "c2": c2,
         "m_sweep": m_sweep,
         "ensemble": ensemble,

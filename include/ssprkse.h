@@ -351,6 +351,19 @@ int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double
                                  const double *ubar, const double *zeta, const double *G,
                                  double *ubar1, double *zeta1, double *Fzeta);
 
+/* Measurement aid for callers that compare the baroclinic edge pass with
+ * the cost of its memory accesses alone: enqueues on the state's stream (and
+ * returns without waiting) one launch that gathers, for every edge, the same
+ * layer columns the direct edge pass reads (u and u^n at the edge, h, rho,
+ * K - nu_h div u and w at its two cells, its 10 stencil edges and the
+ * vorticity of the 10 vertices of their chains; Algorithm 1's operands) from
+ * the state's current arrays and writes their sum into a stage buffer that
+ * every step overwrites before reading.  The state steps on unchanged.
+ * SSE_EINVAL without canonical stencils, above 64 layers or with arrays of
+ * 4 GiB or more; SSE_ESTATE while the state is being recorded into a batch;
+ * SSE_EDEVICE if the launch fails. */
+int sse_debug_edge_gathers(sse_state *s);
+
 /* Polls a grid barrier of the persistent barotropic loop (variant 2) makes
  * before it gives up, reports the timeout and lets every workgroup finish;
  * 0 restores the default (about 0.3 s of waiting).  For tests of that error

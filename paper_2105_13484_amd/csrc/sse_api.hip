@@ -1451,6 +1451,37 @@ extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const 
     return SSE_OK;
 }
 
+extern "C" int sse_debug_edge_gathers(sse_state *s) {
+    if (!s) { set_error("NULL state"); return SSE_EINVAL; }
+    if (s->rec) { set_error("state is being recorded into a batch"); return SSE_ESTATE; }
+    const DevMesh &m = s->mesh->d;
+    const int L = s->p.n_layers;
+    if (!m.chain || L > kWave || (fe_edge_variant(m, L, 0, false) & 8)) {
+        set_error("the gather-only edge pass needs canonical stencils, at most 64 layers and arrays below 4 GiB");
+        return SSE_EINVAL;
+    }
+    Work &w = s->w;
+    auto go = [&](auto zero) {
+        using R = decltype(zero);
+        FEEdgeArgs<R> a{};
+        a.m = m;
+        a.L = L;
+        a.X = rp<R>(w.U);
+        a.Un = rp<R>(w.U);
+        a.h = w.Hs;
+        a.rho = w.rho;
+        a.B = rp<R>(w.B);
+        a.Wtop = rp<R>(w.Wt);
+        a.Z = rp<R>(w.Z);
+        a.out = rp<R>(w.T2);
+        launch_edge_gathers<R>(a, s->geom, s->stream);
+    };
+    if (s->rs == 4) go(0.0f);
+    else go(0.0);
+    SSE_HIP(hipGetLastError());
+    return SSE_OK;
+}
+
 extern "C" int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double dt, const double *ubar,
                                             const double *zeta, const double *G, double *ubar1, double *zeta1,
                                             double *Fzeta) {

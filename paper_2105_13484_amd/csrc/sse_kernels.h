@@ -261,6 +261,7 @@ template <typename R> void launch_fe_edge(const FEEdgeArgs<R> &a, const Geom &g,
 // LDS bytes the tiled edge pass needs for tile set t, L layers and type R.
 template <typename R> size_t fe_edge_tiled_lds(const DevTiles &t, int L);
 template <typename R> void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s);
+template <typename R> void launch_edge_gathers(const FEEdgeArgs<R> &a, const Geom &g, hipStream_t s);
 void set_tiled_lds_limit(size_t bytes);
 template <typename R> void launch_bt_eval(const BTEvalArgs<R> &a, const Geom &g, hipStream_t s);
 // scheme 2 or 3; requires a.t.nP > 0 and the LDS limit set (set_tiled_lds_limit).

@@ -956,6 +956,52 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
 }
 
 // ---------------------------------------------------------------------------
+// Measurement aid: the edge pass's column loads without its arithmetic.
+// Each wavefront gathers the columns the direct edge pass reads for its edge
+// (canonical stencils, one register chunk): u and u^n at the edge, h, rho,
+// K - nu div u and w at both cells, the 10 stencil edges and the 10 chain
+// vertices, and writes their sum; a launch takes the pass's gather time at
+// its access pattern.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(1024, 8) edge_gather_kernel(FEEdgeArgs<R> a) {
+    const DevMesh &m = a.m;
+    const int e = column_id(m.E);
+    if (e >= m.E) return;
+    const int L = a.L;
+    int kk[1];
+    bool ok[1];
+    lane_layers<1>(L, kk, ok);
+    const int k = kk[0];
+    if (!m.emask[e]) {
+        if (ok[0]) col_st(a.out + (size_t)e * L, k, R(0));
+        return;
+    }
+    const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
+    const size_t b1 = (size_t)rec[30] * L, b2 = (size_t)rec[31] * L;
+    R v[30];
+    v[0] = col_ldv<false>(a.X, (size_t)e * L, k);
+    v[1] = col_ldv<false>(a.Un, (size_t)e * L, k);
+    v[2] = (R)col_ldv<false>(a.h, b1, k);
+    v[3] = (R)col_ldv<false>(a.h, b2, k);
+    v[4] = (R)col_ldv<false>(a.rho, b1, k);
+    v[5] = (R)col_ldv<false>(a.rho, b2, k);
+    v[6] = col_ldv<false>(a.B, b1, k);
+    v[7] = col_ldv<false>(a.B, b2, k);
+    v[8] = col_ldv<false>(a.Wtop, b1, k);
+    v[9] = col_ldv<false>(a.Wtop, b2, k);
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        v[10 + j] = col_ldv<false>(a.X, (size_t)rec[j] * L, k);
+        v[20 + j] = col_ldv<false>(a.Z, (size_t)rec[10 + j] * L, k);
+    }
+    R sum = R(0);
+#pragma unroll
+    for (int j = 0; j < 30; ++j) sum += v[j];
+    if (ok[0]) col_st(a.out + (size_t)e * L, k, sum);
+}
+
+// ---------------------------------------------------------------------------
 // Baroclinic forward Euler: edge pass staged through LDS.
 //
 // One workgroup of T wavefronts owns a tile of T consecutive edges.  It first
@@ -2359,6 +2405,12 @@ void launch_fe_edge_batch(const BatchLaunch<FEEdgeArgs<R>> &b, int nk, bool add,
 }
 
 template <typename R>
+void launch_edge_gathers(const FEEdgeArgs<R> &a, const Geom &g0, hipStream_t s) {
+    const Geom g = edge_geom(g0, 1);
+    edge_gather_kernel<R><<<xcd_grid(col_blocks(a.m.E, g)), col_block(g), 0, s>>>(a);
+}
+
+template <typename R>
 void launch_fe_edge_tiled(const FEEdgeArgs<R> &a, const DevTiles &t, hipStream_t s) {
     const size_t lds = fe_edge_tiled_lds<R>(t, a.L);
     const dim3 grid(kXcd * ((t.nT + kXcd - 1) / kXcd)), block((t.T < kTileWaves ? t.T : kTileWaves) * kWave);
@@ -2576,6 +2628,7 @@ void launch_convert_batch(const BatchLaunch<ConvArgs<Tin, Tout>> &b, const Geom 
                                           hipStream_t);                                                    \
     template size_t fe_edge_tiled_lds<R>(const DevTiles &, int);                                           \
     template void launch_fe_edge_tiled<R>(const FEEdgeArgs<R> &, const DevTiles &, hipStream_t);           \
+    template void launch_edge_gathers<R>(const FEEdgeArgs<R> &, const Geom &, hipStream_t);                \
     template void launch_bt_eval<R>(const BTEvalArgs<R> &, const Geom &, hipStream_t);                     \
     template void launch_bt_substep<R>(const BTTileArgs<R> &, int, hipStream_t);                           \
     template int bt_loop_capacity<R>(const DevBtTiles &, int);                                             \

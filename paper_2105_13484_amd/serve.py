@@ -10,11 +10,13 @@ and advances all of them together:
 * one batch per precision (FP64 and mixed), each on its own HIP stream, so
   the two kinds of requests run concurrently on the device; within a batch
   one launch per step phase covers every member;
-* the batches advance in chunks of at most `chunk_steps` steps, never past
-  the nearest completion, so that finished requests leave and waiting ones
-  join between chunks; a request that arrives while a chunk runs is set up
-  (its mesh image built on the host and uploaded) during that chunk, and its
-  batch's program is rebuilt before the next;
+* each batch advances in chunks of at most `chunk_steps` steps, never past
+  the nearest completion of its members, so that finished requests leave and
+  waiting ones join between chunks; a batch gets its next chunk as soon as
+  its last one has finished, without waiting for the other batch; a request
+  that arrives while chunks run is set up (its mesh image built on the host
+  and uploaded) meanwhile, and its batch's program is rebuilt before that
+  batch's next chunk;
 * a finished request's state is read back and its device memory released.
 
 A request's result does not depend on what else runs: a batch member
@@ -63,6 +65,7 @@ class Engine:
     chunk_steps: int = 10
     device: str = "cuda:0"
     keep_results: bool = True
+    poll_s: float = 2e-4          # wait between checks for a finished chunk
     _streams: dict = field(default_factory=dict)
     _batches: dict = field(default_factory=dict)
     _active: dict = field(default_factory=lambda: collections.defaultdict(list))
@@ -115,30 +118,33 @@ class Engine:
                     self.used_bytes + pending[0].footprint <= self.budget_bytes:
                 self._admit(pending.popleft(), clock() - t0)
 
+        in_flight = {}   # precision -> (steps of the chunk, members it advances)
         while len(finished) < total:
-            live = [p for p in self._active if self._active[p]]
-            if not live:
-                admit()
-                if not any(self._active[p] for p in self._active) and pending:
+            # every idle batch with members gets its next chunk
+            for p in list(self._active):
+                if self._active[p] and p not in in_flight:
+                    k = min(self.chunk_steps, min(a.remaining for a in self._active[p]))
+                    self._batches[p].step_async(k)
+                    in_flight[p] = (k, len(self._active[p]))
+            # requests that have arrived are set up while the chunks run; they
+            # join their batch with its next chunk
+            admit()
+            if not in_flight:
+                if pending and not any(self._active[p] for p in self._active):
                     time.sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.01)))
                 continue
-            # advance every non-empty batch by one chunk, the batches concurrently
-            chunk = {}
-            for p in live:
-                k = min(self.chunk_steps, min(a.remaining for a in self._active[p]))
-                chunk[p] = k
-                self._batches[p].step_async(k)
-            # requests that have arrived are set up while the chunk runs; they
-            # join their batch with the next chunk
-            joined = {p: len(self._active[p]) for p in live}
-            admit()
-            for p in live:
+            ready = [p for p in in_flight if self._batches[p].query()]
+            if not ready:
+                time.sleep(self.poll_s)
+                continue
+            for p in ready:
+                k, joined = in_flight.pop(p)
                 rc = self._batches[p].sync()
                 now = clock() - t0
                 still = []
-                ran, newcomers = self._active[p][:joined[p]], self._active[p][joined[p]:]
+                ran, newcomers = self._active[p][:joined], self._active[p][joined:]
                 for a in ran:
-                    a.remaining -= chunk[p]
+                    a.remaining -= k
                     if rc != 0:
                         st_rc = a.state.sync()
                         if st_rc != 0:

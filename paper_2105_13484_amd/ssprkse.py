@@ -35,7 +35,7 @@ EXPORTED = (
     "sse_batch_set_geometry", "sse_batch_program_bytes", "sse_batch_compile", "sse_batch_launches_per_step",
     "sse_batch_use_graph", "sse_batch_step_async", "sse_batch_sync", "sse_batch_step", "sse_footprint_bytes",
     "sse_state_set_bt_variant", "sse_state_get_bt_variant", "sse_state_set_tracer", "sse_read_tracer",
-    "sse_barotropic_substep_noalloc", "sse_debug_set_barrier_spins",
+    "sse_barotropic_substep_noalloc", "sse_debug_set_barrier_spins", "sse_debug_edge_gathers",
 )
 
 # Edge-pass variants: -1 direct gathers, 0 / 1 / 2 LDS tiles of 8 / 16 / 32 edges.
@@ -109,6 +109,7 @@ def load():
         "sse_debug_thickness_stage": (c_int, [P, dp, dp, dp, c_double, dp, dp]),
         "sse_barotropic_substep_noalloc": (c_int, [P, c_int32, c_int32, c_double, P, P, P, P, P, P]),
         "sse_debug_set_barrier_spins": (c_int, [P, ctypes.c_uint32]),
+        "sse_debug_edge_gathers": (c_int, [P]),
         "sse_state_set_edge_variant": (c_int, [P, c_int]),
         "sse_state_get_edge_variant": (c_int, [P, POINTER(c_int)]),
         "sse_state_set_bt_variant": (c_int, [P, c_int]),
@@ -339,6 +340,12 @@ class DeviceState:
     def bt_variant(self, variant: int):
         _check(load().sse_state_set_bt_variant(self.handle, int(variant)))
 
+    def debug_edge_gathers(self):
+        """Enqueue one gather-only edge pass on the state's stream (a
+        measurement aid: the direct edge pass's column loads without its
+        arithmetic; the state is left as it was)."""
+        _check(load().sse_debug_edge_gathers(self.handle))
+
     def set_barrier_spins(self, spins: int = 0):
         """Polls before a grid barrier of the persistent barotropic loop gives up (0: default)."""
         _check(load().sse_debug_set_barrier_spins(self.handle, int(spins)))
@@ -493,6 +500,13 @@ class Batch:
         rc = _check(load().sse_batch_sync(self.handle), allow=(SSE_ENONFINITE,))
         self._retired.clear()
         return rc
+
+    def query(self) -> bool:
+        """True once the steps enqueued on the batch's stream have finished
+        (does not wait; ``sync`` then returns at once with their status)."""
+        import torch
+        s = self.stream if self.stream is not None else torch.cuda.current_stream()
+        return bool(s.query())
 
     def close(self):
         if self.handle:

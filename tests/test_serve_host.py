@@ -53,6 +53,9 @@ class FakeBatch:
         if FakeBatch.clock is not None:
             FakeBatch.clock.t += 1.0       # a chunk takes one time unit
 
+    def query(self):
+        return True             # a chunk has finished by the time anyone asks
+
     def sync(self):
         k, members = self.in_flight
         self.in_flight = None
@@ -174,3 +177,24 @@ def test_oversized_request_is_refused_up_front(engine):
     eng = engine(budget=100, chunk=2)
     with pytest.raises(ValueError):
         eng.run(reqs, clock=StepClock(0.001))
+
+
+def test_a_batch_does_not_wait_for_the_other(engine, monkeypatch):
+    """The FP64 batch's chunks take four polls to finish and the mixed
+    batch's one: the mixed batch gets its next chunks while the FP64 one is
+    still in flight."""
+    reqs = make_requests([(0.0, 8, 0, 10), (0.0, 8, 1, 10)])
+    eng = engine(budget=100, chunk=2)
+    polls = {}
+
+    def query(self):
+        polls[self.prec] = polls.get(self.prec, 0) + 1
+        return self.prec == 1 or polls[self.prec] % 4 == 0
+
+    monkeypatch.setattr(FakeBatch, "query", query)
+    monkeypatch.setattr(serve.time, "sleep", lambda s: None)
+    stats = eng.run(reqs, clock=StepClock(0.001))
+    assert stats["failed"] == 0
+    order = [p for p, *_ in FakeBatch.log]
+    assert order[:5] == [0, 1, 1, 1, 1]
+    assert reqs[0].result == {"steps": 8} and reqs[1].result == {"steps": 8}
