@@ -892,7 +892,8 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.vert_edges.data(), t.vert_curl.data(), t.erec.data(), t.inv_dc.data(),
                          t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
                          t.cell_div_t_f.data(), t.H_f.data(), t.eoe16.data(), t.ecells16.data(),
-                         t.cedges16.data(), t.cnbrs16.data(), ord.cell_old.data(), ord.edge_old.data()};
+                         t.cedges16.data(), t.cnbrs16.data(), ord.cell_old.data(), ord.edge_old.data(),
+                         t.wpair_f.data()};
     static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
     size_t nb[kMeshTables];
     mesh_table_sizes(d->n_cells, d->n_edges, d->n_vertices, nb);
@@ -947,6 +948,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.cnbrs16 = (const int16_t *)P(32);
     dm.cell_old = (const int32_t *)P(33);
     dm.edge_old = (const int32_t *)P(34);
+    dm.wpair_f = (const float *)P(35);
     dm.delta16 = t.delta16;
     dm.ratio_ce = t.ratio_ce;
     dm.ratio_ec = t.ratio_ec;

@@ -66,6 +66,7 @@ struct DevMesh {
     const float *inv_dc_f = nullptr;        // [E]
     const float *cell_div_t_f = nullptr;    // [6][C]
     const float *H_f = nullptr;             // [C]
+    const float *wpair_f = nullptr;         // [E][10][2] wpair rounded to FP32 (the edge pass in mixed precision)
     // 16-bit index tables of the barotropic evaluation (delta16 == 1 when every
     // offset fits): stencil edges as e + eoe16[j][e]; the cells of edge e as
     // bc(e) + low / high half of ecells16[e]; the edges and neighbours of cell
@@ -187,7 +188,7 @@ namespace sse {
 
 // Sizes of the device mesh image (bytes) and the offsets of its tables, in
 // the order in which mesh_create uploads them.
-constexpr int kMeshTables = 35;
+constexpr int kMeshTables = 36;
 void mesh_table_sizes(int C, int E, int V, size_t (&sizes)[kMeshTables]);
 struct MeshLayout {
     size_t off[kMeshTables] = {};
@@ -207,7 +208,7 @@ struct HostMeshTables {
     std::vector<uint8_t> emask;
     std::vector<int32_t> vert_edges;
     std::vector<double> vert_curl;
-    std::vector<float> wf_f, inv_dc_f, cell_div_t_f, H_f;
+    std::vector<float> wf_f, inv_dc_f, cell_div_t_f, H_f, wpair_f;
     std::vector<int16_t> eoe16, cedges16, cnbrs16;
     std::vector<int32_t> ecells16;
     int delta16 = 0;

@@ -638,6 +638,14 @@ __device__ __forceinline__ void div_body(const DivArgs<R> &a, int first) {
 // operand loads: fe_edge_finish receives the column values of the edge, its
 // cells and vertices and the accumulated reconstruction sums.
 // ---------------------------------------------------------------------------
+// TRiSK weight pairs (W / 4, W (f_e + f_j) / 2) of the edge pass in its real type.
+template <typename R>
+__device__ __forceinline__ const R *wpair_of(const DevMesh &m);
+template <>
+__device__ __forceinline__ const double *wpair_of<double>(const DevMesh &m) { return m.wpair; }
+template <>
+__device__ __forceinline__ const float *wpair_of<float>(const DevMesh &m) { return m.wpair_f; }
+
 template <int NK, typename R>
 struct EdgeOperands {
     R u[NK], ut[NK], za[NK], zb[NK], B1[NK], B2[NK], W1[NK], W2[NK];
@@ -925,11 +933,13 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     // (scaling by powers of two is exact).  Padded
     // stencil slots point at the edge itself with zero weights, so the loop
     // runs its full width; its column loads carry no branch between them.
-    const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+    // the weight pairs in R (mixed precision: the FP32 table, the same values
+    // as converting the FP64 ones, without a conversion per term)
+    const R *wp = wpair_of<R>(m) + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
     for (int j = 0; j < kMaxEdges2; ++j) {
         const int ep = rec[j];
-        const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
+        const R wj = wp[2 * j], wfj = wp[2 * j + 1];
         const R ubp = (R)ubar[ep];
         const size_t pb = (size_t)ep * L;
         const size_t pb1 = kChain ? 0 : (size_t)rec[10 + 2 * j] * L;
@@ -1192,10 +1202,10 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
             o.cor[c] = o.vor[c] = R(0);
             o.lap2[c] = R(0);  // the tiled variants run without the biharmonic term
         }
-        const double *wp = m.wpair + (size_t)e * 2 * kMaxEdges2;
+        const R *wp = wpair_of<R>(m) + (size_t)e * 2 * kMaxEdges2;
 #pragma unroll
         for (int j = 0; j < kMaxEdges2; ++j) {
-            const R wj = (R)wp[2 * j], wfj = (R)wp[2 * j + 1];
+            const R wj = wp[2 * j], wfj = wp[2 * j + 1];
             const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
             const R ubp = (R)ubar[rec[j]];
 #pragma unroll

@@ -128,7 +128,8 @@ void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
         E * 32 * 4, E * 8, E * 8, E * 20 * 8,                   // erec, inv_dc, inv_dv, wpair
         E * 10 * 4, E * 4, C * 6 * 4, C * 4,                    // wf_f, inv_dc_f, cell_div_t_f, H_f
         E * 10 * 2, E * 4, C * 6 * 2, C * 6 * 2,                // eoe16, ecells16, cedges16, cnbrs16
-        C * 4, E * 4};                                          // cell_old, edge_old
+        C * 4, E * 4,                                           // cell_old, edge_old
+        E * 20 * 4};                                            // wpair_f
     for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
 }
 
@@ -281,6 +282,7 @@ void build_tables(const sse_mesh_desc *d, HostMeshTables &t) {
     to_f32(t.inv_dc, t.inv_dc_f);
     to_f32(t.cell_div_t, t.cell_div_t_f);
     to_f32(t.H, t.H_f);
+    to_f32(t.wpair, t.wpair_f);
 }
 
 bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t) {
