@@ -878,6 +878,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     size_t need = lay.total;
     for (int q = 0; q < kTileVariants; ++q) need += tiles_bytes(d, kTileSizes[q]);
     need += bt_tiles_bytes(d0);
+    need += wpair_f_bytes(d);
     if (!dev_buf || bytes < need) { set_error("mesh device buffer too small"); return SSE_ENOMEM; }
     if (reinterpret_cast<uintptr_t>(dev_buf) % kAlign) { set_error("mesh device buffer must be 256-byte aligned"); return SSE_EINVAL; }
     HostMeshTables t;
@@ -892,8 +893,7 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                          t.vert_edges.data(), t.vert_curl.data(), t.erec.data(), t.inv_dc.data(),
                          t.inv_dv.data(), t.wpair.data(), t.wf_f.data(), t.inv_dc_f.data(),
                          t.cell_div_t_f.data(), t.H_f.data(), t.eoe16.data(), t.ecells16.data(),
-                         t.cedges16.data(), t.cnbrs16.data(), ord.cell_old.data(), ord.edge_old.data(),
-                         t.wpair_f.data()};
+                         t.cedges16.data(), t.cnbrs16.data(), ord.cell_old.data(), ord.edge_old.data()};
     static_assert(sizeof(src) / sizeof(src[0]) == kMeshTables, "one source per mesh table");
     size_t nb[kMeshTables];
     mesh_table_sizes(d->n_cells, d->n_edges, d->n_vertices, nb);
@@ -948,7 +948,6 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
     dm.cnbrs16 = (const int16_t *)P(32);
     dm.cell_old = (const int32_t *)P(33);
     dm.edge_old = (const int32_t *)P(34);
-    dm.wpair_f = (const float *)P(35);
     dm.delta16 = t.delta16;
     dm.ratio_ce = t.ratio_ce;
     dm.ratio_ec = t.ratio_ec;
@@ -1001,13 +1000,23 @@ extern "C" int sse_mesh_create(const sse_mesh_desc *d, void *dev_buf, size_t byt
                 SSE_HIP(put_err);
                 SSE_HIP(hipStreamSynchronize(s));
                 b.nP = hb.nP;
+                b.dry = std::any_of(t.emask.begin(), t.emask.end(), [](uint8_t x) { return x == 0; }) ? 1 : 0;
                 b.ks = hb.ks;
                 b.lds_d = hb.lds_d;
                 b.lds_f = hb.lds_f;
             }
         }
     }
-    if (cursor > need) { delete m; set_error("internal: tile tables overflow the mesh buffer"); return SSE_EINVAL; }
+    // FP32 weight pairs of the edge pass in mixed precision, last in the image
+    if (cursor + wpair_f_bytes(d) > need) {
+        delete m;
+        set_error("internal: tile tables overflow the mesh buffer");
+        return SSE_EINVAL;
+    }
+    SSE_HIP(hipMemcpyAsync(base + cursor, t.wpair_f.data(), t.wpair_f.size() * 4, hipMemcpyHostToDevice, s));
+    SSE_HIP(hipStreamSynchronize(s));
+    dm.wpair_f = reinterpret_cast<const float *>(base + cursor);
+    cursor += wpair_f_bytes(d);
     m->host_desc.reset(new PermutedDesc(std::move(pd)));
     *out = m;
     return SSE_OK;
@@ -1086,6 +1095,7 @@ extern "C" int sse_footprint_bytes(const sse_mesh_desc *d, const sse_params *p, 
     size_t mb = mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < kTileVariants; ++q) mb += tiles_bytes(d, kTileSizes[q]);
     mb += bt_tiles_bytes(d);
+    mb += wpair_f_bytes(d);
     *bytes = mb + workspace_bytes(d->n_cells, d->n_edges, d->n_vertices, p->n_layers, real_size(p->precision),
                                   bt_size(p->precision), p->hdiff, p->tracer);
     return SSE_OK;

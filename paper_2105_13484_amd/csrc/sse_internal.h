@@ -135,6 +135,7 @@ constexpr int kBtRec = 12;         // ints per patch record
 struct DevBtTiles {
     int nP = 0;                    // patches (0: tiling not available)
     int ks = 0;                    // edge slots per thread needed (1 or 2)
+    int dry = 0;                   // 1: the mesh has land cells or coast edges
     size_t lds_d = 0, lds_f = 0;   // dynamic LDS bytes for R = double / float
     // per patch: e0, es0, c0, cs0, ne[4], nc[4] (offsets into the region
     // lists / the stencil tables, prefix counts per level)
@@ -188,7 +189,7 @@ namespace sse {
 
 // Sizes of the device mesh image (bytes) and the offsets of its tables, in
 // the order in which mesh_create uploads them.
-constexpr int kMeshTables = 36;
+constexpr int kMeshTables = 35;
 void mesh_table_sizes(int C, int E, int V, size_t (&sizes)[kMeshTables]);
 struct MeshLayout {
     size_t off[kMeshTables] = {};
@@ -227,6 +228,9 @@ struct HostTiles {
 // Returns false if a tile needs more than 255 entries in one list.
 bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t);
 size_t tiles_bytes(const sse_mesh_desc *d, int T);
+// Bytes of the FP32 weight pairs (DevMesh::wpair_f), placed after the tile
+// tables so that the other tables keep their offsets in the mesh image.
+size_t wpair_f_bytes(const sse_mesh_desc *d);
 
 // Locality order of a mesh (new -> old and old -> new numbering): cells in
 // compact breadth-first patches of `patch` cells, edges following the first

@@ -128,8 +128,7 @@ void mesh_table_sizes(int C_, int E_, int V_, size_t (&sizes)[kMeshTables]) {
         E * 32 * 4, E * 8, E * 8, E * 20 * 8,                   // erec, inv_dc, inv_dv, wpair
         E * 10 * 4, E * 4, C * 6 * 4, C * 4,                    // wf_f, inv_dc_f, cell_div_t_f, H_f
         E * 10 * 2, E * 4, C * 6 * 2, C * 6 * 2,                // eoe16, ecells16, cedges16, cnbrs16
-        C * 4, E * 4,                                           // cell_old, edge_old
-        E * 20 * 4};                                            // wpair_f
+        C * 4, E * 4};                                          // cell_old, edge_old
     for (int i = 0; i < kMeshTables; ++i) sizes[i] = tab[i];
 }
 
@@ -339,6 +338,10 @@ bool build_tiles(const sse_mesh_desc *d, int T, HostTiles &t) {
 
 // Upper bound of the device bytes of one tile table set (lists at their
 // worst-case length T * 11, 2T * 11 and 2T per tile).
+size_t wpair_f_bytes(const sse_mesh_desc *d) {
+    return ((size_t)d->n_edges * 20 * 4 + kAlign - 1) / kAlign * kAlign;
+}
+
 size_t tiles_bytes(const sse_mesh_desc *d, int T) {
     const size_t E = d->n_edges, nT = (E + T - 1) / T;
     auto al = [](size_t x) { return (x + kAlign - 1) / kAlign * kAlign; };
@@ -949,5 +952,6 @@ extern "C" int sse_mesh_device_bytes(const sse_mesh_desc *d, size_t *bytes) {
     *bytes = sse::mesh_layout(d->n_cells, d->n_edges, d->n_vertices).total;
     for (int q = 0; q < sse::kTileVariants; ++q) *bytes += sse::tiles_bytes(d, sse::kTileSizes[q]);
     *bytes += sse::bt_tiles_bytes(d);
+    *bytes += sse::wpair_f_bytes(d);
     return SSE_OK;
 }
