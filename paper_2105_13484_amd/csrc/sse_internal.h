@@ -128,7 +128,9 @@ constexpr int kBtWavesPerSimd = 4;
 // overlap): 7.98 / 6.23, 5.69 / 4.46; 512 threads and 176 cells: 7.85 /
 // 6.08, 5.77 / 4.49; 160 cells: 7.87 / 6.12, 5.85 / 4.52.  From 192 cells
 // the level-2 edges of many patches exceed 2 x 512, and the split halves
-// cost more (8.45 ms C1).
+// cost more (8.45 ms C1).  256 threads with 72 or 88 cells (four workgroups
+// per CU, a deeper halo per cell): the barotropic class alone takes 4.75 /
+// 5.68 ms per C1 step in FP64 against 2.92.
 constexpr int kBtPatch = 176;
 constexpr int kBtEdgeSlots = 2;    // edges of level 2 per thread (at most)
 constexpr int kBtRec = 12;         // ints per patch record
