@@ -360,8 +360,8 @@ int sse_debug_barotropic_substep(sse_state *s, int32_t scheme, int32_t M, double
  * the state's current arrays and writes their sum into a stage buffer that
  * every step overwrites before reading.  The state steps on unchanged.
  * SSE_EINVAL without canonical stencils, above 64 layers or with arrays of
- * 4 GiB or more; SSE_ESTATE while the state is being recorded into a batch;
- * SSE_EDEVICE if the launch fails. */
+ * 4 GiB or more; SSE_ESTATE before sse_state_init or while the state is being
+ * recorded into a batch; SSE_EDEVICE if the launch fails. */
 int sse_debug_edge_gathers(sse_state *s);
 
 /* Polls a grid barrier of the persistent barotropic loop (variant 2) makes

@@ -1466,6 +1466,7 @@ extern "C" int sse_debug_baroclinic_feuler(sse_state *s, const double *u, const 
 extern "C" int sse_debug_edge_gathers(sse_state *s) {
     if (!s) { set_error("NULL state"); return SSE_EINVAL; }
     if (s->rec) { set_error("state is being recorded into a batch"); return SSE_ESTATE; }
+    if (!s->initialized) { set_error("state not initialised"); return SSE_ESTATE; }
     const DevMesh &m = s->mesh->d;
     const int L = s->p.n_layers;
     if (!m.chain || L > kWave || (fe_edge_variant(m, L, 0, false) & 8)) {
