@@ -76,6 +76,8 @@ struct Work {
                                              // div(lap u) [C][L], curl(lap u) [V][L]
     double *Tn, *T1s, *Th;                   // [C][L], tracer runs only: temperature of the state,
                                              // of the first stage and of the n+1/2 stage
+    void *ubar_r;                            // R [E]: the barotropic velocity an edge pass adds or
+                                             // subtracts, rounded to R (mixed precision)
 };
 
 constexpr int kR3E = 3, kR3C = 2, kR3V = 1, kR2E = 4, kR2C = 4;  // arrays of type R
@@ -91,6 +93,7 @@ size_t bt_size(int precision) { return precision == SSE_MIXED ? sizeof(float) : 
 size_t workspace_bytes(int C, int E, int V, int L, size_t rs, size_t bs, int hdiff, int tracer) {
     size_t b = 0;
     if (tracer) b += 3 * align_up((size_t)C * L * 8);
+    b += align_up((size_t)E * rs);  // ubar_r, last
     if (hdiff == SSE_HDIFF_DEL4)
         b += align_up((size_t)E * L * rs) + 2 * align_up((size_t)C * L * rs) + align_up((size_t)V * L * rs);
     b += kR3E * align_up((size_t)E * L * rs);
@@ -144,6 +147,7 @@ Work carve(void *buf, int C, int E, int V, int L, size_t rs, size_t bs, int hdif
         w.T1s = static_cast<double *>(take((size_t)C * L * 8));
         w.Th = static_cast<double *>(take((size_t)C * L * 8));
     }
+    w.ubar_r = take((size_t)E * rs);
     return w;
 }
 
@@ -339,6 +343,9 @@ bool bt_loop_fits(const sse_state *s, int scheme) {
 }
 
 // ---- building blocks -------------------------------------------------------
+template <typename Tin, typename Tout>
+void convert(sse_state *s, const Tin *src, Tout *dst, size_t n);
+
 template <typename R>
 void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, const double *h, const double *zeta,
              int comb, R *out, double *G, double *sum_h, double *sum_hu, double *sum_hp, double pa, double pb,
@@ -349,6 +356,9 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
     const bool zstar = p.vcoord == SSE_ZSTAR;
     const int nk = nk_of(p.n_layers);
     const bool del4 = p.hdiff == SSE_HDIFF_DEL4;
+    // the FP32 edge pass reads the barotropic velocity of every stencil edge:
+    // rounded to FP32 once here instead of in every gather
+    if constexpr (sizeof(R) == 4) convert<double, float>(s, add ? add : sub, rp<float>(w.ubar_r), (size_t)m.E);
     {
         ProfScope ps(s, SSE_PROF_FE_CELL);
         FECellArgs<R> a{m, p.n_layers, X, add, h, zstar ? w.frac : nullptr, del4 ? 0.0 : p.nu_h, rp<R>(w.B),
@@ -387,6 +397,7 @@ void fe_pass(sse_state *s, const R *X, const double *add, const double *sub, con
         a.X = X;
         a.ubar_add = add;
         a.ubar_sub = sub;
+        if constexpr (sizeof(R) == 4) a.ubar_r = rp<R>(w.ubar_r);
         a.h = h;
         a.rho = w.rho;
         a.B = rp<R>(w.B);

@@ -52,6 +52,7 @@ struct FEEdgeArgs {
     const R *X;               // stage velocity storage
     const double *ubar_add;   // u  = X + ubar_add
     const double *ubar_sub;   // ut = X - ubar_sub
+    const R *ubar_r;          // the one of the two the pass uses, rounded to R (FP32 passes only)
     const double *h;
     const double *rho;        // FP64 in both modes (see the pressure gradient)
     const R *B;

@@ -646,6 +646,14 @@ __device__ __forceinline__ const double *wpair_of<double>(const DevMesh &m) { re
 template <>
 __device__ __forceinline__ const float *wpair_of<float>(const DevMesh &m) { return m.wpair_f; }
 
+// The barotropic velocity at edge e as the pass computes with it: FP64 as
+// stored, or (FP32 pass) the copy rounded to FP32 once per pass.
+template <typename R>
+__device__ __forceinline__ R ubar_at(const FEEdgeArgs<R> &a, const double *ubar, int e) {
+    if constexpr (sizeof(R) == 4) return a.ubar_r[e];
+    else return ubar[e];
+}
+
 template <int NK, typename R>
 struct EdgeOperands {
     R u[NK], ut[NK], za[NK], zb[NK], B1[NK], B2[NK], W1[NK], W2[NK];
@@ -857,7 +865,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
     const int c1 = rec[30], c2 = rec[31];
     const double idc = m.inv_dc[e], idv = m.inv_dv[e];
-    const R ub_e = (R)ubar[e];
+    const R ub_e = ubar_at<R>(a, ubar, e);
     const size_t b1 = (size_t)c1 * L, b2 = (size_t)c2 * L;
 
     EdgeOperands<NK, R> o;
@@ -940,7 +948,7 @@ __device__ __forceinline__ void fe_edge_body(const FEEdgeArgs<R> &a, int col) {
     for (int j = 0; j < kMaxEdges2; ++j) {
         const int ep = rec[j];
         const R wj = wp[2 * j], wfj = wp[2 * j + 1];
-        const R ubp = (R)ubar[ep];
+        const R ubp = ubar_at<R>(a, ubar, ep);
         const size_t pb = (size_t)ep * L;
         const size_t pb1 = kChain ? 0 : (size_t)rec[10 + 2 * j] * L;
         const size_t pb2 = kChain ? 0 : (size_t)rec[11 + 2 * j] * L;
@@ -1173,7 +1181,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
         auto locb = [&](int i) -> int { return (word[i >> 2] >> (8 * (i & 3))) & 0xff; };
         const int ls = locb(0), lv1 = locb(3), lv2 = locb(4);
         const int32_t *rec = m.erec + (size_t)e * kEdgeRec;
-        const R ub_e = (R)ubar[e];
+        const R ub_e = ubar_at<R>(a, ubar, e);
         const int c1 = rec[30], c2 = rec[31];
         const double idcv = m.inv_dc[e], idvv = m.inv_dv[e];
 
@@ -1207,7 +1215,7 @@ __global__ void __launch_bounds__(kTileWaves * kWave) fe_edge_tiled_kernel(FEEdg
         for (int j = 0; j < kMaxEdges2; ++j) {
             const R wj = wp[2 * j], wfj = wp[2 * j + 1];
             const int sl = locb(5 + j), sa = locb(15 + 2 * j), sb = locb(16 + 2 * j);
-            const R ubp = (R)ubar[rec[j]];
+            const R ubp = ubar_at<R>(a, ubar, rec[j]);
 #pragma unroll
             for (int c = 0; c < NK; ++c) {
                 const int k = kk[c];
