@@ -37,7 +37,10 @@ HBM_PEAK_GBS = 8000.0
 # cell-array touches, E = 3C): (13*3 + 14) * 8.
 STEP_BYTES_PER_CELL_LAYER = 424.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2105_13484_amd", "csrc", "sse_kernels.hip")
+# the sources the kernels are compiled from (the argument blocks and tables
+# in the headers shape the code as well)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2105_13484_amd", "csrc", f)
+                  for f in ("sse_kernels.hip", "sse_kernels.h", "sse_internal.h")]
 COPY_PROBE_BYTES = 1 << 30
 
 
@@ -103,9 +106,13 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / s / 1e9
 
 
-def source_sha256(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def kernel_source_sha256():
+    """SHA-256 over the kernel sources, in order."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(dom):
@@ -118,7 +125,7 @@ def measured_traffic(dom):
     except (OSError, ValueError):
         return None
     c = t.get("classes", {}).get(dom)
-    if c is None or t.get("kernel_source_sha256") != source_sha256(KERNEL_SOURCE):
+    if c is None or t.get("kernel_source_sha256") != kernel_source_sha256():
         return None
     return float(c["fetch_bytes_per_launch"]) + float(c["write_bytes_per_launch"])
 
