@@ -607,7 +607,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kb, "intermediate_bytes_per_launch": ib, "launch_ms": avg_ms,
-                     "achievable_copy_gbs": copy_gbs, **(gather if dom == "fe_edge" else {})},
+                     "achievable_copy_gbs": copy_gbs,
+                     # the HBM side as measured: FETCH + WRITE bytes per launch over the launch time
+                     "traffic_gbs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     **(gather if dom == "fe_edge" else {})},
         "edge_gathers": gather,
         "c2": c2,
         "m_sweep": m_sweep,
